@@ -1,0 +1,334 @@
+/*
+ * CPU ORACLE for flow routing -- TEST INFRASTRUCTURE, NOT PART OF THE LIBRARY.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this code.  It shares no code with the GPU library: no headers,
+ * no helpers, no tables.  It is deliberately plain and slow, computes in
+ * float64 / uint64, and follows the paper (W. Bangerth, "Massively parallel
+ * flow routing and drainage area determination") step by step:
+ *
+ *   local flow routing (Section 2.1; Appendix A for multiple receivers)
+ *   -> sort all cells high-to-low (Section 2.1, eq. high-to-low-procedure)
+ *   -> push each cell's water to its receiver(s) in that order
+ *      (Section 2.1 "global flow routing"; Section 3.1 triangular solve)
+ *   -> mass balance check: water leaving through sinks equals total rain
+ *      (Section 4, verification paragraph).
+ *
+ * The result is the unique solution q of (I - W^T) q = r (Section 2.2,
+ * eq. linear-system / Aw=f), W[i][k] being the fraction of cell i's water
+ * given to cell k.  The adjoint solves (I - W) rbar = qbar by the same sweep
+ * in reverse (low-to-high) order.
+ *
+ * Readings of points the paper leaves open (all stated here, once):
+ *  - grid: row-major, row 0 first; neighbour k = 0..7 in row-major window
+ *    order (-1,-1) (-1,0) (-1,+1) (0,-1) (0,+1) (+1,-1) (+1,0) (+1,+1), where
+ *    row -1 is the previous row in memory; off-grid neighbours do not exist.
+ *  - "lower" is strict: z_k < z_i.  A cell with no lower neighbour (boundary
+ *    outlet, pit or flat) is a sink and keeps its water.
+ *  - D8 "steepest downhill gradient" (Section 2.1): slope = drop / distance,
+ *    cell size 1, distance sqrt(2) on diagonals, evaluated in float32 as
+ *    s_k = fl(fl(z_i - z_k) * c_k), c_k = 1 (cardinal) or fl(1/sqrt 2)
+ *    (diagonal); argmax over lower k, ties to the lowest k.  Because this
+ *    float decision picks an integer, it is taken in float32, the GPU's
+ *    precision.  D4 uses the four cardinal neighbours only.
+ *  - MFD (Appendix A): fraction f_k = s_k^p / sum_j s_j^p over strictly lower
+ *    neighbours, s_k = (z_i - z_k) / d_k in float64, d_k = 1 or sqrt(2),
+ *    p = 1.1 by default (Freeman-type slope-power partition).
+ *  - The high-to-low listing sorts pairs by src; it assumes a high-to-low
+ *    numbering, so here cells are sorted by elevation, descending, equal
+ *    elevations by ascending index.  Any order of equal elevations gives the
+ *    same result because equal cells never exchange water.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_SINK 0xFF
+#define OR_D8 0
+#define OR_MFD 1
+#define OR_D4 2
+
+static const int NB_DR[8] = {-1, -1, -1, 0, 0, 1, 1, 1};
+static const int NB_DC[8] = {-1, 0, 1, -1, 1, -1, 0, 1};
+static const int NB_DIAG[8] = {1, 0, 1, 0, 0, 1, 0, 1};
+/* float32 nearest to 1/sqrt(2): bit pattern 0x3F3504F3 */
+static const float INV_SQRT2_F = 0x1.6a09e6p-1f;
+
+/* Neighbour k of cell (r, c), or -1 when it lies off the grid. */
+static inline int64_t neighbour(int64_t nr, int64_t nc, int64_t r, int64_t c, int k) {
+  const int64_t rr = r + NB_DR[k], cc = c + NB_DC[k];
+  if (rr < 0 || rr >= nr || cc < 0 || cc >= nc) return -1;
+  return rr * nc + cc;
+}
+
+/* ---------------------------------------------------------------------------
+ * Local flow routing, single receiver (Section 2.1): D8 or D4 direction code
+ * 0..7 of the steepest strictly lower neighbour, OR_SINK if there is none.
+ */
+static uint8_t single_receiver(const float* z, int64_t nr, int64_t nc, int64_t r, int64_t c,
+                               int rule) {
+  const float zi = z[r * nc + c];
+  int best = -1;
+  float best_s = 0.0f;
+  for (int k = 0; k < 8; ++k) {
+    if (rule == OR_D4 && NB_DIAG[k]) continue;
+    const int64_t j = neighbour(nr, nc, r, c, k);
+    if (j < 0) continue;
+    const float zk = z[j];
+    if (!(zk < zi)) continue;
+    const float drop = zi - zk;
+    const float s = NB_DIAG[k] ? drop * INV_SQRT2_F : drop;
+    if (best < 0 || s > best_s) {
+      best = k;
+      best_s = s;
+    }
+  }
+  return best < 0 ? (uint8_t)OR_SINK : (uint8_t)best;
+}
+
+int or_receivers(const float* z, int64_t nr, int64_t nc, int rule, uint8_t* code) {
+  if (!z || !code || nr < 0 || nc < 0 || (rule != OR_D8 && rule != OR_D4)) return -2;
+  for (int64_t r = 0; r < nr; ++r)
+    for (int64_t c = 0; c < nc; ++c) code[r * nc + c] = single_receiver(z, nr, nc, r, c, rule);
+  return 0;
+}
+
+/* Receiver cell of cell i under direction code cd, or -1 for a sink. */
+static inline int64_t code_target(int64_t nc, int64_t i, uint8_t cd) {
+  if (cd == OR_SINK) return -1;
+  return i + (int64_t)NB_DR[cd] * nc + NB_DC[cd];
+}
+
+/* ---------------------------------------------------------------------------
+ * Local flow routing, multiple receivers (Appendix A): lower-neighbour mask
+ * (bit k set when neighbour k is strictly lower) and fractions f_k.
+ * frac32 != 0 evaluates the same law in float32 arithmetic (used only to
+ * separate fraction rounding from accumulation rounding in error reports).
+ */
+static int mfd_split(const float* z, int64_t nr, int64_t nc, int64_t r, int64_t c, double p,
+                     int frac32, int64_t nb[8], double f[8]) {
+  const int64_t i = r * nc + c;
+  int m = 0;
+  double w[8], sum = 0.0;
+  float w32[8], sum32 = 0.0f;
+  for (int k = 0; k < 8; ++k) {
+    const int64_t j = neighbour(nr, nc, r, c, k);
+    if (j < 0 || !(z[j] < z[i])) continue;
+    nb[m] = j;
+    if (frac32) {
+      const float s = NB_DIAG[k] ? (z[i] - z[j]) * INV_SQRT2_F : (z[i] - z[j]);
+      w32[m] = powf(s, (float)p);
+      sum32 += w32[m];
+    } else {
+      const double s = ((double)z[i] - (double)z[j]) / (NB_DIAG[k] ? sqrt(2.0) : 1.0);
+      w[m] = pow(s, p);
+      sum += w[m];
+    }
+    ++m;
+  }
+  for (int t = 0; t < m; ++t) f[t] = frac32 ? (double)(w32[t] / sum32) : w[t] / sum;
+  return m;
+}
+
+int or_mfd_fractions(const float* z, int64_t nr, int64_t nc, double p, int frac32, uint8_t* mask,
+                     double* frac /* 8 per cell, slot k for neighbour k, or NULL */) {
+  if (!z || nr < 0 || nc < 0) return -2;
+  for (int64_t r = 0; r < nr; ++r) {
+    for (int64_t c = 0; c < nc; ++c) {
+      const int64_t i = r * nc + c;
+      int64_t nb[8];
+      double f[8];
+      const int m = mfd_split(z, nr, nc, r, c, p, frac32, nb, f);
+      uint8_t bits = 0;
+      if (frac) memset(frac + 8 * i, 0, 8 * sizeof(double));
+      int t = 0;
+      for (int k = 0; k < 8 && t < m; ++k) {
+        if (neighbour(nr, nc, r, c, k) == nb[t]) {
+          bits |= (uint8_t)(1u << k);
+          if (frac) frac[8 * i + k] = f[t];
+          ++t;
+        }
+      }
+      if (mask) mask[i] = bits;
+    }
+  }
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * High-to-low order (Section 2.1): sort keys pack a descending float key in
+ * the high 32 bits and the cell index in the low 32 bits, so one ascending
+ * sort of the keys gives elevation descending, index ascending.
+ */
+static int cmp_u64(const void* a, const void* b) {
+  const uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+  return (x > y) - (x < y);
+}
+
+int or_order(const float* z, int64_t n, int64_t* order /* n entries, output */) {
+  if (!z || !order || n < 0 || n > ((int64_t)1 << 32)) return -2;
+  uint64_t* key = (uint64_t*)order; /* sorted in place, then unpacked */
+  for (int64_t i = 0; i < n; ++i) {
+    float v = z[i];
+    if (v == 0.0f) v = 0.0f; /* -0 and +0 are the same elevation */
+    uint32_t u;
+    memcpy(&u, &v, sizeof u);
+    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u); /* ascending with v */
+    key[i] = ((uint64_t)(~u) << 32) | (uint64_t)(uint32_t)i;
+  }
+  qsort(key, (size_t)n, sizeof(uint64_t), cmp_u64);
+  for (int64_t t = 0; t < n; ++t) order[t] = (int64_t)(key[t] & 0xFFFFFFFFu);
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Global flow routing, single receiver (Section 2.1 listing; Section 3.1
+ * in-place triangular solve): q = r, then in high-to-low order
+ * q[dst] += q[src].  rain == NULL means unit rain (drainage area, Section 1).
+ * Either output may be NULL; counts are exact cell counts (unit rain).
+ */
+int or_accumulate_single(const uint8_t* code, int64_t nr, int64_t nc, const int64_t* order,
+                         const float* rain, double* q, uint64_t* counts) {
+  if (!code || !order || nr < 0 || nc < 0) return -2;
+  const int64_t n = nr * nc;
+  if (q) {
+    for (int64_t i = 0; i < n; ++i) q[i] = rain ? (double)rain[i] : 1.0;
+    for (int64_t t = 0; t < n; ++t) {
+      const int64_t i = order[t];
+      const int64_t k = code_target(nc, i, code[i]);
+      if (k >= 0) q[k] += q[i];
+    }
+  }
+  if (counts) {
+    for (int64_t i = 0; i < n; ++i) counts[i] = 1;
+    for (int64_t t = 0; t < n; ++t) {
+      const int64_t i = order[t];
+      const int64_t k = code_target(nc, i, code[i]);
+      if (k >= 0) counts[k] += counts[i];
+    }
+  }
+  return 0;
+}
+
+/*
+ * Global flow routing, multiple receivers (Appendix A): in high-to-low order
+ * q[dst_n] += f_n * q[src], fractions recomputed from z for each cell.
+ */
+int or_accumulate_mfd(const float* z, int64_t nr, int64_t nc, double p, int frac32,
+                      const int64_t* order, const float* rain, double* q) {
+  if (!z || !order || !q || nr < 0 || nc < 0) return -2;
+  const int64_t n = nr * nc;
+  for (int64_t i = 0; i < n; ++i) q[i] = rain ? (double)rain[i] : 1.0;
+  for (int64_t t = 0; t < n; ++t) {
+    const int64_t i = order[t];
+    int64_t nb[8];
+    double f[8];
+    const int m = mfd_split(z, nr, nc, i / nc, i % nc, p, frac32, nb, f);
+    for (int s = 0; s < m; ++s) q[nb[s]] += f[s] * q[i];
+  }
+  return 0;
+}
+
+/*
+ * Adjoint (transpose) solves: (I - W) rbar = qbar.  Row i of I - W couples i
+ * to its receivers only, which are lower and therefore come later in the
+ * high-to-low order, so the sweep runs that order backwards:
+ * rbar[i] = qbar[i] + sum_k f_k * rbar[k].
+ */
+int or_adjoint_single(const uint8_t* code, int64_t nr, int64_t nc, const int64_t* order,
+                      const double* qbar, double* rbar) {
+  if (!code || !order || !qbar || !rbar || nr < 0 || nc < 0) return -2;
+  const int64_t n = nr * nc;
+  for (int64_t i = 0; i < n; ++i) rbar[i] = qbar[i];
+  for (int64_t t = n - 1; t >= 0; --t) {
+    const int64_t i = order[t];
+    const int64_t k = code_target(nc, i, code[i]);
+    if (k >= 0) rbar[i] += rbar[k];
+  }
+  return 0;
+}
+
+int or_adjoint_mfd(const float* z, int64_t nr, int64_t nc, double p, const int64_t* order,
+                   const double* qbar, double* rbar) {
+  if (!z || !order || !qbar || !rbar || nr < 0 || nc < 0) return -2;
+  const int64_t n = nr * nc;
+  for (int64_t i = 0; i < n; ++i) rbar[i] = qbar[i];
+  for (int64_t t = n - 1; t >= 0; --t) {
+    const int64_t i = order[t];
+    int64_t nb[8];
+    double f[8];
+    const int m = mfd_split(z, nr, nc, i / nc, i % nc, p, 0, nb, f);
+    double acc = rbar[i];
+    for (int s = 0; s < m; ++s) acc += f[s] * rbar[nb[s]];
+    rbar[i] = acc;
+  }
+  return 0;
+}
+
+/*
+ * Matrix-free product y = A x with A = I - W^T (Section 3.1, optimized
+ * listing; Appendix A for fractions): y = x, then y[dst] -= f * x[src] for
+ * every routing pair.  Used for the residual r - A q.
+ */
+int or_apply_A_single(const uint8_t* code, int64_t nr, int64_t nc, const double* x, double* y) {
+  if (!code || !x || !y || nr < 0 || nc < 0) return -2;
+  const int64_t n = nr * nc;
+  for (int64_t i = 0; i < n; ++i) y[i] = x[i];
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t k = code_target(nc, i, code[i]);
+    if (k >= 0) y[k] -= x[i];
+  }
+  return 0;
+}
+
+int or_apply_A_mfd(const float* z, int64_t nr, int64_t nc, double p, const double* x, double* y) {
+  if (!z || !x || !y || nr < 0 || nc < 0) return -2;
+  const int64_t n = nr * nc;
+  for (int64_t i = 0; i < n; ++i) y[i] = x[i];
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t nb[8];
+    double f[8];
+    const int m = mfd_split(z, nr, nc, i / nc, i % nc, p, 0, nb, f);
+    for (int s = 0; s < m; ++s) y[nb[s]] -= f[s] * x[i];
+  }
+  return 0;
+}
+
+/*
+ * Mass balance (Section 4 verification): out[0] = water leaving through
+ * sinks (cells with no receiver), out[1] = total rain.
+ */
+int or_mass_single(const uint8_t* code, int64_t n, const float* rain, const double* q,
+                   double out[2]) {
+  if (!code || !q || !out || n < 0) return -2;
+  double s = 0.0, t = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (code[i] == OR_SINK) s += q[i];
+    t += rain ? (double)rain[i] : 1.0;
+  }
+  out[0] = s;
+  out[1] = t;
+  return 0;
+}
+
+int or_mass_mfd(const float* z, int64_t nr, int64_t nc, const float* rain, const double* q,
+                double out[2]) {
+  if (!z || !q || !out || nr < 0 || nc < 0) return -2;
+  double s = 0.0, t = 0.0;
+  for (int64_t r = 0; r < nr; ++r) {
+    for (int64_t c = 0; c < nc; ++c) {
+      const int64_t i = r * nc + c;
+      int lower = 0;
+      for (int k = 0; k < 8; ++k) {
+        const int64_t j = neighbour(nr, nc, r, c, k);
+        if (j >= 0 && z[j] < z[i]) lower = 1;
+      }
+      if (!lower) s += q[i];
+      t += rain ? (double)rain[i] : 1.0;
+    }
+  }
+  out[0] = s;
+  out[1] = t;
+  return 0;
+}
