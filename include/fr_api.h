@@ -1,0 +1,183 @@
+/*
+ * fr_api.h -- C ABI of libflowroute, flow routing on a gridded DEM for AMD
+ * MI355X (gfx950).
+ *
+ * What is computed (W. Bangerth, "Massively parallel flow routing and
+ * drainage area determination"):
+ *   - local flow routing (Section 2.1; Appendix A): for every cell, the
+ *     neighbour(s) that receive its water;
+ *   - global flow routing / drainage area (Section 1, Section 2.1): the water
+ *     q that flows through every cell, i.e. the unique solution of
+ *     (I - W^T) q = r (Section 2.2, eq. linear-system and eq. Aw=f), where r
+ *     is the rain on each cell and W[i][k] the fraction of cell i's water that
+ *     goes to cell k;
+ *   - the adjoint: rbar = (I - W)^{-1} qbar, the gradient of a linear
+ *     functional <qbar, q> with respect to the rain.
+ *
+ * Grids.  Row-major, C-contiguous, row 0 first in memory; cell (r, c) has
+ * linear index r * ncols + c.  Neighbour k = 0..7 of a cell is, in
+ * (drow, dcol): (-1,-1) (-1,0) (-1,+1) (0,-1) (0,+1) (+1,-1) (+1,0) (+1,+1)
+ * ("row-major window order").  Off-grid neighbours do not exist.  Cell size
+ * is 1; diagonal neighbours are at distance sqrt(2).
+ *
+ * Routing rules.
+ *   FR_D8  -- each cell gives all its water to the strictly lower neighbour
+ *             with the steepest slope s_k = fl(fl(z_i - z_k) * c_k),
+ *             c_k = 1 (cardinal) or fl(1/sqrt(2)) (diagonal), computed in
+ *             float32; ties go to the lowest k (Section 2.1, D8 scheme).
+ *   FR_D4  -- as FR_D8 over the four cardinal neighbours (Section 2.1).
+ *   FR_MFD -- each cell splits its water among all strictly lower neighbours
+ *             with fractions f_k = s_k^p / sum_j s_j^p, s_k = (z_i - z_k)/d_k,
+ *             d_k = 1 or sqrt(2) (Appendix A, multiple-flow-direction
+ *             schemes).
+ *   A cell with no strictly lower neighbour (boundary outlet, pit or flat)
+ *   is a sink: its water leaves the grid there (Section 2.1 footnotes).
+ *
+ * Memory ownership.  Every pointer argument is caller-owned memory; the
+ * library never allocates or frees caller memory.  Pointers documented as
+ * "device" must be device (HBM) pointers valid on the current HIP device.
+ * Scratch memory comes only through the (ws, ws_bytes) workspace argument,
+ * sized by fr_workspace_bytes().  Calls on different streams must use
+ * different workspaces.
+ *
+ * Streams.  All device work is enqueued on the given stream.
+ *
+ * Errors.  Return value: FR_OK (0) or a negative FR_ERR_* code from host-side
+ * validation of the arguments, or a HIP error seen while enqueueing.
+ * Conditions only the device can see (non-finite values, malformed codes,
+ * cyclic routing) are reported through the optional device status word
+ * `dev_status` (one int32 in device memory, which the caller zeroes before
+ * the call): the library stores the first such FR_ERR_* code there; the
+ * caller reads it after synchronising the stream.
+ */
+#ifndef FR_API_H
+#define FR_API_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Routing rules. */
+#define FR_D8 0
+#define FR_MFD 1
+#define FR_D4 2
+
+/* Element types of water / rain / adjoint vectors. */
+#define FR_NONE 0
+#define FR_F32 1
+#define FR_F64 2
+
+/* Direction code of a sink in D8/D4 code arrays. */
+#define FR_SINK 0xFF
+
+/* Function identifiers for fr_workspace_bytes. */
+#define FR_FN_ACCUMULATE 1
+#define FR_FN_ADJOINT 2
+
+/* Status codes. */
+#define FR_OK 0
+#define FR_ERR_ARG -1        /* null pointer, negative size, bad flag        */
+#define FR_ERR_RULE -2       /* unknown rule, or output not valid for rule   */
+#define FR_ERR_WORKSPACE -3  /* workspace missing or smaller than required   */
+#define FR_ERR_HIP -4        /* a HIP runtime call failed                    */
+#define FR_ERR_NONFINITE -5  /* device: NaN or Inf in elevation or rain      */
+#define FR_ERR_NOTDAG -6     /* device: routing has a cycle (bad codes)      */
+#define FR_ERR_BADCODE -7    /* device: code not 0..7/0xFF or leaves the grid */
+#define FR_ERR_TOOLARGE -8   /* grid larger than the library supports        */
+
+/*
+ * fr_receivers -- local flow routing (Section 2.1; Appendix A for FR_MFD).
+ *
+ *   z         device, float32[nrows*ncols], elevations.
+ *   nrows,
+ *   ncols     grid shape, >= 0 each (an empty grid is a no-op); at most
+ *             2^31 - 1 cells in total.
+ *   rule      FR_D8, FR_D4 or FR_MFD.
+ *   code_out  device, uint8[nrows*ncols], written:
+ *               D8/D4: direction code k = 0..7 of the receiver, or FR_SINK;
+ *               MFD:   bit k set when neighbour k is strictly lower
+ *                      (0 = sink).
+ *   dev_status optional device int32 (see Errors): FR_ERR_NONFINITE if z
+ *             holds NaN or Inf (codes are then unspecified).
+ *   stream    HIP stream.
+ * Reads z once and writes code_out once.  Needs no workspace.
+ */
+int fr_receivers(const float* z, int64_t nrows, int64_t ncols, int rule, uint8_t* code_out,
+                 int32_t* dev_status, hipStream_t stream);
+
+/*
+ * fr_accumulate -- global flow routing (Section 2.1 high-to-low algorithm,
+ * Section 2.2 linear system, Appendix A for FR_MFD): solves
+ * (I - W^T) q = r for q.  The result equals the high-to-low push; the GPU
+ * reaches it without sorting, by counting unfinished upstream neighbours.
+ *
+ *   z         device float32 elevations; required for FR_MFD (fractions are
+ *             recomputed from it), ignored (may be NULL) for FR_D8/FR_D4.
+ *   code      device uint8 codes as written by fr_receivers for this rule.
+ *   rule      FR_D8, FR_D4 or FR_MFD.
+ *   mfd_p     slope exponent p of FR_MFD (> 0; 1.1 by default); ignored
+ *             otherwise.
+ *   rain      device rain per cell, element type rain_dtype, or NULL for
+ *             unit rain (drainage area, Section 1).
+ *   rain_dtype FR_F32 or FR_F64 (ignored when rain is NULL).
+ *   q_dtype   FR_F32 (compensated float-float accumulation, float32 output),
+ *             FR_F64 (float64 arithmetic and output) or FR_NONE (no q).
+ *   q_out     device float32 or float64 [nrows*ncols] per q_dtype, or NULL
+ *             when q_dtype is FR_NONE.
+ *   counts_out device uint64 [nrows*ncols] exact number of cells draining
+ *             through each cell (unit rain), or NULL.  FR_D8/FR_D4 only.
+ *   mass_out  device float64[2] or NULL: {sum of q over sinks, sum of rain},
+ *             both accumulated in float64 (Section 4 verification check).
+ *             Requires q_dtype != FR_NONE.
+ *   dev_status optional device int32: FR_ERR_NONFINITE (rain not finite),
+ *             FR_ERR_BADCODE, FR_ERR_NOTDAG.
+ *   ws, ws_bytes workspace, at least fr_workspace_bytes(FR_FN_ACCUMULATE,..).
+ *   stream    HIP stream.
+ * The call synchronises the host with the stream a few times while it runs
+ * (it reads back a progress counter); all results are complete when it
+ * returns FR_OK.
+ */
+int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t ncols, int rule,
+                  double mfd_p, const void* rain, int rain_dtype, int q_dtype, void* q_out,
+                  uint64_t* counts_out,
+                  double* mass_out, int32_t* dev_status, void* ws, size_t ws_bytes,
+                  hipStream_t stream);
+
+/*
+ * fr_accumulate_adjoint -- transpose solve (I - W) rbar = qbar, i.e.
+ * rbar_i = qbar_i + sum_k f_{i->k} rbar_k over the receivers k of i, swept
+ * from sinks to sources.  rbar is the gradient of <qbar, q> with respect to
+ * the rain r (A = I - W^T from Section 2.2, transposed).
+ *
+ *   z, code, rule, mfd_p   as for fr_accumulate.
+ *   qbar      device vector of element type dtype (FR_F32 or FR_F64).
+ *   dtype     FR_F32 (float-float accumulation, float32 output) or FR_F64.
+ *   rbar_out  device vector of element type dtype, written.
+ *   dev_status, ws, ws_bytes (FR_FN_ADJOINT), stream as above.
+ */
+int fr_accumulate_adjoint(const float* z, const uint8_t* code, int64_t nrows, int64_t ncols,
+                          int rule, double mfd_p, const void* qbar, int dtype, void* rbar_out,
+                          int32_t* dev_status, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * fr_workspace_bytes -- workspace size for fn = FR_FN_ACCUMULATE or
+ * FR_FN_ADJOINT on an nrows x ncols grid with this rule and dtype (FR_NONE
+ * means counts only).  Returns 0 for invalid arguments.
+ */
+size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dtype);
+
+/* fr_status_string -- static text for a status code. */
+const char* fr_status_string(int code);
+
+/* fr_version -- library version string. */
+const char* fr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FR_API_H */

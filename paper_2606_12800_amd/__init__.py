@@ -1,0 +1,244 @@
+"""Flow routing on a gridded DEM for AMD MI355X (gfx950).
+
+Python binding of ``libflowroute.so`` (C ABI in ``include/fr_api.h``).  Every
+step of the computation runs in the library's HIP kernels; this module only
+marshals torch tensors (device memory, streams) into the C calls.  There is
+no CPU fallback: if the library is missing, importing the binding's compute
+functions raises.
+
+What it computes (W. Bangerth, "Massively parallel flow routing and drainage
+area determination"): local flow routing (Section 2.1, Appendix A) and the
+water q per cell solving (I - W^T) q = r (Section 2.2), plus the adjoint
+solve for gradients with respect to the rain.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libflowroute.so")
+
+# Constants mirrored from include/fr_api.h.
+D8, MFD, D4 = 0, 1, 2
+NONE, F32, F64 = 0, 1, 2
+SINK = 0xFF
+FN_ACCUMULATE, FN_ADJOINT = 1, 2
+OK = 0
+ERR_ARG, ERR_RULE, ERR_WORKSPACE, ERR_HIP = -1, -2, -3, -4
+ERR_NONFINITE, ERR_NOTDAG, ERR_BADCODE, ERR_TOOLARGE = -5, -6, -7, -8
+
+RULES = {"d8": D8, "mfd": MFD, "d4": D4}
+EXPORTS = ["fr_receivers", "fr_accumulate", "fr_accumulate_adjoint", "fr_workspace_bytes",
+           "fr_status_string", "fr_version"]
+
+
+class FlowRouteError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {status_string(code)} ({code})")
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load ``libflowroute.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libflowroute.so not found at {LIB_PATH}; build it with "
+                          f"`python -m paper_2606_12800_amd._build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, ci, cd, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    lib.fr_receivers.argtypes = [vp, i64, i64, ci, vp, vp, vp]
+    lib.fr_receivers.restype = ci
+    lib.fr_accumulate.argtypes = [vp, vp, i64, i64, ci, cd, vp, ci, ci, vp, vp, vp, vp, vp, sz, vp]
+    lib.fr_accumulate.restype = ci
+    lib.fr_accumulate_adjoint.argtypes = [vp, vp, i64, i64, ci, cd, vp, ci, vp, vp, vp, sz, vp]
+    lib.fr_accumulate_adjoint.restype = ci
+    lib.fr_workspace_bytes.argtypes = [ci, i64, i64, ci, ci]
+    lib.fr_workspace_bytes.restype = sz
+    lib.fr_status_string.argtypes = [ci]
+    lib.fr_status_string.restype = ctypes.c_char_p
+    lib.fr_version.argtypes = []
+    lib.fr_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_string(code: int) -> str:
+    return load_library().fr_status_string(int(code)).decode()
+
+
+def workspace_bytes(fn: int, nrows: int, ncols: int, rule: int, dtype: int) -> int:
+    return int(load_library().fr_workspace_bytes(fn, nrows, ncols, rule, dtype))
+
+
+def _rule(rule) -> int:
+    if isinstance(rule, str):
+        return RULES[rule.lower()]
+    return int(rule)
+
+
+def _dtype_code(dtype) -> int:
+    if dtype is None:
+        return NONE
+    if dtype == torch.float32:
+        return F32
+    if dtype == torch.float64:
+        return F64
+    raise ValueError(f"unsupported dtype {dtype}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_grid(t: torch.Tensor, dtype: torch.dtype, name: str):
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D (nrows, ncols)")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be C-contiguous")
+
+
+class Workspace:
+    """Device scratch buffer reused across calls (grows on demand)."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes: int, device) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+        return self.buf
+
+
+_default_ws = Workspace()
+
+
+def _raise_status(status: torch.Tensor, what: str):
+    s = int(status.item())
+    if s != OK:
+        raise FlowRouteError(s, what)
+
+
+def receivers(z: torch.Tensor, rule="d8", check: bool = True) -> torch.Tensor:
+    """Local flow routing: uint8 codes (D8/D4 direction or MFD lower mask)."""
+    _check_grid(z, torch.float32, "z")
+    nr, nc = z.shape
+    code = torch.empty((nr, nc), dtype=torch.uint8, device=z.device)
+    status = torch.zeros(1, dtype=torch.int32, device=z.device)
+    rc = load_library().fr_receivers(_ptr(z), nr, nc, _rule(rule), _ptr(code), _ptr(status),
+                                     _stream(z.device))
+    if rc != OK:
+        raise FlowRouteError(rc, "fr_receivers")
+    if check:
+        _raise_status(status, "fr_receivers")
+    return code
+
+
+def accumulate(code: torch.Tensor, z: torch.Tensor | None = None, rain: torch.Tensor | None = None,
+               rule="d8", dtype=torch.float32, counts: bool = False, mass: bool = False,
+               p: float = 1.1, ws: Workspace | None = None, check: bool = True):
+    """Global flow routing: returns (q, counts, mass) with None for what was not asked."""
+    _check_grid(code, torch.uint8, "code")
+    nr, nc = code.shape
+    dev = code.device
+    r = _rule(rule)
+    if z is not None:
+        _check_grid(z, torch.float32, "z")
+    rdt = F32
+    if rain is not None:
+        if rain.dtype not in (torch.float32, torch.float64):
+            raise TypeError("rain must be float32 or float64")
+        _check_grid(rain, rain.dtype, "rain")
+        rdt = _dtype_code(rain.dtype)
+    dt = _dtype_code(dtype)
+    q = None if dtype is None else torch.empty((nr, nc), dtype=dtype, device=dev)
+    cnt = torch.empty((nr, nc), dtype=torch.uint64, device=dev) if counts else None
+    m = torch.empty(2, dtype=torch.float64, device=dev) if mass else None
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    nbytes = workspace_bytes(FN_ACCUMULATE, nr, nc, r, dt)
+    buf = (ws or _default_ws).get(nbytes, dev)
+    rc = load_library().fr_accumulate(_ptr(z), _ptr(code), nr, nc, r, p, _ptr(rain), rdt, dt, _ptr(q),
+                                      _ptr(cnt), _ptr(m), _ptr(status), _ptr(buf), buf.numel(),
+                                      _stream(dev))
+    if rc != OK:
+        raise FlowRouteError(rc, "fr_accumulate")
+    if check:
+        _raise_status(status, "fr_accumulate")
+    return q, cnt, m
+
+
+def adjoint(code: torch.Tensor, qbar: torch.Tensor, z: torch.Tensor | None = None, rule="d8",
+            p: float = 1.1, ws: Workspace | None = None, check: bool = True) -> torch.Tensor:
+    """Transpose solve (I - W) rbar = qbar; dtype follows qbar (float32 or float64)."""
+    _check_grid(code, torch.uint8, "code")
+    nr, nc = code.shape
+    dev = code.device
+    if qbar.dtype not in (torch.float32, torch.float64):
+        raise TypeError("qbar must be float32 or float64")
+    _check_grid(qbar, qbar.dtype, "qbar")
+    if z is not None:
+        _check_grid(z, torch.float32, "z")
+    r = _rule(rule)
+    dt = _dtype_code(qbar.dtype)
+    rbar = torch.empty_like(qbar)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    nbytes = workspace_bytes(FN_ADJOINT, nr, nc, r, dt)
+    buf = (ws or _default_ws).get(nbytes, dev)
+    rc = load_library().fr_accumulate_adjoint(_ptr(z), _ptr(code), nr, nc, r, p, _ptr(qbar), dt,
+                                              _ptr(rbar), _ptr(status), _ptr(buf), buf.numel(),
+                                              _stream(dev))
+    if rc != OK:
+        raise FlowRouteError(rc, "fr_accumulate_adjoint")
+    if check:
+        _raise_status(status, "fr_accumulate_adjoint")
+    return rbar
+
+
+def route(z: torch.Tensor, rain: torch.Tensor | None = None, rule="d8", dtype=torch.float32,
+          counts: bool = False, mass: bool = False, p: float = 1.1):
+    """Receivers + accumulation.  Returns (code, q, counts, mass)."""
+    code = receivers(z, rule)
+    zz = z if _rule(rule) == MFD else None
+    q, cnt, m = accumulate(code, zz, rain, rule, dtype, counts, mass, p)
+    return code, q, cnt, m
+
+
+class FlowAccumulate(torch.autograd.Function):
+    """q = A^{-1} r with A = I - W^T; backward gives dL/dr = A^{-T} dL/dq.
+
+    ``rain`` float32 uses float-float accumulation with float32 output,
+    float64 uses the float64 path.  The gradient with respect to the
+    elevations is not defined here (routing is piecewise constant in z) and is
+    returned as None.
+    """
+
+    @staticmethod
+    def forward(ctx, rain, z, rule="mfd", p=1.1):
+        code = receivers(z, rule)
+        zz = z if _rule(rule) == MFD else None
+        q, _, _ = accumulate(code, zz, rain.contiguous(), rule, rain.dtype, p=p)
+        ctx.save_for_backward(code, z)
+        ctx.rule, ctx.p = rule, p
+        return q
+
+    @staticmethod
+    def backward(ctx, gq):
+        code, z = ctx.saved_tensors
+        zz = z if _rule(ctx.rule) == MFD else None
+        rbar = adjoint(code, gq.contiguous(), zz, ctx.rule, ctx.p)
+        return rbar, None, None, None

@@ -1,0 +1,606 @@
+// Accumulation engine: solves (I - W^T) q = r (forward) or (I - W) rbar =
+// qbar (adjoint) on the grid's routing DAG without sorting.
+//
+// The paper's sequential algorithm processes cells high-to-low so that every
+// cell is visited after all cells that give it water (Section 2.1); its
+// "optimization 2" notes that only this processing order matters, not the
+// numbering (Section 3.2).  Here the order comes from dependency counting,
+// the shared-memory idea the paper cites as prior art (Section 1, Section
+// 2.1): a cell is ready once all of its inputs (donors for the forward
+// solve, receivers for the adjoint) are final, and then its value is
+//   forward:  v_i = r_i + sum_{donors j} f_{j->i} v_j
+//   adjoint:  v_i = qbar_i + sum_{receivers k} f_{i->k} v_k,
+// pulled in fixed neighbour order, so results do not depend on scheduling.
+//
+// GPU layout.  The grid is cut into ENG_TH x ENG_TW tiles.  A workgroup
+// loads a tile (codes with a one-cell halo, per-cell state) into LDS and
+// peels it: ready cells form a frontier, compacted with wavefront ballots;
+// processing a frontier cell decrements the in-tile pending counts of its
+// outputs in LDS, and cells that reach zero form the next frontier.  Inputs
+// in other tiles are tracked by a per-cell counter in HBM; when a tile
+// finishes a cell whose output lies in another tile it decrements that
+// counter atomically and, at zero, queues the other tile for the next
+// iteration.  Iterations repeat until every cell is final.  On a valid DAG
+// each iteration finishes at least the cells whose inputs were all final, so
+// the number of iterations is bounded by the number of tile boundaries on
+// the longest flow path; on a cyclic input the queue drains with cells left
+// over, which the host reports as FR_ERR_NOTDAG.
+//
+// Precision.  VK_FF keeps every value as an unevaluated float-float sum
+// (hi + lo) so that long rivers accumulate with ~2^-44 relative error while
+// all arithmetic stays in float32; the float32 output is hi.  VK_F64 uses
+// float64.  Counts (unit rain, D8/D4 forward) are exact uint64.
+#include <math.h>
+
+#include "fr_internal.hpp"
+
+namespace fr {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Float-float arithmetic (Dekker 1971; Knuth TAOCP vol. 2, 4.2.2): a value is
+// the unevaluated sum hi + lo with |lo| <= ulp(hi)/2.
+struct ff {
+  float hi, lo;
+};
+
+__device__ __forceinline__ ff ff_two_sum(float a, float b) {
+  const float s = a + b;
+  const float bb = s - a;
+  const float e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+
+__device__ __forceinline__ ff ff_fast_two_sum(float a, float b) {
+  const float s = a + b;
+  return {s, b - (s - a)};
+}
+
+__device__ __forceinline__ ff ff_add(ff x, ff y) {
+  ff s = ff_two_sum(x.hi, y.hi);
+  const float e = s.lo + (x.lo + y.lo);
+  return ff_fast_two_sum(s.hi, e);
+}
+
+// x * f for a float32 factor f.
+__device__ __forceinline__ ff ff_mul_f(ff x, float f) {
+  const float p = x.hi * f;
+  const float e = fmaf(x.hi, f, -p) + x.lo * f;
+  return ff_fast_two_sum(p, e);
+}
+
+// float32 nearest to 1/sqrt(2).
+__device__ constexpr float kInvSqrt2f = 0x1.6a09e6p-1f;
+__device__ constexpr double kSqrt2 = 1.4142135623730950488;
+
+__device__ __forceinline__ void set_status(int32_t* st, int32_t code) {
+  if (st) atomicCAS(st, 0, code);
+}
+
+__device__ __forceinline__ bool is_recv(int rk, uint8_t code, int k) {
+  return rk == RK_SINGLE ? (code == (uint8_t)k) : (((code >> k) & 1u) != 0);
+}
+
+// Weight of the edge from a cell at elevation zh down to a neighbour at zl in
+// direction k (MFD), float32 mode: (s / s_ref)^p with s_ref the cell's
+// steepest slope, so the exponent stays small and exp2/log2 keep ~1 ulp.
+__device__ __forceinline__ float mfd_t32(float zh, float zl, int k, float rs, float p) {
+  const float drop = zh - zl;
+  const float s = nb_diag(k) ? drop * kInvSqrt2f : drop;
+  return exp2f(p * log2f(s * rs));
+}
+
+__device__ __forceinline__ double mfd_w64(float zh, float zl, int k, double p) {
+  const double s = ((double)zh - (double)zl) / (nb_diag(k) ? kSqrt2 : 1.0);
+  return pow(s, p);
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation: per-cell external pending counts, done flags, MFD split
+// constants, argument checks that need the data.
+template <int RK, int DIR, int VK>
+__global__ __launch_bounds__(256) void k_engine_init(EngineParams P) {
+  const int64_t n = P.nrows * P.ncols;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool badcode = false, nonfinite = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t r = i / P.ncols, c = i - r * P.ncols;
+    const int64_t tr = r / ENG_TH, tc = c / ENG_TW;
+    const uint8_t ci = P.code[i];
+    int ext = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int64_t rr = r + nb_dr(k), cc = c + nb_dc(k);
+      const bool in_grid = rr >= 0 && rr < P.nrows && cc >= 0 && cc < P.ncols;
+      const int64_t j = rr * P.ncols + cc;
+      const bool recv = is_recv(RK, ci, k);
+      if (recv && !in_grid) badcode = true;
+      if (!in_grid) continue;
+      bool input;
+      if (DIR == DIR_FWD)
+        input = is_recv(RK, P.code[j], 7 - k);  // neighbour gives water to i
+      else
+        input = recv;  // i gives water to the neighbour
+      if (input && (rr / ENG_TH != tr || cc / ENG_TW != tc)) ++ext;
+      if (RK == RK_MULTI && recv && !(P.z[j] < P.z[i])) badcode = true;
+    }
+    if (RK == RK_SINGLE && ci != SINK && ci > 7) badcode = true;
+    P.ext[i] = (uint8_t)ext;
+    P.done[i] = 0;
+    if (P.src32 && !isfinite(P.src32[i])) nonfinite = true;
+    if (P.src64 && !isfinite(P.src64[i])) nonfinite = true;
+    if (RK == RK_MULTI) {
+      const float zi = P.z[i];
+      if (!isfinite(zi)) nonfinite = true;
+      if (VK == VK_FF) {
+        float smax = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (!is_recv(RK, ci, k)) continue;
+          const int64_t rr = r + nb_dr(k), cc = c + nb_dc(k);
+          if (rr < 0 || rr >= P.nrows || cc < 0 || cc >= P.ncols) continue;
+          const float drop = zi - P.z[rr * P.ncols + cc];
+          const float s = nb_diag(k) ? drop * kInvSqrt2f : drop;
+          smax = s > smax ? s : smax;
+        }
+        const float rs = smax > 0.0f ? 1.0f / smax : 0.0f;
+        float sum = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (!is_recv(RK, ci, k)) continue;
+          const int64_t rr = r + nb_dr(k), cc = c + nb_dc(k);
+          if (rr < 0 || rr >= P.nrows || cc < 0 || cc >= P.ncols) continue;
+          sum += mfd_t32(zi, P.z[rr * P.ncols + cc], k, rs, (float)P.p);
+        }
+        P.rs32[i] = rs;
+        P.iw32[i] = sum > 0.0f ? 1.0f / sum : 0.0f;
+      } else if (VK == VK_F64) {
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (!is_recv(RK, ci, k)) continue;
+          const int64_t rr = r + nb_dr(k), cc = c + nb_dc(k);
+          if (rr < 0 || rr >= P.nrows || cc < 0 || cc >= P.ncols) continue;
+          sum += mfd_w64(zi, P.z[rr * P.ncols + cc], k, P.p);
+        }
+        P.iw64[i] = sum > 0.0 ? 1.0 / sum : 0.0;
+      }
+    }
+  }
+  if (badcode) set_status(P.status, FR_ERR_BADCODE);
+  if (nonfinite) set_status(P.status, FR_ERR_NONFINITE);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int ntiles = P.ntr * P.ntc;
+    P.nlist[0] = ntiles;
+    P.nlist[1] = 0;
+    P.nlist[2] = 0;
+    *P.remaining = (unsigned long long)n;
+  }
+  const int64_t ntiles = (int64_t)P.ntr * P.ntc;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += stride) {
+    P.stamp[t] = 0;
+    P.list0[t] = (int32_t)t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-tile LDS storage.
+template <int RK, int VK, bool CNT>
+struct TileLds {
+  static constexpr int TH = ENG_TH, TW = ENG_TW, HW = ENG_TW + 2;
+  static constexpr int NC = ENG_TH * ENG_TW;
+  static constexpr int NH = (ENG_TH + 2) * (ENG_TW + 2);
+  uint8_t code[NH];
+  // bits 0-7: in-tile inputs not final; bit 8: final; bits 16-23: external
+  // inputs not final when the tile was loaded.
+  uint32_t st[NC];
+  uint16_t front[2][NC];
+  int nf[2];
+  int ndone;
+  ff vff[VK == VK_FF ? NC : 1];
+  double v64[VK == VK_F64 ? NC : 1];
+  uint64_t cnt[CNT ? NC : 1];
+  float z[RK == RK_MULTI ? NH : 1];
+  float rs[(RK == RK_MULTI && VK == VK_FF) ? NH : 1];
+  float iw[(RK == RK_MULTI && VK == VK_FF) ? NH : 1];
+  double iw64[(RK == RK_MULTI && VK == VK_F64) ? NH : 1];
+};
+
+constexpr uint32_t ST_DONE = 1u << 8;
+// Final before this activation loaded the tile: its value is in HBM only.
+constexpr uint32_t ST_PREV = 1u << 9;
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Append local index l to frontier f when pred holds (wavefront ballot +
+// prefix; one LDS atomic per wavefront).  Must be called by all lanes.
+template <class L>
+__device__ __forceinline__ void push_front(L& S, int f, bool pred, int l) {
+  const uint64_t m = __ballot(pred);
+  if (m == 0) return;
+  const int lane = threadIdx.x & 63;
+  int base = 0;
+  if (lane == 0) base = atomicAdd(&S.nf[f], __popcll(m));
+  base = __shfl(base, 0, 64);
+  if (pred) S.front[f][base + __popcll(m & lanemask_lt())] = (uint16_t)l;
+}
+
+// Queue tile t for iteration it + 1 (at most once).
+__device__ __forceinline__ void activate(const EngineParams& P, int it, int64_t t) {
+  if (atomicMax(&P.stamp[t], it + 1) < it + 1) {
+    const int pos = atomicAdd(&P.nlist[(it + 1) % 3], 1);
+    int32_t* next = (it & 1) ? P.list0 : P.list1;
+    next[pos] = (int32_t)t;
+  }
+}
+
+// One output edge of a finished cell leaves the tile: decrement the
+// receiving cell's external counter (byte inside a 32-bit word).
+__device__ __forceinline__ void signal_external(const EngineParams& P, int it, int64_t g, int64_t gr,
+                                                int64_t gc) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(P.ext + (g & ~(int64_t)3));
+  const int sh = 8 * (int)(g & 3);
+  const uint32_t old = atomicSub(w, 1u << sh);
+  if (((old >> sh) & 0xFFu) == 1u) activate(P, it, (gr / ENG_TH) * P.ntc + gc / ENG_TW);
+}
+
+template <int RK, int DIR, int VK, bool CNT>
+__global__ __launch_bounds__(ENG_THREADS) void k_engine_iter(EngineParams P, int it) {
+  using L = TileLds<RK, VK, CNT>;
+  constexpr int TH = L::TH, TW = L::TW, HW = L::HW, NC = L::NC, NH = L::NH;
+  __shared__ L S;
+  const int tid = threadIdx.x;
+  const float pf = (float)P.p;
+  const int n_active = P.nlist[it % 3];
+  const int32_t* list = (it & 1) ? P.list1 : P.list0;
+  if (blockIdx.x == 0 && tid == 0) P.nlist[(it + 2) % 3] = 0;
+
+  for (int e = blockIdx.x; e < n_active; e += gridDim.x) {
+    const int64_t t = list[e];
+    const int64_t tr = t / P.ntc, tc = t - tr * P.ntc;
+    const int64_t r0 = tr * TH, c0 = tc * TW;
+    const int th = (int)(P.nrows - r0 < TH ? P.nrows - r0 : TH);
+    const int tw = (int)(P.ncols - c0 < TW ? P.ncols - c0 : TW);
+
+    // 1. Load codes (and MFD split data) with a one-cell halo.
+    for (int h = tid; h < NH; h += ENG_THREADS) {
+      const int hr = h / HW - 1, hc = h % HW - 1;
+      const int64_t gr = r0 + hr, gc = c0 + hc;
+      const bool in_grid = gr >= 0 && gr < P.nrows && gc >= 0 && gc < P.ncols;
+      const int64_t g = gr * P.ncols + gc;
+      S.code[h] = in_grid ? P.code[g] : (RK == RK_SINGLE ? SINK : (uint8_t)0);
+      if (RK == RK_MULTI) {
+        S.z[h] = in_grid ? P.z[g] : INFINITY;
+        if (VK == VK_FF) {
+          S.rs[h] = in_grid ? P.rs32[g] : 0.0f;
+          S.iw[h] = in_grid ? P.iw32[g] : 0.0f;
+        } else if (VK == VK_F64) {
+          S.iw64[h] = in_grid ? P.iw64[g] : 0.0;
+        }
+      }
+    }
+    // 2. Cell state.
+    for (int l = tid; l < NC; l += ENG_THREADS) {
+      const int lr = l / TW, lc = l % TW;
+      uint32_t st = ST_DONE;
+      if (lr < th && lc < tw) {
+        const int64_t g = (r0 + lr) * P.ncols + (c0 + lc);
+        st = P.done[g] ? (ST_DONE | ST_PREV) : ((uint32_t)P.ext[g] << 16);
+      }
+      S.st[l] = st;
+    }
+    if (tid == 0) {
+      S.nf[0] = 0;
+      S.nf[1] = 0;
+      S.ndone = 0;
+    }
+    // Values read below from other tiles were published before their
+    // external counters reached zero.
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    __syncthreads();
+
+    // 3. In-tile pending inputs of unfinished cells.
+    for (int l = tid; l < NC; l += ENG_THREADS) {
+      if (S.st[l] & ST_DONE) continue;
+      const int lr = l / TW, lc = l % TW;
+      const int h = (lr + 1) * HW + (lc + 1);
+      uint32_t pend = 0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int nr = lr + nb_dr(k), nc = lc + nb_dc(k);
+        if (nr < 0 || nr >= th || nc < 0 || nc >= tw) continue;
+        const int hn = h + nb_dr(k) * HW + nb_dc(k);
+        const bool input = (DIR == DIR_FWD) ? is_recv(RK, S.code[hn], 7 - k) : is_recv(RK, S.code[h], k);
+        if (input && !(S.st[nr * TW + nc] & ST_DONE)) ++pend;
+      }
+      S.st[l] |= pend;
+    }
+    __syncthreads();
+
+    // 4. Initial frontier: unfinished cells with no pending input.
+    for (int l0 = 0; l0 < NC; l0 += ENG_THREADS) {
+      const int l = l0 + tid;
+      const uint32_t st = S.st[l];
+      push_front(S, 0, !(st & ST_DONE) && (st & 0xFFu) == 0 && ((st >> 16) & 0xFFu) == 0, l);
+    }
+
+    // 5. Peel.
+    int cur = 0;
+    for (;;) {
+      __syncthreads();
+      const int nf = S.nf[cur];
+      if (nf == 0) break;
+      if (tid == 0) S.ndone += nf;
+      for (int i0 = 0; i0 < nf; i0 += ENG_THREADS) {
+        const int idx = i0 + tid;
+        const bool act = idx < nf;
+        const int l = act ? S.front[cur][idx] : 0;
+        const int lr = l / TW, lc = l % TW;
+        const int h = (lr + 1) * HW + (lc + 1);
+        const int64_t gr = r0 + lr, gc = c0 + lc;
+        const int64_t g = gr * P.ncols + gc;
+        if (act) {
+          // Value of cell l from its (final) inputs, in neighbour order.
+          ff vf = {0.0f, 0.0f};
+          double vd = 0.0;
+          uint64_t cn = 1;
+          if (VK == VK_FF) {
+            if (P.src64) {
+              const double d = P.src64[g];
+              vf.hi = (float)d;
+              vf.lo = (float)(d - (double)vf.hi);
+            } else {
+              vf.hi = P.src32 ? P.src32[g] : 1.0f;
+            }
+          }
+          if (VK == VK_F64) vd = P.src64 ? P.src64[g] : (P.src32 ? (double)P.src32[g] : 1.0);
+          const uint8_t ci = S.code[h];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int hn = h + nb_dr(k) * HW + nb_dc(k);
+            const bool input = (DIR == DIR_FWD) ? is_recv(RK, S.code[hn], 7 - k) : is_recv(RK, ci, k);
+            if (!input) continue;
+            const int nr = lr + nb_dr(k), nc = lc + nb_dc(k);
+            const int ln = nr * TW + nc;
+            // Inputs finished in this activation are read from LDS, all
+            // others (other tiles, earlier activations) from HBM.
+            const bool in_tile = nr >= 0 && nr < th && nc >= 0 && nc < tw && !(S.st[ln] & ST_PREV);
+            const int64_t gn = g + nb_dr(k) * P.ncols + nb_dc(k);
+            if (gr + nb_dr(k) < 0 || gr + nb_dr(k) >= P.nrows || gc + nb_dc(k) < 0 ||
+                gc + nb_dc(k) >= P.ncols)
+              continue;  // malformed code pointing off the grid
+            if (VK == VK_FF) {
+              ff vj;
+              if (in_tile) vj = S.vff[ln];
+              else vj = {P.vhi[gn], P.vlo[gn]};
+              if (RK == RK_MULTI) {
+                float f;
+                if (DIR == DIR_FWD) f = mfd_t32(S.z[hn], S.z[h], 7 - k, S.rs[hn], pf) * S.iw[hn];
+                else f = mfd_t32(S.z[h], S.z[hn], k, S.rs[h], pf) * S.iw[h];
+                vj = ff_mul_f(vj, f);
+              }
+              vf = ff_add(vf, vj);
+            }
+            if (VK == VK_F64) {
+              double vj = in_tile ? S.v64[ln] : P.v64[gn];
+              if (RK == RK_MULTI) {
+                double f;
+                if (DIR == DIR_FWD) f = mfd_w64(S.z[hn], S.z[h], 7 - k, P.p) * S.iw64[hn];
+                else f = mfd_w64(S.z[h], S.z[hn], k, P.p) * S.iw64[h];
+                vj *= f;
+              }
+              vd += vj;
+            }
+            if (CNT) cn += in_tile ? S.cnt[ln] : P.cnt[gn];
+          }
+          if (VK == VK_FF) {
+            S.vff[l] = vf;
+            P.vhi[g] = vf.hi;
+            P.vlo[g] = vf.lo;
+          }
+          if (VK == VK_F64) {
+            S.v64[l] = vd;
+            P.v64[g] = vd;
+          }
+          if (CNT) {
+            S.cnt[l] = cn;
+            P.cnt[g] = cn;
+          }
+          S.st[l] |= ST_DONE;
+          // Publish the value before any other tile can observe a zero
+          // counter for its consumers.
+          __threadfence();
+        }
+        // Signal outputs: in-tile ones may join the next frontier.
+        const uint8_t ci = act ? S.code[h] : (uint8_t)0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          bool ready = false;
+          int ln = 0;
+          if (act) {
+            const int hn = h + nb_dr(k) * HW + nb_dc(k);
+            const bool out = (DIR == DIR_FWD) ? is_recv(RK, ci, k) : is_recv(RK, S.code[hn], 7 - k);
+            if (out) {
+              const int nr = lr + nb_dr(k), nc = lc + nb_dc(k);
+              if (nr >= 0 && nr < th && nc >= 0 && nc < tw) {
+                ln = nr * TW + nc;
+                const uint32_t old = atomicSub(&S.st[ln], 1u);
+                ready = (old & 0xFFu) == 1u && ((old >> 16) & 0xFFu) == 0u;
+              } else {
+                const int64_t ngr = gr + nb_dr(k), ngc = gc + nb_dc(k);
+                if (ngr >= 0 && ngr < P.nrows && ngc >= 0 && ngc < P.ncols)
+                  signal_external(P, it, ngr * P.ncols + ngc, ngr, ngc);
+              }
+            }
+          }
+          push_front(S, cur ^ 1, ready, ln);
+        }
+      }
+      __syncthreads();
+      if (tid == 0) S.nf[cur] = 0;
+      cur ^= 1;
+    }
+
+    // 6. Persist done flags of this tile (owner-only bytes).
+    for (int l = tid; l < NC; l += ENG_THREADS) {
+      const int lr = l / TW, lc = l % TW;
+      if (lr < th && lc < tw && (S.st[l] & ST_DONE)) P.done[(r0 + lr) * P.ncols + (c0 + lc)] = 1;
+    }
+    if (tid == 0 && S.ndone) atomicAdd(P.remaining, (unsigned long long)(-(long long)S.ndone));
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mass balance (Section 4 verification): {sum over sinks of q, sum of rain},
+// float64, two deterministic stages.
+template <int RK, int VK>
+__global__ __launch_bounds__(256) void k_mass_partial(EngineParams P, double* partial) {
+  const int64_t n = P.nrows * P.ncols;
+  double s = 0.0, t = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint8_t ci = P.code[i];
+    const bool sink = RK == RK_SINGLE ? (ci > 7) : (ci == 0);
+    if (sink) s += VK == VK_FF ? (double)P.vhi[i] + (double)P.vlo[i] : P.v64[i];
+    t += P.src64 ? P.src64[i] : (P.src32 ? (double)P.src32[i] : 1.0);
+  }
+  __shared__ double rs[256], rt[256];
+  rs[threadIdx.x] = s;
+  rt[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      rs[threadIdx.x] += rs[threadIdx.x + w];
+      rt[threadIdx.x] += rt[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = rs[0];
+    partial[2 * blockIdx.x + 1] = rt[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mass_final(const double* partial, int nblocks, double* out) {
+  __shared__ double rs[256], rt[256];
+  double s = 0.0, t = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += 256) {
+    s += partial[2 * b];
+    t += partial[2 * b + 1];
+  }
+  rs[threadIdx.x] = s;
+  rt[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      rs[threadIdx.x] += rs[threadIdx.x + w];
+      rt[threadIdx.x] += rt[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = rs[0];
+    out[1] = rt[0];
+  }
+}
+
+__global__ void k_set_status(int32_t* st, int32_t code) {
+  if (threadIdx.x == 0) atomicCAS(st, 0, code);
+}
+
+__global__ void k_zero_f64(double* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
+}
+
+int init_grid(const EngineParams& P) {
+  const int64_t n = P.nrows * P.ncols;
+  int64_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  return (int)(b < 1 ? 1 : b);
+}
+
+template <int RK, int DIR>
+hipError_t init_dispatch_vk(ValKind vk, const EngineParams& P, hipStream_t s) {
+  const int g = init_grid(P);
+  switch (vk) {
+    case VK_FF: hipLaunchKernelGGL((k_engine_init<RK, DIR, VK_FF>), dim3(g), dim3(256), 0, s, P); break;
+    case VK_F64: hipLaunchKernelGGL((k_engine_init<RK, DIR, VK_F64>), dim3(g), dim3(256), 0, s, P); break;
+    default: hipLaunchKernelGGL((k_engine_init<RK, DIR, VK_NONE>), dim3(g), dim3(256), 0, s, P); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_engine_init(const EngineConfig& cfg, const EngineParams& P, hipStream_t s) {
+  if (cfg.rk == RK_SINGLE)
+    return cfg.dir == DIR_FWD ? init_dispatch_vk<RK_SINGLE, DIR_FWD>(cfg.vk, P, s)
+                              : init_dispatch_vk<RK_SINGLE, DIR_ADJ>(cfg.vk, P, s);
+  return cfg.dir == DIR_FWD ? init_dispatch_vk<RK_MULTI, DIR_FWD>(cfg.vk, P, s)
+                            : init_dispatch_vk<RK_MULTI, DIR_ADJ>(cfg.vk, P, s);
+}
+
+#define FR_ITER(RK, DIR, VK, CNT) \
+  hipLaunchKernelGGL((k_engine_iter<RK, DIR, VK, CNT>), dim3(grid), dim3(ENG_THREADS), 0, s, P, it)
+
+hipError_t launch_engine_iter(const EngineConfig& cfg, const EngineParams& P, int it, int grid,
+                              hipStream_t s) {
+  if (cfg.rk == RK_SINGLE) {
+    if (cfg.dir == DIR_FWD) {
+      if (cfg.counts) {
+        switch (cfg.vk) {
+          case VK_FF: FR_ITER(RK_SINGLE, DIR_FWD, VK_FF, true); break;
+          case VK_F64: FR_ITER(RK_SINGLE, DIR_FWD, VK_F64, true); break;
+          default: FR_ITER(RK_SINGLE, DIR_FWD, VK_NONE, true); break;
+        }
+      } else {
+        switch (cfg.vk) {
+          case VK_FF: FR_ITER(RK_SINGLE, DIR_FWD, VK_FF, false); break;
+          default: FR_ITER(RK_SINGLE, DIR_FWD, VK_F64, false); break;
+        }
+      }
+    } else {
+      if (cfg.vk == VK_FF) FR_ITER(RK_SINGLE, DIR_ADJ, VK_FF, false);
+      else FR_ITER(RK_SINGLE, DIR_ADJ, VK_F64, false);
+    }
+  } else {
+    if (cfg.dir == DIR_FWD) {
+      if (cfg.vk == VK_FF) FR_ITER(RK_MULTI, DIR_FWD, VK_FF, false);
+      else FR_ITER(RK_MULTI, DIR_FWD, VK_F64, false);
+    } else {
+      if (cfg.vk == VK_FF) FR_ITER(RK_MULTI, DIR_ADJ, VK_FF, false);
+      else FR_ITER(RK_MULTI, DIR_ADJ, VK_F64, false);
+    }
+  }
+  return hipGetLastError();
+}
+#undef FR_ITER
+
+hipError_t launch_mass(RuleKind rk, ValKind vk, const EngineParams& P, double* partial, int nblocks,
+                       double* mass_out, hipStream_t s) {
+  if (rk == RK_SINGLE) {
+    if (vk == VK_FF) hipLaunchKernelGGL((k_mass_partial<RK_SINGLE, VK_FF>), dim3(nblocks), dim3(256), 0, s, P, partial);
+    else hipLaunchKernelGGL((k_mass_partial<RK_SINGLE, VK_F64>), dim3(nblocks), dim3(256), 0, s, P, partial);
+  } else {
+    if (vk == VK_FF) hipLaunchKernelGGL((k_mass_partial<RK_MULTI, VK_FF>), dim3(nblocks), dim3(256), 0, s, P, partial);
+    else hipLaunchKernelGGL((k_mass_partial<RK_MULTI, VK_F64>), dim3(nblocks), dim3(256), 0, s, P, partial);
+  }
+  hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(256), 0, s, partial, nblocks, mass_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(double* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_status(int32_t* status, int32_t code, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_status, dim3(1), dim3(64), 0, s, status, code);
+  return hipGetLastError();
+}
+
+}  // namespace fr

@@ -1,0 +1,81 @@
+// Internal declarations of libflowroute (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "fr_api.h"
+
+namespace fr {
+
+// Neighbour k = 0..7 in row-major window order; the neighbour in direction
+// 7 - k is the opposite one, so cell j = i + off[k] reaches i by direction
+// 7 - k.
+__host__ __device__ constexpr int nb_dr(int k) { return k < 3 ? -1 : (k < 5 ? 0 : 1); }
+__host__ __device__ constexpr int nb_dc(int k) {
+  return (k == 0 || k == 3 || k == 5) ? -1 : ((k == 1 || k == 6) ? 0 : 1);
+}
+__host__ __device__ constexpr bool nb_diag(int k) { return k == 0 || k == 2 || k == 5 || k == 7; }
+
+constexpr uint8_t SINK = 0xFF;
+
+// Rule families inside the engine: one receiver per cell (D8 / D4 codes) or
+// several (MFD lower-neighbour masks).
+enum RuleKind { RK_SINGLE = 0, RK_MULTI = 1 };
+// Sweep direction: forward accumulation (sources -> sinks) or adjoint
+// (sinks -> sources).
+enum Dir { DIR_FWD = 0, DIR_ADJ = 1 };
+// Value arithmetic: none (counts only), float-float (float32 output), float64.
+enum ValKind { VK_NONE = 0, VK_FF = 1, VK_F64 = 2 };
+
+// Tile shape of the peeling engine (cells held in LDS by one workgroup).
+constexpr int ENG_TH = 32;
+constexpr int ENG_TW = 64;
+constexpr int ENG_THREADS = 256;
+
+struct EngineParams {
+  int64_t nrows, ncols;
+  int32_t ntr, ntc;            // tile grid
+  const uint8_t* code;         // D8/D4 direction codes or MFD masks
+  const float* z;              // elevations (MFD)
+  double p;                    // MFD slope exponent
+  const float* src32;          // source term (rain or qbar), float32, or NULL
+  const double* src64;         // source term float64, or NULL (both NULL: unit)
+  float* vhi;                  // float-float value, high part (= float32 output)
+  float* vlo;                  // float-float value, low part (workspace)
+  double* v64;                 // float64 value (output)
+  uint64_t* cnt;               // exact counts (D8 forward), or NULL
+  float* rs32;                 // MFD: 1 / steepest slope of the cell (float32 mode)
+  float* iw32;                 // MFD: 1 / sum of normalised weights (float32 mode)
+  double* iw64;                // MFD: 1 / sum of weights (float64 mode)
+  uint8_t* ext;                // per cell: inputs in other tiles not yet finished
+  uint8_t* done;               // per cell: 1 once its value is final
+  int32_t* stamp;              // per tile: last iteration it was queued for
+  int32_t* list0;              // active tile lists (ping-pong)
+  int32_t* list1;
+  int32_t* nlist;              // [3] ring of list lengths
+  unsigned long long* remaining;  // cells not yet finished
+  int32_t* status;             // device status word or NULL
+};
+
+// Launchers (defined in the .hip files).
+hipError_t launch_receivers(const float* z, int64_t nrows, int64_t ncols, int rule, uint8_t* code,
+                            int32_t* status, hipStream_t s);
+
+struct EngineConfig {
+  RuleKind rk;
+  Dir dir;
+  ValKind vk;
+  bool counts;
+};
+
+hipError_t launch_engine_init(const EngineConfig& cfg, const EngineParams& P, hipStream_t s);
+hipError_t launch_engine_iter(const EngineConfig& cfg, const EngineParams& P, int it, int grid,
+                              hipStream_t s);
+hipError_t launch_mass(RuleKind rk, ValKind vk, const EngineParams& P, double* partial,
+                       int nblocks, double* mass_out, hipStream_t s);
+hipError_t launch_set_status(int32_t* status, int32_t code, hipStream_t s);
+hipError_t launch_zero_f64(double* p, int n, hipStream_t s);
+
+}  // namespace fr

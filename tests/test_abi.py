@@ -1,0 +1,127 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol its
+header declares, and rejects bad arguments on the host before any device
+work is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2606_12800_amd as fr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fr_api.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(fr.LIB_PATH):
+        from paper_2606_12800_amd import _build
+        _build.build()
+    return fr.load_library()
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fr_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert "fr_receivers" in names and "fr_accumulate" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(fr.EXPORTS) <= set(names)
+
+
+def test_header_constants_match_binding():
+    text = open(HEADER).read()
+    consts = dict((m.group(1), int(m.group(2), 0)) for m in
+                  re.finditer(r"#define\s+(FR_[A-Z_0-9]+)\s+(-?(?:0x)?[0-9A-Fa-f]+)", text))
+    assert consts["FR_D8"] == fr.D8 and consts["FR_MFD"] == fr.MFD and consts["FR_D4"] == fr.D4
+    assert consts["FR_F32"] == fr.F32 and consts["FR_F64"] == fr.F64 and consts["FR_NONE"] == fr.NONE
+    assert consts["FR_SINK"] == fr.SINK
+    for name in ["ARG", "RULE", "WORKSPACE", "HIP", "NONFINITE", "NOTDAG", "BADCODE", "TOOLARGE"]:
+        assert consts[f"FR_ERR_{name}"] == getattr(fr, f"ERR_{name}")
+
+
+def test_status_strings(lib):
+    for code in [0, -1, -2, -3, -4, -5, -6, -7, -8]:
+        s = fr.status_string(code)
+        assert s and s != "unknown status"
+    assert fr.status_string(12345) == "unknown status"
+    assert b"gfx950" in lib.fr_version()
+
+
+def test_workspace_bytes(lib):
+    a = fr.workspace_bytes(fr.FN_ACCUMULATE, 256, 256, fr.D8, fr.F32)
+    b = fr.workspace_bytes(fr.FN_ACCUMULATE, 256, 256, fr.D8, fr.NONE)
+    c = fr.workspace_bytes(fr.FN_ACCUMULATE, 256, 256, fr.MFD, fr.F32)
+    assert a > b > 0 and c > a
+    assert fr.workspace_bytes(fr.FN_ACCUMULATE, 256, 256, fr.MFD, fr.NONE) == 0
+    assert fr.workspace_bytes(fr.FN_ADJOINT, 256, 256, fr.D8, fr.NONE) == 0
+    assert fr.workspace_bytes(fr.FN_ADJOINT, 64, 64, fr.MFD, fr.F64) > 0
+    assert fr.workspace_bytes(99, 64, 64, fr.D8, fr.F32) == 0
+    assert fr.workspace_bytes(fr.FN_ACCUMULATE, -1, 64, fr.D8, fr.F32) == 0
+    assert fr.workspace_bytes(fr.FN_ACCUMULATE, 64, 64, 7, fr.F32) == 0
+    # too many cells for int32 indices
+    assert fr.workspace_bytes(fr.FN_ACCUMULATE, 1 << 16, 1 << 16, fr.D8, fr.F32) == 0
+    # grows linearly with the cell count
+    big = fr.workspace_bytes(fr.FN_ACCUMULATE, 2048, 2048, fr.D8, fr.F32)
+    assert big > 2048 * 2048 * 6
+
+
+NULL = None
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+
+
+def test_receivers_validation(lib):
+    assert lib.fr_receivers(NULL, -1, 4, fr.D8, FAKE, NULL, NULL) == fr.ERR_ARG
+    assert lib.fr_receivers(FAKE, 4, 4, 9, FAKE, NULL, NULL) == fr.ERR_RULE
+    assert lib.fr_receivers(NULL, 4, 4, fr.D8, FAKE, NULL, NULL) == fr.ERR_ARG
+    assert lib.fr_receivers(FAKE, 4, 4, fr.D8, NULL, NULL, NULL) == fr.ERR_ARG
+    assert lib.fr_receivers(NULL, 0, 5, fr.D8, NULL, NULL, NULL) == fr.OK  # empty grid: no-op
+    assert lib.fr_receivers(FAKE, 1 << 16, 1 << 16, fr.D8, FAKE, NULL, NULL) == fr.ERR_TOOLARGE
+
+
+def _acc(lib, z=FAKE, code=FAKE, nr=8, nc=8, rule=fr.D8, p=1.1, rain=NULL, rdt=fr.F32, qdt=fr.F32,
+         q=FAKE, cnt=NULL, mass=NULL, ws=FAKE, wsb=1 << 40):
+    return lib.fr_accumulate(z, code, nr, nc, rule, p, rain, rdt, qdt, q, cnt, mass, NULL, ws, wsb, NULL)
+
+
+def test_accumulate_validation(lib):
+    assert _acc(lib, nr=-1) == fr.ERR_ARG
+    assert _acc(lib, rule=5) == fr.ERR_RULE
+    assert _acc(lib, qdt=7) == fr.ERR_ARG
+    assert _acc(lib, qdt=fr.NONE) == fr.ERR_ARG            # q_out given but no dtype
+    assert _acc(lib, q=NULL) == fr.ERR_ARG                  # dtype given but no q_out
+    assert _acc(lib, qdt=fr.NONE, q=NULL, cnt=NULL) == fr.ERR_ARG  # nothing to compute
+    assert _acc(lib, qdt=fr.NONE, q=NULL, cnt=FAKE, mass=FAKE) == fr.ERR_ARG
+    assert _acc(lib, rule=fr.MFD, cnt=FAKE) == fr.ERR_RULE  # counts are single-receiver only
+    assert _acc(lib, rule=fr.MFD, qdt=fr.NONE, q=NULL) == fr.ERR_RULE
+    assert _acc(lib, rule=fr.MFD, p=0.0) == fr.ERR_ARG
+    assert _acc(lib, rule=fr.MFD, p=float("nan")) == fr.ERR_ARG
+    assert _acc(lib, rule=fr.MFD, z=NULL) == fr.ERR_ARG
+    assert _acc(lib, code=NULL) == fr.ERR_ARG
+    assert _acc(lib, rain=FAKE, rdt=3) == fr.ERR_ARG
+    assert _acc(lib, ws=NULL) == fr.ERR_WORKSPACE
+    need = fr.workspace_bytes(fr.FN_ACCUMULATE, 8, 8, fr.D8, fr.F32)
+    assert _acc(lib, wsb=need - 1) == fr.ERR_WORKSPACE
+    assert _acc(lib, nr=1 << 16, nc=1 << 16) == fr.ERR_TOOLARGE
+    assert _acc(lib, nr=0, q=NULL, code=NULL, ws=NULL) == fr.OK  # empty grid: no-op
+
+
+def test_adjoint_validation(lib):
+    def adj(z=FAKE, code=FAKE, nr=8, nc=8, rule=fr.D8, p=1.1, qb=FAKE, dt=fr.F32, rb=FAKE, ws=FAKE,
+            wsb=1 << 40):
+        return lib.fr_accumulate_adjoint(z, code, nr, nc, rule, p, qb, dt, rb, NULL, ws, wsb, NULL)
+    assert adj(nr=-3) == fr.ERR_ARG
+    assert adj(rule=4) == fr.ERR_RULE
+    assert adj(dt=fr.NONE) == fr.ERR_ARG
+    assert adj(qb=NULL) == fr.ERR_ARG
+    assert adj(rb=NULL) == fr.ERR_ARG
+    assert adj(rule=fr.MFD, z=NULL) == fr.ERR_ARG
+    assert adj(rule=fr.MFD, p=-1.0) == fr.ERR_ARG
+    assert adj(ws=NULL) == fr.ERR_WORKSPACE
+    assert adj(nr=0) == fr.OK
