@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in fr_api.h: argument validation,
 // workspace carving, kernel enqueue and the iteration driver.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "fr_internal.hpp"
@@ -40,6 +41,46 @@ Layout layout(int64_t nrows, int64_t ncols, int rule, int vdtype) {
   L.list1 = o; o += up(nt * sizeof(int32_t));
   L.ctr = o; o += kAlign;
   L.partial = o; o += up(2 * kMassBlocks * sizeof(double));
+  L.total = o + kAlign;
+  return L;
+}
+
+// Workspace of the row-sweep single-receiver path (fr_d8.hip).  It shares
+// the workspace with the engine: the engine only runs when this path gives up
+// (exit list overflow), after which this path's data is dead.
+struct D8Layout {
+  size_t root_of, node_of, ex_cell, anc0, anc1, cnt0, cnt1, hi0, hi1, lo0, lo1, q0, q1, ctr, mass, total;
+  uint32_t cap;
+};
+
+uint32_t d8_capacity(int64_t n) {
+  if (n <= ((int64_t)1 << 22)) return (uint32_t)(n > 0 ? n : 1);
+  const int64_t c = n / 8;
+  return (uint32_t)(c > ((int64_t)1 << 22) ? c : ((int64_t)1 << 22));
+}
+
+D8Layout d8_layout(int64_t nrows, int64_t ncols, int vdtype, bool counts) {
+  D8Layout L{};
+  const size_t n = (size_t)(nrows * ncols);
+  const size_t nt = (size_t)(((nrows + D8_TH - 1) / D8_TH) * ((ncols + D8_TW - 1) / D8_TW));
+  L.cap = d8_capacity((int64_t)n);
+  const size_t cap = L.cap;
+  size_t o = 0;
+  L.root_of = o; o += up(n * 4);
+  L.node_of = o; o += up(n * 4);
+  L.ex_cell = o; o += up(cap * 4);
+  L.anc0 = o; o += up(cap * 4);
+  L.anc1 = o; o += up(cap * 4);
+  L.cnt0 = o; if (counts) o += up(cap * 8);
+  L.cnt1 = o; if (counts) o += up(cap * 8);
+  L.hi0 = o; if (vdtype == FR_F32) o += up(cap * 4);
+  L.hi1 = o; if (vdtype == FR_F32) o += up(cap * 4);
+  L.lo0 = o; if (vdtype == FR_F32) o += up(cap * 4);
+  L.lo1 = o; if (vdtype == FR_F32) o += up(cap * 4);
+  L.q0 = o; if (vdtype == FR_F64) o += up(cap * 8);
+  L.q1 = o; if (vdtype == FR_F64) o += up(cap * 8);
+  L.ctr = o; o += kAlign;
+  L.mass = o; o += up(nt * 2 * sizeof(double));
   L.total = o + kAlign;
   return L;
 }
@@ -91,6 +132,85 @@ int run_engine(const EngineConfig& cfg, EngineParams P, char* base, const Layout
     if (batch < 64) batch *= 2;
   }
   return FR_OK;
+}
+
+// Row-sweep path for single-receiver codes, forward solve.  Returns FR_OK,
+// an error, or 1 when the exit list overflowed (the caller then runs the
+// engine).
+int run_d8(const uint8_t* code, int64_t nrows, int64_t ncols, const float* rain32, const double* rain64,
+           ValKind vk, float* q32, double* q64, uint64_t* cnt, double* mass_out, int32_t* status, char* base,
+           hipStream_t s) {
+  const bool counts = cnt != nullptr;
+  const D8Layout L = d8_layout(nrows, ncols, vk == VK_FF ? FR_F32 : (vk == VK_F64 ? FR_F64 : FR_NONE), counts);
+  D8Params P{};
+  P.nrows = nrows;
+  P.ncols = ncols;
+  P.ntr = (int32_t)((nrows + D8_TH - 1) / D8_TH);
+  P.ntc = (int32_t)((ncols + D8_TW - 1) / D8_TW);
+  P.code = code;
+  P.rain32 = rain32;
+  P.rain64 = rain64;
+  P.q32 = q32;
+  P.q64 = q64;
+  P.cnt = cnt;
+  P.root_of = reinterpret_cast<uint32_t*>(base + L.root_of);
+  P.node_of = reinterpret_cast<uint32_t*>(base + L.node_of);
+  P.ex_cell = reinterpret_cast<uint32_t*>(base + L.ex_cell);
+  P.anc[0] = reinterpret_cast<uint32_t*>(base + L.anc0);
+  P.anc[1] = reinterpret_cast<uint32_t*>(base + L.anc1);
+  P.ex_cnt[0] = reinterpret_cast<uint64_t*>(base + L.cnt0);
+  P.ex_cnt[1] = reinterpret_cast<uint64_t*>(base + L.cnt1);
+  P.ex_hi[0] = reinterpret_cast<float*>(base + L.hi0);
+  P.ex_hi[1] = reinterpret_cast<float*>(base + L.hi1);
+  P.ex_lo[0] = reinterpret_cast<float*>(base + L.lo0);
+  P.ex_lo[1] = reinterpret_cast<float*>(base + L.lo1);
+  P.ex_q64[0] = reinterpret_cast<double*>(base + L.q0);
+  P.ex_q64[1] = reinterpret_cast<double*>(base + L.q1);
+  uint32_t* ctr = reinterpret_cast<uint32_t*>(base + L.ctr);
+  P.n_exits = ctr;
+  P.flags = reinterpret_cast<int32_t*>(ctr + 4);
+  P.cap = L.cap;
+  P.mass_part = mass_out ? reinterpret_cast<double*>(base + L.mass) : nullptr;
+  P.status = status;
+
+  if (launch_zero_u32(ctr, 16, s) != hipSuccess) return FR_ERR_HIP;
+  if (launch_d8_up(vk, counts, P, s) != hipSuccess) return FR_ERR_HIP;
+  uint32_t n = 0;
+  if (hipMemcpyAsync(&n, ctr, sizeof n, hipMemcpyDeviceToHost, s) != hipSuccess) return FR_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return FR_ERR_HIP;
+  if (n > L.cap) return 1;
+  P.n_ex = n;
+  int fb = 0;
+  if (n > 0) {
+    if (launch_d8_link(P, n, s) != hipSuccess) return FR_ERR_HIP;
+    // A forest of n nodes is at most n deep: 33 rounds always suffice; more
+    // means the exits form a cycle (malformed codes).
+    for (int round = 0;; ++round) {
+      if (round > 33) {
+        if (status && launch_set_status(status, FR_ERR_NOTDAG, s) != hipSuccess) return FR_ERR_HIP;
+        break;
+      }
+      if (launch_zero_u32(reinterpret_cast<uint32_t*>(P.flags), 4, s) != hipSuccess) return FR_ERR_HIP;
+      if (launch_d8_round(vk, counts, P, n, fb, s) != hipSuccess) return FR_ERR_HIP;
+      fb ^= 1;
+      int32_t flag = 0;
+      if (hipMemcpyAsync(&flag, P.flags + 1, sizeof flag, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return FR_ERR_HIP;
+      if (hipStreamSynchronize(s) != hipSuccess) return FR_ERR_HIP;
+      if (!flag) break;
+    }
+  }
+  if (launch_d8_down(vk, counts, P, fb, s) != hipSuccess) return FR_ERR_HIP;
+  if (mass_out) {
+    const int nt = P.ntr * P.ntc;
+    if (launch_mass_final(P.mass_part, nt, mass_out, s) != hipSuccess) return FR_ERR_HIP;
+  }
+  return FR_OK;
+}
+
+bool d8_path_enabled() {
+  const char* e = getenv("FLOWROUTE_D8_PATH");
+  return !(e && strcmp(e, "engine") == 0);
 }
 
 char* aligned_base(void* ws) {
@@ -159,7 +279,13 @@ size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dt
   } else {
     return 0;
   }
-  return layout(nrows, ncols, rule, dtype).total;
+  size_t t = layout(nrows, ncols, rule, dtype).total;
+  if (fn == FR_FN_ACCUMULATE && rule != FR_MFD) {
+    // The counts buffers are sized in, whether or not counts are requested.
+    const size_t t8 = d8_layout(nrows, ncols, dtype, true).total;
+    if (t8 > t) t = t8;
+  }
+  return t;
 }
 
 int fr_receivers(const float* z, int64_t nrows, int64_t ncols, int rule, uint8_t* code_out,
@@ -196,7 +322,8 @@ int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t nc
   if (ncols > kMaxCells / nrows) return FR_ERR_TOOLARGE;
   if (!code || (rule == FR_MFD && !z)) return FR_ERR_ARG;
   const Layout L = layout(nrows, ncols, rule, q_dtype);
-  if (!ws || ws_bytes < L.total) return FR_ERR_WORKSPACE;
+  if (!ws || ws_bytes < fr_workspace_bytes(FR_FN_ACCUMULATE, nrows, ncols, rule, q_dtype))
+    return FR_ERR_WORKSPACE;
   char* base = aligned_base(ws);
 
   EngineConfig cfg;
@@ -204,6 +331,15 @@ int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t nc
   cfg.dir = DIR_FWD;
   cfg.vk = q_dtype == FR_F32 ? VK_FF : (q_dtype == FR_F64 ? VK_F64 : VK_NONE);
   cfg.counts = counts_out != nullptr;
+  if (cfg.rk == RK_SINGLE && d8_path_enabled()) {
+    const float* r32 = (rain && rain_dtype == FR_F32) ? static_cast<const float*>(rain) : nullptr;
+    const double* r64 = (rain && rain_dtype == FR_F64) ? static_cast<const double*>(rain) : nullptr;
+    const int rc = run_d8(code, nrows, ncols, r32, r64, cfg.vk,
+                          q_dtype == FR_F32 ? static_cast<float*>(q_out) : nullptr,
+                          q_dtype == FR_F64 ? static_cast<double*>(q_out) : nullptr, counts_out, mass_out,
+                          dev_status, base, stream);
+    if (rc != 1) return rc;  // 1: exit list overflow, fall back to the engine
+  }
   EngineParams P = common_params(nrows, ncols, code, z, mfd_p, base, L, dev_status);
   P.src32 = (rain && rain_dtype == FR_F32) ? static_cast<const float*>(rain) : nullptr;
   P.src64 = (rain && rain_dtype == FR_F64) ? static_cast<const double*>(rain) : nullptr;

@@ -206,6 +206,37 @@ struct TileLds {
   double iw64[(RK == RK_MULTI && VK == VK_F64) ? NH : 1];
 };
 
+// Device-coherent (agent scope) loads and stores.  The L2 of each XCD is
+// not coherent with the others inside a launch; these accesses are, without
+// the whole-L2 write-back / invalidate that device-scope fences cost.
+__device__ __forceinline__ void st_dev(float* p, float v) {
+  __hip_atomic_store(reinterpret_cast<uint32_t*>(p), __float_as_uint(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float ld_dev(const float* p) {
+  return __uint_as_float(__hip_atomic_load(reinterpret_cast<uint32_t*>(const_cast<float*>(p)),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ double ld_dev(const double* p) {
+  return __longlong_as_double((long long)__hip_atomic_load(
+      reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED,
+      __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ uint64_t ld_dev(const uint64_t* p) {
+  return (uint64_t)__hip_atomic_load(reinterpret_cast<unsigned long long*>(const_cast<uint64_t*>(p)),
+                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until this wavefront's outstanding memory operations have completed.
+__device__ __forceinline__ void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 constexpr uint32_t ST_DONE = 1u << 8;
 // Final before this activation loaded the tile: its value is in HBM only.
 constexpr uint32_t ST_PREV = 1u << 9;
@@ -247,6 +278,35 @@ __device__ __forceinline__ void signal_external(const EngineParams& P, int it, i
   if (((old >> sh) & 0xFFu) == 1u) activate(P, it, (gr / ENG_TH) * P.ntc + gc / ENG_TW);
 }
 
+// Fraction of the water on the edge between cell h and its neighbour hn in
+// direction k (from h): forward solves pull along donor -> h edges (the
+// donor's split), adjoint solves along h -> receiver edges (h's split).
+template <int DIR, class L>
+__device__ __forceinline__ float edge_f32(const L& S, int h, int hn, int k, float p) {
+  if (DIR == DIR_FWD) return mfd_t32(S.z[hn], S.z[h], 7 - k, S.rs[hn], p) * S.iw[hn];
+  return mfd_t32(S.z[h], S.z[hn], k, S.rs[h], p) * S.iw[h];
+}
+template <int DIR, class L>
+__device__ __forceinline__ double edge_f64(const L& S, int h, int hn, int k, double p) {
+  if (DIR == DIR_FWD) return mfd_w64(S.z[hn], S.z[h], 7 - k, p) * S.iw64[hn];
+  return mfd_w64(S.z[h], S.z[hn], k, p) * S.iw64[h];
+}
+
+// Does cell (lr, lc) have an output outside the tile?
+template <int RK, int DIR, class L>
+__device__ __forceinline__ bool leaves(const L& S, int h, int lr, int lc, int th, int tw) {
+  const uint8_t ci = S.code[h];
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int hn = h + nb_dr(k) * L::HW + nb_dc(k);
+    const bool out = (DIR == DIR_FWD) ? is_recv(RK, ci, k) : is_recv(RK, S.code[hn], 7 - k);
+    const int nr = lr + nb_dr(k), nc = lc + nb_dc(k);
+    if (out && !(nr >= 0 && nr < th && nc >= 0 && nc < tw)) any = true;
+  }
+  return any;
+}
+
 template <int RK, int DIR, int VK, bool CNT>
 __global__ __launch_bounds__(ENG_THREADS) void k_engine_iter(EngineParams P, int it) {
   using L = TileLds<RK, VK, CNT>;
@@ -285,7 +345,7 @@ __global__ __launch_bounds__(ENG_THREADS) void k_engine_iter(EngineParams P, int
     // 2. Cell state.
     for (int l = tid; l < NC; l += ENG_THREADS) {
       const int lr = l / TW, lc = l % TW;
-      uint32_t st = ST_DONE;
+      uint32_t st = ST_DONE | ST_PREV;  // outside the grid: never written
       if (lr < th && lc < tw) {
         const int64_t g = (r0 + lr) * P.ncols + (c0 + lc);
         st = P.done[g] ? (ST_DONE | ST_PREV) : ((uint32_t)P.ext[g] << 16);
@@ -297,26 +357,74 @@ __global__ __launch_bounds__(ENG_THREADS) void k_engine_iter(EngineParams P, int
       S.nf[1] = 0;
       S.ndone = 0;
     }
-    // Values read below from other tiles were published before their
-    // external counters reached zero.
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
     __syncthreads();
 
-    // 3. In-tile pending inputs of unfinished cells.
+    // 3. For each unfinished cell: in-tile inputs still pending, and the
+    //    part of its value that is already known -- its source term plus
+    //    every input that was final when the tile was loaded (inputs in
+    //    other tiles, inputs of this tile finished in earlier launches).  A
+    //    cell with an unfinished input in another tile cannot finish in this
+    //    activation; it is skipped.
     for (int l = tid; l < NC; l += ENG_THREADS) {
-      if (S.st[l] & ST_DONE) continue;
+      const uint32_t st = S.st[l];
+      if (st & ST_DONE) continue;
+      const bool ext_ready = ((st >> 16) & 0xFFu) == 0u;
       const int lr = l / TW, lc = l % TW;
       const int h = (lr + 1) * HW + (lc + 1);
+      const int64_t gr = r0 + lr, gc = c0 + lc;
+      const int64_t g = gr * P.ncols + gc;
+      const uint8_t ci = S.code[h];
       uint32_t pend = 0;
+      ff vf = {0.0f, 0.0f};
+      double vd = 0.0;
+      uint64_t cn = 1;
+      if (ext_ready) {
+        if (VK == VK_FF) {
+          if (P.src64) {
+            const double d = P.src64[g];
+            vf.hi = (float)d;
+            vf.lo = (float)(d - (double)vf.hi);
+          } else {
+            vf.hi = P.src32 ? P.src32[g] : 1.0f;
+          }
+        }
+        if (VK == VK_F64) vd = P.src64 ? P.src64[g] : (P.src32 ? (double)P.src32[g] : 1.0);
+      }
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const int nr = lr + nb_dr(k), nc = lc + nb_dc(k);
-        if (nr < 0 || nr >= th || nc < 0 || nc >= tw) continue;
         const int hn = h + nb_dr(k) * HW + nb_dc(k);
-        const bool input = (DIR == DIR_FWD) ? is_recv(RK, S.code[hn], 7 - k) : is_recv(RK, S.code[h], k);
-        if (input && !(S.st[nr * TW + nc] & ST_DONE)) ++pend;
+        const bool input = (DIR == DIR_FWD) ? is_recv(RK, S.code[hn], 7 - k) : is_recv(RK, ci, k);
+        if (!input) continue;
+        const int nr = lr + nb_dr(k), nc = lc + nb_dc(k);
+        if (gr + nb_dr(k) < 0 || gr + nb_dr(k) >= P.nrows || gc + nb_dc(k) < 0 || gc + nb_dc(k) >= P.ncols)
+          continue;  // malformed code pointing off the grid
+        const bool same = nr >= 0 && nr < th && nc >= 0 && nc < tw;
+        if (same && !(S.st[nr * TW + nc] & ST_DONE)) {
+          ++pend;
+          continue;
+        }
+        if (!ext_ready) continue;
+        // Final input: this tile from an earlier launch (plain load) or
+        // another tile, possibly finished during this launch (coherent load).
+        const int64_t gn = g + nb_dr(k) * P.ncols + nb_dc(k);
+        if (VK == VK_FF) {
+          ff vj = same ? ff{P.vhi[gn], P.vlo[gn]} : ff{ld_dev(P.vhi + gn), ld_dev(P.vlo + gn)};
+          if (RK == RK_MULTI) vj = ff_mul_f(vj, edge_f32<DIR>(S, h, hn, k, pf));
+          vf = ff_add(vf, vj);
+        }
+        if (VK == VK_F64) {
+          double vj = same ? P.v64[gn] : ld_dev(P.v64 + gn);
+          if (RK == RK_MULTI) vj *= edge_f64<DIR>(S, h, hn, k, P.p);
+          vd += vj;
+        }
+        if (CNT) cn += same ? P.cnt[gn] : ld_dev(P.cnt + gn);
       }
-      S.st[l] |= pend;
+      S.st[l] = st | pend;
+      if (ext_ready) {
+        if (VK == VK_FF) S.vff[l] = vf;
+        if (VK == VK_F64) S.v64[l] = vd;
+        if (CNT) S.cnt[l] = cn;
+      }
     }
     __syncthreads();
 
@@ -327,7 +435,9 @@ __global__ __launch_bounds__(ENG_THREADS) void k_engine_iter(EngineParams P, int
       push_front(S, 0, !(st & ST_DONE) && (st & 0xFFu) == 0 && ((st >> 16) & 0xFFu) == 0, l);
     }
 
-    // 5. Peel.
+    // 5. Peel, in LDS only: a frontier cell adds the values of its in-tile
+    //    inputs finished in this activation (in neighbour order) to its known
+    //    part, then releases its in-tile outputs.
     int cur = 0;
     for (;;) {
       __syncthreads();
@@ -340,82 +450,40 @@ __global__ __launch_bounds__(ENG_THREADS) void k_engine_iter(EngineParams P, int
         const int l = act ? S.front[cur][idx] : 0;
         const int lr = l / TW, lc = l % TW;
         const int h = (lr + 1) * HW + (lc + 1);
-        const int64_t gr = r0 + lr, gc = c0 + lc;
-        const int64_t g = gr * P.ncols + gc;
+        const uint8_t ci = act ? S.code[h] : (uint8_t)0;
         if (act) {
-          // Value of cell l from its (final) inputs, in neighbour order.
           ff vf = {0.0f, 0.0f};
           double vd = 0.0;
-          uint64_t cn = 1;
-          if (VK == VK_FF) {
-            if (P.src64) {
-              const double d = P.src64[g];
-              vf.hi = (float)d;
-              vf.lo = (float)(d - (double)vf.hi);
-            } else {
-              vf.hi = P.src32 ? P.src32[g] : 1.0f;
-            }
-          }
-          if (VK == VK_F64) vd = P.src64 ? P.src64[g] : (P.src32 ? (double)P.src32[g] : 1.0);
-          const uint8_t ci = S.code[h];
+          uint64_t cn = 0;
+          if (VK == VK_FF) vf = S.vff[l];
+          if (VK == VK_F64) vd = S.v64[l];
+          if (CNT) cn = S.cnt[l];
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
             const int hn = h + nb_dr(k) * HW + nb_dc(k);
             const bool input = (DIR == DIR_FWD) ? is_recv(RK, S.code[hn], 7 - k) : is_recv(RK, ci, k);
             if (!input) continue;
             const int nr = lr + nb_dr(k), nc = lc + nb_dc(k);
+            if (!(nr >= 0 && nr < th && nc >= 0 && nc < tw)) continue;
             const int ln = nr * TW + nc;
-            // Inputs finished in this activation are read from LDS, all
-            // others (other tiles, earlier activations) from HBM.
-            const bool in_tile = nr >= 0 && nr < th && nc >= 0 && nc < tw && !(S.st[ln] & ST_PREV);
-            const int64_t gn = g + nb_dr(k) * P.ncols + nb_dc(k);
-            if (gr + nb_dr(k) < 0 || gr + nb_dr(k) >= P.nrows || gc + nb_dc(k) < 0 ||
-                gc + nb_dc(k) >= P.ncols)
-              continue;  // malformed code pointing off the grid
+            if (S.st[ln] & ST_PREV) continue;  // already in the known part
             if (VK == VK_FF) {
-              ff vj;
-              if (in_tile) vj = S.vff[ln];
-              else vj = {P.vhi[gn], P.vlo[gn]};
-              if (RK == RK_MULTI) {
-                float f;
-                if (DIR == DIR_FWD) f = mfd_t32(S.z[hn], S.z[h], 7 - k, S.rs[hn], pf) * S.iw[hn];
-                else f = mfd_t32(S.z[h], S.z[hn], k, S.rs[h], pf) * S.iw[h];
-                vj = ff_mul_f(vj, f);
-              }
+              ff vj = S.vff[ln];
+              if (RK == RK_MULTI) vj = ff_mul_f(vj, edge_f32<DIR>(S, h, hn, k, pf));
               vf = ff_add(vf, vj);
             }
             if (VK == VK_F64) {
-              double vj = in_tile ? S.v64[ln] : P.v64[gn];
-              if (RK == RK_MULTI) {
-                double f;
-                if (DIR == DIR_FWD) f = mfd_w64(S.z[hn], S.z[h], 7 - k, P.p) * S.iw64[hn];
-                else f = mfd_w64(S.z[h], S.z[hn], k, P.p) * S.iw64[h];
-                vj *= f;
-              }
+              double vj = S.v64[ln];
+              if (RK == RK_MULTI) vj *= edge_f64<DIR>(S, h, hn, k, P.p);
               vd += vj;
             }
-            if (CNT) cn += in_tile ? S.cnt[ln] : P.cnt[gn];
+            if (CNT) cn += S.cnt[ln];
           }
-          if (VK == VK_FF) {
-            S.vff[l] = vf;
-            P.vhi[g] = vf.hi;
-            P.vlo[g] = vf.lo;
-          }
-          if (VK == VK_F64) {
-            S.v64[l] = vd;
-            P.v64[g] = vd;
-          }
-          if (CNT) {
-            S.cnt[l] = cn;
-            P.cnt[g] = cn;
-          }
-          S.st[l] |= ST_DONE;
-          // Publish the value before any other tile can observe a zero
-          // counter for its consumers.
-          __threadfence();
+          if (VK == VK_FF) S.vff[l] = vf;
+          if (VK == VK_F64) S.v64[l] = vd;
+          if (CNT) S.cnt[l] = cn;
+          atomicOr(&S.st[l], ST_DONE);
         }
-        // Signal outputs: in-tile ones may join the next frontier.
-        const uint8_t ci = act ? S.code[h] : (uint8_t)0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           bool ready = false;
@@ -423,17 +491,11 @@ __global__ __launch_bounds__(ENG_THREADS) void k_engine_iter(EngineParams P, int
           if (act) {
             const int hn = h + nb_dr(k) * HW + nb_dc(k);
             const bool out = (DIR == DIR_FWD) ? is_recv(RK, ci, k) : is_recv(RK, S.code[hn], 7 - k);
-            if (out) {
-              const int nr = lr + nb_dr(k), nc = lc + nb_dc(k);
-              if (nr >= 0 && nr < th && nc >= 0 && nc < tw) {
-                ln = nr * TW + nc;
-                const uint32_t old = atomicSub(&S.st[ln], 1u);
-                ready = (old & 0xFFu) == 1u && ((old >> 16) & 0xFFu) == 0u;
-              } else {
-                const int64_t ngr = gr + nb_dr(k), ngc = gc + nb_dc(k);
-                if (ngr >= 0 && ngr < P.nrows && ngc >= 0 && ngc < P.ncols)
-                  signal_external(P, it, ngr * P.ncols + ngc, ngr, ngc);
-              }
+            const int nr = lr + nb_dr(k), nc = lc + nb_dc(k);
+            if (out && nr >= 0 && nr < th && nc >= 0 && nc < tw) {
+              ln = nr * TW + nc;
+              const uint32_t old = atomicSub(&S.st[ln], 1u);
+              ready = (old & 0xFFu) == 1u && ((old >> 16) & 0xFFu) == 0u;
             }
           }
           push_front(S, cur ^ 1, ready, ln);
@@ -444,10 +506,54 @@ __global__ __launch_bounds__(ENG_THREADS) void k_engine_iter(EngineParams P, int
       cur ^= 1;
     }
 
-    // 6. Persist done flags of this tile (owner-only bytes).
+    // 6. Write the cells finished in this activation (coalesced rows).
+    //    Values that other tiles consume go out device-coherently, and the
+    //    stores complete before their consumers' counters are released.
     for (int l = tid; l < NC; l += ENG_THREADS) {
+      const uint32_t st = S.st[l];
+      if (!(st & ST_DONE) || (st & ST_PREV)) continue;
       const int lr = l / TW, lc = l % TW;
-      if (lr < th && lc < tw && (S.st[l] & ST_DONE)) P.done[(r0 + lr) * P.ncols + (c0 + lc)] = 1;
+      const int h = (lr + 1) * HW + (lc + 1);
+      const int64_t g = (r0 + lr) * P.ncols + (c0 + lc);
+      const bool lv = leaves<RK, DIR>(S, h, lr, lc, th, tw);
+      if (VK == VK_FF) {
+        if (lv) {
+          st_dev(P.vhi + g, S.vff[l].hi);
+          st_dev(P.vlo + g, S.vff[l].lo);
+        } else {
+          P.vhi[g] = S.vff[l].hi;
+          P.vlo[g] = S.vff[l].lo;
+        }
+      }
+      if (VK == VK_F64) {
+        if (lv) st_dev(P.v64 + g, S.v64[l]);
+        else P.v64[g] = S.v64[l];
+      }
+      if (CNT) {
+        if (lv) st_dev(P.cnt + g, S.cnt[l]);
+        else P.cnt[g] = S.cnt[l];
+      }
+      P.done[g] = 1;
+    }
+    wait_stores();
+    // 7. Release the external outputs of the newly finished cells.
+    for (int l = tid; l < NC; l += ENG_THREADS) {
+      const uint32_t st = S.st[l];
+      if (!(st & ST_DONE) || (st & ST_PREV)) continue;
+      const int lr = l / TW, lc = l % TW;
+      const int h = (lr + 1) * HW + (lc + 1);
+      const int64_t gr = r0 + lr, gc = c0 + lc;
+      const uint8_t ci = S.code[h];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int hn = h + nb_dr(k) * HW + nb_dc(k);
+        const bool out = (DIR == DIR_FWD) ? is_recv(RK, ci, k) : is_recv(RK, S.code[hn], 7 - k);
+        const int nr = lr + nb_dr(k), nc = lc + nb_dc(k);
+        if (!out || (nr >= 0 && nr < th && nc >= 0 && nc < tw)) continue;
+        const int64_t ngr = gr + nb_dr(k), ngc = gc + nb_dc(k);
+        if (ngr >= 0 && ngr < P.nrows && ngc >= 0 && ngc < P.ncols)
+          signal_external(P, it, ngr * P.ncols + ngc, ngr, ngc);
+      }
     }
     if (tid == 0 && S.ndone) atomicAdd(P.remaining, (unsigned long long)(-(long long)S.ndone));
     __syncthreads();
@@ -510,6 +616,10 @@ __global__ __launch_bounds__(256) void k_mass_final(const double* partial, int n
 
 __global__ void k_set_status(int32_t* st, int32_t code) {
   if (threadIdx.x == 0) atomicCAS(st, 0, code);
+}
+
+__global__ void k_zero_u32(uint32_t* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
 __global__ void k_zero_f64(double* p, int n) {
@@ -590,6 +700,16 @@ hipError_t launch_mass(RuleKind rk, ValKind vk, const EngineParams& P, double* p
     else hipLaunchKernelGGL((k_mass_partial<RK_MULTI, VK_F64>), dim3(nblocks), dim3(256), 0, s, P, partial);
   }
   hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(256), 0, s, partial, nblocks, mass_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mass_final(const double* partial, int nblocks, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(256), 0, s, partial, nblocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, p, n);
   return hipGetLastError();
 }
 

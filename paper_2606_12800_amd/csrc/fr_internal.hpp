@@ -59,7 +59,43 @@ struct EngineParams {
   int32_t* status;             // device status word or NULL
 };
 
+// Row-sweep single-receiver path (fr_d8.hip): tile = D8_TH rows x one
+// wavefront of columns.
+constexpr int D8_TW = 64;
+constexpr int D8_TH = 256;
+
+struct D8Params {
+  int64_t nrows, ncols;
+  int32_t ntr, ntc;
+  const uint8_t* code;
+  const float* rain32;         // or NULL
+  const double* rain64;        // or NULL (both NULL: unit rain)
+  float* q32;                  // outputs (NULL when not requested)
+  double* q64;
+  uint64_t* cnt;
+  uint32_t* root_of;           // per cell, written for inlets: root cell
+  uint32_t* node_of;           // per cell, written for exits: exit index
+  uint32_t* ex_cell;           // exit list [cap]
+  uint64_t* ex_cnt[2];         // exit sums, two buffers for pointer doubling
+  float* ex_hi[2];
+  float* ex_lo[2];
+  double* ex_q64[2];
+  uint32_t* anc[2];
+  uint32_t* n_exits;           // exit counter
+  uint32_t cap;
+  uint32_t n_ex;               // number of exits (set after phase A)
+  int32_t* flags;              // [1]: some exit still has an ancestor
+  double* mass_part;           // per tile {sum over sinks, sum of rain}, or NULL
+  int32_t* status;
+};
+
 // Launchers (defined in the .hip files).
+hipError_t launch_d8_up(ValKind vk, bool cnt, const D8Params& P, hipStream_t s);
+hipError_t launch_d8_link(const D8Params& P, uint32_t n, hipStream_t s);
+hipError_t launch_d8_round(ValKind vk, bool cnt, const D8Params& P, uint32_t n, int b, hipStream_t s);
+hipError_t launch_d8_down(ValKind vk, bool cnt, const D8Params& P, int fb, hipStream_t s);
+hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
+hipError_t launch_mass_final(const double* partial, int nblocks, double* out, hipStream_t s);
 hipError_t launch_receivers(const float* z, int64_t nrows, int64_t ncols, int rule, uint8_t* code,
                             int32_t* status, hipStream_t s);
 

@@ -54,6 +54,14 @@ def relnorm(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+@pytest.fixture(params=["sweep", "engine"])
+def d8path(request, monkeypatch):
+    """Single-receiver accumulation has two GPU paths: row sweeps with an exit
+    forest (default) and the general peeling engine (its fallback)."""
+    monkeypatch.setenv("FLOWROUTE_D8_PATH", "engine" if request.param == "engine" else "auto")
+    return request.param
+
+
 SHAPES = [(256, 256, 1), (97, 131, 7), (1, 1, 8), (1, 300, 9), (300, 1, 10), (64, 64, 11),
           (200, 1030, 12), (513, 777, 2)]
 
@@ -103,7 +111,7 @@ def test_receivers_unaligned_width_and_flat():
 
 @pytest.mark.parametrize("nr,nc,seed", SHAPES)
 @pytest.mark.parametrize("rule", ["d8", "d4"])
-def test_counts_bitexact(nr, nc, seed, rule):
+def test_counts_bitexact(nr, nc, seed, rule, d8path):
     print(f"counts {rule} {nr}x{nc} seed {seed}", flush=True)
     z = synth.dem(seed, nr, nc)
     code = fr.receivers(dev(z), rule)
@@ -115,7 +123,7 @@ def test_counts_bitexact(nr, nc, seed, rule):
 
 
 @pytest.mark.parametrize("nr,nc,seed", [(256, 256, 1), (513, 777, 2), (97, 131, 7), (1, 300, 9)])
-def test_d8_rain_float32_and_counts(nr, nc, seed):
+def test_d8_rain_float32_and_counts(nr, nc, seed, d8path):
     print(f"d8 rain f32 {nr}x{nc} seed {seed}", flush=True)
     z = synth.dem(seed, nr, nc)
     rain = synth.rain(seed, nr, nc)
@@ -130,7 +138,7 @@ def test_d8_rain_float32_and_counts(nr, nc, seed):
 
 
 @pytest.mark.parametrize("nr,nc,seed", [(256, 256, 1), (513, 777, 2), (1, 300, 9), (300, 1, 10)])
-def test_d8_float64(nr, nc, seed):
+def test_d8_float64(nr, nc, seed, d8path):
     z = synth.dem(seed, nr, nc)
     rain = synth.rain(seed, nr, nc)
     code = fr.receivers(dev(z), "d8")
@@ -141,12 +149,43 @@ def test_d8_float64(nr, nc, seed):
     assert abs(s - t) <= 1e-11 * t
 
 
-def test_d8_unit_rain_float32_equals_counts():
+def test_d8_unit_rain_float32_equals_counts(d8path):
     z = synth.dem(1, 256, 256)
     code = fr.receivers(dev(z), "d8")
     q, cnt, _ = fr.accumulate(code, None, None, "d8", torch.float32, counts=True)
     # counts < 2^24 here, so float32 holds them exactly
     assert np.array_equal(host(q).astype(np.uint64), host(cnt))
+
+
+@pytest.mark.parametrize("kind", ["rows_up", "cols_left", "cols_right", "diag", "bowl"])
+def test_d8_terrain_orientations(kind, d8path):
+    """Terrain draining against or across the sweep direction: every edge is
+    then cut, so the exit forest carries the whole solve."""
+    nr, nc = 300, 270
+    rr, cc = np.meshgrid(np.arange(nr), np.arange(nc), indexing="ij")
+    noise = synth.uniform(9, synth.STREAM_NOISE, nr * nc).reshape(nr, nc) * 1e-3
+    base = {"rows_up": -0.01 * rr, "cols_left": 0.01 * cc, "cols_right": -0.01 * cc,
+            "diag": 0.01 * (rr + cc), "bowl": 1e-4 * ((rr - 150.5) ** 2 + (cc - 130.5) ** 2)}[kind]
+    z = (base + noise).astype(np.float32)
+    rain = synth.rain(9, nr, nc)
+    code = fr.receivers(dev(z), "d8")
+    q, cnt, _ = fr.accumulate(code, None, dev(rain), "d8", torch.float32, counts=True)
+    qref, cref = oracle.accumulate_single(host(code), rain, z=z)
+    assert np.array_equal(host(cnt), cref)
+    assert relmax(host(q), qref) <= 1e-6
+
+
+def test_d8_exit_list_overflow_falls_back():
+    # Flow along rows only: every cell is an exit of the row sweep, more than
+    # the exit list holds on a grid above 2^22 cells.
+    nr, nc = 2100, 2100
+    cc = np.arange(nc, dtype=np.float64)[None, :] * np.ones((nr, 1))
+    noise = synth.uniform(3, synth.STREAM_NOISE, nr * nc).reshape(nr, nc) * 1e-3
+    z = (0.01 * cc + noise).astype(np.float32)
+    code = fr.receivers(dev(z), "d8")
+    _, cnt, _ = fr.accumulate(code, None, None, "d8", None, counts=True)
+    _, cref = oracle.accumulate_single(host(code), None, z=z, q=False)
+    assert np.array_equal(host(cnt), cref)
 
 
 # ---------------------------------------------------------------------------
@@ -244,7 +283,7 @@ def test_nonfinite_elevation_and_rain():
     assert e.value.code == fr.ERR_NONFINITE
 
 
-def test_cycle_and_bad_codes_reported():
+def test_cycle_and_bad_codes_reported(d8path):
     code = np.full((8, 70), 0xFF, dtype=np.uint8)
     code[3, 5] = 4   # -> (3, 6)
     code[3, 6] = 3   # -> (3, 5): a 2-cycle
