@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--cpu-size", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after timing, run one 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -137,6 +139,13 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     log(f"  timed {args.steps} steps in {wall:.3f}s")
+
+    if args.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     m = mass.cpu().numpy()
     total_cells_counts = int(cnt.view(torch.int64)[code == 0xFF].sum().item())

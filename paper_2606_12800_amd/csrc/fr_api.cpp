@@ -62,7 +62,8 @@ uint32_t d8_capacity(int64_t n) {
 D8Layout d8_layout(int64_t nrows, int64_t ncols, int vdtype, bool counts) {
   D8Layout L{};
   const size_t n = (size_t)(nrows * ncols);
-  const size_t nt = (size_t)(((nrows + D8_TH - 1) / D8_TH) * ((ncols + D8_TW - 1) / D8_TW));
+  const int th = d8_tile_height(nrows, ncols);
+  const size_t nt = (size_t)(((nrows + th - 1) / th) * ((ncols + D8_TW - 1) / D8_TW));
   L.cap = d8_capacity((int64_t)n);
   const size_t cap = L.cap;
   size_t o = 0;
@@ -145,7 +146,8 @@ int run_d8(const uint8_t* code, int64_t nrows, int64_t ncols, const float* rain3
   D8Params P{};
   P.nrows = nrows;
   P.ncols = ncols;
-  P.ntr = (int32_t)((nrows + D8_TH - 1) / D8_TH);
+  P.th = d8_tile_height(nrows, ncols);
+  P.ntr = (int32_t)((nrows + P.th - 1) / P.th);
   P.ntc = (int32_t)((ncols + D8_TW - 1) / D8_TW);
   P.code = code;
   P.rain32 = rain32;

@@ -59,14 +59,19 @@ struct EngineParams {
   int32_t* status;             // device status word or NULL
 };
 
-// Row-sweep single-receiver path (fr_d8.hip): tile = D8_TH rows x one
-// wavefront of columns.
-constexpr int D8_TW = 64;
-constexpr int D8_TH = 256;
+// Row-sweep single-receiver path (fr_d8.hip): tile = D8Params::th rows x
+// D8_TW columns, one wavefront per tile with 4 columns per lane.
+constexpr int D8_TW = 256;
+// Tile height: taller tiles mean fewer exits (fewer, shallower forest
+// rounds); shorter tiles mean more wavefronts on small grids.
+inline int d8_tile_height(int64_t nrows, int64_t ncols) {
+  return nrows * ncols >= ((int64_t)1 << 28) ? 512 : 256;
+}
 
 struct D8Params {
   int64_t nrows, ncols;
   int32_t ntr, ntc;
+  int32_t th;                  // tile height
   const uint8_t* code;
   const float* rain32;         // or NULL
   const double* rain64;        // or NULL (both NULL: unit rain)
@@ -76,7 +81,7 @@ struct D8Params {
   uint32_t* root_of;           // per cell, written for inlets: root cell
   uint32_t* node_of;           // per cell, written for exits: exit index
   uint32_t* ex_cell;           // exit list [cap]
-  uint64_t* ex_cnt[2];         // exit sums, two buffers for pointer doubling
+  uint64_t* ex_cnt[2];         // exit sums [0] and snapshots [1] for pointer doubling
   float* ex_hi[2];
   float* ex_lo[2];
   double* ex_q64[2];

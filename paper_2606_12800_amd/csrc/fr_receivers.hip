@@ -25,29 +25,45 @@ struct Row6 {
   float v[6];  // columns c0-1 .. c0+4
 };
 
+// A row as loaded: this lane's four columns, plus (lanes 0 and 63) the
+// column just outside the lane group.  Cross-lane assembly happens later, so
+// the load can stay in flight while other rows are computed.
+struct RawRow {
+  float a[4];
+  float side;
+};
+
 template <bool VEC>
-__device__ __forceinline__ void load_row(const float* __restrict__ z, int64_t nrows, int64_t ncols,
-                                         int64_t r, int64_t c0, int lane, Row6& out) {
-  float a0 = INFINITY, a1 = INFINITY, a2 = INFINITY, a3 = INFINITY;
-  const bool row_ok = (r >= 0 && r < nrows);
-  if (row_ok) {
+__device__ __forceinline__ RawRow load_raw(const float* __restrict__ z, int64_t nrows, int64_t ncols,
+                                           int64_t r, int64_t c0, int lane) {
+  RawRow x;
+  x.a[0] = x.a[1] = x.a[2] = x.a[3] = INFINITY;
+  x.side = INFINITY;
+  if (r >= 0 && r < nrows) {
     const float* rp = z + r * ncols;
     if (VEC && c0 + 3 < ncols) {
       const float4 q = *reinterpret_cast<const float4*>(rp + c0);
-      a0 = q.x; a1 = q.y; a2 = q.z; a3 = q.w;
+      x.a[0] = q.x; x.a[1] = q.y; x.a[2] = q.z; x.a[3] = q.w;
     } else {
-      if (c0 + 0 < ncols) a0 = rp[c0 + 0];
-      if (c0 + 1 < ncols) a1 = rp[c0 + 1];
-      if (c0 + 2 < ncols) a2 = rp[c0 + 2];
-      if (c0 + 3 < ncols) a3 = rp[c0 + 3];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (c0 + j < ncols) x.a[j] = rp[c0 + j];
     }
+    if (lane == 0 && c0 - 1 >= 0 && c0 - 1 < ncols) x.side = rp[c0 - 1];
+    if (lane == 63 && c0 + 4 < ncols) x.side = rp[c0 + 4];
   }
-  // Neighbour columns c0-1 and c0+4 from adjacent lanes.
-  float left = __shfl_up(a3, 1, 64);
-  float right = __shfl_down(a0, 1, 64);
-  if (lane == 0) left = (row_ok && c0 - 1 >= 0 && c0 - 1 < ncols) ? z[r * ncols + c0 - 1] : INFINITY;
-  if (lane == 63) right = (row_ok && c0 + 4 < ncols) ? z[r * ncols + c0 + 4] : INFINITY;
-  out.v[0] = left; out.v[1] = a0; out.v[2] = a1; out.v[3] = a2; out.v[4] = a3; out.v[5] = right;
+  return x;
+}
+
+__device__ __forceinline__ Row6 assemble(const RawRow& x, int lane) {
+  Row6 out;
+  float left = __shfl_up(x.a[3], 1, 64);
+  float right = __shfl_down(x.a[0], 1, 64);
+  if (lane == 0) left = x.side;
+  if (lane == 63) right = x.side;
+  out.v[0] = left; out.v[1] = x.a[0]; out.v[2] = x.a[1]; out.v[3] = x.a[2]; out.v[4] = x.a[3];
+  out.v[5] = right;
+  return out;
 }
 
 // Code of the cell at column offset j (1..4) of the middle row.
@@ -88,12 +104,14 @@ __global__ __launch_bounds__(RCV_THREADS) void k_receivers(const float* __restri
   const int64_t c0 = (int64_t)blockIdx.x * RCV_COLS + (int64_t)threadIdx.x * 4;
   const int64_t r0 = (int64_t)blockIdx.y * RCV_RPB;
   const int64_t r1 = r0 + RCV_RPB < nrows ? r0 + RCV_RPB : nrows;
-  Row6 up, mid, dn;
-  load_row<VEC>(z, nrows, ncols, r0 - 1, c0, lane, up);
-  load_row<VEC>(z, nrows, ncols, r0, c0, lane, mid);
+  Row6 up = assemble(load_raw<VEC>(z, nrows, ncols, r0 - 1, c0, lane), lane);
+  Row6 mid = assemble(load_raw<VEC>(z, nrows, ncols, r0, c0, lane), lane);
+  RawRow dn_raw = load_raw<VEC>(z, nrows, ncols, r0 + 1, c0, lane);
   bool bad = false;
   for (int64_t r = r0; r < r1; ++r) {
-    load_row<VEC>(z, nrows, ncols, r + 1, c0, lane, dn);
+    // Row r+2 is fetched now and used two iterations later.
+    const RawRow nn_raw = load_raw<VEC>(z, nrows, ncols, r + 2, c0, lane);
+    const Row6 dn = assemble(dn_raw, lane);
     uint8_t o[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -111,6 +129,7 @@ __global__ __launch_bounds__(RCV_THREADS) void k_receivers(const float* __restri
     }
     up = mid;
     mid = dn;
+    dn_raw = nn_raw;
   }
   if (bad && status) atomicCAS(status, 0, FR_ERR_NONFINITE);
 }
