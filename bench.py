@@ -21,9 +21,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per cell (each ABI-visible array touched once):
-RECV_BYTES = 4 + 1            # z read, code written
-ACC_BYTES = 1 + 4 + 4 + 8     # code, rain read; q (f32) and counts (u64) written
+# Algorithmic bytes per cell of each single-kernel phase (each array the
+# kernel must touch, counted once):
+PHASE_BYTES = {
+    "receivers": 4 + 1,        # z read, code written
+    "d8_up": 1 + 4,            # code, rain read (local sweep; exits are sparse)
+    "d8_down": 1 + 4 + 4 + 8,  # code, rain read; q (f32), counts (u64) written
+}
+PHASE_KERNEL = {"receivers": "k_receivers", "d8_up": "k_d8_up", "d8_down": "k_d8_down"}
+ACC_BYTES = 1 + 4 + 4 + 8     # whole accumulate call: code, rain in; q, counts out
 
 
 def log(msg):
@@ -55,8 +61,74 @@ def cpu_baseline(size: int, seed: int):
     }
 
 
+def run_secondary(args, workload):
+    """MFD (16384^2, seed 3) or adjoint (MFD 4096^2, seed 5) timing lines."""
+    import torch
+    import synth
+    import paper_2606_12800_amd as fr
+    lib = fr.load_library()
+    dev = torch.device("cuda:0")
+    n = args.size if args.size_given else (16384 if workload == "mfd" else 4096)
+    seed = 3 if workload == "mfd" else 5
+    log(f"generating {n}x{n} DEM (seed {seed}) ...")
+    z = torch.from_numpy(synth.dem(seed, n, n)).to(dev)
+    code = torch.empty((n, n), dtype=torch.uint8, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    out = {}
+    for name, dt, tdt in [("f32", fr.F32, torch.float32), ("f64", fr.F64, torch.float64)]:
+        q = torch.empty((n, n), dtype=tdt, device=dev)
+        wsb = fr.workspace_bytes(fr.FN_ACCUMULATE if workload == "mfd" else fr.FN_ADJOINT, n, n, fr.MFD, dt)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        gbar = None
+        if workload == "adjoint":
+            gbar = torch.zeros((n, n), dtype=tdt, device=dev)
+            cells = synth.distinct_cells(6, synth.STREAM_PICK, 64, n * n)
+            w = synth.normal(6, synth.STREAM_NORMAL, 64)
+            gbar.view(-1)[torch.from_numpy(cells).to(dev)] = torch.from_numpy(w).to(dev, tdt)
+        times = []
+        for i in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if lib.fr_receivers(P(z), n, n, fr.MFD, P(code), P(status), sp) != 0:
+                raise RuntimeError("fr_receivers failed")
+            if workload == "mfd":
+                rc = lib.fr_accumulate(P(z), P(code), n, n, fr.MFD, 1.1, None, fr.F32, dt, P(q), None, None,
+                                       P(status), P(ws), wsb, sp)
+            else:
+                rc = lib.fr_accumulate_adjoint(P(z), P(code), n, n, fr.MFD, 1.1, P(gbar), dt, P(q), P(status),
+                                               P(ws), wsb, sp)
+            if rc != 0:
+                raise fr.FlowRouteError(rc, workload)
+            torch.cuda.synchronize()
+            if i >= args.warmup:
+                times.append(time.perf_counter() - t0)
+        if int(status.item()) != 0:
+            raise fr.FlowRouteError(int(status.item()), "device status")
+        t = sum(times) / len(times)
+        out[name] = {"ms_per_step": 1e3 * t, "cells_per_s": n * n / t}
+        del q, ws
+        torch.cuda.empty_cache()
+        log(f"  {name}: {1e3 * t:.2f} ms per step")
+    line = {
+        "metric": "cells routed/sec (D8 & MFD) at 1 MI355X; % HBM peak; batched vs per-tile",
+        "value": out["f32"]["cells_per_s"], "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": out["f32"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": (f"MFD {n}x{n} fractal DEM (seed {seed}), unit rain, p=1.1" if workload == "mfd"
+                                else f"MFD adjoint {n}x{n} (seed {seed}), 64 gauges (seed 6)"),
+                   "cells": n * n},
+        "detail": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="d8", choices=["d8", "mfd", "adjoint"],
+                    help="d8: the headline 1.88e9-cell route (default); mfd / adjoint: secondary lines")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
@@ -73,6 +145,10 @@ def main():
         print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
               f"(asked for --gpus {args.gpus}, WORLD_SIZE {world})", flush=True)
         sys.exit(2)
+    args.size_given = "--size" in sys.argv
+    if args.workload != "d8":
+        run_secondary(args, args.workload)
+        return
 
     import numpy as np
     import torch
@@ -107,6 +183,8 @@ def main():
 
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     recv_ms, acc_ms = [], []
+    phase_ms = {}
+    fr.timing_enable(True)
 
     def step(record: bool):
         ev[0].record(stream)
@@ -114,12 +192,16 @@ def main():
         ev[1].record(stream)
         if rc != 0:
             raise fr.FlowRouteError(rc, "fr_receivers")
+        ph = fr.timing_last() if record else {}
         rc = lib.fr_accumulate(None, P(code), n, n, fr.D8, 1.1, P(rain), fr.F32, fr.F32, P(q), P(cnt),
                                P(mass), P(status), P(ws), wsb, sp)
         ev[2].record(stream)
         if rc != 0:
             raise fr.FlowRouteError(rc, "fr_accumulate")
         if record:
+            ph.update(fr.timing_last())
+            for k, v in ph.items():
+                phase_ms.setdefault(k, []).append(v)
             ev[2].synchronize()
             recv_ms.append(ev[0].elapsed_time(ev[1]))
             acc_ms.append(ev[1].elapsed_time(ev[2]))
@@ -153,10 +235,13 @@ def main():
     value = ncell * args.steps / wall
     recv_avg = sum(recv_ms) / len(recv_ms)
     acc_avg = sum(acc_ms) / len(acc_ms)
-    recv_gbs = RECV_BYTES * ncell / (recv_avg * 1e-3) / 1e9
     acc_gbs = ACC_BYTES * ncell / (acc_avg * 1e-3) / 1e9
-    dominant = "accumulate" if acc_avg >= recv_avg else "receivers"
-    achieved = acc_gbs if dominant == "accumulate" else recv_gbs
+    phase_avg = {k: sum(v) / len(v) for k, v in phase_ms.items()}
+    # Dominant single-kernel phase: the one with the largest device time.
+    single = {k: v for k, v in phase_avg.items() if k in PHASE_BYTES}
+    dom = max(single, key=single.get)
+    achieved = PHASE_BYTES[dom] * ncell / (single[dom] * 1e-3) / 1e9
+    phase_gbs = {k: PHASE_BYTES[k] * ncell / (single[k] * 1e-3) / 1e9 for k in single}
     out = {
         "metric": "cells routed/sec (D8 & MFD) at 1 MI355X; % HBM peak; batched vs per-tile",
         "value": value,
@@ -174,9 +259,11 @@ def main():
                    "cells": ncell},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": dominant},
+                     "kernel": PHASE_KERNEL[dom], "bytes_per_cell": PHASE_BYTES[dom],
+                     "ms_per_launch": single[dom]},
         "detail": {"receivers_ms": recv_avg, "accumulate_ms": acc_avg,
-                   "receivers_alg_GBs": recv_gbs, "accumulate_alg_GBs": acc_gbs,
+                   "accumulate_alg_GBs": acc_gbs,
+                   "phase_ms": phase_avg, "phase_alg_GBs": phase_gbs,
                    "mass_sinks": float(m[0]), "mass_rain": float(m[1]),
                    "mass_rel_err": abs(float(m[0]) - float(m[1])) / float(m[1]),
                    "sink_counts_total": total_cells_counts},

@@ -170,6 +170,20 @@ int fr_accumulate_adjoint(const float* z, const uint8_t* code, int64_t nrows, in
  */
 size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dtype);
 
+/*
+ * Phase timing (instrumentation).  fr_timing_enable(1) makes subsequent
+ * fr_receivers / fr_accumulate / fr_accumulate_adjoint calls on this process
+ * record HIP events around each of their GPU phases, on the call's stream;
+ * fr_timing_enable(0) stops it (the default).  fr_timing_last fills up to
+ * `max` entries of names[] (static strings) and ms[] (device milliseconds)
+ * for the phases of the most recent timed call and returns how many it
+ * filled; the call is complete when it returns, so reading is synchronous.
+ * Phases: "receivers"; "d8_up", "d8_forest", "d8_down", "mass" (row-sweep
+ * single-receiver path); "engine" (peeling engine).  Not thread-safe.
+ */
+int fr_timing_enable(int on);
+int fr_timing_last(const char** names, float* ms, int max);
+
 /* fr_status_string -- static text for a status code. */
 const char* fr_status_string(int code);
 

@@ -32,7 +32,7 @@ ERR_NONFINITE, ERR_NOTDAG, ERR_BADCODE, ERR_TOOLARGE = -5, -6, -7, -8
 
 RULES = {"d8": D8, "mfd": MFD, "d4": D4}
 EXPORTS = ["fr_receivers", "fr_accumulate", "fr_accumulate_adjoint", "fr_workspace_bytes",
-           "fr_status_string", "fr_version"]
+           "fr_status_string", "fr_version", "fr_timing_enable", "fr_timing_last"]
 
 
 class FlowRouteError(RuntimeError):
@@ -66,6 +66,10 @@ def load_library() -> ctypes.CDLL:
     lib.fr_status_string.restype = ctypes.c_char_p
     lib.fr_version.argtypes = []
     lib.fr_version.restype = ctypes.c_char_p
+    lib.fr_timing_enable.argtypes = [ci]
+    lib.fr_timing_enable.restype = ci
+    lib.fr_timing_last.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_float), ci]
+    lib.fr_timing_last.restype = ci
     _lib = lib
     return lib
 
@@ -76,6 +80,25 @@ def status_string(code: int) -> str:
 
 def workspace_bytes(fn: int, nrows: int, ncols: int, rule: int, dtype: int) -> int:
     return int(load_library().fr_workspace_bytes(fn, nrows, ncols, rule, dtype))
+
+
+def timing_enable(on: bool = True) -> None:
+    """Record per-phase device times of subsequent library calls."""
+    load_library().fr_timing_enable(1 if on else 0)
+
+
+def timing_last() -> dict:
+    """{phase name: milliseconds} of the most recent timed library call."""
+    names = (ctypes.c_char_p * 8)()
+    ms = (ctypes.c_float * 8)()
+    k = load_library().fr_timing_last(names, ms, 8)
+    if k < 0:
+        raise FlowRouteError(k, "fr_timing_last")
+    out = {}
+    for i in range(k):
+        key = names[i].decode()
+        out[key] = out.get(key, 0.0) + float(ms[i])
+    return out
 
 
 def _rule(rule) -> int:

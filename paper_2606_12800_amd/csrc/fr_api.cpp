@@ -107,9 +107,62 @@ int cu_count() {
   return cache[dev];
 }
 
+// ---------------------------------------------------------------------------
+// Phase timing (instrumentation only; off by default).
+constexpr int kMaxPhases = 8;
+struct Timing {
+  bool on = false;
+  int n = 0;
+  const char* names[kMaxPhases];
+  hipEvent_t ev[kMaxPhases][2];
+  bool created = false;
+  int device = -1;
+};
+Timing g_timing;
+
+bool timing_ready() {
+  if (!g_timing.on) return false;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  if (!g_timing.created || g_timing.device != dev) {
+    for (int i = 0; i < kMaxPhases; ++i)
+      for (int j = 0; j < 2; ++j)
+        if (hipEventCreate(&g_timing.ev[i][j]) != hipSuccess) return false;
+    g_timing.created = true;
+    g_timing.device = dev;
+  }
+  return true;
+}
+
+void timing_reset() { g_timing.n = 0; }
+
+// Returns the slot of a new phase, or -1 when timing is off.
+int phase_begin(const char* name, hipStream_t s) {
+  if (!timing_ready() || g_timing.n >= kMaxPhases) return -1;
+  const int i = g_timing.n++;
+  g_timing.names[i] = name;
+  (void)hipEventRecord(g_timing.ev[i][0], s);
+  return i;
+}
+
+void phase_end(int i, hipStream_t s) {
+  if (i >= 0) (void)hipEventRecord(g_timing.ev[i][1], s);
+}
+
+int run_engine_body(const EngineConfig& cfg, EngineParams P, char* base, const Layout& L, int32_t* status,
+                    hipStream_t s);
+
 // Runs the peeling engine to completion (see fr_engine.hip).
 int run_engine(const EngineConfig& cfg, EngineParams P, char* base, const Layout& L, int32_t* status,
                hipStream_t s) {
+  const int ph = phase_begin("engine", s);
+  const int rc = run_engine_body(cfg, P, base, L, status, s);
+  phase_end(ph, s);
+  return rc;
+}
+
+int run_engine_body(const EngineConfig& cfg, EngineParams P, char* base, const Layout& L, int32_t* status,
+                    hipStream_t s) {
   if (launch_engine_init(cfg, P, s) != hipSuccess) return FR_ERR_HIP;
   const int64_t ntiles = (int64_t)P.ntr * P.ntc;
   int grid = 2 * cu_count();
@@ -176,13 +229,16 @@ int run_d8(const uint8_t* code, int64_t nrows, int64_t ncols, const float* rain3
   P.status = status;
 
   if (launch_zero_u32(ctr, 16, s) != hipSuccess) return FR_ERR_HIP;
+  int ph = phase_begin("d8_up", s);
   if (launch_d8_up(vk, counts, P, s) != hipSuccess) return FR_ERR_HIP;
+  phase_end(ph, s);
   uint32_t n = 0;
   if (hipMemcpyAsync(&n, ctr, sizeof n, hipMemcpyDeviceToHost, s) != hipSuccess) return FR_ERR_HIP;
   if (hipStreamSynchronize(s) != hipSuccess) return FR_ERR_HIP;
   if (n > L.cap) return 1;
   P.n_ex = n;
   int fb = 0;
+  ph = phase_begin("d8_forest", s);
   if (n > 0) {
     if (launch_d8_link(P, n, s) != hipSuccess) return FR_ERR_HIP;
     // A forest of n nodes is at most n deep: 33 rounds always suffice; more
@@ -202,10 +258,15 @@ int run_d8(const uint8_t* code, int64_t nrows, int64_t ncols, const float* rain3
       if (!flag) break;
     }
   }
+  phase_end(ph, s);
+  ph = phase_begin("d8_down", s);
   if (launch_d8_down(vk, counts, P, fb, s) != hipSuccess) return FR_ERR_HIP;
+  phase_end(ph, s);
   if (mass_out) {
     const int nt = P.ntr * P.ntc;
+    ph = phase_begin("mass", s);
     if (launch_mass_final(P.mass_part, nt, mass_out, s) != hipSuccess) return FR_ERR_HIP;
+    phase_end(ph, s);
   }
   return FR_OK;
 }
@@ -255,6 +316,26 @@ extern "C" {
 
 const char* fr_version(void) { return "libflowroute 0.1 (gfx950)"; }
 
+int fr_timing_enable(int on) {
+  g_timing.on = on != 0;
+  g_timing.n = 0;
+  return FR_OK;
+}
+
+int fr_timing_last(const char** names, float* ms, int max) {
+  if (!names || !ms || max < 0) return FR_ERR_ARG;
+  int k = 0;
+  for (int i = 0; i < g_timing.n && k < max; ++i) {
+    float t = 0.0f;
+    if (hipEventSynchronize(g_timing.ev[i][1]) != hipSuccess) return FR_ERR_HIP;
+    if (hipEventElapsedTime(&t, g_timing.ev[i][0], g_timing.ev[i][1]) != hipSuccess) return FR_ERR_HIP;
+    names[k] = g_timing.names[i];
+    ms[k] = t;
+    ++k;
+  }
+  return k;
+}
+
 const char* fr_status_string(int code) {
   switch (code) {
     case FR_OK: return "ok";
@@ -297,8 +378,11 @@ int fr_receivers(const float* z, int64_t nrows, int64_t ncols, int rule, uint8_t
   if (nrows == 0 || ncols == 0) return FR_OK;
   if (ncols > kMaxCells / nrows) return FR_ERR_TOOLARGE;
   if (!z || !code_out) return FR_ERR_ARG;
-  return launch_receivers(z, nrows, ncols, rule, code_out, dev_status, stream) == hipSuccess ? FR_OK
-                                                                                           : FR_ERR_HIP;
+  timing_reset();
+  const int ph = phase_begin("receivers", stream);
+  const hipError_t e = launch_receivers(z, nrows, ncols, rule, code_out, dev_status, stream);
+  phase_end(ph, stream);
+  return e == hipSuccess ? FR_OK : FR_ERR_HIP;
 }
 
 int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t ncols, int rule, double mfd_p,
@@ -327,6 +411,7 @@ int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t nc
   if (!ws || ws_bytes < fr_workspace_bytes(FR_FN_ACCUMULATE, nrows, ncols, rule, q_dtype))
     return FR_ERR_WORKSPACE;
   char* base = aligned_base(ws);
+  timing_reset();
 
   EngineConfig cfg;
   cfg.rk = rule == FR_MFD ? RK_MULTI : RK_SINGLE;
@@ -352,7 +437,9 @@ int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t nc
   if (rc != FR_OK) return rc;
   if (mass_out) {
     double* partial = reinterpret_cast<double*>(base + L.partial);
+    const int ph = phase_begin("mass", stream);
     if (launch_mass(cfg.rk, cfg.vk, P, partial, kMassBlocks, mass_out, stream) != hipSuccess) return FR_ERR_HIP;
+    phase_end(ph, stream);
   }
   return FR_OK;
 }
@@ -370,6 +457,7 @@ int fr_accumulate_adjoint(const float* z, const uint8_t* code, int64_t nrows, in
   const Layout L = layout(nrows, ncols, rule, dtype);
   if (!ws || ws_bytes < L.total) return FR_ERR_WORKSPACE;
   char* base = aligned_base(ws);
+  timing_reset();
 
   EngineConfig cfg;
   cfg.rk = rule == FR_MFD ? RK_MULTI : RK_SINGLE;
