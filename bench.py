@@ -78,6 +78,7 @@ def run_secondary(args, workload):
     sp = ctypes.c_void_p(stream.cuda_stream)
     P = lambda t: ctypes.c_void_p(t.data_ptr())
     out = {}
+    fr.timing_enable(True)
     for name, dt, tdt in [("f32", fr.F32, torch.float32), ("f64", fr.F64, torch.float64)]:
         q = torch.empty((n, n), dtype=tdt, device=dev)
         wsb = fr.workspace_bytes(fr.FN_ACCUMULATE if workload == "mfd" else fr.FN_ADJOINT, n, n, fr.MFD, dt)
@@ -89,6 +90,7 @@ def run_secondary(args, workload):
             w = synth.normal(6, synth.STREAM_NORMAL, 64)
             gbar.view(-1)[torch.from_numpy(cells).to(dev)] = torch.from_numpy(w).to(dev, tdt)
         times = []
+        phases = {}
         for i in range(args.warmup + args.steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -105,10 +107,13 @@ def run_secondary(args, workload):
             torch.cuda.synchronize()
             if i >= args.warmup:
                 times.append(time.perf_counter() - t0)
+                for k, v in fr.timing_last().items():
+                    phases.setdefault(k, []).append(v)
         if int(status.item()) != 0:
             raise fr.FlowRouteError(int(status.item()), "device status")
         t = sum(times) / len(times)
-        out[name] = {"ms_per_step": 1e3 * t, "cells_per_s": n * n / t}
+        out[name] = {"ms_per_step": 1e3 * t, "cells_per_s": n * n / t,
+                     "phase_ms": {k: sum(v) / len(v) for k, v in phases.items()}}
         del q, ws
         torch.cuda.empty_cache()
         log(f"  {name}: {1e3 * t:.2f} ms per step")

@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in fr_api.h: argument validation,
 // workspace carving, kernel enqueue and the iteration driver.
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -82,6 +83,26 @@ D8Layout d8_layout(int64_t nrows, int64_t ncols, int vdtype, bool counts) {
   L.q1 = o; if (vdtype == FR_F64) o += up(cap * 8);
   L.ctr = o; o += kAlign;
   L.mass = o; o += up(nt * 2 * sizeof(double));
+  L.total = o + kAlign;
+  return L;
+}
+
+// Workspace of the wavefront sweep (fr_wsweep.hip).  Like the row-sweep
+// path it overlays the engine's workspace; the engine only runs after the
+// sweep gave up.
+struct WsLayout {
+  size_t vlo, edge, progress, ctr, partial, total;
+};
+
+WsLayout ws_layout(int64_t nrows, int64_t ncols, int vdtype) {
+  WsLayout L{};
+  const size_t n = (size_t)(nrows * ncols);
+  size_t o = 0;
+  L.vlo = o; if (vdtype == FR_F32) o += up(n * sizeof(float));
+  L.edge = o; o += up(ws_edge_words(nrows, ncols) * sizeof(uint64_t));
+  L.progress = o; o += up((size_t)ws_strips(ncols) * sizeof(int32_t));
+  L.ctr = o; o += kAlign;
+  L.partial = o; o += up(2 * kMassBlocks * sizeof(double));
   L.total = o + kAlign;
   return L;
 }
@@ -271,9 +292,98 @@ int run_d8(const uint8_t* code, int64_t nrows, int64_t ncols, const float* rain3
   return FR_OK;
 }
 
-bool d8_path_enabled() {
-  const char* e = getenv("FLOWROUTE_D8_PATH");
-  return !(e && strcmp(e, "engine") == 0);
+// Accumulation path: "auto" (row sweeps for D8/D4 forward, the wavefront
+// sweep otherwise), "sweep" (the wavefront sweep for everything) or
+// "engine" (the peeling engine for everything), from FLOWROUTE_ACC.
+enum AccPath { ACC_AUTO, ACC_SWEEP, ACC_ENGINE };
+AccPath acc_path() {
+  const char* e = getenv("FLOWROUTE_ACC");
+  if (e && strcmp(e, "engine") == 0) return ACC_ENGINE;
+  if (e && strcmp(e, "sweep") == 0) return ACC_SWEEP;
+  return ACC_AUTO;
+}
+
+constexpr int kMaxSweepPasses = 32;
+
+// Diagnostics on stderr when FLOWROUTE_VERBOSE is set.
+bool verbose() {
+  static const bool v = getenv("FLOWROUTE_VERBOSE") != nullptr;
+  return v;
+}
+
+// Wavefront-sweep passes until every cell is final.  Returns FR_OK, an
+// error, or 1 when the pass budget ran out (the caller then runs the
+// engine from scratch).
+int run_ws(const EngineConfig& cfg, WsParams P, int32_t* status, hipStream_t s) {
+  if (launch_ws_setup(cfg, P, s) != hipSuccess) return FR_ERR_HIP;
+  uint32_t h[4] = {0, 0, 0, 0};
+  if (hipMemcpyAsync(h, P.ctr, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess) return FR_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return FR_ERR_HIP;
+  // Visit the rows holding most inputs first: forward inputs are donors,
+  // upstream of their receivers; adjoint inputs are the receivers.
+  const bool flows_up = h[1] >= h[2];
+  int dir = ((cfg.dir == DIR_FWD) == flows_up) ? -1 : 1;
+  int64_t remaining = P.nrows * P.ncols;
+  // FLOWROUTE_WS_MAXPASS (diagnostics): stop after that many passes and
+  // leave unfinished cells as they are.
+  const char* mp = getenv("FLOWROUTE_WS_MAXPASS");
+  const int max_pass = mp ? atoi(mp) : -1;
+  for (int pass = 0;; ++pass) {
+    if (max_pass >= 0 && pass >= max_pass) return FR_OK;
+    if (pass >= kMaxSweepPasses) return 1;
+    if (launch_zero_u32(P.ctr, 1, s) != hipSuccess) return FR_ERR_HIP;
+    if (P.debug && launch_zero_u32(P.ctr + 3, 3, s) != hipSuccess) return FR_ERR_HIP;
+    if (launch_ws_progress_reset(P, s) != hipSuccess) return FR_ERR_HIP;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (verbose() && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess)
+      (void)hipEventRecord(e0, s);
+    if (launch_ws_pass(cfg, P, dir, pass == 0 ? 1 : 0, s) != hipSuccess) return FR_ERR_HIP;
+    if (e1) (void)hipEventRecord(e1, s);
+    uint32_t fin = 0;
+    int32_t st = 0;
+    if (hipMemcpyAsync(&fin, P.ctr, sizeof fin, hipMemcpyDeviceToHost, s) != hipSuccess) return FR_ERR_HIP;
+    if (status && hipMemcpyAsync(&st, status, sizeof st, hipMemcpyDeviceToHost, s) != hipSuccess)
+      return FR_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return FR_ERR_HIP;
+    remaining -= fin;
+    if (verbose()) {
+      float ms = 0.0f;
+      if (e1) (void)hipEventElapsedTime(&ms, e0, e1);
+      uint32_t d[6] = {0, 0, 0, 0, 0, 0};
+      if (P.debug && hipMemcpy(d, P.ctr, sizeof d, hipMemcpyDeviceToHost) != hipSuccess) return FR_ERR_HIP;
+      fprintf(stderr,
+              "flowroute: sweep pass %d dir %+d finished %u remaining %lld (%.3f ms) edge-waits %u pace-spins %u "
+              "resolves %u\n",
+              pass, dir, fin, (long long)remaining, ms, d[3], d[4], d[5]);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (remaining <= 0 || st != 0) break;
+    if (fin == 0) {
+      // A pass finishes at least the highest unfinished cell of a DAG.
+      if (status && launch_set_status(status, FR_ERR_NOTDAG, s) != hipSuccess) return FR_ERR_HIP;
+      break;
+    }
+    dir = -dir;
+  }
+  return FR_OK;
+}
+
+WsParams ws_params(const EngineConfig& cfg, int64_t nrows, int64_t ncols, const uint8_t* code, const float* z,
+                   double p, char* base, const WsLayout& L, int32_t* status) {
+  WsParams P{};
+  P.nrows = nrows;
+  P.ncols = ncols;
+  P.code = code;
+  P.z = z;
+  P.p = p;
+  P.vlo = cfg.vk == VK_FF ? reinterpret_cast<float*>(base + L.vlo) : nullptr;
+  P.edge = reinterpret_cast<uint64_t*>(base + L.edge);
+  P.progress = reinterpret_cast<int32_t*>(base + L.progress);
+  P.ctr = reinterpret_cast<uint32_t*>(base + L.ctr);
+  P.status = status;
+  P.debug = getenv("FLOWROUTE_WS_DEBUG") != nullptr;
+  return P;
 }
 
 char* aligned_base(void* ws) {
@@ -363,6 +473,8 @@ size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dt
     return 0;
   }
   size_t t = layout(nrows, ncols, rule, dtype).total;
+  const size_t tw = ws_layout(nrows, ncols, dtype).total;
+  if (tw > t) t = tw;
   if (fn == FR_FN_ACCUMULATE && rule != FR_MFD) {
     // The counts buffers are sized in, whether or not counts are requested.
     const size_t t8 = d8_layout(nrows, ncols, dtype, true).total;
@@ -418,22 +530,38 @@ int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t nc
   cfg.dir = DIR_FWD;
   cfg.vk = q_dtype == FR_F32 ? VK_FF : (q_dtype == FR_F64 ? VK_F64 : VK_NONE);
   cfg.counts = counts_out != nullptr;
-  if (cfg.rk == RK_SINGLE && d8_path_enabled()) {
-    const float* r32 = (rain && rain_dtype == FR_F32) ? static_cast<const float*>(rain) : nullptr;
-    const double* r64 = (rain && rain_dtype == FR_F64) ? static_cast<const double*>(rain) : nullptr;
-    const int rc = run_d8(code, nrows, ncols, r32, r64, cfg.vk,
-                          q_dtype == FR_F32 ? static_cast<float*>(q_out) : nullptr,
-                          q_dtype == FR_F64 ? static_cast<double*>(q_out) : nullptr, counts_out, mass_out,
-                          dev_status, base, stream);
-    if (rc != 1) return rc;  // 1: exit list overflow, fall back to the engine
+  const float* r32 = (rain && rain_dtype == FR_F32) ? static_cast<const float*>(rain) : nullptr;
+  const double* r64 = (rain && rain_dtype == FR_F64) ? static_cast<const double*>(rain) : nullptr;
+  float* q32 = q_dtype == FR_F32 ? static_cast<float*>(q_out) : nullptr;
+  double* q64 = q_dtype == FR_F64 ? static_cast<double*>(q_out) : nullptr;
+  const AccPath path = acc_path();
+  if (cfg.rk == RK_SINGLE && path == ACC_AUTO) {
+    const int rc = run_d8(code, nrows, ncols, r32, r64, cfg.vk, q32, q64, counts_out, mass_out, dev_status,
+                          base, stream);
+    if (rc != 1) return rc;  // 1: exit list overflow, fall back to the wavefront sweep
   }
   EngineParams P = common_params(nrows, ncols, code, z, mfd_p, base, L, dev_status);
-  P.src32 = (rain && rain_dtype == FR_F32) ? static_cast<const float*>(rain) : nullptr;
-  P.src64 = (rain && rain_dtype == FR_F64) ? static_cast<const double*>(rain) : nullptr;
-  P.vhi = q_dtype == FR_F32 ? static_cast<float*>(q_out) : nullptr;
-  P.v64 = q_dtype == FR_F64 ? static_cast<double*>(q_out) : nullptr;
+  P.src32 = r32;
+  P.src64 = r64;
+  P.vhi = q32;
+  P.v64 = q64;
   P.cnt = counts_out;
-  int rc = run_engine(cfg, P, base, L, dev_status, stream);
+  int rc = 1;
+  if (path != ACC_ENGINE) {
+    const WsLayout WL = ws_layout(nrows, ncols, q_dtype);
+    WsParams W = ws_params(cfg, nrows, ncols, code, z, mfd_p, base, WL, dev_status);
+    W.src32 = r32;
+    W.src64 = r64;
+    W.vhi = q32;
+    W.v64 = q64;
+    W.cnt = counts_out;
+    const int ph = phase_begin("sweep", stream);
+    rc = run_ws(cfg, W, dev_status, stream);
+    phase_end(ph, stream);
+    if (rc != FR_OK && rc != 1) return rc;
+    if (rc == FR_OK) P.vlo = W.vlo;  // the float-float low parts the mass sum reads
+  }
+  if (rc == 1) rc = run_engine(cfg, P, base, L, dev_status, stream);
   if (rc != FR_OK) return rc;
   if (mass_out) {
     double* partial = reinterpret_cast<double*>(base + L.partial);
@@ -455,7 +583,7 @@ int fr_accumulate_adjoint(const float* z, const uint8_t* code, int64_t nrows, in
   if (ncols > kMaxCells / nrows) return FR_ERR_TOOLARGE;
   if (!code || !qbar || !rbar_out || (rule == FR_MFD && !z)) return FR_ERR_ARG;
   const Layout L = layout(nrows, ncols, rule, dtype);
-  if (!ws || ws_bytes < L.total) return FR_ERR_WORKSPACE;
+  if (!ws || ws_bytes < fr_workspace_bytes(FR_FN_ADJOINT, nrows, ncols, rule, dtype)) return FR_ERR_WORKSPACE;
   char* base = aligned_base(ws);
   timing_reset();
 
@@ -464,11 +592,28 @@ int fr_accumulate_adjoint(const float* z, const uint8_t* code, int64_t nrows, in
   cfg.dir = DIR_ADJ;
   cfg.vk = dtype == FR_F32 ? VK_FF : VK_F64;
   cfg.counts = false;
+  const float* s32 = dtype == FR_F32 ? static_cast<const float*>(qbar) : nullptr;
+  const double* s64 = dtype == FR_F64 ? static_cast<const double*>(qbar) : nullptr;
+  float* o32 = dtype == FR_F32 ? static_cast<float*>(rbar_out) : nullptr;
+  double* o64 = dtype == FR_F64 ? static_cast<double*>(rbar_out) : nullptr;
+  int rc = 1;
+  if (acc_path() != ACC_ENGINE) {
+    const WsLayout WL = ws_layout(nrows, ncols, dtype);
+    WsParams W = ws_params(cfg, nrows, ncols, code, z, mfd_p, base, WL, dev_status);
+    W.src32 = s32;
+    W.src64 = s64;
+    W.vhi = o32;
+    W.v64 = o64;
+    const int ph = phase_begin("sweep", stream);
+    rc = run_ws(cfg, W, dev_status, stream);
+    phase_end(ph, stream);
+    if (rc != 1) return rc;
+  }
   EngineParams P = common_params(nrows, ncols, code, z, mfd_p, base, L, dev_status);
-  P.src32 = dtype == FR_F32 ? static_cast<const float*>(qbar) : nullptr;
-  P.src64 = dtype == FR_F64 ? static_cast<const double*>(qbar) : nullptr;
-  P.vhi = dtype == FR_F32 ? static_cast<float*>(rbar_out) : nullptr;
-  P.v64 = dtype == FR_F64 ? static_cast<double*>(rbar_out) : nullptr;
+  P.src32 = s32;
+  P.src64 = s64;
+  P.vhi = o32;
+  P.v64 = o64;
   P.cnt = nullptr;
   return run_engine(cfg, P, base, L, dev_status, stream);
 }

@@ -111,6 +111,34 @@ struct EngineConfig {
   bool counts;
 };
 
+// Windowed wavefront sweep (fr_wsweep.hip): one wavefront per 64-column
+// strip, rows visited in passes of alternating direction.
+constexpr int WS_EW = 4;  // 64-bit words per edge record
+
+struct WsParams {
+  int64_t nrows, ncols;
+  const uint8_t* code;
+  const float* z;          // elevations (MFD)
+  double p;                // MFD slope exponent
+  const float* src32;      // source term float32, or NULL
+  const double* src64;     // source term float64, or NULL (both NULL: unit)
+  float* vhi;              // float-float value, high part (= float32 output)
+  float* vlo;              // float-float low part (workspace; NaN = unfinished)
+  double* v64;             // float64 value (output; NaN = unfinished)
+  uint64_t* cnt;           // counts (output; all ones = unfinished when no value)
+  uint64_t* edge;          // [strip][row][side][WS_EW] edge records
+  int32_t* progress;       // [strip] last row step finished in this pass (-1 before)
+  uint32_t* ctr;           // [0] cells finished by the last pass, [1]/[2] probe counts
+  int32_t* status;
+  int debug;               // float64 value: unfinished cells carry their state in the NaN payload
+};
+
+size_t ws_edge_words(int64_t nrows, int64_t ncols);
+int64_t ws_strips(int64_t ncols);
+hipError_t launch_ws_progress_reset(const WsParams& P, hipStream_t s);
+hipError_t launch_ws_setup(const EngineConfig& cfg, const WsParams& P, hipStream_t s);
+hipError_t launch_ws_pass(const EngineConfig& cfg, const WsParams& P, int dir, int first, hipStream_t s);
+
 hipError_t launch_engine_init(const EngineConfig& cfg, const EngineParams& P, hipStream_t s);
 hipError_t launch_engine_iter(const EngineConfig& cfg, const EngineParams& P, int it, int grid,
                               hipStream_t s);

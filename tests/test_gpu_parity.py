@@ -54,11 +54,23 @@ def relnorm(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.fixture(params=["sweep", "engine"])
+_ACC_ENV = {"rows": "auto", "sweep": "sweep", "engine": "engine"}
+
+
+@pytest.fixture(params=["rows", "sweep", "engine"])
 def d8path(request, monkeypatch):
-    """Single-receiver accumulation has two GPU paths: row sweeps with an exit
-    forest (default) and the general peeling engine (its fallback)."""
-    monkeypatch.setenv("FLOWROUTE_D8_PATH", "engine" if request.param == "engine" else "auto")
+    """Single-receiver forward accumulation has three GPU paths: row sweeps
+    with an exit forest (default), the windowed wavefront sweep (its
+    fallback) and the peeling engine (the sweep's fallback)."""
+    monkeypatch.setenv("FLOWROUTE_ACC", _ACC_ENV[request.param])
+    return request.param
+
+
+@pytest.fixture(params=["sweep", "engine"])
+def accpath(request, monkeypatch):
+    """MFD and adjoint accumulation: the wavefront sweep (default) or the
+    peeling engine."""
+    monkeypatch.setenv("FLOWROUTE_ACC", _ACC_ENV[request.param])
     return request.param
 
 
@@ -193,8 +205,8 @@ def test_d8_exit_list_overflow_falls_back():
 
 
 @pytest.mark.parametrize("nr,nc,seed", [(256, 256, 3), (300, 517, 4), (97, 131, 7), (1, 200, 9),
-                                        (200, 1, 10)])
-def test_mfd_float32_float64(nr, nc, seed):
+                                        (200, 1, 10), (64, 65, 13), (700, 129, 14)])
+def test_mfd_float32_float64(nr, nc, seed, accpath):
     print(f"mfd {nr}x{nc} seed {seed}", flush=True)
     z = synth.dem(seed, nr, nc)
     rain = synth.rain(seed, nr, nc)
@@ -214,12 +226,70 @@ def test_mfd_float32_float64(nr, nc, seed):
           f"e_max64={relmax(q64, qref):.2e}")
 
 
-def test_mfd_unit_rain():
+def test_mfd_unit_rain(accpath):
     z = synth.dem(3, 256, 300)
     zt = dev(z)
     code = fr.receivers(zt, "mfd")
     q, _, _ = fr.accumulate(code, zt, None, "mfd", torch.float64)
     assert relmax(host(q), oracle.accumulate_mfd(z, None, 1.1)) <= 1e-10
+
+
+def _oriented_terrain(kind, nr, nc, seed):
+    rr, cc = np.meshgrid(np.arange(nr), np.arange(nc), indexing="ij")
+    noise = synth.uniform(seed, synth.STREAM_NOISE, nr * nc).reshape(nr, nc) * 1e-3
+    cr, ccen = (nr - 1) / 2 + 0.5, (nc - 1) / 2 + 0.5
+    base = {"rows_down": 0.01 * rr, "rows_up": -0.01 * rr, "cols_left": 0.01 * cc,
+            "cols_right": -0.01 * cc, "diag": 0.01 * (rr + cc), "antidiag": 0.01 * (rr - cc),
+            "bowl": 1e-4 * ((rr - cr) ** 2 + (cc - ccen) ** 2),
+            "ridge": -1e-4 * ((rr - cr) ** 2 + (cc - ccen) ** 2)}[kind]
+    return (base + noise).astype(np.float32)
+
+
+@pytest.mark.parametrize("kind", ["rows_down", "rows_up", "cols_left", "cols_right", "diag", "antidiag",
+                                  "bowl", "ridge"])
+def test_mfd_terrain_orientations(kind, accpath):
+    """MFD on terrain draining along, against and across the row order, and
+    toward / away from the centre: the sweep needs several passes in both
+    directions and long chains across strip boundaries."""
+    nr, nc = 190, 333
+    print(f"mfd orientation {kind}", flush=True)
+    z = _oriented_terrain(kind, nr, nc, 15)
+    rain = synth.rain(15, nr, nc)
+    zt = dev(z)
+    code = fr.receivers(zt, "mfd")
+    qref = oracle.accumulate_mfd(z, rain, 1.1)
+    q64, _, m64 = fr.accumulate(code, zt, dev(rain), "mfd", torch.float64, mass=True)
+    q32, _, _ = fr.accumulate(code, zt, dev(rain), "mfd", torch.float32)
+    assert relmax(host(q64), qref) <= 1e-10
+    assert relnorm(host(q32), qref) <= 1e-6
+    s, t = host(m64)
+    assert abs(s - t) <= 1e-11 * t
+    qbar = synth.normal(15, synth.STREAM_NORMAL, nr * nc).reshape(nr, nc)
+    ref = oracle.adjoint_mfd(z, qbar, 1.1)
+    r64 = host(fr.adjoint(code, dev(qbar), zt, "mfd"))
+    assert np.max(np.abs(r64 - ref)) <= 1e-10 * np.abs(ref).max()
+
+
+def test_snake_path_many_passes(d8path):
+    """A single river that reverses its row direction in every column: the
+    wavefront sweep would need one pass per column, so it hands over to the
+    peeling engine; every path must still give count = position + 1."""
+    nr, nc = 40, 75
+    code = np.empty((nr, nc), dtype=np.uint8)
+    pos = np.empty((nr, nc), dtype=np.int64)
+    for c in range(nc):
+        for r in range(nr):
+            down = c % 2 == 0
+            last = (r == nr - 1) if down else (r == 0)
+            code[r, c] = 4 if last else (6 if down else 1)
+            pos[r, c] = c * nr + (r if down else nr - 1 - r)
+    code[0 if nc % 2 == 0 else nr - 1, nc - 1] = 0xFF
+    _, cnt, _ = fr.accumulate(dev(code), None, None, "d8", None, counts=True)
+    assert np.array_equal(host(cnt), (pos + 1).astype(np.uint64))
+    qbar = np.zeros((nr, nc))
+    qbar[0 if nc % 2 == 0 else nr - 1, nc - 1] = 1.0
+    rbar = host(fr.adjoint(dev(code), dev(qbar), None, "d8"))
+    assert (rbar == 1.0).all()
 
 
 # ---------------------------------------------------------------------------
@@ -228,7 +298,7 @@ def test_mfd_unit_rain():
 
 @pytest.mark.parametrize("rule", ["d8", "mfd"])
 @pytest.mark.parametrize("nr,nc,seed", [(256, 256, 5), (97, 131, 7)])
-def test_adjoint_matches_transpose_solve(rule, nr, nc, seed):
+def test_adjoint_matches_transpose_solve(rule, nr, nc, seed, accpath):
     print(f"adjoint {rule} {nr}x{nc}", flush=True)
     z = synth.dem(seed, nr, nc)
     zt = dev(z)
@@ -284,6 +354,7 @@ def test_nonfinite_elevation_and_rain():
 
 
 def test_cycle_and_bad_codes_reported(d8path):
+    print(f"bad codes, path {d8path}", flush=True)
     code = np.full((8, 70), 0xFF, dtype=np.uint8)
     code[3, 5] = 4   # -> (3, 6)
     code[3, 6] = 3   # -> (3, 5): a 2-cycle
