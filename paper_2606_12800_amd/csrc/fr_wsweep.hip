@@ -40,8 +40,6 @@
 namespace fr {
 namespace {
 
-constexpr int RING = 16;       // rows held in LDS
-constexpr int WIN = RING - 2;  // rows that may still finish (plus one ahead, one behind)
 constexpr int LW = 66;         // LDS row: side cell, 64 lanes, side cell
 // Strips overlap: a wavefront computes 64 columns, owns the middle WS_OWN
 // and recomputes GHOST columns of each neighbour (as GHOST columns of its
@@ -58,6 +56,14 @@ constexpr int REC_LANE_R = WS_OWN - 1;   // read by the right neighbour's lane 0
 // (bounded wait), so neighbours stay within the exchange's slack.
 constexpr int LEAD = 4;
 constexpr int LEAD_SPIN = 1 << 14;  // polls before a neighbour counts as absent
+// Longest wait (in 100 MHz ticks) before a row leaves the window with edge
+// cells still waiting for side cells: the neighbour may itself be waiting
+// for rows this strip has not reached, so the cell is left to a later pass.
+constexpr uint64_t EDGE_WAIT_TICKS = 500;
+// Side cells delivered by the I/O wavefront are taken every ARRIVE_EVERY
+// steps: edge lanes are ghost columns, so their cells may lag a few rows,
+// and taking several deliveries at once retries each affected row once.
+constexpr int ARRIVE_EVERY = 4;
 
 constexpr uint32_t S_DONE = 1u << 8;
 constexpr uint32_t S_PRIOR = 1u << 9;  // finished in an earlier pass
@@ -186,15 +192,35 @@ constexpr int rec_words() {
 }
 static_assert(rec_words<RK_MULTI, DIR_FWD, VK_F64, false>() <= WS_EW, "edge record too small");
 
+// Ring geometry per configuration (LDS per workgroup stays below 80 KB so
+// that two workgroups fit on a compute unit): RING rows in LDS; a row may
+// finish during the WIN steps after it became the newest; rows up to
+// RING - WIN - 2 ahead of the newest are staged; BATCH rows are staged at a
+// time.
+template <int RK, int VK>
+struct Dims {
+  static constexpr bool F64M = RK == RK_MULTI && VK == VK_F64;
+  static constexpr int RING = RK == RK_SINGLE ? 32 : (F64M ? 16 : 24);
+  static constexpr int WIN = RK == RK_SINGLE ? 22 : (F64M ? 10 : 14);
+  static constexpr int BATCH = (RING - WIN - 2) / 2;
+};
+
 template <int RK, int VK, bool CNT>
 struct WsShared {
   using V = typename ValOf<VK>::T;
   using F = typename FracOf<RK, VK>::T;
-  uint32_t st[RING][LW];   // bits 0-7 routing code, S_DONE, S_PRIOR
-  uint8_t miss[RING][LW];  // pending cells: directions of inputs not yet final
-  V val[RING][LW];         // final value, or the source term while pending
-  uint64_t cnt[CNT ? RING : 1][LW];
-  F frac[RK == RK_MULTI ? RING : 1][8][LW];  // MFD: fraction sent in direction k
+  static constexpr int R = Dims<RK, VK>::RING;
+  uint32_t st[R][LW];   // bits 0-7 routing code, S_DONE, S_PRIOR
+  uint8_t miss[R][LW];  // pending cells: directions of inputs not yet final
+  V val[R][LW];         // final value, or the source term while pending
+  uint64_t cnt[CNT ? R : 1][LW];
+  F frac[RK == RK_MULTI ? R : 1][8][LW];  // MFD: fraction sent in direction k
+  // Hand-over between the two wavefronts.
+  int staged;         // rows (steps) 0 .. staged-1 are in the ring
+  int tcomp;          // the compute wavefront's current step
+  int done;           // the compute wavefront has finished
+  uint32_t arrived;   // slots whose side cell was delivered since last taken
+  int nbp[2];         // neighbours' progress (left, right) as last read
 };
 
 // One row of geometry for this lane: own cell and (lanes 0, 63) the cell
@@ -211,23 +237,35 @@ struct Src {
   bool prior;
 };
 
-// Orders this wavefront's LDS accesses across lanes.  One wavefront per
-// workgroup executes its LDS instructions in order, so only the compiler
-// must not move accesses across this point; no wait for global memory.
+// Orders one wavefront's LDS accesses: a wavefront executes its LDS
+// instructions in order, so only the compiler must not move them across.
 __device__ __forceinline__ void lds_sync() { asm volatile("" ::: "memory"); }
+__device__ __forceinline__ int lds_ld(const int* p) { return *(const volatile int*)p; }
+__device__ __forceinline__ void lds_st(int* p, int v) { *(volatile int*)p = v; }
 
+// Two wavefronts per workgroup.  Wavefront 1 (I/O) stages rows into the
+// ring ahead of use -- codes, elevations, source terms, earlier passes'
+// results, MFD fractions -- polls the neighbours' edge records and progress,
+// and delivers them into LDS.  Wavefront 0 (compute) only reads and writes
+// LDS and stores results, so it never waits for global memory.
 template <int RK, int DK, int VK, bool CNT>
-__global__ __launch_bounds__(64) void k_ws_pass(WsParams P, int dir, int first) {
+__global__ __launch_bounds__(128) void k_ws_pass(WsParams P, int dir, int first) {
   using V = typename ValOf<VK>::T;
   using F = typename FracOf<RK, VK>::T;
+  constexpr int R = Dims<RK, VK>::RING;
+  constexpr int WIN = Dims<RK, VK>::WIN;
+  constexpr int BATCH = Dims<RK, VK>::BATCH;
   constexpr int EWN = rec_words<RK, DK, VK, CNT>();
   constexpr uint32_t NOC = RK == RK_SINGLE ? (uint32_t)SINK : 0u;
   __shared__ WsShared<RK, VK, CNT> S;
 
-  const int lane = threadIdx.x;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int li = lane + 1;
   const int64_t strip = blockIdx.x;
-  const int64_t nr = P.nrows, nc = P.ncols;
+  const int nr = (int)P.nrows;
+  const int64_t nc = P.ncols;
+  const int64_t nstrips = (nc + WS_OWN - 1) / WS_OWN;
   const int64_t c = strip * WS_OWN - GHOST + lane;
   const bool live = c >= 0 && c < nc;
   const bool owned = live && lane >= GHOST && lane < GHOST + WS_OWN;
@@ -235,210 +273,389 @@ __global__ __launch_bounds__(64) void k_ws_pass(WsParams P, int dir, int first) 
   const bool sideR = lane == 63 && c + 1 >= 0 && c + 1 < nc;
   const bool has_side = sideL || sideR;
   const bool edge_lane = lane == 0 || lane == 63;
-  // This lane publishes its cells for a neighbour's edge lane.
-  const int64_t nstrips = (nc + WS_OWN - 1) / WS_OWN;
-  const bool has_record = live && ((lane == REC_LANE_L && strip > 0) || (lane == REC_LANE_R && strip + 1 < nstrips));
   const int64_t cs = lane == 0 ? c - 1 : c + 1;
   const int sidx = lane == 0 ? 0 : LW - 1;
-  // Records this lane writes (its strip's edge) and reads (the neighbour's).
-  const int my_side = lane == REC_LANE_L ? 0 : 1;
-  const int64_t rd_strip = lane == 0 ? strip - 1 : strip + 1;
-  const int rd_side = lane == 0 ? 1 : 0;
+  // Neighbour strips exist (per side) with an edge cell next to ours.
+  const int64_t c_first = strip * WS_OWN - GHOST, c_last = c_first + 63;
+  const bool nb_exists[2] = {c_first - 1 >= 0 && c_first - 1 < nc, c_last + 1 >= 0 && c_last + 1 < nc};
   const float pf = (float)P.p;
 
-  auto row_of = [&](int64_t t) -> int64_t { return dir < 0 ? nr - 1 - t : t; };
+  auto row_of = [&](int t) -> int64_t { return dir < 0 ? (int64_t)nr - 1 - t : (int64_t)t; };
+  auto slot = [&](int t) -> int { return t % R; };
 
-  auto load_geo = [&](int64_t t) -> Geo {
-    Geo g{NOC, NOC, INFINITY, INFINITY};
-    if (t < 0 || t >= nr) return g;
-    const int64_t rb = row_of(t) * nc;
-    if (live) {
-      g.code = P.code[rb + c];
-      if (RK == RK_MULTI) g.z = P.z[rb + c];
-    }
-    if (has_side) {
-      g.scode = P.code[rb + cs];
-      if (RK == RK_MULTI) g.sz = P.z[rb + cs];
-    }
-    return g;
-  };
+  if (threadIdx.x == 0) {
+    S.staged = 0;
+    S.tcomp = -1;
+    S.done = 0;
+    S.arrived = 0u;
+    S.nbp[0] = nb_exists[0] ? -1 : 0x3FFFFFFF;
+    S.nbp[1] = nb_exists[1] ? -1 : 0x3FFFFFFF;
+  }
+  __syncthreads();
 
-  auto load_src = [&](int64_t t) -> Src<VK> {
-    Src<VK> s;
-    vzero(s.v);
-    s.n = 1;
-    s.prior = false;
-    if (t < 0 || t >= nr || !live) return s;
-    const int64_t i = row_of(t) * nc + c;
-    if constexpr (VK == VK_FF) {
-      if (P.src64) {
-        const double d = P.src64[i];
-        s.v.hi = (float)d;
-        s.v.lo = (float)(d - (double)s.v.hi);
-      } else {
-        s.v = {P.src32 ? P.src32[i] : 1.0f, 0.0f};
+  if (wave == 1) {
+    // ======================= I/O wavefront ===============================
+    auto load_geo = [&](int t) -> Geo {
+      Geo g{NOC, NOC, INFINITY, INFINITY};
+      if (t < 0 || t >= nr) return g;
+      const int64_t rb = row_of(t) * nc;
+      if (live) {
+        g.code = P.code[rb + c];
+        if (RK == RK_MULTI) g.z = P.z[rb + c];
       }
-      if (!first) {
-        const float lo = P.vlo[i];
-        if (!isnan(lo)) {
-          s.v = {P.vhi[i], lo};
-          s.prior = true;
-        }
+      if (has_side) {
+        g.scode = P.code[rb + cs];
+        if (RK == RK_MULTI) g.sz = P.z[rb + cs];
       }
-    } else if constexpr (VK == VK_F64) {
-      s.v = P.src64 ? P.src64[i] : (P.src32 ? (double)P.src32[i] : 1.0);
-      if (!first) {
-        const double y = P.v64[i];
-        if (!isnan(y)) {
-          s.v = y;
-          s.prior = true;
-        }
-      }
-    } else {
-      if (CNT && !first && P.cnt[i] != ~0ull) s.prior = true;
-    }
-    if (CNT && s.prior) s.n = P.cnt[i];
-    return s;
-  };
-
-  bool bad = false, nonfinite = false;
-  uint32_t n_wait = 0, n_pace = 0, n_resolve = 0;  // diagnostics
-
-  // A row enters its slot: state, source term, MFD fractions (from the rows
-  // at steps y-1, y, y+1) and the side cells' codes.
-  auto enter_row = [&](int64_t y, const Geo& ga, const Geo& gb, const Geo& gc, const Src<VK>& sr) {
-    const int sb = (int)(y & (RING - 1));
-    const uint32_t code = gb.code;
-    if constexpr (RK == RK_MULTI) {
-      const Geo& gu = dir < 0 ? gc : ga;  // grid row r - 1
-      const Geo& gd = dir < 0 ? ga : gc;  // grid row r + 1
-      float zn[8];
-      zn[0] = from_left(gu.z);
-      zn[1] = gu.z;
-      zn[2] = from_right(gu.z);
-      zn[3] = from_left(gb.z);
-      zn[4] = from_right(gb.z);
-      zn[5] = from_left(gd.z);
-      zn[6] = gd.z;
-      zn[7] = from_right(gd.z);
-      if (lane == 0) {
-        zn[0] = sideL ? gu.sz : INFINITY;
-        zn[3] = sideL ? gb.sz : INFINITY;
-        zn[5] = sideL ? gd.sz : INFINITY;
-      }
-      if (lane == 63) {
-        zn[2] = sideR ? gu.sz : INFINITY;
-        zn[4] = sideR ? gb.sz : INFINITY;
-        zn[7] = sideR ? gd.sz : INFINITY;
-      }
-      const float zi = gb.z;
-      if (live && !isfinite(zi)) nonfinite = true;
-      F fr[8];
-      if constexpr (VK == VK_F64) {
-        double w[8], sum = 0.0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          w[k] = 0.0;
-          if (!live || !sends<RK>(code, k)) continue;
-          if (!(zn[k] < zi)) {
-            bad = true;
-            continue;
-          }
-          const double sl = ((double)zi - (double)zn[k]) / (nb_diag(k) ? kSqrt2 : 1.0);
-          w[k] = pow(sl, P.p);
-          sum += w[k];
-        }
-        const double iw = sum > 0.0 ? 1.0 / sum : 0.0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) fr[k] = w[k] * iw;
-      } else {
-        float sl[8], smax = 0.0f;
-        bool rcv[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          sl[k] = 0.0f;
-          rcv[k] = false;
-          if (!live || !sends<RK>(code, k)) continue;
-          if (!(zn[k] < zi)) {
-            bad = true;
-            continue;
-          }
-          rcv[k] = true;
-          const float drop = zi - zn[k];
-          sl[k] = nb_diag(k) ? drop * kInvSqrt2f : drop;
-          smax = sl[k] > smax ? sl[k] : smax;
-        }
-        const float rs = smax > 0.0f ? 1.0f / smax : 0.0f;
-        float tk[8], sum = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          tk[k] = rcv[k] ? exp2f(pf * log2f(sl[k] * rs)) : 0.0f;
-          sum += tk[k];
-        }
-        const float iw = sum > 0.0f ? 1.0f / sum : 0.0f;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) fr[k] = tk[k] * iw;
-      }
-#pragma unroll
-      for (int k = 0; k < 8; ++k) S.frac[sb][k][li] = fr[k];
-    } else {
-      if (live && code != SINK) {
-        if (code > 7) {
-          bad = true;
+      return g;
+    };
+    auto load_src = [&](int t) -> Src<VK> {
+      Src<VK> sr;
+      vzero(sr.v);
+      sr.n = 1;
+      sr.prior = false;
+      if (t < 0 || t >= nr || !live) return sr;
+      const int64_t i = row_of(t) * nc + c;
+      if constexpr (VK == VK_FF) {
+        if (P.src64) {
+          const double d = P.src64[i];
+          sr.v.hi = (float)d;
+          sr.v.lo = (float)(d - (double)sr.v.hi);
         } else {
-          const int k = (int)code;
-          const int64_t rr = row_of(y) + nb_dr(k), cc = c + nb_dc(k);
-          if (rr < 0 || rr >= nr || cc < 0 || cc >= nc) bad = true;
+          sr.v = {P.src32 ? P.src32[i] : 1.0f, 0.0f};
+        }
+        if (!first) {
+          const float lo = P.vlo[i];
+          if (!isnan(lo)) {
+            sr.v = {P.vhi[i], lo};
+            sr.prior = true;
+          }
+        }
+      } else if constexpr (VK == VK_F64) {
+        sr.v = P.src64 ? P.src64[i] : (P.src32 ? (double)P.src32[i] : 1.0);
+        if (!first) {
+          const double y = P.v64[i];
+          if (!isnan(y)) {
+            sr.v = y;
+            sr.prior = true;
+          }
+        }
+      } else {
+        if (CNT && !first && P.cnt[i] != ~0ull) sr.prior = true;
+      }
+      if (CNT && sr.prior) sr.n = P.cnt[i];
+      return sr;
+    };
+
+    bool bad = false, nonfinite = false;
+    // Wanted side cells not yet delivered, per side (left, right), by slot.
+    uint32_t want0 = 0u, want1 = 0u;
+    // Adjoint: an edge cell gives water to the side cell one step ahead
+    // (kept in the edge lane itself).
+    bool want_next = false;
+
+    // Writes the row at step y (geometry of steps y-1, y, y+1) into its slot.
+    auto stage_row = [&](int y, const Geo& ga, const Geo& gb, const Geo& gc, const Src<VK>& sr) {
+      const int sb = slot(y);
+      const uint32_t code = gb.code;
+      if constexpr (RK == RK_MULTI) {
+        const Geo& gu = dir < 0 ? gc : ga;  // grid row r - 1
+        const Geo& gd = dir < 0 ? ga : gc;  // grid row r + 1
+        float zn[8];
+        zn[0] = from_left(gu.z);
+        zn[1] = gu.z;
+        zn[2] = from_right(gu.z);
+        zn[3] = from_left(gb.z);
+        zn[4] = from_right(gb.z);
+        zn[5] = from_left(gd.z);
+        zn[6] = gd.z;
+        zn[7] = from_right(gd.z);
+        if (lane == 0) {
+          zn[0] = sideL ? gu.sz : INFINITY;
+          zn[3] = sideL ? gb.sz : INFINITY;
+          zn[5] = sideL ? gd.sz : INFINITY;
+        }
+        if (lane == 63) {
+          zn[2] = sideR ? gu.sz : INFINITY;
+          zn[4] = sideR ? gb.sz : INFINITY;
+          zn[7] = sideR ? gd.sz : INFINITY;
+        }
+        const float zi = gb.z;
+        if (live && !isfinite(zi)) nonfinite = true;
+        F fr[8];
+        if constexpr (VK == VK_F64) {
+          double w[8], sum = 0.0;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            w[k] = 0.0;
+            if (!live || !sends<RK>(code, k)) continue;
+            if (!(zn[k] < zi)) {
+              bad = true;
+              continue;
+            }
+            const double sl = ((double)zi - (double)zn[k]) / (nb_diag(k) ? kSqrt2 : 1.0);
+            w[k] = pow(sl, P.p);
+            sum += w[k];
+          }
+          const double iw = sum > 0.0 ? 1.0 / sum : 0.0;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) fr[k] = w[k] * iw;
+        } else {
+          float sl[8], smax = 0.0f;
+          bool rcv[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            sl[k] = 0.0f;
+            rcv[k] = false;
+            if (!live || !sends<RK>(code, k)) continue;
+            if (!(zn[k] < zi)) {
+              bad = true;
+              continue;
+            }
+            rcv[k] = true;
+            const float drop = zi - zn[k];
+            sl[k] = nb_diag(k) ? drop * kInvSqrt2f : drop;
+            smax = sl[k] > smax ? sl[k] : smax;
+          }
+          const float rs = smax > 0.0f ? 1.0f / smax : 0.0f;
+          float tk[8], sum = 0.0f;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            tk[k] = rcv[k] ? exp2f(pf * log2f(sl[k] * rs)) : 0.0f;
+            sum += tk[k];
+          }
+          const float iw = sum > 0.0f ? 1.0f / sum : 0.0f;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) fr[k] = tk[k] * iw;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) S.frac[sb][k][li] = fr[k];
+      } else {
+        if (live && code != SINK) {
+          if (code > 7) {
+            bad = true;
+          } else {
+            const int k = (int)code;
+            const int64_t rr = row_of(y) + nb_dr(k), cc = c + nb_dc(k);
+            if (rr < 0 || rr >= nr || cc < 0 || cc >= nc) bad = true;
+          }
         }
       }
-    }
-    if constexpr (VK == VK_FF) {
-      if (live && !isfinite(sr.v.hi)) nonfinite = true;
-    } else if constexpr (VK == VK_F64) {
-      if (live && !isfinite(sr.v)) nonfinite = true;
-    }
-    uint32_t st = live ? (code & 0xFFu) : (NOC | S_DONE);
-    if (live && sr.prior) st |= S_DONE | S_PRIOR;
-    S.st[sb][li] = st;
-    S.miss[sb][li] = 0;
-    V v = sr.v;
-    if (!live) vzero(v);
-    S.val[sb][li] = v;
-    if constexpr (CNT) S.cnt[sb][li] = live ? sr.n : 0;
-    if (edge_lane) {
-      S.st[sb][sidx] = has_side ? (gb.scode & 0xFFu) : (NOC | S_DONE);
-      V v0;
-      vzero(v0);
-      S.val[sb][sidx] = v0;
-      if constexpr (CNT) S.cnt[sb][sidx] = 0;
-      if constexpr (RK == RK_MULTI) {
+      if constexpr (VK == VK_FF) {
+        if (live && !isfinite(sr.v.hi)) nonfinite = true;
+      } else if constexpr (VK == VK_F64) {
+        if (live && !isfinite(sr.v)) nonfinite = true;
+      }
+      uint32_t st = live ? (code & 0xFFu) : (NOC | S_DONE);
+      if (live && sr.prior) st |= S_DONE | S_PRIOR;
+      S.st[sb][li] = st;
+      S.miss[sb][li] = 0;
+      V v = sr.v;
+      if (!live) vzero(v);
+      S.val[sb][li] = v;
+      if constexpr (CNT) S.cnt[sb][li] = live ? sr.n : 0;
+      if (edge_lane) {
+        S.st[sb][sidx] = has_side ? (gb.scode & 0xFFu) : (NOC | S_DONE);
+        V v0;
+        vzero(v0);
+        S.val[sb][sidx] = v0;
+        if constexpr (CNT) S.cnt[sb][sidx] = 0;
+        if constexpr (RK == RK_MULTI) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) S.frac[sb][k][sidx] = (F)0;
+          for (int k = 0; k < 8; ++k) S.frac[sb][k][sidx] = (F)0;
+        }
+      }
+      // Wanted side cells (uniform masks from the edge lanes).
+      bool wl = false, wprev = false;
+      if (has_side) {
+        if (DK == DIR_FWD) {
+          // The side cell gives water toward this strip's edge column.
+          wl = lane == 0 ? (sends<RK>(gb.scode, 2) || sends<RK>(gb.scode, 4) || sends<RK>(gb.scode, 7))
+                         : (sends<RK>(gb.scode, 0) || sends<RK>(gb.scode, 3) || sends<RK>(gb.scode, 5));
+        } else {
+          // The edge cell gives water to side cells at grid rows r-1, r, r+1.
+          const int ka = lane == 0 ? 0 : 2, kb = lane == 0 ? 3 : 4, kc = lane == 0 ? 5 : 7;
+          const bool up = sends<RK>(code, ka), mid = sends<RK>(code, kb), dn = sends<RK>(code, kc);
+          const bool prev = dir < 0 ? dn : up, next = dir < 0 ? up : dn;  // steps y-1, y+1
+          wl = mid || want_next;
+          wprev = prev && y >= 1;
+          want_next = next;
+        }
+      }
+      const uint64_t bw = __ballot(wl), bp = __ballot(wprev);
+      want0 &= ~(1u << sb);
+      want1 &= ~(1u << sb);
+      if (bw & 1ull) want0 |= 1u << sb;
+      if ((bw >> 63) & 1ull) want1 |= 1u << sb;
+      if (y >= 1) {
+        if (bp & 1ull) want0 |= 1u << slot(y - 1);
+        if ((bp >> 63) & 1ull) want1 |= 1u << slot(y - 1);
+      }
+    };
+
+    Geo gp = load_geo(-1), gcur = load_geo(0);
+    int y = 0;  // next step to stage
+    // The next batch is loaded one iteration ahead of its use.
+    Geo g[BATCH];
+    Src<VK> sr[BATCH];
+#pragma unroll
+    for (int j = 0; j < BATCH; ++j) {
+      g[j] = load_geo(1 + j);
+      sr[j] = load_src(j);
+    }
+    int idle = 0;
+    uint64_t io_stage = 0, io_poll = 0, io_iter = 0;  // diagnostics
+    for (;;) {
+      if (lds_ld(&S.done)) break;
+      const int tc = lds_ld(&S.tcomp);
+      bool busy = false;
+      ++io_iter;
+      uint64_t q0 = __builtin_amdgcn_s_memrealtime();
+      // Stage a batch once its slots are free: the compute wavefront reads
+      // steps tc - WIN .. tc + 1.
+      if (y < nr && y + BATCH - 1 <= tc - WIN - 1 + R) {
+#pragma unroll
+        for (int j = 0; j < BATCH; ++j) {
+          const Geo& ga = j == 0 ? gp : (j == 1 ? gcur : g[j - 2]);
+          const Geo& gb = j == 0 ? gcur : g[j - 1];
+          if (y + j < nr) stage_row(y + j, ga, gb, g[j], sr[j]);
+        }
+        gp = BATCH >= 2 ? g[BATCH - 2] : gcur;
+        gcur = g[BATCH - 1];
+        y += BATCH;
+        lds_sync();
+        if (lane == 0) lds_st(&S.staged, y < nr ? y : nr);
+        busy = true;
+        if (y < nr) {
+#pragma unroll
+          for (int j = 0; j < BATCH; ++j) {
+            g[j] = load_geo(y + 1 + j);
+            sr[j] = load_src(y + j);
+          }
+        }
+      }
+      uint64_t q1 = __builtin_amdgcn_s_memrealtime();
+      io_stage += q1 - q0;
+      q0 = q1;
+      // Poll the neighbours' records for wanted rows still in the ring,
+      // lane-parallel: lanes 0-31 the left neighbour, 32-63 the right one;
+      // four lanes (words) per row, eight rows per load.
+      const int plo = tc - WIN > 0 ? tc - WIN : 0;
+      const int phi = (y < nr ? y : nr) - 1;
+      if ((want0 | want1) && plo <= phi) {
+        const int sd = lane >> 5, j = lane & 31, r8 = j >> 2, w = j & 3;
+        const int64_t rstrip = sd == 0 ? strip - 1 : strip + 1;
+        const int rside = sd == 0 ? 1 : 0;
+        const int ksd0 = sd == 0 ? 2 : 0, ksd1 = sd == 0 ? 4 : 3, ksd2 = sd == 0 ? 7 : 5;
+        const int sx_idx = sd == 0 ? 0 : LW - 1;
+        uint32_t arr = 0;
+        constexpr int NB = (R + 7) / 8;
+        uint64_t wd[NB];
+        bool actb[NB];
+#pragma unroll
+        for (int bb = 0; bb < NB; ++bb) {
+          const int x = plo + bb * 8 + r8;
+          actb[bb] = w < EWN && x <= phi && nb_exists[sd] && ((((sd == 0 ? want0 : want1)) >> slot(x)) & 1u);
+          wd[bb] = actb[bb] ? rec_get(P.edge + ((rstrip * P.nrows + row_of(x)) * 2 + rside) * WS_EW + w)
+                            : REC_EMPTY;
+        }
+#pragma unroll
+        for (int bb = 0; bb < NB; ++bb) {
+          const int b0 = plo + bb * 8;
+          if (b0 > phi) break;
+          const int x = b0 + r8;
+          const bool act = actb[bb];
+          const uint64_t word = wd[bb];
+          const uint64_t okm = __ballot(act && word != REC_EMPTY);
+          const uint64_t rowm = (((1ull << EWN) - 1ull) << (sd * 32 + r8 * 4));
+          const bool complete = act && (okm & rowm) == rowm;
+          if (complete) {
+            const int sx = slot(x);
+            if (w == 0) {
+              V v;
+              vzero(v);
+              if constexpr (VK == VK_FF) {
+                v.hi = lo_f(word);
+                v.lo = hi_f(word);
+              } else if constexpr (VK == VK_F64) {
+                v = bitsd(word);
+              }
+              if constexpr (VK != VK_NONE) S.val[sx][sx_idx] = v;
+              if constexpr (DK == DIR_FWD && RK == RK_SINGLE && CNT && VK == VK_NONE) S.cnt[sx][sx_idx] = word;
+            } else if constexpr (DK == DIR_FWD && RK == RK_MULTI) {
+              if constexpr (VK == VK_F64) {
+                S.frac[sx][w == 1 ? ksd0 : (w == 2 ? ksd1 : ksd2)][sx_idx] = bitsd(word);
+              } else {
+                if (w == 1) {
+                  S.frac[sx][ksd0][sx_idx] = lo_f(word);
+                  S.frac[sx][ksd1][sx_idx] = hi_f(word);
+                } else {
+                  S.frac[sx][ksd2][sx_idx] = lo_f(word);
+                }
+              }
+            } else if constexpr (DK == DIR_FWD && RK == RK_SINGLE && CNT) {
+              S.cnt[sx][sx_idx] = word;
+            }
+          }
+          lds_sync();
+          if (complete && w == 0) {
+            const int sx = slot(x);
+            S.st[sx][sx_idx] |= S_DONE;
+            arr |= 1u << sx;
+          }
+          // Delivered rows leave the wanted sets.
+          const uint64_t done_rows = __ballot(complete && w == 0);
+          for (int qr = 0; qr < 8; ++qr) {
+            if ((done_rows >> (qr * 4)) & 1ull) want0 &= ~(1u << slot(b0 + qr));
+            if ((done_rows >> (32 + qr * 4)) & 1ull) want1 &= ~(1u << slot(b0 + qr));
+          }
+        }
+        // Publish deliveries after their payload.
+        for (int off = 32; off > 0; off >>= 1) arr |= (uint32_t)__shfl_xor((int)arr, off, 64);
+        lds_sync();
+        if (lane == 0 && arr) {
+          atomicOr(&S.arrived, arr);
+          busy = true;
+        }
+      }
+      // Neighbours' progress, for pacing and for knowing what they froze.
+      if ((lane == 0 && nb_exists[0]) || (lane == 32 && nb_exists[1])) {
+        const int sd = lane == 0 ? 0 : 1;
+        const int v = prog_get(P.progress + (sd == 0 ? strip - 1 : strip + 1));
+        if (v != lds_ld(&S.nbp[sd])) {
+          lds_st(&S.nbp[sd], v);
+        }
+      }
+      io_poll += __builtin_amdgcn_s_memrealtime() - q0;
+      if (!busy) {
+        if (++idle > 4) __builtin_amdgcn_s_sleep(2);
+      } else {
+        idle = 0;
       }
     }
-  };
+    if (lane == 0 && P.debug) {
+      unsigned long long* tm = reinterpret_cast<unsigned long long*>(P.ctr + 8);
+      atomicAdd(tm + 5, (unsigned long long)io_stage);
+      atomicAdd(tm + 6, (unsigned long long)io_poll);
+      atomicAdd(tm + 7, (unsigned long long)io_iter);
+    }
+    if (first && P.status) {
+      if (__ballot(bad) && lane == 0) atomicCAS(P.status, 0, FR_ERR_BADCODE);
+      if (__ballot(nonfinite) && lane == 0) atomicCAS(P.status, 0, FR_ERR_NONFINITE);
+    }
+    return;
+  }
 
-  // Forward: whether a row's side cell gives water to this strip's edge
-  // column (directions from the side cell toward it).
-  auto side_gives = [&](uint32_t scode) -> bool {
-    if (!has_side) return false;
-    if (lane == 0) return sends<RK>(scode, 2) || sends<RK>(scode, 4) || sends<RK>(scode, 7);
-    return sends<RK>(scode, 0) || sends<RK>(scode, 3) || sends<RK>(scode, 5);
-  };
-  // Adjoint: the side cells (as steps relative to the edge cell's step) that
-  // the edge cell gives water to, as bits 0 (step - 1), 1 (same), 2 (step + 1).
-  auto own_gives_side = [&](uint32_t code) -> uint32_t {
-    if (!has_side) return 0u;
-    const int ka = lane == 0 ? 0 : 2, kb = lane == 0 ? 3 : 4, kc = lane == 0 ? 5 : 7;
-    // Grid row offsets -1, 0, +1 map to step offsets -dir, 0, +dir.
-    const uint32_t up = sends<RK>(code, ka) ? 1u : 0u, mid = sends<RK>(code, kb) ? 1u : 0u,
-                   dn = sends<RK>(code, kc) ? 1u : 0u;
-    return dir < 0 ? (dn | (mid << 1) | (up << 2)) : (up | (mid << 1) | (dn << 2));
-  };
+  // ======================== compute wavefront ============================
+  const int my_side = lane == REC_LANE_L ? 0 : 1;
+  const bool has_record = live && ((lane == REC_LANE_L && strip > 0) || (lane == REC_LANE_R && strip + 1 < nstrips));
+  uint32_t pend_rows = 0, nfin = 0;
+  uint32_t n_wait = 0, n_pace = 0, n_resolve = 0;  // diagnostics
+  bool fail = false;
 
-  // Publishes a newly final edge cell for the neighbouring strip.
-  auto put_record = [&](int64_t x, int sb, const V& v, uint64_t n) {
-    uint64_t* rec = P.edge + ((strip * nr + row_of(x)) * 2 + my_side) * WS_EW;
+  // Publishes a newly final cell that a neighbour reads as its side cell.
+  auto put_record = [&](int x, int sb, const V& v, uint64_t n) {
+    uint64_t* rec = P.edge + ((strip * P.nrows + row_of(x)) * 2 + my_side) * WS_EW;
     int w = 0;
     if constexpr (VK == VK_FF) rec_put(rec + w++, pack2(v.hi, v.lo));
     else if constexpr (VK == VK_F64) rec_put(rec + w++, dbits(v));
@@ -462,7 +679,7 @@ __global__ __launch_bounds__(64) void k_ws_pass(WsParams P, int dir, int first) 
 
   // Tries to finish the pending cells of the row at step x (slot sb).
   // Returns the lanes finished.
-  auto resolve = [&](int64_t x, int sb) -> uint64_t {
+  auto resolve = [&](int x, int sb) -> uint64_t {
     const uint32_t me = S.st[sb][li];
     const bool pend = !(me & S_DONE);
     const uint32_t code = me & 0xFFu;
@@ -470,27 +687,42 @@ __global__ __launch_bounds__(64) void k_ws_pass(WsParams P, int dir, int first) 
     uint64_t accn = CNT ? S.cnt[sb][li] : 0;
     bool ok = pend;
     uint32_t miss = 0;
+    // Gather the six neighbours in the rows before and after without
+    // branches, so that all LDS reads are in flight together; rows off the
+    // grid read as finished cells that give nothing.
+    uint32_t sj[8];
+    V vj[8];
+    F fj[8];
+    uint64_t nj[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       if (k == 3 || k == 4) continue;
-      const int64_t xn = x + nb_dr(k) * dir;
-      if (xn < 0 || xn >= nr) continue;
-      const int sn = (int)(xn & (RING - 1));
+      const int xn = x + nb_dr(k) * dir;
+      const bool row_ok = xn >= 0 && xn < nr;
+      const int sn = slot(row_ok ? xn : x);
       const int ln = li + nb_dc(k);
-      const uint32_t sj = S.st[sn][ln];
-      const bool input = pend && (DK == DIR_FWD ? sends<RK>(sj & 0xFFu, 7 - k) : sends<RK>(code, k));
-      if (!input) continue;
-      if (!(sj & S_DONE)) {
+      sj[k] = row_ok ? S.st[sn][ln] : (NOC | S_DONE);
+      if constexpr (VK != VK_NONE) vj[k] = S.val[sn][ln];
+      if constexpr (RK == RK_MULTI) fj[k] = DK == DIR_FWD ? S.frac[sn][7 - k][ln] : S.frac[sb][k][li];
+      if constexpr (CNT) nj[k] = S.cnt[sn][ln];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (k == 3 || k == 4) continue;
+      const bool input = pend && (DK == DIR_FWD ? sends<RK>(sj[k] & 0xFFu, 7 - k) : sends<RK>(code, k)) &&
+                         x + nb_dr(k) * dir >= 0 && x + nb_dr(k) * dir < nr;
+      const bool fin = (sj[k] & S_DONE) != 0;
+      if (input && !fin) {
         ok = false;
         miss |= 1u << k;
-        continue;
       }
-      if constexpr (VK != VK_NONE) {
-        V vj = S.val[sn][ln];
-        if constexpr (RK == RK_MULTI) vj = vmul(vj, DK == DIR_FWD ? S.frac[sn][7 - k][ln] : S.frac[sb][k][li]);
-        vadd(acc, vj);
+      if (input && fin) {
+        if constexpr (VK != VK_NONE) {
+          if constexpr (RK == RK_MULTI) vadd(acc, vmul(vj[k], fj[k]));
+          else vadd(acc, vj[k]);
+        }
+        if constexpr (CNT) accn += nj[k];
       }
-      if constexpr (CNT) accn += S.cnt[sn][ln];
     }
     // Same-row inputs, iterated along the row with lane shifts.
     const uint32_t sl = S.st[sb][li - 1], sr = S.st[sb][li + 1];
@@ -569,8 +801,8 @@ __global__ __launch_bounds__(64) void k_ws_pass(WsParams P, int dir, int first) 
   };
 
   // Whether pending cells of row y wait for cells of row x finished in D.
-  auto affected = [&](int64_t y, int64_t x, uint64_t D) -> bool {
-    const int sy = (int)(y & (RING - 1));
+  auto affected = [&](int y, int x, uint64_t D) -> bool {
+    const int sy = slot(y);
     const uint32_t m = S.miss[sy][li];
     const bool pend = !(S.st[sy][li] & S_DONE);
     const int kb = ((x - y) * dir) < 0 ? 0 : 5;
@@ -583,110 +815,15 @@ __global__ __launch_bounds__(64) void k_ws_pass(WsParams P, int dir, int first) 
     return __ballot(a) != 0;
   };
 
-  // pend_rows: a bit per slot whose row (in the window) has pending cells.
-  // want (edge lanes): slots whose side cell is wanted and not yet final.
-  uint32_t pend_rows = 0, want = 0, nfin = 0;
-
-  // Polls in flight (edge lanes): step of the row polled, record words.
-  // Wanted rows are polled round-robin, so rows whose side cell finishes
-  // only in a later pass cannot starve the others.
-  constexpr int NPOLL = 3;
-  int64_t prow[NPOLL];
-  uint64_t pw[NPOLL][EWN];
-  int64_t pcur = 0;
-#pragma unroll
-  for (int p = 0; p < NPOLL; ++p) prow[p] = -1;
-
-  auto issue_polls = [&](int64_t lo, int64_t hi) {
-    int64_t x = (pcur < lo || pcur > hi) ? lo : pcur;
-    int rem = want ? (int)(hi - lo + 1) : 0;
-#pragma unroll
-    for (int p = 0; p < NPOLL; ++p) {
-      prow[p] = -1;
-      while (rem > 0) {
-        const int64_t y = x;
-        x = (x == hi) ? lo : x + 1;
-        --rem;
-        if ((want >> (y & (RING - 1))) & 1u) {
-          prow[p] = y;
-          break;
-        }
-      }
-      if (prow[p] < 0) continue;
-      pcur = x;
-      const uint64_t* rec = P.edge + ((rd_strip * nr + row_of(prow[p])) * 2 + rd_side) * WS_EW;
-#pragma unroll
-      for (int w = 0; w < EWN; ++w) pw[p][w] = rec_get(rec + w);
-    }
-  };
-
-  // Moves arrived records into LDS; returns the slots to retry (rows
-  // lo..hi whose edge cell waits for an arrived side cell).
-  auto consume_polls = [&](int64_t lo, int64_t hi) -> uint32_t {
-    uint32_t dirty = 0;
-#pragma unroll
-    for (int p = 0; p < NPOLL; ++p) {
-      const int64_t x = prow[p];
-      bool okp = x >= 0;
-#pragma unroll
-      for (int w = 0; w < EWN; ++w) okp = okp && pw[p][w] != REC_EMPTY;
-      if (okp) {
-        const int sx = (int)(x & (RING - 1));
-        int w = 0;
-        V v;
-        vzero(v);
-        if constexpr (VK == VK_FF) {
-          v.hi = lo_f(pw[p][w]);
-          v.lo = hi_f(pw[p][w]);
-          ++w;
-        } else if constexpr (VK == VK_F64) {
-          v = bitsd(pw[p][w]);
-          ++w;
-        }
-        S.val[sx][sidx] = v;
-        if constexpr (DK == DIR_FWD && RK == RK_MULTI) {
-          // The side cell's fractions toward this strip's edge column.
-          F f0, f1, f2;
-          if constexpr (VK == VK_F64) {
-            f0 = bitsd(pw[p][w]);
-            f1 = bitsd(pw[p][w + 1]);
-            f2 = bitsd(pw[p][w + 2]);
-            w += 3;
-          } else {
-            f0 = lo_f(pw[p][w]);
-            f1 = hi_f(pw[p][w]);
-            f2 = lo_f(pw[p][w + 1]);
-            w += 2;
-          }
-          S.frac[sx][lane == 0 ? 2 : 0][sidx] = f0;
-          S.frac[sx][lane == 0 ? 4 : 3][sidx] = f1;
-          S.frac[sx][lane == 0 ? 7 : 5][sidx] = f2;
-        }
-        if constexpr (DK == DIR_FWD && RK == RK_SINGLE && CNT) S.cnt[sx][sidx] = pw[p][w++];
-        S.st[sx][sidx] |= S_DONE;
-        want &= ~(1u << sx);
-#pragma unroll
-        for (int d = -1; d <= 1; ++d) {
-          const int64_t y = x + d;
-          if (y < lo || y > hi) continue;
-          const int sy = (int)(y & (RING - 1));
-          // Direction from the edge cell at step y to the side cell at step x.
-          const int dr = (int)((x - y) * dir);
-          const int k = lane == 0 ? (dr < 0 ? 0 : (dr == 0 ? 3 : 5)) : (dr < 0 ? 2 : (dr == 0 ? 4 : 7));
-          if (!(S.st[sy][li] & S_DONE) && ((S.miss[sy][li] >> k) & 1u)) dirty |= 1u << sy;
-        }
-      }
-      prow[p] = -1;
-    }
-    return (uint32_t)__builtin_amdgcn_readlane((int)dirty, 0) | (uint32_t)__builtin_amdgcn_readlane((int)dirty, 63);
-  };
+  // Step of the row held in slot sb among steps t - R + 1 .. t.
+  auto step_of = [&](int sb, int t) -> int { return t - (((t % R) - sb + R) % R); };
 
   // Retries rows until nothing changes; window = steps lo..t.
-  auto settle = [&](uint32_t dirty, int64_t lo, int64_t t) {
+  auto settle = [&](uint32_t dirty, int lo, int t) {
     while (dirty) {
       const int sb = __builtin_ctz(dirty);
       dirty &= dirty - 1;
-      const int64_t x = t - (int64_t)((((int)(t & (RING - 1))) - sb) & (RING - 1));
+      const int x = step_of(sb, t);
       if (x < lo || !((pend_rows >> sb) & 1u)) continue;
       lds_sync();
       ++n_resolve;
@@ -697,19 +834,75 @@ __global__ __launch_bounds__(64) void k_ws_pass(WsParams P, int dir, int first) 
       if (D) {
 #pragma unroll
         for (int d = -1; d <= 1; d += 2) {
-          const int64_t y = x + d;
-          if (y < lo || y > t) continue;
-          const int sy = (int)(y & (RING - 1));
-          if (((pend_rows >> sy) & 1u) && affected(y, x, D)) dirty |= 1u << sy;
+          const int yy = x + d;
+          if (yy < lo || yy > t) continue;
+          const int sy = slot(yy);
+          if (((pend_rows >> sy) & 1u) && affected(yy, x, D)) dirty |= 1u << sy;
         }
       }
     }
   };
 
+  // Side cells delivered since the last call: rows lo..t whose edge cell
+  // waits for one of them.
+  auto take_arrivals = [&](int lo, int t) -> uint32_t {
+    uint32_t arr = 0;
+    if (lane == 0) arr = atomicExch(&S.arrived, 0u);
+    arr = (uint32_t)__builtin_amdgcn_readfirstlane((int)arr);
+    if (!arr) return 0u;
+    lds_sync();
+    uint32_t dirty = 0;
+    while (arr) {
+      const int sx = __builtin_ctz(arr);
+      arr &= arr - 1;
+      const int x = step_of(sx, t + R - WIN - 1);  // deliveries reach up to the staged rows
+#pragma unroll
+      for (int d = -1; d <= 1; ++d) {
+        const int yy = x + d;
+        if (yy < lo || yy > t || !has_side) continue;
+        const int sy = slot(yy);
+        const int dr = (x - yy) * dir;
+        const int k = lane == 0 ? (dr < 0 ? 0 : (dr == 0 ? 3 : 5)) : (dr < 0 ? 2 : (dr == 0 ? 4 : 7));
+        if (!(S.st[sy][li] & S_DONE) && ((S.miss[sy][li] >> k) & 1u)) dirty |= 1u << sy;
+      }
+    }
+    return (uint32_t)__builtin_amdgcn_readlane((int)dirty, 0) | (uint32_t)__builtin_amdgcn_readlane((int)dirty, 63);
+  };
+
+  // Neighbours that stopped answering are not waited for.
+  bool absent[2] = {false, false};
+  int nb_last[2] = {-2, -2}, nb_same[2] = {0, 0};
+
+  // Whether the edge lanes of row f still wait for side cells that the
+  // neighbour has not given up on (it freezes row x at step x + WIN - 1).
+  auto edge_wait_needed = [&](int f) -> bool {
+    const int sf = slot(f);
+    bool need = false;
+    const int sd = lane == 0 ? 0 : 1;
+    if (has_side && !absent[sd] && !(S.st[sf][li] & S_DONE)) {
+      const uint32_t m = S.miss[sf][li] & (lane == 0 ? 0x29u : 0x94u);
+      const int nb = lds_ld(&S.nbp[sd]);
+      need = m != 0 && nb < f + 1 + WIN + 1;
+    }
+    return __ballot(need) != 0;
+  };
+
+  auto wait_edges = [&](int f, int lo, int t) {
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    for (int it = 0; it < (1 << 16); ++it) {
+      if (!edge_wait_needed(f)) break;
+      if (__builtin_amdgcn_s_memrealtime() - t0 > EDGE_WAIT_TICKS) break;
+      ++n_wait;
+      const uint32_t dirty = take_arrivals(lo, t);
+      if (dirty) settle(dirty, lo, t);
+      else __builtin_amdgcn_s_sleep(1);
+    }
+  };
+
   // Writes a row leaving the window to HBM; in the first pass unfinished
   // cells get the sentinel so a later pass can tell them apart.
-  auto freeze = [&](int64_t f) {
-    const int sf = (int)(f & (RING - 1));
+  auto freeze = [&](int f) {
+    const int sf = slot(f);
     const uint32_t me = S.st[sf][li];
     pend_rows &= ~(1u << sf);
     if (!owned) return;
@@ -736,154 +929,97 @@ __global__ __launch_bounds__(64) void k_ws_pass(WsParams P, int dir, int first) 
     }
   };
 
-  // Side rows wanted by the adjoint: set when the row that needs them has
-  // entered; the bit for the step after the newest entered row waits here.
-  uint32_t want_next = 0;
-  auto mark_wanted = [&](int64_t y, uint32_t code, uint32_t scode) {
-    const int sy = (int)(y & (RING - 1));
-    if (DK == DIR_FWD) {
-      if (side_gives(scode)) want |= 1u << sy;
-    } else {
-      const uint32_t g = own_gives_side(code);
-      uint32_t w = (want_next || (g & 2u)) ? (1u << sy) : 0u;
-      if ((g & 1u) && y >= 1) {
-        const int sp = (int)((y - 1) & (RING - 1));
-        if (!(S.st[sp][sidx] & S_DONE)) w |= 1u << sp;
-      }
-      want |= w;
-      want_next = (g & 4u) ? 1u : 0u;
+  // Bounded wait for the I/O wavefront to stage rows up to step need - 1.
+  auto wait_staged = [&](int need) -> bool {
+    for (int it = 0; it < (1 << 24); ++it) {
+      if (lds_ld(&S.staged) >= need) return true;
+      __builtin_amdgcn_s_sleep(1);
     }
+    return false;
   };
 
-  // Bounded wait, before row f leaves the window, for side cells that its
-  // edge cells still need; other strips are never waited for otherwise.
-  auto wait_edges = [&](int64_t f, int64_t lo, int64_t t) {
-    const int sf = (int)(f & (RING - 1));
-    int idle = 0;
-    for (int it = 0; it < 128 && idle < 16; ++it) {
-      bool need = false;
-      if (has_side && !(S.st[sf][li] & S_DONE)) need = (S.miss[sf][li] & (lane == 0 ? 0x29u : 0x94u)) != 0;
-      if (__ballot(need) == 0) break;
-      ++n_wait;
-      issue_polls(lo, t);
-      const uint32_t dirty = consume_polls(lo, t);
-      if (dirty) {
-        idle = 0;
-        settle(dirty, lo, t);
-      } else {
-        ++idle;
-        __builtin_amdgcn_s_sleep(4);
-      }
+  uint64_t tm_stage = 0, tm_pace = 0, tm_settle = 0, tm_freeze = 0, tm_all = 0;  // diagnostics
+  const uint64_t tm_begin = __builtin_amdgcn_s_memrealtime();
+  for (int t = 0; t < nr && !fail; ++t) {
+    lds_st(&S.tcomp, t);
+    uint64_t tm0 = __builtin_amdgcn_s_memrealtime();
+    if (!wait_staged(t + 2 < nr ? t + 2 : nr)) {
+      fail = true;
+      break;
     }
-  };
-
-  // ---- prologue: row 0 enters ---------------------------------------------
-  Geo g0 = load_geo(0), g1 = load_geo(1), g2 = load_geo(2);
-  Src<VK> s1 = load_src(1);
-  {
-    const Geo gm = load_geo(-1);
-    const Src<VK> s0 = load_src(0);
-    enter_row(0, gm, g0, g1, s0);
-    if (__ballot(live && !s0.prior)) pend_rows |= 1u;
-    mark_wanted(0, g0.code, g0.scode);
-  }
-
-  // Pacing: the neighbours' progress as last read (edge lanes), and whether
-  // a neighbour stopped answering (then it is no longer waited for).
-  const bool has_nb = (lane == 0 && strip > 0) || (lane == 63 && strip + 1 < nstrips);
-  const int32_t* nb_prog = P.progress + (lane == 0 ? strip - 1 : strip + 1);
-  int32_t nb_seen = -1;
-  bool nb_absent = !has_nb;
-
-  for (int64_t t = 0; t < nr; ++t) {
-    // Wait while a neighbour is more than LEAD rows behind (nb_seen was
-    // read at the start of the previous step).
+    lds_sync();
+    uint64_t tm1 = __builtin_amdgcn_s_memrealtime();
+    tm_stage += tm1 - tm0;
+    tm0 = tm1;
+    // Pacing: wait while a neighbour is more than LEAD rows behind.
     if (t > LEAD) {
-      int spins = 0;
-      for (;;) {
-        const bool behind = !nb_absent && (int64_t)nb_seen < t - 1 - LEAD;
-        if (__ballot(behind) == 0) break;
-        ++n_pace;
-        if (behind) {
-          nb_seen = prog_get(nb_prog);
-          if (++spins > LEAD_SPIN) nb_absent = true;
+      for (int it = 0; it < (1 << 24); ++it) {
+        bool behind = false;
+        for (int sd = 0; sd < 2; ++sd) {
+          if (absent[sd]) continue;
+          const int nb = lds_ld(&S.nbp[sd]);
+          if (nb >= t - 1 - LEAD) continue;
+          behind = true;
+          if (nb == nb_last[sd]) {
+            if (++nb_same[sd] > LEAD_SPIN) absent[sd] = true;
+          } else {
+            nb_last[sd] = nb;
+            nb_same[sd] = 0;
+          }
         }
-        if ((int64_t)nb_seen < t - 1 - LEAD) __builtin_amdgcn_s_sleep(1);
+        if (!behind) break;
+        ++n_pace;
+        __builtin_amdgcn_s_sleep(1);
       }
     }
-    // Loads for later steps go out first, ahead of this step's stores, so
-    // that waiting for them never waits for the stores as well.
-    const Geo g3 = load_geo(t + 3);
-    const Src<VK> s2 = load_src(t + 2);
-    const int32_t nb_next = (has_nb && !nb_absent) ? prog_get(nb_prog) : nb_seen;
-    const int64_t lo = t - (WIN - 1) > 0 ? t - (WIN - 1) : 0;
-    // Polls issued in the previous step (their rows are still in LDS); the
-    // next ones go out at once so that they complete during this step.
-    uint32_t dirty = consume_polls(lo, t);
-    issue_polls(lo, t);
+    tm1 = __builtin_amdgcn_s_memrealtime();
+    tm_pace += tm1 - tm0;
+    tm0 = tm1;
+    const int lo = t - WIN + 1 > 0 ? t - WIN + 1 : 0;
+    if (t == 0 && __ballot(!(S.st[slot(0)][li] & S_DONE))) pend_rows |= 1u << slot(0);
     if (t + 1 < nr) {
-      // Row t + 1 enters; its slot's old row left the window two steps ago.
-      const int sn = (int)((t + 1) & (RING - 1));
-      want &= ~(1u << sn);
+      const int sn = slot(t + 1);
       pend_rows &= ~(1u << sn);
-      lds_sync();
-      enter_row(t + 1, g0, g1, g2, s1);
-      if (__ballot(live && !s1.prior)) pend_rows |= 1u << sn;
-      mark_wanted(t + 1, g1.code, g1.scode);
+      if (__ballot(!(S.st[sn][li] & S_DONE))) pend_rows |= 1u << sn;
     }
-    dirty |= 1u << (t & (RING - 1));
+    const uint32_t dirty = ((t % ARRIVE_EVERY) == 0 ? take_arrivals(lo, t) : 0u) | (1u << slot(t));
     settle(dirty, lo, t);
-    if (t - (WIN - 1) >= 0) {
-      const int64_t f = t - (WIN - 1);
-      if ((pend_rows >> (f & (RING - 1))) & 1u) {
-        // Finish the polls in flight first: they are consumed here.
-        dirty = consume_polls(lo, t);
-        if (dirty) settle(dirty, lo, t);
-        wait_edges(f, lo, t);
-        issue_polls(lo, t);
+    tm1 = __builtin_amdgcn_s_memrealtime();
+    tm_settle += tm1 - tm0;
+    tm0 = tm1;
+    if (t - WIN + 1 >= 0) {
+      const int f = t - WIN + 1;
+      if ((pend_rows >> slot(f)) & 1u) {
+        // Deliveries not yet taken may finish this row's cells.
+        const uint32_t d2 = take_arrivals(lo, t);
+        if (d2) settle(d2, lo, t);
+        if ((pend_rows >> slot(f)) & 1u) wait_edges(f, lo, t);
       }
       lds_sync();
       freeze(f);
     }
-    if (lane == 0) prog_put(P.progress + strip, (int32_t)t);
-    nb_seen = nb_next;
-    g0 = g1;
-    g1 = g2;
-    g2 = g3;
-    s1 = s2;
+    if (lane == 0) prog_put(P.progress + strip, t);
+    tm1 = __builtin_amdgcn_s_memrealtime();
+    tm_freeze += tm1 - tm0;
   }
+  tm_all = __builtin_amdgcn_s_memrealtime() - tm_begin;
 
-  // ---- drain: bounded wait for the last edge records ----------------------
-  {
-    const int64_t t = nr - 1;
-    const int64_t lo = t - (WIN - 2) > 0 ? t - (WIN - 2) : 0;
-    uint32_t dirty = consume_polls(lo, t);
-    if (dirty) settle(dirty, lo, t);
-    int idle = 0;
-    for (int it = 0; it < 4096 && idle < 64; ++it) {
-      const uint32_t pr = (uint32_t)__builtin_amdgcn_readfirstlane((int)pend_rows);
-      const uint32_t wa = (uint32_t)__builtin_amdgcn_readlane((int)want, 0) |
-                          (uint32_t)__builtin_amdgcn_readlane((int)want, 63);
-      if (pr == 0 || wa == 0) break;
-      issue_polls(lo, t);
-      dirty = consume_polls(lo, t);
-      if (dirty) {
-        idle = 0;
-        settle(dirty, lo, t);
-      } else {
-        ++idle;
-        __builtin_amdgcn_s_sleep(8);
-      }
+  // Drain: the last rows wait (bounded) for their side cells, then leave.
+  if (!fail) {
+    const int t = nr - 1;
+    const int lo = t - WIN + 2 > 0 ? t - WIN + 2 : 0;
+    const uint32_t d2 = take_arrivals(lo, t);
+    if (d2) settle(d2, lo, t);
+    for (int f = lo; f <= t; ++f) {
+      if ((pend_rows >> slot(f)) & 1u) wait_edges(f, lo, t);
     }
     lds_sync();
-    for (int64_t f = lo; f <= t; ++f) freeze(f);
+    for (int f = lo; f <= t; ++f) freeze(f);
   }
-
-  if (lane == 0) prog_put(P.progress + strip, (int32_t)nr + LEAD + 1);
-  if (first && P.status) {
-    if (bad) atomicCAS(P.status, 0, FR_ERR_BADCODE);
-    if (nonfinite) atomicCAS(P.status, 0, FR_ERR_NONFINITE);
-  }
+  if (lane == 0) prog_put(P.progress + strip, nr + WIN + LEAD + 2);
+  lds_sync();
+  if (lane == 0) lds_st(&S.done, 1);
+  if (fail && lane == 0 && P.status) atomicCAS(P.status, 0, FR_ERR_HIP);
   uint32_t tot = nfin;
   for (int off = 32; off > 0; off >>= 1) tot += (uint32_t)__shfl_xor((int)tot, off, 64);
   if (lane == 0 && tot) atomicAdd(P.ctr, tot);
@@ -891,6 +1027,13 @@ __global__ __launch_bounds__(64) void k_ws_pass(WsParams P, int dir, int first) 
     atomicAdd(P.ctr + 3, n_wait);
     atomicAdd(P.ctr + 4, n_pace);
     atomicAdd(P.ctr + 5, n_resolve);
+    // Time in 100 MHz ticks, summed over strips.
+    unsigned long long* tm = reinterpret_cast<unsigned long long*>(P.ctr + 8);
+    atomicAdd(tm + 0, (unsigned long long)tm_stage);
+    atomicAdd(tm + 1, (unsigned long long)tm_pace);
+    atomicAdd(tm + 2, (unsigned long long)tm_settle);
+    atomicAdd(tm + 3, (unsigned long long)tm_freeze);
+    atomicAdd(tm + 4, (unsigned long long)tm_all);
   }
 }
 
@@ -928,7 +1071,7 @@ __global__ __launch_bounds__(256) void k_fill_u64(uint64_t* p, int64_t n, uint64
 template <int RK, int DK, int VK, bool CNT>
 hipError_t pass_t(const WsParams& P, int dir, int first, hipStream_t s) {
   const unsigned strips = (unsigned)((P.ncols + WS_OWN - 1) / WS_OWN);
-  hipLaunchKernelGGL((k_ws_pass<RK, DK, VK, CNT>), dim3(strips), dim3(64), 0, s, P, dir, first);
+  hipLaunchKernelGGL((k_ws_pass<RK, DK, VK, CNT>), dim3(strips), dim3(128), 0, s, P, dir, first);
   return hipGetLastError();
 }
 
