@@ -78,6 +78,10 @@ extern "C" {
 #define FR_FN_ACCUMULATE 1
 #define FR_FN_ADJOINT 2
 
+/* Tile orders of fr_batch_plan.order. */
+#define FR_ORDER_GIVEN 0
+#define FR_ORDER_ROWS_DESC 1
+
 /* Status codes. */
 #define FR_OK 0
 #define FR_ERR_ARG -1        /* null pointer, negative size, bad flag        */
@@ -113,7 +117,10 @@ int fr_receivers(const float* z, int64_t nrows, int64_t ncols, int rule, uint8_t
  * fr_accumulate -- global flow routing (Section 2.1 high-to-low algorithm,
  * Section 2.2 linear system, Appendix A for FR_MFD): solves
  * (I - W^T) q = r for q.  The result equals the high-to-low push; the GPU
- * reaches it without sorting, by counting unfinished upstream neighbours.
+ * reaches it without sorting: a cell is computed once all cells that give
+ * it water are final, visiting rows in flow order (row sweeps with an exit
+ * forest for D8/D4, wavefront sweeps for MFD, a peeling engine as the last
+ * resort).
  *
  *   z         device float32 elevations; required for FR_MFD (fractions are
  *             recomputed from it), ignored (may be NULL) for FR_D8/FR_D4.
@@ -179,10 +186,88 @@ size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dt
  * for the phases of the most recent timed call and returns how many it
  * filled; the call is complete when it returns, so reading is synchronous.
  * Phases: "receivers"; "d8_up", "d8_forest", "d8_down", "mass" (row-sweep
- * single-receiver path); "engine" (peeling engine).  Not thread-safe.
+ * single-receiver path); "sweep" (wavefront sweep passes); "engine"
+ * (peeling engine); "batch" (fr_accumulate_batched).  Not thread-safe.
  */
 int fr_timing_enable(int on);
 int fr_timing_last(const char** names, float* ms, int max);
+
+/*
+ * Batched routing: many independent DEM tiles of uneven size routed by one
+ * persistent kernel launch (receivers and accumulation, as fr_receivers +
+ * fr_accumulate per tile), without any host synchronisation, so that the
+ * call can be captured in a HIP graph.
+ *
+ * fr_tile describes one tile; all pointers are device pointers:
+ *   z          float32[nrows*ncols] elevations (required).
+ *   rain       float32[nrows*ncols] rain, or NULL for unit rain.
+ *   q_out      float32[nrows*ncols] water (compensated float-float sums), or
+ *              NULL; required for FR_MFD.
+ *   counts_out uint64[nrows*ncols] drainage counts, or NULL; FR_D8/FR_D4
+ *              only.  A D8/D4 tile gives exactly one of q_out and
+ *              counts_out.
+ *   code_out   uint8[nrows*ncols] receivers as fr_receivers writes them, or
+ *              NULL (they are then kept in the workspace).
+ *   nrows, ncols  tile shape, >= 1 each, at most 2^31 - 1 cells.
+ *   rule       FR_D8, FR_D4 or FR_MFD (slope exponent 1.1).
+ */
+typedef struct fr_tile {
+  const float* z;
+  const float* rain;
+  float* q_out;
+  uint64_t* counts_out;
+  uint8_t* code_out;
+  int64_t nrows;
+  int64_t ncols;
+  int32_t rule;
+  int32_t reserved;
+} fr_tile;
+
+/*
+ * fr_batch_plan -- schedule of a batch: `workers` persistent workgroups
+ * (0: two per compute unit; at least ceil(ncols / 48) of the widest tile,
+ * whose column strips must all run at once -- a tile that needs more is
+ * reported as FR_ERR_ARG in dev_status) and the tile `order`
+ * (FR_ORDER_GIVEN, or FR_ORDER_ROWS_DESC: tiles with more rows first).
+ * fr_batch_autotune picks one by timing candidates.
+ */
+typedef struct fr_batch_plan {
+  int32_t workers;
+  int32_t order;
+} fr_batch_plan;
+
+/*
+ * fr_batched_workspace_bytes -- workspace for a batch; tiles_host is a host
+ * copy of the tile array (only shapes, rules and which outputs are NULL are
+ * read).  Returns 0 for an invalid tile.
+ */
+size_t fr_batched_workspace_bytes(const fr_tile* tiles_host, int32_t ntiles);
+
+/*
+ * fr_accumulate_batched -- routes ntiles tiles.
+ *   tiles_dev  device copy of the fr_tile array (read by the kernels).
+ *   ntiles     >= 0.
+ *   plan       schedule, or NULL for the default.
+ *   dev_status optional device int32: FR_ERR_NONFINITE, FR_ERR_BADCODE,
+ *              FR_ERR_NOTDAG as for fr_accumulate (first error of any tile).
+ *   ws, ws_bytes workspace of at least fr_batched_workspace_bytes(); the
+ *              caller passes the value it computed on the host copy.
+ *   stream     HIP stream.
+ * Enqueues three kernels (set-up, workspace fill, the persistent router) and
+ * returns without synchronising.  Tile shapes are read on the device; the
+ * caller guarantees that they match the ones ws_bytes was computed for.
+ */
+int fr_accumulate_batched(const fr_tile* tiles_dev, int32_t ntiles, const fr_batch_plan* plan,
+                          int32_t* dev_status, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * fr_batch_autotune -- times fr_accumulate_batched on this batch for a few
+ * candidate plans (worker counts and tile orders; `reps` timed runs each
+ * after one warm-up) and writes the fastest to *plan_out.  Synchronises the
+ * stream.  Outputs of the tiles are overwritten.
+ */
+int fr_batch_autotune(const fr_tile* tiles_dev, int32_t ntiles, int32_t* dev_status, void* ws,
+                      size_t ws_bytes, int reps, fr_batch_plan* plan_out, hipStream_t stream);
 
 /* fr_status_string -- static text for a status code. */
 const char* fr_status_string(int code);

@@ -32,7 +32,21 @@ ERR_NONFINITE, ERR_NOTDAG, ERR_BADCODE, ERR_TOOLARGE = -5, -6, -7, -8
 
 RULES = {"d8": D8, "mfd": MFD, "d4": D4}
 EXPORTS = ["fr_receivers", "fr_accumulate", "fr_accumulate_adjoint", "fr_workspace_bytes",
-           "fr_status_string", "fr_version", "fr_timing_enable", "fr_timing_last"]
+           "fr_status_string", "fr_version", "fr_timing_enable", "fr_timing_last",
+           "fr_batched_workspace_bytes", "fr_accumulate_batched", "fr_batch_autotune"]
+ORDER_GIVEN, ORDER_ROWS_DESC = 0, 1
+
+
+class Tile(ctypes.Structure):
+    """``fr_tile`` of the C ABI (device pointers, shape, rule)."""
+    _fields_ = [("z", ctypes.c_void_p), ("rain", ctypes.c_void_p), ("q_out", ctypes.c_void_p),
+                ("counts_out", ctypes.c_void_p), ("code_out", ctypes.c_void_p), ("nrows", ctypes.c_int64),
+                ("ncols", ctypes.c_int64), ("rule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class BatchPlan(ctypes.Structure):
+    """``fr_batch_plan`` of the C ABI."""
+    _fields_ = [("workers", ctypes.c_int32), ("order", ctypes.c_int32)]
 
 
 class FlowRouteError(RuntimeError):
@@ -70,6 +84,13 @@ def load_library() -> ctypes.CDLL:
     lib.fr_timing_enable.restype = ci
     lib.fr_timing_last.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_float), ci]
     lib.fr_timing_last.restype = ci
+    i32 = ctypes.c_int32
+    lib.fr_batched_workspace_bytes.argtypes = [vp, i32]
+    lib.fr_batched_workspace_bytes.restype = sz
+    lib.fr_accumulate_batched.argtypes = [vp, i32, vp, vp, vp, sz, vp]
+    lib.fr_accumulate_batched.restype = ci
+    lib.fr_batch_autotune.argtypes = [vp, i32, vp, vp, sz, ci, vp, vp]
+    lib.fr_batch_autotune.restype = ci
     _lib = lib
     return lib
 
@@ -265,3 +286,69 @@ class FlowAccumulate(torch.autograd.Function):
         zz = z if _rule(ctx.rule) == MFD else None
         rbar = adjoint(code, gq.contiguous(), zz, ctx.rule, ctx.p)
         return rbar, None, None, None
+
+
+class Batch:
+    """A batch of independent tiles routed by one persistent launch
+    (``fr_accumulate_batched``).  Each tile is given as its elevation tensor,
+    rule, optional float32 rain, and the outputs to fill: ``q`` (float32 water,
+    required for MFD) or ``counts`` (uint64 drainage counts, D8/D4).  The batch
+    keeps the device copy of the tile table and the workspace, so it can be
+    routed repeatedly (and captured in a HIP graph)."""
+
+    def __init__(self, tiles, device=None):
+        self.tiles = []
+        arr = (Tile * max(len(tiles), 1))()
+        for i, t in enumerate(tiles):
+            z = t["z"]
+            _check_grid(z, torch.float32, "z")
+            rule = _rule(t.get("rule", "d8"))
+            rain, q, cnt, code = t.get("rain"), t.get("q"), t.get("counts"), t.get("code")
+            for name, x, dt in [("rain", rain, torch.float32), ("q", q, torch.float32), ("counts", cnt, torch.int64),
+                                ("code", code, torch.uint8)]:
+                if x is not None:
+                    _check_grid(x, dt if name != "counts" else x.dtype, name)
+                    if x.shape != z.shape:
+                        raise ValueError(f"{name} shape differs from z")
+                    if name == "counts" and x.dtype not in (torch.int64, torch.uint64):
+                        raise TypeError("counts must be 64-bit integers")
+            arr[i] = Tile(z.data_ptr(), rain.data_ptr() if rain is not None else None,
+                          q.data_ptr() if q is not None else None, cnt.data_ptr() if cnt is not None else None,
+                          code.data_ptr() if code is not None else None, z.shape[0], z.shape[1], rule, 0)
+            self.tiles.append(t)
+        self.n = len(tiles)
+        self.device = device if device is not None else (tiles[0]["z"].device if tiles else torch.device("cuda"))
+        lib = load_library()
+        self.ws_bytes = int(lib.fr_batched_workspace_bytes(ctypes.addressof(arr), self.n))
+        if self.n and self.ws_bytes == 0:
+            raise FlowRouteError(ERR_ARG, "fr_batched_workspace_bytes")
+        raw = bytes(memoryview(arr).cast("B"))[: ctypes.sizeof(Tile) * self.n]
+        self.table = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device) if self.n else None
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=self.device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.plan = None
+
+    def run(self, check: bool = True, plan=None):
+        """Enqueue the routing of every tile on the current stream."""
+        if check:
+            self.status.zero_()
+        p = plan if plan is not None else self.plan
+        rc = load_library().fr_accumulate_batched(
+            _ptr(self.table), self.n, ctypes.byref(p) if p is not None else None, _ptr(self.status),
+            _ptr(self.ws), self.ws_bytes, _stream(self.device))
+        if rc != OK:
+            raise FlowRouteError(rc, "fr_accumulate_batched")
+        if check:
+            _raise_status(self.status, "fr_accumulate_batched")
+
+    def autotune(self, reps: int = 2) -> BatchPlan:
+        """Pick the fastest schedule among the library's candidates."""
+        plan = BatchPlan()
+        self.status.zero_()
+        rc = load_library().fr_batch_autotune(_ptr(self.table), self.n, _ptr(self.status), _ptr(self.ws),
+                                              self.ws_bytes, reps, ctypes.byref(plan), _stream(self.device))
+        if rc != OK:
+            raise FlowRouteError(rc, "fr_batch_autotune")
+        _raise_status(self.status, "fr_batch_autotune")
+        self.plan = plan
+        return plan

@@ -627,4 +627,74 @@ int fr_accumulate_adjoint(const float* z, const uint8_t* code, int64_t nrows, in
   return run_engine(cfg, P, base, L, dev_status, stream);
 }
 
+size_t fr_batched_workspace_bytes(const fr_tile* tiles_host, int32_t ntiles) {
+  if (ntiles < 0 || (ntiles > 0 && !tiles_host)) return 0;
+  size_t off = batch_head_bytes(ntiles);
+  for (int32_t i = 0; i < ntiles; ++i) {
+    const fr_tile& t = tiles_host[i];
+    if (t.nrows < 1 || t.ncols < 1 || !valid_rule(t.rule)) return 0;
+    if (t.ncols > kMaxCells / t.nrows) return 0;
+    if (t.rule == FR_MFD && !t.q_out) return 0;
+    if (t.rule != FR_MFD && (t.q_out != nullptr) == (t.counts_out != nullptr)) return 0;
+    const BatchTileLayout L =
+        batch_tile_layout(t.nrows, t.ncols, t.code_out == nullptr, batch_tile_ff(t.rule, t.q_out != nullptr));
+    off += L.total;
+  }
+  return off + kAlign;
+}
+
+int fr_accumulate_batched(const fr_tile* tiles_dev, int32_t ntiles, const fr_batch_plan* plan,
+                          int32_t* dev_status, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (ntiles < 0) return FR_ERR_ARG;
+  timing_reset();
+  if (ntiles == 0) return FR_OK;
+  if (!tiles_dev) return FR_ERR_ARG;
+  if (plan && (plan->workers < 0 || (plan->order != FR_ORDER_GIVEN && plan->order != FR_ORDER_ROWS_DESC)))
+    return FR_ERR_ARG;
+  if (!ws || ws_bytes < batch_head_bytes(ntiles) + kAlign) return FR_ERR_WORKSPACE;
+  char* base = aligned_base(ws);
+  const size_t avail = ws_bytes - (size_t)(base - static_cast<char*>(ws));
+  const int workers = (plan && plan->workers > 0) ? plan->workers : 2 * cu_count();
+  const int order = plan ? plan->order : FR_ORDER_ROWS_DESC;
+  const int ph = phase_begin("batch", stream);
+  const hipError_t e = launch_batch(tiles_dev, ntiles, order, workers, dev_status, base, avail, stream);
+  phase_end(ph, stream);
+  return e == hipSuccess ? FR_OK : FR_ERR_HIP;
+}
+
+int fr_batch_autotune(const fr_tile* tiles_dev, int32_t ntiles, int32_t* dev_status, void* ws, size_t ws_bytes,
+                      int reps, fr_batch_plan* plan_out, hipStream_t stream) {
+  if (!plan_out || reps < 1) return FR_ERR_ARG;
+  const int cu = cu_count();
+  const fr_batch_plan cand[] = {{2 * cu, FR_ORDER_ROWS_DESC}, {2 * cu, FR_ORDER_GIVEN}, {cu, FR_ORDER_ROWS_DESC},
+                                {cu, FR_ORDER_GIVEN}};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return FR_ERR_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) return FR_ERR_HIP;
+  float best = -1.0f;
+  int rc = FR_OK;
+  for (const fr_batch_plan& p : cand) {
+    rc = fr_accumulate_batched(tiles_dev, ntiles, &p, dev_status, ws, ws_bytes, stream);
+    if (rc != FR_OK) break;
+    if (hipEventRecord(e0, stream) != hipSuccess) { rc = FR_ERR_HIP; break; }
+    for (int r = 0; r < reps && rc == FR_OK; ++r)
+      rc = fr_accumulate_batched(tiles_dev, ntiles, &p, dev_status, ws, ws_bytes, stream);
+    if (rc != FR_OK) break;
+    if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      rc = FR_ERR_HIP;
+      break;
+    }
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = FR_ERR_HIP; break; }
+    if (verbose()) fprintf(stderr, "flowroute: batch plan workers %d order %d: %.3f ms\n", p.workers, p.order, ms / reps);
+    if (best < 0.0f || ms < best) {
+      best = ms;
+      *plan_out = p;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
 }  // extern "C"

@@ -111,9 +111,96 @@ struct EngineConfig {
   bool counts;
 };
 
-// Windowed wavefront sweep (fr_wsweep.hip): one wavefront per 64-column
-// strip, rows visited in passes of alternating direction.
-constexpr int WS_EW = 4;  // 64-bit words per edge record
+// Receiver code of a cell at elevation zi whose neighbours (row-major window
+// order) are at zk[8], +inf off the grid: D8/D4 -- the strictly lower
+// neighbour with the steepest float32 slope fl(fl(zi - zk) * c_k), ties to
+// the lowest k, or SINK; MFD -- the mask of strictly lower neighbours.
+template <int RULE>
+__device__ __forceinline__ uint8_t route_code(float zi, const float zk[8]) {
+  if (RULE == FR_MFD) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m |= (zk[k] < zi) ? (1u << k) : 0u;
+    return (uint8_t)m;
+  }
+  int best = -1;
+  float bs = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (RULE == FR_D4 && nb_diag(k)) continue;
+    if (!(zk[k] < zi)) continue;
+    const float drop = zi - zk[k];
+    const float sl = nb_diag(k) ? drop * 0x1.6a09e6p-1f : drop;
+    if (best < 0 || sl > bs) {
+      best = k;
+      bs = sl;
+    }
+  }
+  return best < 0 ? SINK : (uint8_t)best;
+}
+
+// Windowed wavefront sweep (fr_wsweep.hip): one wavefront per strip of
+// WS_OWN owned columns (64 computed), rows visited in passes of alternating
+// direction.
+constexpr int WS_EW = 4;      // 64-bit words per edge record
+constexpr int WS_GHOST = 8;   // columns recomputed on each side of a strip
+constexpr int WS_OWN = 64 - 2 * WS_GHOST;
+constexpr int BATCH_MAXPASS = 32;
+constexpr int BATCH_CTR_WORDS = 64;  // per tile: [pass] finished, then the words below
+constexpr int BCTR_BAR = 32, BCTR_UP = 33, BCTR_DN = 34;
+
+inline __host__ __device__ size_t ws_align(size_t x) { return (x + 255) / 256 * 256; }
+inline __host__ __device__ int64_t ws_strip_count(int64_t ncols) { return (ncols + WS_OWN - 1) / WS_OWN; }
+
+// Workspace of one tile of a batch (offsets within the tile's block).
+struct BatchTileLayout {
+  size_t code, vlo, edge, progress, ctr, total;
+};
+inline __host__ __device__ BatchTileLayout batch_tile_layout(int64_t nrows, int64_t ncols, bool own_codes,
+                                                             bool ff) {
+  BatchTileLayout L{};
+  const size_t n = (size_t)(nrows * ncols);
+  const size_t strips = (size_t)ws_strip_count(ncols);
+  size_t o = 0;
+  L.code = o; if (own_codes) o += ws_align(n);
+  L.vlo = o; if (ff) o += ws_align(n * 4);
+  L.edge = o; o += ws_align(strips * (size_t)nrows * 2 * WS_EW * 8);
+  L.progress = o; o += ws_align(strips * BATCH_MAXPASS * 4);
+  L.ctr = o; o += ws_align(BATCH_CTR_WORDS * 4);
+  L.total = o;
+  return L;
+}
+
+// Per-tile record the set-up kernel writes into the batch workspace.
+struct BatchTileInfo {
+  const float* z;
+  const float* rain;
+  float* q;
+  uint64_t* cnt;
+  uint8_t* code;
+  float* vlo;
+  uint64_t* edge;
+  int32_t* progress;
+  uint32_t* ctr;
+  int64_t nrows, ncols;
+  int64_t strip_base;  // first work item of the tile in schedule order
+  int32_t nstrips, rule;
+};
+
+struct BatchHeader {
+  unsigned long long ticket;  // next work item
+  int64_t total_items;
+  int64_t ws_needed;
+  int32_t ntiles, order;
+};
+
+// Batch workspace: header, tile records, schedule (tile index by position),
+// first work item by position (ntiles + 1 entries), then the tile blocks.
+inline __host__ __device__ size_t batch_head_bytes(int64_t ntiles) {
+  return ws_align(sizeof(BatchHeader)) + ws_align((size_t)ntiles * sizeof(BatchTileInfo)) +
+         ws_align((size_t)ntiles * 4) + ws_align((size_t)(ntiles + 1) * 8);
+}
+inline __host__ __device__ bool batch_tile_ff(int rule, bool has_q) { return rule == FR_MFD || has_q; }
 
 struct WsParams {
   int64_t nrows, ncols;
@@ -134,6 +221,8 @@ struct WsParams {
 };
 
 size_t ws_edge_words(int64_t nrows, int64_t ncols);
+hipError_t launch_batch(const void* tiles_dev, int32_t ntiles, int order, int workers, int32_t* status,
+                        char* ws, size_t ws_bytes, hipStream_t s);
 int64_t ws_strips(int64_t ncols);
 hipError_t launch_ws_progress_reset(const WsParams& P, hipStream_t s);
 hipError_t launch_ws_setup(const EngineConfig& cfg, const WsParams& P, hipStream_t s);

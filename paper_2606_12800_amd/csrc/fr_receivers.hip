@@ -18,9 +18,6 @@ constexpr int RCV_THREADS = 256;
 constexpr int RCV_COLS = RCV_THREADS * 4;  // columns per workgroup
 constexpr int RCV_RPB = 32;                // rows per workgroup
 
-// float32 nearest to 1/sqrt(2) (0x3F3504F3).
-__device__ constexpr float kInvSqrt2 = 0x1.6a09e6p-1f;
-
 struct Row6 {
   float v[6];  // columns c0-1 .. c0+4
 };
@@ -69,31 +66,11 @@ __device__ __forceinline__ Row6 assemble(const RawRow& x, int lane) {
 // Code of the cell at column offset j (1..4) of the middle row.
 template <int RULE>
 __device__ __forceinline__ uint8_t cell_code(const Row6& up, const Row6& mid, const Row6& dn, int j) {
-  const float zi = mid.v[j];
   // Neighbour elevations in row-major window order; "up" is the previous row
   // in memory (row - 1).
   const float zk[8] = {up.v[j - 1], up.v[j], up.v[j + 1], mid.v[j - 1],
                        mid.v[j + 1], dn.v[j - 1], dn.v[j], dn.v[j + 1]};
-  if (RULE == FR_MFD) {
-    uint32_t m = 0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) m |= (zk[k] < zi) ? (1u << k) : 0u;
-    return (uint8_t)m;
-  }
-  int best = -1;
-  float bs = 0.0f;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    if (RULE == FR_D4 && nb_diag(k)) continue;
-    if (!(zk[k] < zi)) continue;
-    const float drop = zi - zk[k];
-    const float s = nb_diag(k) ? drop * kInvSqrt2 : drop;
-    if (best < 0 || s > bs) {
-      best = k;
-      bs = s;
-    }
-  }
-  return best < 0 ? SINK : (uint8_t)best;
+  return route_code<RULE>(mid.v[j], zk);
 }
 
 template <int RULE, bool VEC>

@@ -47,8 +47,7 @@ constexpr int LW = 66;         // LDS row: side cell, 64 lanes, side cell
 // boundary then reaches the other strip's owned columns only after passing
 // 2 * GHOST columns, which along lateral flow takes as many rows: the
 // exchange has that many rows of slack.
-constexpr int GHOST = 8;
-constexpr int WS_OWN = 64 - 2 * GHOST;
+constexpr int GHOST = WS_GHOST;
 // Lanes whose cells the neighbours read as their side cells.
 constexpr int REC_LANE_L = 2 * GHOST;    // read by the left neighbour's lane 63
 constexpr int REC_LANE_R = WS_OWN - 1;   // read by the right neighbour's lane 0
@@ -248,8 +247,11 @@ __device__ __forceinline__ void lds_st(int* p, int v) { *(volatile int*)p = v; }
 // results, MFD fractions -- polls the neighbours' edge records and progress,
 // and delivers them into LDS.  Wavefront 0 (compute) only reads and writes
 // LDS and stores results, so it never waits for global memory.
+// One pass over one strip by a workgroup of two wavefronts (see above);
+// returns when both have finished.
 template <int RK, int DK, int VK, bool CNT>
-__global__ __launch_bounds__(128) void k_ws_pass(WsParams P, int dir, int first) {
+__device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int64_t strip, const int dir,
+                         const int first) {
   using V = typename ValOf<VK>::T;
   using F = typename FracOf<RK, VK>::T;
   constexpr int R = Dims<RK, VK>::RING;
@@ -257,12 +259,10 @@ __global__ __launch_bounds__(128) void k_ws_pass(WsParams P, int dir, int first)
   constexpr int BATCH = Dims<RK, VK>::BATCH;
   constexpr int EWN = rec_words<RK, DK, VK, CNT>();
   constexpr uint32_t NOC = RK == RK_SINGLE ? (uint32_t)SINK : 0u;
-  __shared__ WsShared<RK, VK, CNT> S;
 
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int li = lane + 1;
-  const int64_t strip = blockIdx.x;
   const int nr = (int)P.nrows;
   const int64_t nc = P.ncols;
   const int64_t nstrips = (nc + WS_OWN - 1) / WS_OWN;
@@ -643,9 +643,7 @@ __global__ __launch_bounds__(128) void k_ws_pass(WsParams P, int dir, int first)
       if (__ballot(bad) && lane == 0) atomicCAS(P.status, 0, FR_ERR_BADCODE);
       if (__ballot(nonfinite) && lane == 0) atomicCAS(P.status, 0, FR_ERR_NONFINITE);
     }
-    return;
-  }
-
+  } else {
   // ======================== compute wavefront ============================
   const int my_side = lane == REC_LANE_L ? 0 : 1;
   const bool has_record = live && ((lane == REC_LANE_L && strip > 0) || (lane == REC_LANE_R && strip + 1 < nstrips));
@@ -1035,6 +1033,14 @@ __global__ __launch_bounds__(128) void k_ws_pass(WsParams P, int dir, int first)
     atomicAdd(tm + 3, (unsigned long long)tm_freeze);
     atomicAdd(tm + 4, (unsigned long long)tm_all);
   }
+  }
+  __syncthreads();
+}
+
+template <int RK, int DK, int VK, bool CNT>
+__global__ __launch_bounds__(128) void k_ws_pass(WsParams P, int dir, int first) {
+  __shared__ WsShared<RK, VK, CNT> S;
+  ws_strip<RK, DK, VK, CNT>(S, P, (int64_t)blockIdx.x, dir, first);
 }
 
 // Samples rows for the prevailing vertical flow direction: ctr[1] counts
@@ -1066,6 +1072,310 @@ __global__ __launch_bounds__(256) void k_ws_probe(WsParams P, int nsample) {
 __global__ __launch_bounds__(256) void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Batched routing: one persistent launch for many tiles.  Work items are the
+// tiles' strips in schedule order; a workgroup takes the next item from a
+// ticket counter.  For its strip it computes the receivers of its owned
+// columns, meets the tile's other strips at a barrier (items of a tile are
+// consecutive tickets and a tile has far fewer strips than there are
+// workgroups, so every strip of a tile is running before any waits long),
+// then runs wavefront-sweep passes, with a barrier after each, until the
+// tile is complete.
+
+// Bounded barrier of the strips of one tile: release this workgroup's
+// global writes, count in, wait for `target` arrivals, acquire.
+__device__ bool tile_barrier(uint32_t* bar, uint32_t target) {
+  __threadfence();
+  __syncthreads();
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    ok = 0;
+    atomicAdd(bar, 1u);
+    for (int it = 0; it < (1 << 22); ++it) {
+      if (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) {
+        ok = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(8);
+    }
+  }
+  __syncthreads();
+  __threadfence();
+  return ok != 0;
+}
+
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
+  return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Receivers of the strip's owned columns, every row; the two wavefronts
+// take half of the rows each.  Adds the receivers in the row above / below
+// to *up / *dn (prevailing flow direction of the tile).
+template <int RULE>
+__device__ void batch_receivers(const BatchTileInfo& T, int64_t strip, uint32_t* up, uint32_t* dn,
+                                int32_t* status) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t nr = T.nrows, nc = T.ncols;
+  const int64_t c = strip * WS_OWN - WS_GHOST + lane;
+  const bool live = c >= 0 && c < nc;
+  const bool owned = live && lane >= WS_GHOST && lane < WS_GHOST + WS_OWN;
+  const bool sideL = lane == 0 && c - 1 >= 0 && c - 1 < nc;
+  const bool sideR = lane == 63 && c + 1 >= 0 && c + 1 < nc;
+  const int64_t cs = lane == 0 ? c - 1 : c + 1;
+  const int64_t r0 = wave == 0 ? 0 : nr / 2, r1 = wave == 0 ? nr / 2 : nr;
+  struct Z {
+    float own, side;
+  };
+  auto ld = [&](int64_t r) -> Z {
+    Z v{INFINITY, INFINITY};
+    if (r < 0 || r >= nr) return v;
+    if (live) v.own = T.z[r * nc + c];
+    if (sideL || sideR) v.side = T.z[r * nc + cs];
+    return v;
+  };
+  uint32_t nu = 0, nd = 0;
+  bool nonfinite = false;
+  // Rows r-1 .. r+4 in W; the next four rows are loaded one iteration early.
+  Z W[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) W[j] = ld(r0 - 1 + j);
+  for (int64_t r = r0; r < r1; r += 4) {
+    Z N[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) N[j] = ld(r + 5 + j);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const Z& u = W[j];
+      const Z& m = W[j + 1];
+      const Z& d = W[j + 2];
+      float zk[8];
+      zk[0] = from_left(u.own);
+      zk[1] = u.own;
+      zk[2] = from_right(u.own);
+      zk[3] = from_left(m.own);
+      zk[4] = from_right(m.own);
+      zk[5] = from_left(d.own);
+      zk[6] = d.own;
+      zk[7] = from_right(d.own);
+      if (lane == 0) {
+        zk[0] = sideL ? u.side : INFINITY;
+        zk[3] = sideL ? m.side : INFINITY;
+        zk[5] = sideL ? d.side : INFINITY;
+      }
+      if (lane == 63) {
+        zk[2] = sideR ? u.side : INFINITY;
+        zk[4] = sideR ? m.side : INFINITY;
+        zk[7] = sideR ? d.side : INFINITY;
+      }
+      const uint8_t code = route_code<RULE>(m.own, zk);
+      if (owned && r + j < r1 && !isfinite(m.own)) nonfinite = true;
+      if (owned && r + j < r1) {
+        T.code[(r + j) * nc + c] = code;
+        if (RULE == FR_MFD) {
+          nu += (uint32_t)__popc(code & 0x07u);
+          nd += (uint32_t)__popc(code & 0xE0u);
+        } else {
+          nu += code <= 2u ? 1u : 0u;
+          nd += (code >= 5u && code <= 7u) ? 1u : 0u;
+        }
+      }
+    }
+    W[0] = W[4];
+    W[1] = W[5];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) W[2 + j] = N[j];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    nu += (uint32_t)__shfl_xor((int)nu, off, 64);
+    nd += (uint32_t)__shfl_xor((int)nd, off, 64);
+  }
+  if (lane == 0) {
+    if (nu) atomicAdd(up, nu);
+    if (nd) atomicAdd(dn, nd);
+  }
+  if (__ballot(nonfinite) && lane == 0 && status) atomicCAS(status, 0, FR_ERR_NONFINITE);
+}
+
+// Bytes of LDS the persistent kernel reserves: the largest sweep variant.
+constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
+constexpr size_t BATCH_LDS = cmax(sizeof(WsShared<RK_MULTI, VK_FF, false>),
+                                  cmax(sizeof(WsShared<RK_SINGLE, VK_NONE, true>), sizeof(WsShared<RK_SINGLE, VK_FF, false>)));
+
+struct BatchParams {
+  BatchHeader* hdr;
+  const BatchTileInfo* info;
+  const int32_t* sched;
+  const int64_t* base;
+  int32_t* status;
+};
+
+template <int RK, int VK, bool CNT>
+__device__ __forceinline__ void batch_sweep(unsigned char* lds, const WsParams& P, int64_t strip, int dir,
+                                            int first) {
+  ws_strip<RK, DIR_FWD, VK, CNT>(*reinterpret_cast<WsShared<RK, VK, CNT>*>(lds), P, strip, dir, first);
+}
+
+__global__ __launch_bounds__(128) void k_batch(BatchParams B) {
+  __shared__ __align__(16) unsigned char lds[BATCH_LDS];
+  __shared__ long long item_sh;
+  const int64_t total = B.hdr->total_items;
+  const int ntiles = B.hdr->ntiles;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = (long long)atomicAdd(&B.hdr->ticket, 1ull);
+    __syncthreads();
+    // Uniform across the workgroup: keep it (and all tile data) in scalars.
+    const uint64_t iu = (uint64_t)item_sh;
+    const int64_t item = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(iu >> 32)) << 32) |
+                                   (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)iu));
+    __syncthreads();
+    if (item >= total) break;
+    // Schedule position k with base[k] <= item < base[k + 1].
+    int lo = 0, hi = ntiles - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (B.base[mid] <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchTileInfo T = B.info[B.sched[lo]];
+    const int64_t strip = item - B.base[lo];
+    const uint32_t ns = (uint32_t)T.nstrips;
+    if (ns > gridDim.x) {
+      // The tile's strips could never all run at once on this many workers.
+      if (threadIdx.x == 0 && B.status && strip == 0) atomicCAS(B.status, 0, FR_ERR_ARG);
+      continue;
+    }
+    if (T.rule == FR_MFD) batch_receivers<FR_MFD>(T, strip, T.ctr + BCTR_UP, T.ctr + BCTR_DN, B.status);
+    else if (T.rule == FR_D4) batch_receivers<FR_D4>(T, strip, T.ctr + BCTR_UP, T.ctr + BCTR_DN, B.status);
+    else batch_receivers<FR_D8>(T, strip, T.ctr + BCTR_UP, T.ctr + BCTR_DN, B.status);
+    if (!tile_barrier(T.ctr + BCTR_BAR, ns)) {
+      if (threadIdx.x == 0 && B.status) atomicCAS(B.status, 0, FR_ERR_HIP);
+      continue;
+    }
+    // Forward inputs are donors: visit first the rows water comes from.
+    int dir = ld_agent(T.ctr + BCTR_UP) >= ld_agent(T.ctr + BCTR_DN) ? -1 : 1;
+    const int64_t ncell = T.nrows * T.ncols;
+    int64_t done = 0;
+    bool complete = false;
+    for (int pass = 0; pass < BATCH_MAXPASS; ++pass) {
+      WsParams P{};
+      P.nrows = T.nrows;
+      P.ncols = T.ncols;
+      P.code = T.code;
+      P.z = T.z;
+      P.p = 1.1;
+      P.src32 = T.rain;
+      P.src64 = nullptr;
+      P.vhi = T.q;
+      P.vlo = T.vlo;
+      P.v64 = nullptr;
+      P.cnt = T.cnt;
+      P.edge = T.edge;
+      P.progress = T.progress + (int64_t)pass * T.nstrips;
+      P.ctr = T.ctr + pass;
+      P.status = B.status;
+      P.debug = 0;
+      const int first = pass == 0 ? 1 : 0;
+      if (T.rule == FR_MFD) batch_sweep<RK_MULTI, VK_FF, false>(lds, P, strip, dir, first);
+      else if (T.q) batch_sweep<RK_SINGLE, VK_FF, false>(lds, P, strip, dir, first);
+      else batch_sweep<RK_SINGLE, VK_NONE, true>(lds, P, strip, dir, first);
+      if (!tile_barrier(T.ctr + BCTR_BAR, (uint32_t)(2 + pass) * ns)) {
+        if (threadIdx.x == 0 && B.status) atomicCAS(B.status, 0, FR_ERR_HIP);
+        break;
+      }
+      const uint32_t fin = ld_agent(T.ctr + pass);
+      done += fin;
+      if (done >= ncell) {
+        complete = true;
+        break;
+      }
+      if (fin == 0) break;
+      dir = -dir;
+    }
+    // A pass that finished nothing, or too many passes: a cycle (or a tile
+    // the sweep cannot finish, reported the same way).
+    if (!complete && threadIdx.x == 0 && B.status && strip == 0) atomicCAS(B.status, 0, FR_ERR_NOTDAG);
+  }
+}
+
+// Set-up (one workgroup): tile records, schedule and work-item bases.
+__global__ __launch_bounds__(1024) void k_batch_setup(const fr_tile* tiles, int32_t ntiles, int order,
+                                                     char* ws, size_t ws_bytes, int32_t* status) {
+  BatchHeader* hdr = reinterpret_cast<BatchHeader*>(ws);
+  char* p = ws + ws_align(sizeof(BatchHeader));
+  BatchTileInfo* info = reinterpret_cast<BatchTileInfo*>(p);
+  p += ws_align((size_t)ntiles * sizeof(BatchTileInfo));
+  int32_t* sched = reinterpret_cast<int32_t*>(p);
+  p += ws_align((size_t)ntiles * 4);
+  int64_t* base = reinterpret_cast<int64_t*>(p);
+  // Schedule: given order, or more rows first (stable), by parallel ranking.
+  for (int i = threadIdx.x; i < ntiles; i += blockDim.x) {
+    int rank = i;
+    if (order == FR_ORDER_ROWS_DESC && ntiles <= 16384) {
+      rank = 0;
+      const int64_t ki = tiles[i].nrows;
+      for (int j = 0; j < ntiles; ++j) {
+        const int64_t kj = tiles[j].nrows;
+        rank += (kj > ki || (kj == ki && j < i)) ? 1 : 0;
+      }
+    }
+    sched[rank] = i;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    size_t off = batch_head_bytes(ntiles);
+    bool bad = false;
+    for (int i = 0; i < ntiles; ++i) {
+      const fr_tile& t = tiles[i];
+      const bool has_q = t.q_out != nullptr;
+      const BatchTileLayout L = batch_tile_layout(t.nrows, t.ncols, t.code_out == nullptr, batch_tile_ff(t.rule, has_q));
+      BatchTileInfo I{};
+      I.z = t.z;
+      I.rain = t.rain;
+      I.q = t.q_out;
+      I.cnt = t.rule == FR_MFD ? nullptr : t.counts_out;
+      if (t.rule != FR_MFD && t.q_out) I.cnt = nullptr;
+      I.code = t.code_out ? t.code_out : reinterpret_cast<uint8_t*>(ws + off + L.code);
+      I.vlo = reinterpret_cast<float*>(ws + off + L.vlo);
+      I.edge = reinterpret_cast<uint64_t*>(ws + off + L.edge);
+      I.progress = reinterpret_cast<int32_t*>(ws + off + L.progress);
+      I.ctr = reinterpret_cast<uint32_t*>(ws + off + L.ctr);
+      I.nrows = t.nrows;
+      I.ncols = t.ncols;
+      I.nstrips = (int32_t)ws_strip_count(t.ncols);
+      I.rule = t.rule;
+      if (t.nrows < 1 || t.ncols < 1 || !t.z || (t.rule == FR_MFD && !t.q_out) ||
+          (t.rule != FR_MFD && (t.q_out != nullptr) == (t.counts_out != nullptr)))
+        bad = true;
+      info[i] = I;
+      off += L.total;
+    }
+    int64_t item = 0;
+    for (int k = 0; k < ntiles; ++k) {
+      base[k] = item;
+      info[sched[k]].strip_base = item;
+      item += info[sched[k]].nstrips;
+    }
+    base[ntiles] = item;
+    hdr->ticket = 0ull;
+    hdr->ntiles = ntiles;
+    hdr->order = order;
+    hdr->ws_needed = (int64_t)off;
+    const bool fits = off <= ws_bytes && !bad;
+    hdr->total_items = fits ? item : 0;
+    if (!fits && status) atomicCAS(status, 0, bad ? FR_ERR_ARG : FR_ERR_WORKSPACE);
+  }
+}
+
+// Fills each tile's edge records (empty), progress (-1) and counters (0).
+__global__ __launch_bounds__(256) void k_batch_fill(const BatchHeader* hdr, const BatchTileInfo* info) {
+  if (hdr->total_items == 0) return;
+  const BatchTileInfo& T = info[blockIdx.x];
+  const int64_t ne = (int64_t)T.nstrips * T.nrows * 2 * WS_EW;
+  for (int64_t i = threadIdx.x; i < ne; i += blockDim.x) T.edge[i] = REC_EMPTY;
+  for (int64_t i = threadIdx.x; i < (int64_t)T.nstrips * BATCH_MAXPASS; i += blockDim.x) T.progress[i] = -1;
+  for (int i = threadIdx.x; i < BATCH_CTR_WORDS; i += blockDim.x) T.ctr[i] = 0u;
 }
 
 template <int RK, int DK, int VK, bool CNT>
@@ -1130,6 +1440,23 @@ hipError_t launch_ws_pass(const EngineConfig& cfg, const WsParams& P, int dir, i
   }
   if (cfg.vk == VK_F64) return pass_t<RK_SINGLE, DIR_ADJ, VK_F64, false>(P, dir, first, s);
   return pass_t<RK_SINGLE, DIR_ADJ, VK_FF, false>(P, dir, first, s);
+}
+
+hipError_t launch_batch(const void* tiles_dev, int32_t ntiles, int order, int workers, int32_t* status,
+                        char* ws, size_t ws_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_setup, dim3(1), dim3(1024), 0, s, static_cast<const fr_tile*>(tiles_dev), ntiles,
+                     order, ws, ws_bytes, status);
+  char* p = ws + ws_align(sizeof(BatchHeader));
+  const BatchTileInfo* info = reinterpret_cast<const BatchTileInfo*>(p);
+  p += ws_align((size_t)ntiles * sizeof(BatchTileInfo));
+  const int32_t* sched = reinterpret_cast<const int32_t*>(p);
+  p += ws_align((size_t)ntiles * 4);
+  const int64_t* base = reinterpret_cast<const int64_t*>(p);
+  hipLaunchKernelGGL(k_batch_fill, dim3((unsigned)ntiles), dim3(256), 0, s,
+                     reinterpret_cast<const BatchHeader*>(ws), info);
+  BatchParams B{reinterpret_cast<BatchHeader*>(ws), info, sched, base, status};
+  hipLaunchKernelGGL(k_batch, dim3((unsigned)workers), dim3(128), 0, s, B);
+  return hipGetLastError();
 }
 
 }  // namespace fr
