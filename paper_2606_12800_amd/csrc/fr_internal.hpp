@@ -154,8 +154,10 @@ inline __host__ __device__ int64_t ws_strip_count(int64_t ncols) { return (ncols
 
 // Workspace of one tile of a batch (offsets within the tile's block).
 struct BatchTileLayout {
-  size_t code, vlo, edge, progress, ctr, total;
+  size_t code, vhi, vlo, edge, progress, ctr, total;
 };
+// ff: the tile has a float32 water output (else its float-float values live
+// in the workspace and only counts are written).
 inline __host__ __device__ BatchTileLayout batch_tile_layout(int64_t nrows, int64_t ncols, bool own_codes,
                                                              bool ff) {
   BatchTileLayout L{};
@@ -163,7 +165,8 @@ inline __host__ __device__ BatchTileLayout batch_tile_layout(int64_t nrows, int6
   const size_t strips = (size_t)ws_strip_count(ncols);
   size_t o = 0;
   L.code = o; if (own_codes) o += ws_align(n);
-  L.vlo = o; if (ff) o += ws_align(n * 4);
+  L.vhi = o; if (!ff) o += ws_align(n * 4);
+  L.vlo = o; o += ws_align(n * 4);
   L.edge = o; o += ws_align(strips * (size_t)nrows * 2 * WS_EW * 8);
   L.progress = o; o += ws_align(strips * BATCH_MAXPASS * 4);
   L.ctr = o; o += ws_align(BATCH_CTR_WORDS * 4);
@@ -178,6 +181,7 @@ struct BatchTileInfo {
   float* q;
   uint64_t* cnt;
   uint8_t* code;
+  float* vhi;
   float* vlo;
   uint64_t* edge;
   int32_t* progress;
@@ -218,6 +222,11 @@ struct WsParams {
   uint32_t* ctr;           // [0] cells finished by the last pass, [1]/[2] probe counts
   int32_t* status;
   int debug;               // float64 value: unfinished cells carry their state in the NaN payload
+  // MFD float-float variant only: codes are D8/D4 directions (turned into
+  // one-bit masks, fraction 1), and counts written from the (integer)
+  // float-float values, exact below 2^31.
+  int codes_single;
+  uint64_t* cnt_ff;
 };
 
 size_t ws_edge_words(int64_t nrows, int64_t ncols);

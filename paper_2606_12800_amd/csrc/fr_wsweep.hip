@@ -55,10 +55,14 @@ constexpr int REC_LANE_R = WS_OWN - 1;   // read by the right neighbour's lane 0
 // (bounded wait), so neighbours stay within the exchange's slack.
 constexpr int LEAD = 4;
 constexpr int LEAD_SPIN = 1 << 14;  // polls before a neighbour counts as absent
-// Longest wait (in 100 MHz ticks) before a row leaves the window with edge
-// cells still waiting for side cells: the neighbour may itself be waiting
-// for rows this strip has not reached, so the cell is left to a later pass.
-constexpr uint64_t EDGE_WAIT_TICKS = 500;
+// Before a row leaves the window with edge cells still waiting for side
+// cells, the strip waits while the neighbour keeps making progress: a cell
+// left unfinished here holds back everything downstream of it until a later
+// pass.  The wait ends when the neighbour froze the rows in question, or
+// made no progress for EDGE_STALL_TICKS (100 MHz ticks), or after
+// EDGE_WAIT_MAX_TICKS in all.
+constexpr uint64_t EDGE_STALL_TICKS = 2000;
+constexpr uint64_t EDGE_WAIT_MAX_TICKS = 200000;
 // Side cells delivered by the I/O wavefront are taken every ARRIVE_EVERY
 // steps: edge lanes are ghost columns, so their cells may lag a few rows,
 // and taking several deliveries at once retries each affected row once.
@@ -123,6 +127,14 @@ __device__ __forceinline__ void vadd(double& a, double b) { a += b; }
 __device__ __forceinline__ float vmul(float v, float) { return v; }
 __device__ __forceinline__ ff vmul(ff v, float f) { return ff_mul_f(v, f); }
 __device__ __forceinline__ double vmul(double v, double f) { return v * f; }
+// v * f * (1 + d): a float32 fraction with the sender's conservation
+// correction d (see the staging of MFD fractions).
+__device__ __forceinline__ ff vmulc(ff v, float f, float d) {
+  const ff p = ff_mul_f(v, f);
+  return ff_fast_two_sum(p.hi, fmaf(p.hi, d, p.lo));
+}
+__device__ __forceinline__ double vmulc(double v, double f, float) { return v * f; }
+__device__ __forceinline__ float vmulc(float v, float, float) { return v; }
 
 // Lane shifts across the whole wavefront (DPP wave_shr:1 / wave_shl:1); the
 // lane shifted in receives 0.
@@ -199,8 +211,8 @@ static_assert(rec_words<RK_MULTI, DIR_FWD, VK_F64, false>() <= WS_EW, "edge reco
 template <int RK, int VK>
 struct Dims {
   static constexpr bool F64M = RK == RK_MULTI && VK == VK_F64;
-  static constexpr int RING = RK == RK_SINGLE ? 32 : (F64M ? 16 : 24);
-  static constexpr int WIN = RK == RK_SINGLE ? 22 : (F64M ? 10 : 14);
+  static constexpr int RING = RK == RK_SINGLE ? 32 : (F64M ? 15 : 24);
+  static constexpr int WIN = RK == RK_SINGLE ? 22 : (F64M ? 9 : 14);
   static constexpr int BATCH = (RING - WIN - 2) / 2;
 };
 
@@ -214,6 +226,9 @@ struct WsShared {
   V val[R][LW];         // final value, or the source term while pending
   uint64_t cnt[CNT ? R : 1][LW];
   F frac[RK == RK_MULTI ? R : 1][8][LW];  // MFD: fraction sent in direction k
+  // MFD float32: d with (sum_k frac_k) * (1 + d) = 1 to float-float accuracy,
+  // so that a cell passes on exactly the water it holds.
+  float fd[RK == RK_MULTI && VK == VK_FF ? R : 1][LW];
   // Hand-over between the two wavefronts.
   int staged;         // rows (steps) 0 .. staged-1 are in the ring
   int tcomp;          // the compute wavefront's current step
@@ -295,16 +310,21 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
 
   if (wave == 1) {
     // ======================= I/O wavefront ===============================
+    // Direction codes run as one-bit masks (fraction 1) in the MFD variant.
+    auto as_mask = [&](uint32_t code) -> uint32_t {
+      if (RK == RK_MULTI && P.codes_single) return code <= 7u ? (1u << code) : 0u;
+      return code;
+    };
     auto load_geo = [&](int t) -> Geo {
       Geo g{NOC, NOC, INFINITY, INFINITY};
       if (t < 0 || t >= nr) return g;
       const int64_t rb = row_of(t) * nc;
       if (live) {
-        g.code = P.code[rb + c];
+        g.code = as_mask(P.code[rb + c]);
         if (RK == RK_MULTI) g.z = P.z[rb + c];
       }
       if (has_side) {
-        g.scode = P.code[rb + cs];
+        g.scode = as_mask(P.code[rb + cs]);
         if (RK == RK_MULTI) g.sz = P.z[rb + cs];
       }
       return g;
@@ -417,16 +437,24 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
             sl[k] = nb_diag(k) ? drop * kInvSqrt2f : drop;
             smax = sl[k] > smax ? sl[k] : smax;
           }
-          const float rs = smax > 0.0f ? 1.0f / smax : 0.0f;
+          // t_k = (s_k / s_max)^p from a correctly rounded quotient (the
+          // steepest direction gets exactly 1), f_k = t_k / sum t: a few ulp
+          // per fraction.
           float tk[8], sum = 0.0f;
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
-            tk[k] = rcv[k] ? exp2f(pf * log2f(sl[k] * rs)) : 0.0f;
+            tk[k] = rcv[k] ? exp2f(pf * log2f(sl[k] / smax)) : 0.0f;
             sum += tk[k];
           }
-          const float iw = sum > 0.0f ? 1.0f / sum : 0.0f;
 #pragma unroll
-          for (int k = 0; k < 8; ++k) fr[k] = tk[k] * iw;
+          for (int k = 0; k < 8; ++k) fr[k] = sum > 0.0f ? tk[k] / sum : 0.0f;
+          // Rounded fractions do not sum to 1 exactly; over thousands of
+          // cells along a flow path the excess would compound.  With the
+          // exact sum s (float-float), d = 1/s - 1 ~ -(s - 1) restores it.
+          ff es = {0.0f, 0.0f};
+#pragma unroll
+          for (int k = 0; k < 8; ++k) es = ff_add(es, ff{fr[k], 0.0f});
+          S.fd[sb][li] = sum > 0.0f ? -((es.hi - 1.0f) + es.lo) : 0.0f;
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) S.frac[sb][k][li] = fr[k];
@@ -463,6 +491,7 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
         if constexpr (RK == RK_MULTI) {
 #pragma unroll
           for (int k = 0; k < 8; ++k) S.frac[sb][k][sidx] = (F)0;
+          if constexpr (VK == VK_FF) S.fd[sb][sidx] = 0.0f;
         }
       }
       // Wanted side cells (uniform masks from the edge lanes).
@@ -591,6 +620,7 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
                   S.frac[sx][ksd1][sx_idx] = hi_f(word);
                 } else {
                   S.frac[sx][ksd2][sx_idx] = lo_f(word);
+                  S.fd[sx][sx_idx] = hi_f(word);
                 }
               }
             } else if constexpr (DK == DIR_FWD && RK == RK_SINGLE && CNT) {
@@ -668,7 +698,7 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
         rec_put(rec + w++, dbits(f2));
       } else {
         rec_put(rec + w++, pack2(f0, f1));
-        rec_put(rec + w++, pack2(f2, 0.0f));
+        rec_put(rec + w++, pack2(f2, S.fd[sb][li]));
       }
     }
     if constexpr (DK == DIR_FWD && RK == RK_SINGLE && CNT) rec_put(rec + w++, n);
@@ -691,6 +721,7 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
     uint32_t sj[8];
     V vj[8];
     F fj[8];
+    float dj[8];
     uint64_t nj[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -702,6 +733,8 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
       sj[k] = row_ok ? S.st[sn][ln] : (NOC | S_DONE);
       if constexpr (VK != VK_NONE) vj[k] = S.val[sn][ln];
       if constexpr (RK == RK_MULTI) fj[k] = DK == DIR_FWD ? S.frac[sn][7 - k][ln] : S.frac[sb][k][li];
+      if constexpr (RK == RK_MULTI && VK == VK_FF) dj[k] = DK == DIR_FWD ? S.fd[sn][ln] : S.fd[sb][li];
+      else dj[k] = 0.0f;
       if constexpr (CNT) nj[k] = S.cnt[sn][ln];
     }
 #pragma unroll
@@ -716,7 +749,7 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
       }
       if (input && fin) {
         if constexpr (VK != VK_NONE) {
-          if constexpr (RK == RK_MULTI) vadd(acc, vmul(vj[k], fj[k]));
+          if constexpr (RK == RK_MULTI) vadd(acc, vmulc(vj[k], fj[k], dj[k]));
           else vadd(acc, vj[k]);
         }
         if constexpr (CNT) accn += nj[k];
@@ -727,9 +760,14 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
     const bool in_l = pend && (DK == DIR_FWD ? sends<RK>(sl & 0xFFu, 4) : sends<RK>(code, 3));
     const bool in_r = pend && (DK == DIR_FWD ? sends<RK>(sr & 0xFFu, 3) : sends<RK>(code, 4));
     F fl = (F)1, fr_ = (F)1;
+    float dfl = 0.0f, dfr = 0.0f;
     if constexpr (RK == RK_MULTI) {
       fl = DK == DIR_FWD ? S.frac[sb][4][li - 1] : S.frac[sb][3][li];
       fr_ = DK == DIR_FWD ? S.frac[sb][3][li + 1] : S.frac[sb][4][li];
+    }
+    if constexpr (RK == RK_MULTI && VK == VK_FF) {
+      dfl = DK == DIR_FWD ? S.fd[sb][li - 1] : S.fd[sb][li];
+      dfr = DK == DIR_FWD ? S.fd[sb][li + 1] : S.fd[sb][li];
     }
     // Side cells of lanes 0 and 63 (another strip) come from LDS.
     bool dside = false;
@@ -769,12 +807,12 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
         V w = acc;
         uint64_t wn = accn;
         if (in_l) {
-          if constexpr (RK == RK_MULTI) vadd(w, vmul(vl, fl));
+          if constexpr (RK == RK_MULTI) vadd(w, vmulc(vl, fl, dfl));
           else vadd(w, vl);
           wn += nl;
         }
         if (in_r) {
-          if constexpr (RK == RK_MULTI) vadd(w, vmul(vr, fr_));
+          if constexpr (RK == RK_MULTI) vadd(w, vmulc(vr, fr_, dfr));
           else vadd(w, vr);
           wn += nrr;
         }
@@ -887,13 +925,26 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
 
   auto wait_edges = [&](int f, int lo, int t) {
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-    for (int it = 0; it < (1 << 16); ++it) {
+    uint64_t t_last = t0;
+    int seen0 = lds_ld(&S.nbp[0]), seen1 = lds_ld(&S.nbp[1]);
+    for (int it = 0; it < (1 << 20); ++it) {
       if (!edge_wait_needed(f)) break;
-      if (__builtin_amdgcn_s_memrealtime() - t0 > EDGE_WAIT_TICKS) break;
+      const uint64_t now = __builtin_amdgcn_s_memrealtime();
+      const int p0 = lds_ld(&S.nbp[0]), p1 = lds_ld(&S.nbp[1]);
+      if (p0 != seen0 || p1 != seen1) {
+        seen0 = p0;
+        seen1 = p1;
+        t_last = now;
+      }
+      if (now - t_last > EDGE_STALL_TICKS || now - t0 > EDGE_WAIT_MAX_TICKS) break;
       ++n_wait;
       const uint32_t dirty = take_arrivals(lo, t);
-      if (dirty) settle(dirty, lo, t);
-      else __builtin_amdgcn_s_sleep(1);
+      if (dirty) {
+        settle(dirty, lo, t);
+        t_last = now;
+      } else {
+        __builtin_amdgcn_s_sleep(1);
+      }
     }
   };
 
@@ -911,6 +962,7 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
         const ff v = S.val[sf][li];
         P.vhi[i] = v.hi;
         P.vlo[i] = v.lo;
+        if (RK == RK_MULTI && P.cnt_ff) P.cnt_ff[i] = (uint64_t)((int64_t)v.hi + (int64_t)v.lo);
       } else if constexpr (VK == VK_F64) {
         P.v64[i] = S.val[sf][li];
       }
@@ -1198,10 +1250,20 @@ __device__ void batch_receivers(const BatchTileInfo& T, int64_t strip, uint32_t*
   if (__ballot(nonfinite) && lane == 0 && status) atomicCAS(status, 0, FR_ERR_NONFINITE);
 }
 
+// Receivers of one strip for any rule.  Kept out of line: it runs once per
+// work item and touches no LDS, and inlining it into the router would
+// crowd the sweep's registers.
+__device__ __attribute__((noinline)) void batch_receivers_any(const BatchTileInfo* Tp, int64_t strip,
+                                                              int32_t* status) {
+  const BatchTileInfo& T = *Tp;
+  if (T.rule == FR_MFD) batch_receivers<FR_MFD>(T, strip, T.ctr + BCTR_UP, T.ctr + BCTR_DN, status);
+  else if (T.rule == FR_D4) batch_receivers<FR_D4>(T, strip, T.ctr + BCTR_UP, T.ctr + BCTR_DN, status);
+  else batch_receivers<FR_D8>(T, strip, T.ctr + BCTR_UP, T.ctr + BCTR_DN, status);
+}
+
 // Bytes of LDS the persistent kernel reserves: the largest sweep variant.
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
-constexpr size_t BATCH_LDS = cmax(sizeof(WsShared<RK_MULTI, VK_FF, false>),
-                                  cmax(sizeof(WsShared<RK_SINGLE, VK_NONE, true>), sizeof(WsShared<RK_SINGLE, VK_FF, false>)));
+constexpr size_t BATCH_LDS = sizeof(WsShared<RK_MULTI, VK_FF, false>);
 
 struct BatchParams {
   BatchHeader* hdr;
@@ -1238,7 +1300,8 @@ __global__ __launch_bounds__(128) void k_batch(BatchParams B) {
       if (B.base[mid] <= item) lo = mid;
       else hi = mid - 1;
     }
-    const BatchTileInfo T = B.info[B.sched[lo]];
+    const BatchTileInfo* Tp = B.info + B.sched[lo];
+    const BatchTileInfo T = *Tp;
     const int64_t strip = item - B.base[lo];
     const uint32_t ns = (uint32_t)T.nstrips;
     if (ns > gridDim.x) {
@@ -1246,9 +1309,7 @@ __global__ __launch_bounds__(128) void k_batch(BatchParams B) {
       if (threadIdx.x == 0 && B.status && strip == 0) atomicCAS(B.status, 0, FR_ERR_ARG);
       continue;
     }
-    if (T.rule == FR_MFD) batch_receivers<FR_MFD>(T, strip, T.ctr + BCTR_UP, T.ctr + BCTR_DN, B.status);
-    else if (T.rule == FR_D4) batch_receivers<FR_D4>(T, strip, T.ctr + BCTR_UP, T.ctr + BCTR_DN, B.status);
-    else batch_receivers<FR_D8>(T, strip, T.ctr + BCTR_UP, T.ctr + BCTR_DN, B.status);
+    batch_receivers_any(Tp, strip, B.status);
     if (!tile_barrier(T.ctr + BCTR_BAR, ns)) {
       if (threadIdx.x == 0 && B.status) atomicCAS(B.status, 0, FR_ERR_HIP);
       continue;
@@ -1265,21 +1326,24 @@ __global__ __launch_bounds__(128) void k_batch(BatchParams B) {
       P.code = T.code;
       P.z = T.z;
       P.p = 1.1;
-      P.src32 = T.rain;
+      P.src32 = T.rule == FR_MFD || T.q ? T.rain : nullptr;
       P.src64 = nullptr;
-      P.vhi = T.q;
+      P.vhi = T.q ? T.q : T.vhi;
       P.vlo = T.vlo;
       P.v64 = nullptr;
-      P.cnt = T.cnt;
+      P.cnt = nullptr;
+      P.codes_single = T.rule != FR_MFD;
+      P.cnt_ff = T.cnt;
       P.edge = T.edge;
       P.progress = T.progress + (int64_t)pass * T.nstrips;
       P.ctr = T.ctr + pass;
       P.status = B.status;
       P.debug = 0;
       const int first = pass == 0 ? 1 : 0;
-      if (T.rule == FR_MFD) batch_sweep<RK_MULTI, VK_FF, false>(lds, P, strip, dir, first);
-      else if (T.q) batch_sweep<RK_SINGLE, VK_FF, false>(lds, P, strip, dir, first);
-      else batch_sweep<RK_SINGLE, VK_NONE, true>(lds, P, strip, dir, first);
+      // Every tile runs the MFD float-float variant; a D8/D4 code is a
+      // one-bit mask whose fraction is exactly 1, and counts are the
+      // float-float values of unit rain, exact integers below 2^31.
+      batch_sweep<RK_MULTI, VK_FF, false>(lds, P, strip, dir, first);
       if (!tile_barrier(T.ctr + BCTR_BAR, (uint32_t)(2 + pass) * ns)) {
         if (threadIdx.x == 0 && B.status) atomicCAS(B.status, 0, FR_ERR_HIP);
         break;
@@ -1337,6 +1401,7 @@ __global__ __launch_bounds__(1024) void k_batch_setup(const fr_tile* tiles, int3
       I.cnt = t.rule == FR_MFD ? nullptr : t.counts_out;
       if (t.rule != FR_MFD && t.q_out) I.cnt = nullptr;
       I.code = t.code_out ? t.code_out : reinterpret_cast<uint8_t*>(ws + off + L.code);
+      I.vhi = reinterpret_cast<float*>(ws + off + L.vhi);
       I.vlo = reinterpret_cast<float*>(ws + off + L.vlo);
       I.edge = reinterpret_cast<uint64_t*>(ws + off + L.edge);
       I.progress = reinterpret_cast<int32_t*>(ws + off + L.progress);
