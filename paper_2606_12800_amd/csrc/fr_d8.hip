@@ -64,6 +64,8 @@ __device__ __forceinline__ uint32_t from_left(uint32_t x, uint32_t edge) {
 __device__ __forceinline__ uint32_t from_right(uint32_t x, uint32_t edge) {
   return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)x, 0x130, 0xF, 0xF, false);
 }
+__device__ __forceinline__ uint32_t from_left(uint32_t x) { return from_left(x, 0u); }
+__device__ __forceinline__ uint32_t from_right(uint32_t x) { return from_right(x, 0u); }
 __device__ __forceinline__ float from_left(float x) {
   return __uint_as_float(from_left(__float_as_uint(x), 0u));
 }
@@ -113,6 +115,16 @@ __device__ __forceinline__ Tile tile_of(const D8Params& P, int b) {
   return T;
 }
 
+// Rain source of a launch: none (unit rain), float32 or float64.
+enum RainKind { RAIN_UNIT = 0, RAIN_F32 = 1, RAIN_F64 = 2 };
+
+// Rows whose loads are in flight ahead of a sweep.  Every load is issued
+// unconditionally (addresses clamped into the grid, rows and columns outside
+// it replaced after arrival) into a ring of registers indexed by the
+// unrolled step, so the wait for a row's data never waits for the rows
+// behind it.
+constexpr int PF = 8;
+
 // One grid row as seen by a lane: the W codes of its columns packed in a
 // dword (byte j = column 4*lane + j of the tile) and the codes just left and
 // right of them.  Off-grid cells read as sinks.
@@ -123,40 +135,98 @@ struct Row {
   __device__ __forceinline__ uint32_t right(int j) const { return j == W - 1 ? r : code(j + 1); }
 };
 
-struct RawRow {
+// Raw codes of one row for one lane, as loaded.
+struct CodeIn {
   uint32_t w;     // own codes
-  uint32_t side;  // lane 0: column left of the tile; lane 63: right of it
+  uint32_t side;  // lane 0: the column left of the tile; lane 63: right of it
 };
 
 template <bool VEC>
-__device__ __forceinline__ RawRow fetch_row(const D8Params& P, const Tile& T, int r, int lane) {
+__device__ __forceinline__ CodeIn load_codes(const D8Params& P, const Tile& T, int r, int lane) {
   const int nr = (int)P.nrows, nc = (int)P.ncols;
-  RawRow x{0xFFFFFFFFu, SINK};
-  if (r >= 0 && r < nr) {
-    const uint8_t* row = P.code + (size_t)r * (size_t)nc;
-    const int c = T.c0 + W * lane;
-    if (VEC) {
-      if (c < nc) x.w = *reinterpret_cast<const uint32_t*>(row + c);
-    } else {
-      uint32_t w = 0;
+  const uint8_t* row = P.code + (size_t)min(max(r, 0), nr - 1) * (size_t)nc;
+  const int c = T.c0 + W * lane;
+  CodeIn x;
+  if (VEC) {
+    x.w = *reinterpret_cast<const uint32_t*>(row + min(c, nc - W));
+  } else {
+    uint32_t w = 0;
 #pragma unroll
-      for (int j = 0; j < W; ++j) w |= (c + j < nc ? (uint32_t)row[c + j] : SINK) << (8 * j);
-      x.w = w;
-    }
-    if (lane == 0 && T.c0 > 0) x.side = row[T.c0 - 1];
-    if (lane == 63 && T.c0 + TW < nc) x.side = row[T.c0 + TW];
+    for (int j = 0; j < W; ++j) w |= (uint32_t)row[min(c + j, nc - 1)] << (8 * j);
+    x.w = w;
   }
+  const int sc = lane == 0 ? T.c0 - 1 : (lane == 63 ? T.c0 + TW : c);
+  x.side = row[min(max(sc, 0), nc - 1)];
   return x;
 }
 
-__device__ __forceinline__ Row expand(const RawRow& x, int lane) {
+// The row at grid row r from its loaded codes.  A tile away from the grid
+// border only ever touches rows and columns inside the grid.
+template <bool BORDER>
+__device__ __forceinline__ Row expand_row(const CodeIn& x, const D8Params& P, const Tile& T, int r, int lane) {
+  uint32_t w = x.w, side = x.side;
+  if (BORDER) {
+    const int nr = (int)P.nrows, nc = (int)P.ncols;
+    const int c = T.c0 + W * lane;
+    const bool row_ok = r >= 0 && r < nr;
+    uint32_t oob = 0;
+#pragma unroll
+    for (int j = 0; j < W; ++j) oob |= (c + j >= nc) ? (0xFFu << (8 * j)) : 0u;
+    w = row_ok ? (w | oob) : 0xFFFFFFFFu;
+    const bool side_ok = row_ok && (lane == 0 ? T.c0 > 0 : T.c0 + TW < nc);
+    side = side_ok ? side : (uint32_t)SINK;
+  }
   Row y;
-  y.w = x.w;
-  y.l = from_left(x.w, 0xFFFFFFFFu) >> 24;
-  y.r = from_right(x.w, 0xFFFFFFFFu) & 0xFFu;
-  if (lane == 0) y.l = x.side;
-  if (lane == 63) y.r = x.side;
+  y.w = w;
+  y.l = from_left(w, 0xFFFFFFFFu) >> 24;
+  y.r = from_right(w, 0xFFFFFFFFu) & 0xFFu;
+  if (lane == 0) y.l = side;
+  if (lane == 63) y.r = side;
   return y;
+}
+
+// Rain of the lane's W cells of grid row r (clamped address; values of
+// columns beyond the grid are never used).
+template <int RAIN, bool VEC>
+struct RainIn {
+  using RT = typename std::conditional<RAIN == RAIN_F64, double, float>::type;
+  RT v[W];
+};
+
+template <int RAIN, bool VEC>
+__device__ __forceinline__ RainIn<RAIN, VEC> load_rain(const D8Params& P, const Tile& T, int r, int lane) {
+  RainIn<RAIN, VEC> x;
+  if (RAIN == RAIN_UNIT) {
+#pragma unroll
+    for (int j = 0; j < W; ++j) x.v[j] = 1;
+    return x;
+  }
+  const int nr = (int)P.nrows, nc = (int)P.ncols;
+  const size_t rb = (size_t)min(max(r, 0), nr - 1) * (size_t)nc;
+  const int c = T.c0 + W * lane;
+  if (VEC && RAIN == RAIN_F32) {
+    const float4 q = *reinterpret_cast<const float4*>(P.rain32 + rb + min(c, nc - W));
+    x.v[0] = q.x;
+    x.v[1] = q.y;
+    x.v[2] = q.z;
+    x.v[3] = q.w;
+  } else if (VEC) {
+    const double* p = P.rain64 + rb + min(c, nc - W);
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    x.v[0] = a.x;
+    x.v[1] = a.y;
+    x.v[2] = b.x;
+    x.v[3] = b.y;
+  } else {
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const size_t g = rb + (size_t)min(c + j, nc - 1);
+      if (RAIN == RAIN_F32) x.v[j] = P.rain32[g];
+      else x.v[j] = (typename RainIn<RAIN, VEC>::RT)P.rain64[g];
+    }
+  }
+  return x;
 }
 
 // Classification of the cell in row r, tile column k = W*lane + j.
@@ -166,16 +236,20 @@ struct Cell {
   bool exit;  // receiver across a cut edge
 };
 
-__device__ __forceinline__ Cell classify(const D8Params& P, const Tile& T, int r, int k, uint32_t cd) {
+template <bool BORDER>
+__device__ __forceinline__ Cell classify(const D8Params& P, const Tile& T, int r, int k, uint32_t cd, bool bottom) {
   Cell x;
   bool bad = false;
-  if (T.border && cd <= 7) {
-    const int rr = r + nb_dr((int)cd), cc = T.c0 + k + nb_dc((int)cd);
-    bad = rr < 0 || rr >= (int)P.nrows || cc < 0 || cc >= (int)P.ncols;
+  if (BORDER) {
+    // A code whose receiver lies off the grid is malformed.
+    const int dr = cd <= 2u ? -1 : (cd <= 4u ? 0 : 1);
+    const int dc = (cd == 0u || cd == 3u || cd == 5u) ? -1 : ((cd == 1u || cd == 6u) ? 0 : 1);
+    const int rr = r + dr, cc = T.c0 + k + dc;
+    bad = cd <= 7u && (rr < 0 || rr >= (int)P.nrows || cc < 0 || cc >= (int)P.ncols);
   }
-  x.sink = cd > 7 || bad || k >= T.tw;
+  x.sink = cd > 7u || bad || (BORDER && k >= T.tw);
   const int tk = k + (int)cd - 1;  // target column of a down-row code
-  x.down = !x.sink && cd <= 2 && r - 1 >= T.r0 && tk >= 0 && tk < T.tw;
+  x.down = !x.sink && cd <= 2u && !bottom && tk >= 0 && tk < (BORDER ? T.tw : TW);
   x.exit = !x.sink && !x.down;
   return x;
 }
@@ -186,7 +260,6 @@ __device__ __forceinline__ Cell classify(const D8Params& P, const Tile& T, int r
 // whether any same-row or towards-higher-row donor can exist in this row.
 __device__ __forceinline__ uint32_t cut_donors(const Row& above, const Row& here, const Row& below, int j,
                                                int k, bool top, bool rare, int tw) {
-  if (k >= tw) return 0u;
   uint32_t m = 0;
   if (rare) {
     m |= (uint32_t)(below.left(j) == 7) << 0;
@@ -198,7 +271,7 @@ __device__ __forceinline__ uint32_t cut_donors(const Row& above, const Row& here
   m |= (uint32_t)(above.left(j) == 2 && (top || k == 0)) << 5;
   m |= (uint32_t)(above.code(j) == 1 && top) << 6;
   m |= (uint32_t)(above.right(j) == 0 && (top || k == tw - 1)) << 7;
-  return m;
+  return k < tw ? m : 0u;
 }
 
 // Can a same-row (codes 3, 4 in `here`) or towards-higher-row (codes 5, 6, 7
@@ -214,14 +287,15 @@ __device__ __forceinline__ bool rare_donors(const Row& here, const Row& below) {
   return __ballot(any) != 0;
 }
 
-template <int VK, bool CNT>
+// Value carried down a sweep: float-float water, float64 water, count.
+template <typename CT>
 struct Val {
   ff f;
   double d;
-  uint64_t n;
+  CT n;
 };
 
-// v + (cond ? x : 0), float-float with one renormalisation per call site.
+// s + (cond ? x : 0), float-float with one renormalisation per call site.
 __device__ __forceinline__ void acc_ff(float& s, float& e, bool cond, float xh, float xl) {
   xh = cond ? xh : 0.0f;
   xl = cond ? xl : 0.0f;
@@ -230,204 +304,200 @@ __device__ __forceinline__ void acc_ff(float& s, float& e, bool cond, float xh, 
   e += t.lo + xl;
 }
 
-constexpr int CHUNK = 4;  // rows fetched ahead of the sweep
-
 // Top-down sweep over the tile (rows r0+th-1 .. r0), one wavefront, W
 // columns per lane.  A cell's value is its rain, plus (phase C) the totals of
 // its cut donors, plus the values of its donors in the row above inside the
 // tile, which the previous step left in registers.  Codes and rain stream
-// through registers CHUNK rows ahead; no LDS.
-//   UP   (phase A): record every exit with its local value.
+// through a ring of registers PF rows ahead; no LDS.
+//   UP   (phase A): record every exit with its local value (local counts of
+//                   one tile fit in 32 bits).
 //   DOWN (phase C): write the final water / counts and the mass balance.
-template <bool UP, int VK, bool CNT, bool R64, bool VEC>
-__device__ void sweep(const D8Params& P, const Tile& T, int fb, double* mass, bool* nonfinite) {
-  using RT = typename std::conditional<R64, double, float>::type;
+template <bool UP, int VK, bool CNT, int RAIN, bool VEC, bool BORDER>
+__device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* mass, bool* nonfinite) {
+  using CT = typename std::conditional<UP, uint32_t, uint64_t>::type;
+  using V = Val<CT>;
   const int lane = threadIdx.x;
   const int k0 = W * lane;  // first tile column of this lane
   const int c = T.c0 + k0;
   const int nc = (int)P.ncols;
-  const bool has_rain = VK != VK_NONE && (R64 ? P.rain64 != nullptr : P.rain32 != nullptr);
   const int rtop = T.r0 + T.th - 1;
+  const int tw = BORDER ? T.tw : TW;
+  const bool lane_in = !BORDER || c < nc;
   double m_sink = 0.0, m_rain = 0.0;
-  Val<VK, CNT> pv[W];
+  bool nf = false;
+  V pv[W];
 #pragma unroll
-  for (int j = 0; j < W; ++j) pv[j] = Val<VK, CNT>{};
-  Row above = expand(fetch_row<VEC>(P, T, rtop + 1, lane), lane);
-  Row here = expand(fetch_row<VEC>(P, T, rtop, lane), lane);
-  RawRow cbuf[CHUNK];
-  RT rbuf[CHUNK][W];
-#define FR_FETCH(RSTART, CB, RB)                                                        \
-  _Pragma("unroll") for (int i_ = 0; i_ < CHUNK; ++i_) {                                \
-    const int rr_ = (RSTART) - i_;                                                      \
-    CB[i_] = fetch_row<VEC>(P, T, rr_ - 1, lane);                                       \
-    _Pragma("unroll") for (int j_ = 0; j_ < W; ++j_) RB[i_][j_] = (RT)1;               \
-    if (has_rain && rr_ >= T.r0 && c < nc) {                                            \
-      const size_t g_ = (size_t)rr_ * (size_t)nc + (size_t)c;                           \
-      if (VEC && !R64) {                                                                \
-        const float4 q_ = *reinterpret_cast<const float4*>(P.rain32 + g_);             \
-        RB[i_][0] = (RT)q_.x; RB[i_][1] = (RT)q_.y; RB[i_][2] = (RT)q_.z; RB[i_][3] = (RT)q_.w; \
-      } else {                                                                          \
-        _Pragma("unroll") for (int j_ = 0; j_ < W; ++j_) if (c + j_ < nc)               \
-          RB[i_][j_] = R64 ? (RT)P.rain64[g_ + j_] : (RT)P.rain32[g_ + j_];             \
-      }                                                                                 \
-    }                                                                                   \
+  for (int j = 0; j < W; ++j) pv[j] = V{};
+  Row above = expand_row<BORDER>(load_codes<VEC>(P, T, rtop + 1, lane), P, T, rtop + 1, lane);
+  Row here = expand_row<BORDER>(load_codes<VEC>(P, T, rtop, lane), P, T, rtop, lane);
+  // Slot i of the ring holds, for step s = i (mod PF): the codes of row
+  // rtop - s - 1 (the row below) and the rain of row rtop - s.
+  CodeIn cq[PF];
+  RainIn<RAIN, VEC> rq[PF];
+#pragma unroll
+  for (int i = 0; i < PF; ++i) {
+    cq[i] = load_codes<VEC>(P, T, rtop - i - 1, lane);
+    rq[i] = load_rain<RAIN, VEC>(P, T, rtop - i, lane);
   }
-  FR_FETCH(rtop, cbuf, rbuf)
-  for (int rc = rtop; rc >= T.r0; rc -= CHUNK) {
-    RawRow cnext[CHUNK];
-    RT rnext[CHUNK][W];
-    if (rc - CHUNK >= T.r0) {
-      FR_FETCH(rc - CHUNK, cnext, rnext)
-    }
+  for (int s0 = 0; s0 < T.th; s0 += PF) {
 #pragma unroll
-    for (int i = 0; i < CHUNK; ++i) {
-      const int r = rc - i;
-      if (r < T.r0) continue;  // uniform: past the bottom row of the tile
-      const Row below = expand(cbuf[i], lane);
-      const size_t g = (size_t)r * (size_t)nc + (size_t)c;
-      const bool top = (r == rtop);
-      const bool rare = !UP && rare_donors(here, below);
-      // Values of the row above at the columns left and right of this lane.
-      Val<VK, CNT> lv, rv;
-      if (VK == VK_FF) {
-        lv.f = {from_left(pv[W - 1].f.hi), from_left(pv[W - 1].f.lo)};
-        rv.f = {from_right(pv[0].f.hi), from_right(pv[0].f.lo)};
-      }
-      if (VK == VK_F64) {
-        lv.d = from_left(pv[W - 1].d);
-        rv.d = from_right(pv[0].d);
-      }
-      if (CNT) {
-        lv.n = from_left(pv[W - 1].n);
-        rv.n = from_right(pv[0].n);
-      }
-      Val<VK, CNT> nv[W];
-      bool exits[W], sinks[W];
-#pragma unroll
-      for (int j = 0; j < W; ++j) {
-        const int k = k0 + j;
-        const uint32_t cd = here.code(j);
-        const Cell x = classify(P, T, r, k, cd);
-        exits[j] = x.exit;
-        sinks[j] = x.sink;
-        const bool d5 = !top && k > 0 && above.left(j) == 2;
-        const bool d6 = !top && above.code(j) == 1;
-        const bool d7 = !top && k + 1 < T.tw && above.right(j) == 0;
-        const Val<VK, CNT>& a5 = j == 0 ? lv : pv[j == 0 ? 0 : j - 1];
-        const Val<VK, CNT>& a7 = j == W - 1 ? rv : pv[j == W - 1 ? 0 : j + 1];
-        const double rain = (double)rbuf[i][j];
-        if (!isfinite(rain)) *nonfinite = true;
-        Val<VK, CNT> v;
+    for (int i = 0; i < PF; ++i) {
+      const int s = s0 + i;
+      const int r = rtop - s;
+      if (s < T.th) {  // uniform
+        const Row below = expand_row<BORDER>(cq[i], P, T, r - 1, lane);
+        const size_t g = (size_t)r * (size_t)nc + (size_t)c;
+        const bool top = s == 0;
+        const bool bottom = r == T.r0;
+        const bool rare = !UP && rare_donors(here, below);
+        // Values of the row above at the columns left and right of this lane.
+        V lv, rv;
         if (VK == VK_FF) {
-          float sh = (float)rbuf[i][j], se = R64 ? (float)(rain - (double)(float)rain) : 0.0f;
-          acc_ff(sh, se, d5, a5.f.hi, a5.f.lo);
-          acc_ff(sh, se, d6, pv[j].f.hi, pv[j].f.lo);
-          acc_ff(sh, se, d7, a7.f.hi, a7.f.lo);
-          v.f = ff_fast(sh, se);
+          lv.f = {from_left(pv[W - 1].f.hi), from_left(pv[W - 1].f.lo)};
+          rv.f = {from_right(pv[0].f.hi), from_right(pv[0].f.lo)};
         }
-        if (VK == VK_F64) v.d = rain + (d5 ? a5.d : 0.0) + (d6 ? pv[j].d : 0.0) + (d7 ? a7.d : 0.0);
-        if (CNT) v.n = 1 + (d5 ? a5.n : 0) + (d6 ? pv[j].n : 0) + (d7 ? a7.n : 0);
-        if (!UP) {
-          // Totals of donors across cut edges (sparse).
-          const uint32_t cut = cut_donors(above, here, below, j, k, top, rare, T.tw);
-          if (cut) {
-            for (int n = 0; n < 8; ++n) {
-              if (!((cut >> n) & 1u)) continue;
+        if (VK == VK_F64) {
+          lv.d = from_left(pv[W - 1].d);
+          rv.d = from_right(pv[0].d);
+        }
+        if (CNT) {
+          lv.n = from_left(pv[W - 1].n);
+          rv.n = from_right(pv[0].n);
+        }
+        V nv[W];
+        bool exits[W], sinks[W];
+        uint32_t cut[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+          const int k = k0 + j;
+          const uint32_t cd = here.code(j);
+          const Cell x = classify<BORDER>(P, T, r, k, cd, bottom);
+          exits[j] = x.exit;
+          sinks[j] = x.sink;
+          const bool d5 = !top && k > 0 && above.left(j) == 2;
+          const bool d6 = !top && above.code(j) == 1;
+          const bool d7 = !top && k + 1 < tw && above.right(j) == 0;
+          const V& a5 = j == 0 ? lv : pv[j == 0 ? 0 : j - 1];
+          const V& a7 = j == W - 1 ? rv : pv[j == W - 1 ? 0 : j + 1];
+          const auto rain = rq[i].v[j];
+          if (UP && RAIN != RAIN_UNIT) nf |= !isfinite(rain);
+          V v;
+          if (VK == VK_FF) {
+            float sh = (float)rain, se = RAIN == RAIN_F64 ? (float)((double)rain - (double)(float)rain) : 0.0f;
+            acc_ff(sh, se, d5, a5.f.hi, a5.f.lo);
+            acc_ff(sh, se, d6, pv[j].f.hi, pv[j].f.lo);
+            acc_ff(sh, se, d7, a7.f.hi, a7.f.lo);
+            v.f = ff_fast(sh, se);
+          }
+          if (VK == VK_F64)
+            v.d = (double)rain + (d5 ? a5.d : 0.0) + (d6 ? pv[j].d : 0.0) + (d7 ? a7.d : 0.0);
+          if (CNT) v.n = (CT)1 + (d5 ? a5.n : (CT)0) + (d6 ? pv[j].n : (CT)0) + (d7 ? a7.n : (CT)0);
+          cut[j] = UP ? 0u : cut_donors(above, here, below, j, k, top, rare, tw);
+          nv[j] = v;
+        }
+        if (!UP && __ballot((cut[0] | cut[1] | cut[2] | cut[3]) != 0u)) {
+          // Totals of donors across cut edges (sparse: the top row, the
+          // outer columns and rare rows).
+#pragma unroll
+          for (int j = 0; j < W; ++j) {
+            uint32_t m = cut[j];
+            while (m) {
+              const int n = __builtin_ctz(m);
+              m &= m - 1;
               const size_t gj = (size_t)((int64_t)(g + j) + (int64_t)nb_dr(n) * nc + nb_dc(n));
               const uint32_t nd = P.node_of[gj];
               if (nd >= P.n_ex) {  // inconsistent bookkeeping: never follow it
                 set_status(P.status, FR_ERR_BADCODE);
                 continue;
               }
-              if (VK == VK_FF) v.f = ff_add(v.f, ff{P.ex_hi[0][nd], P.ex_lo[0][nd]});
-              if (VK == VK_F64) v.d += P.ex_q64[0][nd];
-              if (CNT) v.n += P.ex_cnt[0][nd];
+              if (VK == VK_FF) nv[j].f = ff_add(nv[j].f, ff{P.ex_hi[0][nd], P.ex_lo[0][nd]});
+              if (VK == VK_F64) nv[j].d += P.ex_q64[0][nd];
+              if (CNT) nv[j].n += (CT)P.ex_cnt[0][nd];
             }
           }
         }
-        nv[j] = v;
-      }
-      bool any_exit = false;
+        if (UP && __ballot(exits[0] || exits[1] || exits[2] || exits[3])) {
+          // Record exits (wavefront-compacted append).
 #pragma unroll
-      for (int j = 0; j < W; ++j) any_exit |= exits[j];
-      if (UP && __ballot(any_exit)) {
-        // Record exits (wavefront-compacted append).
-#pragma unroll
-        for (int j = 0; j < W; ++j) {
-          const bool ex = exits[j];
-          const uint64_t m = __ballot(ex);
-          if (m) {
-            uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(P.n_exits, (uint32_t)__popcll(m));
-            base = __shfl(base, 0, 64);
-            if (ex) {
-              const uint32_t idx =
-                  base + (uint32_t)__popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-              if (idx < P.cap) {
-                P.node_of[g + j] = idx;
-                P.ex_cell[idx] = (uint32_t)(g + j);
-                if (VK == VK_FF) {
-                  P.ex_hi[0][idx] = nv[j].f.hi;
-                  P.ex_lo[0][idx] = nv[j].f.lo;
+          for (int j = 0; j < W; ++j) {
+            const bool ex = exits[j];
+            const uint64_t m = __ballot(ex);
+            if (m) {
+              uint32_t base = 0;
+              if (lane == 0) base = atomicAdd(P.n_exits, (uint32_t)__popcll(m));
+              base = __shfl(base, 0, 64);
+              if (ex) {
+                const uint32_t idx = base + (uint32_t)__popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+                if (idx < P.cap) {
+                  P.node_of[g + j] = idx;
+                  P.ex_cell[idx] = (uint32_t)(g + j);
+                  if (VK == VK_FF) {
+                    P.ex_hi[0][idx] = nv[j].f.hi;
+                    P.ex_lo[0][idx] = nv[j].f.lo;
+                  }
+                  if (VK == VK_F64) P.ex_q64[0][idx] = nv[j].d;
+                  if (CNT) P.ex_cnt[0][idx] = (uint64_t)nv[j].n;
                 }
-                if (VK == VK_F64) P.ex_q64[0][idx] = nv[j].d;
-                if (CNT) P.ex_cnt[0][idx] = nv[j].n;
               }
             }
           }
         }
-      }
-      if (!UP && c < nc) {
-        if (VEC) {
-          if (VK == VK_FF) {
-            float4 o;
-            o.x = nv[0].f.hi + nv[0].f.lo;
-            o.y = nv[1].f.hi + nv[1].f.lo;
-            o.z = nv[2].f.hi + nv[2].f.lo;
-            o.w = nv[3].f.hi + nv[3].f.lo;
-            *reinterpret_cast<float4*>(P.q32 + g) = o;
-          }
-          if (VK == VK_F64) {
-            *reinterpret_cast<double2*>(P.q64 + g) = make_double2(nv[0].d, nv[1].d);
-            *reinterpret_cast<double2*>(P.q64 + g + 2) = make_double2(nv[2].d, nv[3].d);
-          }
-          if (CNT) {
-            ulonglong2 a, b;
-            a.x = nv[0].n; a.y = nv[1].n; b.x = nv[2].n; b.y = nv[3].n;
-            *reinterpret_cast<ulonglong2*>(P.cnt + g) = a;
-            *reinterpret_cast<ulonglong2*>(P.cnt + g + 2) = b;
-          }
-        } else {
+        if (!UP && lane_in) {
+          if (VEC) {
+            if (VK == VK_FF) {
+              float4 o;
+              o.x = nv[0].f.hi + nv[0].f.lo;
+              o.y = nv[1].f.hi + nv[1].f.lo;
+              o.z = nv[2].f.hi + nv[2].f.lo;
+              o.w = nv[3].f.hi + nv[3].f.lo;
+              *reinterpret_cast<float4*>(P.q32 + g) = o;
+            }
+            if (VK == VK_F64) {
+              *reinterpret_cast<double2*>(P.q64 + g) = make_double2(nv[0].d, nv[1].d);
+              *reinterpret_cast<double2*>(P.q64 + g + 2) = make_double2(nv[2].d, nv[3].d);
+            }
+            if (CNT) {
+              ulonglong2 a, b;
+              a.x = nv[0].n;
+              a.y = nv[1].n;
+              b.x = nv[2].n;
+              b.y = nv[3].n;
+              *reinterpret_cast<ulonglong2*>(P.cnt + g) = a;
+              *reinterpret_cast<ulonglong2*>(P.cnt + g + 2) = b;
+            }
+          } else {
 #pragma unroll
-          for (int j = 0; j < W; ++j) {
-            if (c + j >= nc) continue;
-            if (VK == VK_FF) P.q32[g + j] = nv[j].f.hi + nv[j].f.lo;
-            if (VK == VK_F64) P.q64[g + j] = nv[j].d;
-            if (CNT) P.cnt[g + j] = nv[j].n;
-          }
-        }
-        if (VK != VK_NONE) {
-#pragma unroll
-          for (int j = 0; j < W; ++j) {
-            if (c + j >= nc) continue;
-            if (sinks[j]) m_sink += VK == VK_FF ? (double)nv[j].f.hi + (double)nv[j].f.lo : nv[j].d;
-            m_rain += (double)rbuf[i][j];
+            for (int j = 0; j < W; ++j) {
+              if (c + j >= nc) continue;
+              if (VK == VK_FF) P.q32[g + j] = nv[j].f.hi + nv[j].f.lo;
+              if (VK == VK_F64) P.q64[g + j] = nv[j].d;
+              if (CNT) P.cnt[g + j] = nv[j].n;
+            }
           }
         }
+        if (!UP && VK != VK_NONE) {
+#pragma unroll
+          for (int j = 0; j < W; ++j)
+            if (!BORDER || c + j < nc) m_rain += (double)rq[i].v[j];
+          if (__ballot(sinks[0] || sinks[1] || sinks[2] || sinks[3])) {
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+              if (sinks[j] && (!BORDER || c + j < nc))
+                m_sink += VK == VK_FF ? (double)nv[j].f.hi + (double)nv[j].f.lo : nv[j].d;
+            }
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < W; ++j) pv[j] = nv[j];
+        above = here;
+        here = below;
       }
-#pragma unroll
-      for (int j = 0; j < W; ++j) pv[j] = nv[j];
-      above = here;
-      here = below;
-    }
-#pragma unroll
-    for (int i = 0; i < CHUNK; ++i) {
-      cbuf[i] = cnext[i];
-#pragma unroll
-      for (int j = 0; j < W; ++j) rbuf[i][j] = rnext[i][j];
+      // Refill the slot for step s + PF.
+      cq[i] = load_codes<VEC>(P, T, r - PF - 1, lane);
+      rq[i] = load_rain<RAIN, VEC>(P, T, r - PF, lane);
     }
   }
-#undef FR_FETCH
+  if (nf) *nonfinite = true;
   if (mass) {
     mass[0] = m_sink;
     mass[1] = m_rain;
@@ -436,70 +506,79 @@ __device__ void sweep(const D8Params& P, const Tile& T, int fb, double* mass, bo
 
 // Bottom-up sweep (rows r0 .. r0+th-1): the root of every inlet -- the exit
 // or sink where its path through the tile ends.
-template <bool VEC>
-__device__ void root_sweep(const D8Params& P, const Tile& T, bool* badcode) {
+template <bool VEC, bool BORDER>
+__device__ __forceinline__ void root_sweep(const D8Params& P, const Tile& T, bool* badcode) {
   const int lane = threadIdx.x;
   const int k0 = W * lane;
   const int nc = (int)P.ncols;
-  const int rtop = T.r0 + T.th - 1;
-  Row below = expand(fetch_row<VEC>(P, T, T.r0 - 1, lane), lane);
-  Row here = expand(fetch_row<VEC>(P, T, T.r0, lane), lane);
+  const int tw = BORDER ? T.tw : TW;
+  Row below = expand_row<BORDER>(load_codes<VEC>(P, T, T.r0 - 1, lane), P, T, T.r0 - 1, lane);
+  Row here = expand_row<BORDER>(load_codes<VEC>(P, T, T.r0, lane), P, T, T.r0, lane);
   uint32_t rp[W];  // roots of the row below
 #pragma unroll
   for (int j = 0; j < W; ++j) rp[j] = NONE;
-  RawRow cbuf[CHUNK];
+  bool bad = false;
+  // Slot i holds, for step s = i (mod PF), the codes of row r0 + s + 1.
+  CodeIn cq[PF];
 #pragma unroll
-  for (int i = 0; i < CHUNK; ++i) cbuf[i] = fetch_row<VEC>(P, T, T.r0 + i + 1, lane);
-  for (int rc = T.r0; rc <= rtop; rc += CHUNK) {
-    RawRow cnext[CHUNK];
-    if (rc + CHUNK <= rtop) {
+  for (int i = 0; i < PF; ++i) cq[i] = load_codes<VEC>(P, T, T.r0 + i + 1, lane);
+  for (int s0 = 0; s0 < T.th; s0 += PF) {
 #pragma unroll
-      for (int i = 0; i < CHUNK; ++i) cnext[i] = fetch_row<VEC>(P, T, rc + CHUNK + i + 1, lane);
-    }
+    for (int i = 0; i < PF; ++i) {
+      const int s = s0 + i;
+      const int r = T.r0 + s;
+      if (s < T.th) {  // uniform
+        const Row above = expand_row<BORDER>(cq[i], P, T, r + 1, lane);
+        const bool top = s == T.th - 1;
+        const bool bottom = s == 0;
+        const bool rare = rare_donors(here, below);
+        const uint32_t left = from_left(rp[W - 1], NONE), right = from_right(rp[0], NONE);
+        const uint32_t base = (uint32_t)((size_t)r * (size_t)nc + (size_t)(T.c0 + k0));
+        uint32_t nr[W];
+        bool inlet[W];
 #pragma unroll
-    for (int i = 0; i < CHUNK; ++i) {
-      const int r = rc + i;
-      if (r > rtop) continue;  // uniform
-      const Row above = expand(cbuf[i], lane);
-      const bool top = (r == rtop);
-      const bool rare = rare_donors(here, below);
-      const uint32_t left = from_left(rp[W - 1], NONE), right = from_right(rp[0], NONE);
-      const uint32_t base = (uint32_t)((size_t)r * (size_t)nc + (size_t)(T.c0 + k0));
-      uint32_t nr[W];
+        for (int j = 0; j < W; ++j) {
+          const int k = k0 + j;
+          const uint32_t cd = here.code(j);
+          const Cell x = classify<BORDER>(P, T, r, k, cd, bottom);
+          if (BORDER) bad |= k < tw && cd != SINK && x.sink;
+          else bad |= cd > 7u && cd != SINK;
+          const uint32_t rl = j == 0 ? left : rp[j == 0 ? 0 : j - 1];
+          const uint32_t rr = j == W - 1 ? right : rp[j == W - 1 ? 0 : j + 1];
+          nr[j] = x.down ? (cd == 0u ? rl : (cd == 1u ? rp[j] : rr)) : base + j;
+          // Inlets: the top row, the two outer columns, and rows where a
+          // same-row / towards-higher-row donor exists.
+          inlet[j] = (top || rare || k == 0 || k == tw - 1) && cut_donors(above, here, below, j, k, top, rare, tw);
+        }
+        if (__ballot(inlet[0] || inlet[1] || inlet[2] || inlet[3])) {
 #pragma unroll
-      for (int j = 0; j < W; ++j) {
-        const int k = k0 + j;
-        const uint32_t cd = here.code(j);
-        const Cell x = classify(P, T, r, k, cd);
-        if (k < T.tw && cd != SINK && x.sink) *badcode = true;
-        const uint32_t rl = j == 0 ? left : rp[j == 0 ? 0 : j - 1];
-        const uint32_t rr = j == W - 1 ? right : rp[j == W - 1 ? 0 : j + 1];
-        uint32_t root = base + j;
-        if (x.down) root = cd == 0 ? rl : (cd == 1 ? rp[j] : rr);
-        nr[j] = root;
-        // Inlets: the top row, the two outer columns, and rows where a
-        // same-row / towards-higher-row donor exists.
-        if ((top || rare || k == 0 || k == T.tw - 1) && cut_donors(above, here, below, j, k, top, rare, T.tw))
-          P.root_of[base + j] = root;
+          for (int j = 0; j < W; ++j)
+            if (inlet[j]) P.root_of[base + j] = nr[j];
+        }
+#pragma unroll
+        for (int j = 0; j < W; ++j) rp[j] = nr[j];
+        below = here;
+        here = above;
       }
-#pragma unroll
-      for (int j = 0; j < W; ++j) rp[j] = nr[j];
-      below = here;
-      here = above;
+      cq[i] = load_codes<VEC>(P, T, r + PF + 1, lane);
     }
-#pragma unroll
-    for (int i = 0; i < CHUNK; ++i) cbuf[i] = cnext[i];
   }
+  if (bad) *badcode = true;
 }
 
 // ---------------------------------------------------------------------------
 // Phase A.
-template <int VK, bool CNT, bool R64, bool VEC>
+template <int VK, bool CNT, int RAIN, bool VEC>
 __global__ __launch_bounds__(64) void k_d8_up(D8Params P) {
   const Tile T = tile_of(P, blockIdx.x);
   bool badcode = false, nonfinite = false;
-  root_sweep<VEC>(P, T, &badcode);
-  sweep<true, VK, CNT, R64, VEC>(P, T, 0, nullptr, &nonfinite);
+  if (T.border) {
+    root_sweep<VEC, true>(P, T, &badcode);
+    sweep<true, VK, CNT, RAIN, VEC, true>(P, T, nullptr, &nonfinite);
+  } else {
+    root_sweep<VEC, false>(P, T, &badcode);
+    sweep<true, VK, CNT, RAIN, VEC, false>(P, T, nullptr, &nonfinite);
+  }
   if (badcode) set_status(P.status, FR_ERR_BADCODE);
   if (nonfinite) set_status(P.status, FR_ERR_NONFINITE);
 }
@@ -540,6 +619,9 @@ __global__ __launch_bounds__(256) void k_d8_link(D8Params P, uint32_t n) {
 // sum over its subtree within distance < 2^k) and jumps its pointer.
 template <int VK, bool CNT>
 __global__ __launch_bounds__(256) void k_d8_copy(D8Params P, uint32_t n, int b) {
+  __shared__ int s_active;
+  if (threadIdx.x == 0) s_active = 0;
+  __syncthreads();
   bool active = false;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const uint32_t a = P.anc[b][i];
@@ -556,7 +638,12 @@ __global__ __launch_bounds__(256) void k_d8_copy(D8Params P, uint32_t n, int b) 
     P.anc[b ^ 1][i] = a2;
     active |= (a2 != NONE);
   }
-  if (__ballot(active) && (threadIdx.x & 63) == 0) atomicOr(&P.flags[1], 1);
+  // One store per workgroup, and only while the flag is still clear: an
+  // atomic from every wavefront on one word serialises the whole kernel.
+  if (__ballot(active) && (threadIdx.x & 63) == 0) s_active = 1;
+  __syncthreads();
+  if (threadIdx.x == 0 && s_active && __hip_atomic_load(&P.flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+    __hip_atomic_store(&P.flags[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Part 2: each such exit adds its snapshot to the ancestor's sum in place.
@@ -579,14 +666,15 @@ __global__ __launch_bounds__(256) void k_d8_scatter(D8Params P, uint32_t n, int 
 
 // ---------------------------------------------------------------------------
 // Phase C.
-template <int VK, bool CNT, bool R64, bool VEC>
-__global__ __launch_bounds__(64) void k_d8_down(D8Params P, int fb) {
+template <int VK, bool CNT, int RAIN, bool VEC>
+__global__ __launch_bounds__(64) void k_d8_down(D8Params P) {
   __shared__ double s_mass[2][64];
   const int lane = threadIdx.x;
   const Tile T = tile_of(P, blockIdx.x);
   double m[2] = {0.0, 0.0};
   bool nonfinite = false;
-  sweep<false, VK, CNT, R64, VEC>(P, T, fb, m, &nonfinite);
+  if (T.border) sweep<false, VK, CNT, RAIN, VEC, true>(P, T, m, &nonfinite);
+  else sweep<false, VK, CNT, RAIN, VEC, false>(P, T, m, &nonfinite);
   if (P.mass_part) {
     s_mass[0][lane] = m[0];
     s_mass[1][lane] = m[1];
@@ -625,35 +713,53 @@ int grid_for(uint32_t n) {
     }                                                                                           \
   } while (0)
 
-#define D8_LAUNCH(KERNEL, VKV, CNTV, ...)                                                     \
-  do {                                                                                         \
-    const dim3 g((unsigned)((int64_t)P.ntr * P.ntc)), b(64);                                   \
-    const bool r64 = P.rain64 != nullptr;                                                      \
-    const bool vec = (P.ncols % 4) == 0;                                                       \
-    if (r64) {                                                                                 \
-      if (vec) hipLaunchKernelGGL((KERNEL<VKV, CNTV, true, true>), g, b, 0, s, __VA_ARGS__);    \
-      else hipLaunchKernelGGL((KERNEL<VKV, CNTV, true, false>), g, b, 0, s, __VA_ARGS__);       \
-    } else {                                                                                   \
-      if (vec) hipLaunchKernelGGL((KERNEL<VKV, CNTV, false, true>), g, b, 0, s, __VA_ARGS__);   \
-      else hipLaunchKernelGGL((KERNEL<VKV, CNTV, false, false>), g, b, 0, s, __VA_ARGS__);      \
-    }                                                                                          \
-  } while (0)
+// Launches a phase A / phase C kernel for the rain source and the row
+// alignment of the grid (float4 / dword row loads when ncols % 4 == 0).
+template <int VK, bool CNT, template <int, bool, int, bool> class K>
+void d8_sweep_launch(const D8Params& P, hipStream_t s) {
+  const dim3 g((unsigned)((int64_t)P.ntr * P.ntc)), b(64);
+  const bool vec = (P.ncols % 4) == 0;
+  const int rain = P.rain64 ? RAIN_F64 : (P.rain32 ? RAIN_F32 : RAIN_UNIT);
+  if (VK == VK_NONE || rain == RAIN_UNIT) {
+    if (vec) K<VK, CNT, RAIN_UNIT, true>::launch(g, b, s, P);
+    else K<VK, CNT, RAIN_UNIT, false>::launch(g, b, s, P);
+  } else if (rain == RAIN_F32) {
+    if (vec) K<VK, CNT, RAIN_F32, true>::launch(g, b, s, P);
+    else K<VK, CNT, RAIN_F32, false>::launch(g, b, s, P);
+  } else {
+    if (vec) K<VK, CNT, RAIN_F64, true>::launch(g, b, s, P);
+    else K<VK, CNT, RAIN_F64, false>::launch(g, b, s, P);
+  }
+}
 
-#define D8_SWEEP_DISPATCH(KERNEL, ...)                                                          \
-  do {                                                                                          \
-    if (vk == VK_FF) {                                                                          \
-      if (cnt) D8_LAUNCH(KERNEL, VK_FF, true, __VA_ARGS__);                                      \
-      else D8_LAUNCH(KERNEL, VK_FF, false, __VA_ARGS__);                                         \
-    } else if (vk == VK_F64) {                                                                  \
-      if (cnt) D8_LAUNCH(KERNEL, VK_F64, true, __VA_ARGS__);                                     \
-      else D8_LAUNCH(KERNEL, VK_F64, false, __VA_ARGS__);                                        \
-    } else {                                                                                    \
-      D8_LAUNCH(KERNEL, VK_NONE, true, __VA_ARGS__);                                             \
-    }                                                                                           \
-  } while (0)
+template <int VK, bool CNT, int RAIN, bool VEC>
+struct UpK {
+  static void launch(dim3 g, dim3 b, hipStream_t s, const D8Params& P) {
+    hipLaunchKernelGGL((k_d8_up<VK, CNT, VK == VK_NONE ? RAIN_UNIT : RAIN, VEC>), g, b, 0, s, P);
+  }
+};
+template <int VK, bool CNT, int RAIN, bool VEC>
+struct DownK {
+  static void launch(dim3 g, dim3 b, hipStream_t s, const D8Params& P) {
+    hipLaunchKernelGGL((k_d8_down<VK, CNT, VK == VK_NONE ? RAIN_UNIT : RAIN, VEC>), g, b, 0, s, P);
+  }
+};
+
+template <template <int, bool, int, bool> class K>
+void d8_sweep_dispatch(ValKind vk, bool cnt, const D8Params& P, hipStream_t s) {
+  if (vk == VK_FF) {
+    if (cnt) d8_sweep_launch<VK_FF, true, K>(P, s);
+    else d8_sweep_launch<VK_FF, false, K>(P, s);
+  } else if (vk == VK_F64) {
+    if (cnt) d8_sweep_launch<VK_F64, true, K>(P, s);
+    else d8_sweep_launch<VK_F64, false, K>(P, s);
+  } else {
+    d8_sweep_launch<VK_NONE, true, K>(P, s);
+  }
+}
 
 hipError_t launch_d8_up(ValKind vk, bool cnt, const D8Params& P, hipStream_t s) {
-  D8_SWEEP_DISPATCH(k_d8_up, P);
+  d8_sweep_dispatch<UpK>(vk, cnt, P, s);
   return hipGetLastError();
 }
 
@@ -671,11 +777,10 @@ hipError_t launch_d8_round(ValKind vk, bool cnt, const D8Params& P, uint32_t n, 
 }
 
 hipError_t launch_d8_down(ValKind vk, bool cnt, const D8Params& P, int fb, hipStream_t s) {
-  D8_SWEEP_DISPATCH(k_d8_down, P, fb);
+  (void)fb;  // the forest sums are summed in place in slot 0
+  d8_sweep_dispatch<DownK>(vk, cnt, P, s);
   return hipGetLastError();
 }
-#undef D8_SWEEP_DISPATCH
-#undef D8_LAUNCH
 #undef D8_DISPATCH
 
 }  // namespace fr
