@@ -30,6 +30,11 @@ PHASE_BYTES = {
 }
 PHASE_KERNEL = {"receivers": "k_receivers", "d8_up": "k_d8_up", "d8_down": "k_d8_down"}
 ACC_BYTES = 1 + 4 + 4 + 8     # whole accumulate call: code, rain in; q, counts out
+# HBM bytes per launch of the single-kernel phases at the 43360^2 workload,
+# from rocprofv3 FETCH_SIZE / WRITE_SIZE runs calibrated against a 1 GiB
+# device copy (profiles/d8_43360_hbm_traffic.md).  They describe the kernels
+# as they were when counted; other sizes report null.
+MEASURED_TRAFFIC = {43360: {"receivers": 10.63e9, "d8_up": 11.86e9, "d8_down": 33.35e9}}
 
 
 def log(msg):
@@ -346,7 +351,7 @@ def main():
         "config": {"workload": f"D8 {n}x{n} fractal DEM (seed {args.seed}), f32 rain + u64 counts",
                    "cells": ncell},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get(n, {}).get(dom),
                      "kernel": PHASE_KERNEL[dom], "bytes_per_cell": PHASE_BYTES[dom],
                      "ms_per_launch": single[dom]},
         "detail": {"receivers_ms": recv_avg, "accumulate_ms": acc_avg,

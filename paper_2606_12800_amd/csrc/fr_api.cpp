@@ -332,7 +332,7 @@ int run_ws(const EngineConfig& cfg, WsParams P, int32_t* status, hipStream_t s) 
     if (max_pass >= 0 && pass >= max_pass) return FR_OK;
     if (pass >= kMaxSweepPasses) return 1;
     if (launch_zero_u32(P.ctr, 1, s) != hipSuccess) return FR_ERR_HIP;
-    if (P.debug && launch_zero_u32(P.ctr + 3, 21, s) != hipSuccess) return FR_ERR_HIP;
+    if (P.debug && launch_zero_u32(P.ctr + 3, 25, s) != hipSuccess) return FR_ERR_HIP;
     if (launch_ws_progress_reset(P, s) != hipSuccess) return FR_ERR_HIP;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (verbose() && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess)
@@ -349,20 +349,21 @@ int run_ws(const EngineConfig& cfg, WsParams P, int32_t* status, hipStream_t s) 
     if (verbose()) {
       float ms = 0.0f;
       if (e1) (void)hipEventElapsedTime(&ms, e0, e1);
-      uint32_t d[24] = {0};
+      uint32_t d[28] = {0};
       if (P.debug && hipMemcpy(d, P.ctr, sizeof d, hipMemcpyDeviceToHost) != hipSuccess) return FR_ERR_HIP;
       fprintf(stderr,
               "flowroute: sweep pass %d dir %+d finished %u remaining %lld (%.3f ms) edge-waits %u pace-spins %u "
-              "resolves %u\n",
-              pass, dir, fin, (long long)remaining, ms, d[3], d[4], d[5]);
+              "resolves %u row-iterations %u\n",
+              pass, dir, fin, (long long)remaining, ms, d[3], d[4], d[5], d[6]);
       if (P.debug) {
         const uint64_t* tm = reinterpret_cast<const uint64_t*>(d + 8);
         const double steps = (double)P.nrows * (double)ws_strips(P.ncols);
         fprintf(stderr,
-                "flowroute:   per strip-step (us): wait-staged %.3f pace %.3f settle %.3f freeze %.3f all %.3f | "
-                "io stage %.3f poll %.3f iterations/step %.2f\n",
-                tm[0] / steps / 100.0, tm[1] / steps / 100.0, tm[2] / steps / 100.0, tm[3] / steps / 100.0,
-                tm[4] / steps / 100.0, tm[5] / steps / 100.0, tm[6] / steps / 100.0, tm[7] / steps);
+                "flowroute:   per strip-step (us): wait-staged %.3f pace %.3f settle %.3f (resolve %.3f, row loop %.3f) freeze %.3f "
+                "all %.3f | io stage %.3f poll %.3f iterations/step %.2f\n",
+                tm[0] / steps / 100.0, tm[1] / steps / 100.0, tm[2] / steps / 100.0, tm[8] / steps / 100.0, tm[9] / steps / 100.0,
+                tm[3] / steps / 100.0, tm[4] / steps / 100.0, tm[5] / steps / 100.0, tm[6] / steps / 100.0,
+                tm[7] / steps);
       }
     }
     if (e0) (void)hipEventDestroy(e0);

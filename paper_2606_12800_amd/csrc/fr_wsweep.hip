@@ -254,8 +254,13 @@ struct Src {
 // Orders one wavefront's LDS accesses: a wavefront executes its LDS
 // instructions in order, so only the compiler must not move them across.
 __device__ __forceinline__ void lds_sync() { asm volatile("" ::: "memory"); }
-__device__ __forceinline__ int lds_ld(const int* p) { return *(const volatile int*)p; }
-__device__ __forceinline__ void lds_st(int* p, int v) { *(volatile int*)p = v; }
+// Hand-over words between the two wavefronts live in LDS; the accesses name
+// the LDS address space so that they compile to ds_read / ds_write (a
+// volatile access through a generic pointer becomes a flat, system-coherent
+// access that waits for all of the wavefront's outstanding memory traffic).
+typedef __attribute__((address_space(3))) int lds_int;
+__device__ __forceinline__ int lds_ld(const int* p) { return *(const volatile lds_int*)p; }
+__device__ __forceinline__ void lds_st(int* p, int v) { *(volatile lds_int*)p = v; }
 
 // Two wavefronts per workgroup.  Wavefront 1 (I/O) stages rows into the
 // ring ahead of use -- codes, elevations, source terms, earlier passes'
@@ -678,7 +683,8 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
   const int my_side = lane == REC_LANE_L ? 0 : 1;
   const bool has_record = live && ((lane == REC_LANE_L && strip > 0) || (lane == REC_LANE_R && strip + 1 < nstrips));
   uint32_t pend_rows = 0, nfin = 0;
-  uint32_t n_wait = 0, n_pace = 0, n_resolve = 0;  // diagnostics
+  uint32_t n_wait = 0, n_pace = 0, n_resolve = 0, n_iter = 0;  // diagnostics
+  uint64_t tm_resolve = 0, tm_loop = 0;
   bool fail = false;
 
   // Publishes a newly final cell that a neighbour reads as its side cell.
@@ -783,6 +789,7 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
     V cv = S.val[sb][li];
     uint64_t cn = CNT ? S.cnt[sb][li] : 0;
     bool newly = false, dl = false, dr = false;
+    const uint64_t tl0 = P.debug ? __builtin_amdgcn_s_memrealtime() : 0;
     for (int it = 0; it < 66; ++it) {
       dl = from_left(cd) != 0;
       dr = from_right(cd) != 0;
@@ -821,8 +828,10 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
         cd = 1u;
         newly = true;
       }
+      ++n_iter;
       if (__ballot(can) == 0) break;
     }
+    if (P.debug) tm_loop += __builtin_amdgcn_s_memrealtime() - tl0;
     if (newly) {
       S.st[sb][li] = me | S_DONE;
       S.val[sb][li] = cv;
@@ -863,7 +872,9 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
       if (x < lo || !((pend_rows >> sb) & 1u)) continue;
       lds_sync();
       ++n_resolve;
+      const uint64_t tr0 = P.debug ? __builtin_amdgcn_s_memrealtime() : 0;
       const uint64_t D = resolve(x, sb);
+      if (P.debug) tm_resolve += __builtin_amdgcn_s_memrealtime() - tr0;
       lds_sync();
       const bool still = __ballot(!(S.st[sb][li] & S_DONE)) != 0;
       pend_rows = still ? (pend_rows | (1u << sb)) : (pend_rows & ~(1u << sb));
@@ -1077,6 +1088,7 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
     atomicAdd(P.ctr + 3, n_wait);
     atomicAdd(P.ctr + 4, n_pace);
     atomicAdd(P.ctr + 5, n_resolve);
+    atomicAdd(P.ctr + 6, n_iter);
     // Time in 100 MHz ticks, summed over strips.
     unsigned long long* tm = reinterpret_cast<unsigned long long*>(P.ctr + 8);
     atomicAdd(tm + 0, (unsigned long long)tm_stage);
@@ -1084,6 +1096,8 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
     atomicAdd(tm + 2, (unsigned long long)tm_settle);
     atomicAdd(tm + 3, (unsigned long long)tm_freeze);
     atomicAdd(tm + 4, (unsigned long long)tm_all);
+    atomicAdd(tm + 8, (unsigned long long)tm_resolve);
+    atomicAdd(tm + 9, (unsigned long long)tm_loop);
   }
   }
   __syncthreads();
