@@ -135,6 +135,17 @@ __device__ __forceinline__ ff vmulc(ff v, float f, float d) {
 }
 __device__ __forceinline__ double vmulc(double v, double f, float) { return v * f; }
 __device__ __forceinline__ float vmulc(float v, float, float) { return v; }
+// cond ? v : 0.
+__device__ __forceinline__ float vsel(bool c, float v) { return c ? v : 0.0f; }
+__device__ __forceinline__ ff vsel(bool c, ff v) { return {c ? v.hi : 0.0f, c ? v.lo : 0.0f}; }
+__device__ __forceinline__ double vsel(bool c, double v) { return c ? v : 0.0; }
+// What a donor with value v passes on along an edge of fraction f (with
+// the sender's conservation correction d); a single receiver takes all.
+template <int RK, typename V, typename F>
+__device__ __forceinline__ V contrib(V v, F f, float d) {
+  if constexpr (RK == RK_MULTI) return vmulc(v, f, d);
+  else return v;
+}
 
 // Lane shifts across the whole wavefront (DPP wave_shr:1 / wave_shl:1); the
 // lane shifted in receives 0.
@@ -743,6 +754,10 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
       else dj[k] = 0.0f;
       if constexpr (CNT) nj[k] = S.cnt[sn][ln];
     }
+    // Contributions of the final inputs (zero for the others), summed
+    // pairwise in a fixed order: shorter dependency chains than a running
+    // sum, and the same result whichever resolve finishes the cell.
+    V cj[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       if (k == 3 || k == 4) continue;
@@ -753,13 +768,18 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
         ok = false;
         miss |= 1u << k;
       }
-      if (input && fin) {
-        if constexpr (VK != VK_NONE) {
-          if constexpr (RK == RK_MULTI) vadd(acc, vmulc(vj[k], fj[k], dj[k]));
-          else vadd(acc, vj[k]);
-        }
-        if constexpr (CNT) accn += nj[k];
-      }
+      const bool take = input && fin;
+      if constexpr (VK != VK_NONE) cj[k] = vsel(take, contrib<RK>(vj[k], fj[k], dj[k]));
+      if constexpr (CNT) accn += take ? nj[k] : 0;
+    }
+    if constexpr (VK != VK_NONE) {
+      V s0 = cj[0], s1 = cj[2], s2 = cj[6];
+      vadd(s0, cj[1]);
+      vadd(s1, cj[5]);
+      vadd(s2, cj[7]);
+      vadd(s0, s1);
+      vadd(s0, s2);
+      vadd(acc, s0);
     }
     // Same-row inputs, iterated along the row with lane shifts.
     const uint32_t sl = S.st[sb][li - 1], sr = S.st[sb][li + 1];
@@ -814,13 +834,11 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
         V w = acc;
         uint64_t wn = accn;
         if (in_l) {
-          if constexpr (RK == RK_MULTI) vadd(w, vmulc(vl, fl, dfl));
-          else vadd(w, vl);
+          vadd(w, contrib<RK>(vl, fl, dfl));
           wn += nl;
         }
         if (in_r) {
-          if constexpr (RK == RK_MULTI) vadd(w, vmulc(vr, fr_, dfr));
-          else vadd(w, vr);
+          vadd(w, contrib<RK>(vr, fr_, dfr));
           wn += nrr;
         }
         cv = w;
