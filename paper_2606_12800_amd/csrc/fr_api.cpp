@@ -324,6 +324,7 @@ int run_ws(const EngineConfig& cfg, WsParams P, int32_t* status, hipStream_t s) 
   const bool flows_up = h[1] >= h[2];
   int dir = ((cfg.dir == DIR_FWD) == flows_up) ? -1 : 1;
   int64_t remaining = P.nrows * P.ncols;
+  uint32_t last_fin[2] = {0, 0};  // cells finished by the last pass going up (dir -1) / down (dir +1)
   // FLOWROUTE_WS_MAXPASS (diagnostics): stop after that many passes and
   // leave unfinished cells as they are.
   const char* mp = getenv("FLOWROUTE_WS_MAXPASS");
@@ -374,7 +375,13 @@ int run_ws(const EngineConfig& cfg, WsParams P, int32_t* status, hipStream_t s) 
       if (status && launch_set_status(status, FR_ERR_NOTDAG, s) != hipSuccess) return FR_ERR_HIP;
       break;
     }
-    dir = -dir;
+    // Either direction finishes the highest unfinished cell, so the next
+    // pass may go either way: after one pass each way, repeat the direction
+    // whose last pass finished more (terrain that drains mostly one way
+    // leaves cells that the reverse sweep barely touches).
+    last_fin[dir > 0] = fin;
+    if (pass == 0 || last_fin[0] == last_fin[1]) dir = -dir;
+    else dir = last_fin[1] > last_fin[0] ? 1 : -1;
   }
   return FR_OK;
 }

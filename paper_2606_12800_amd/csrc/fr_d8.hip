@@ -123,7 +123,7 @@ enum RainKind { RAIN_UNIT = 0, RAIN_F32 = 1, RAIN_F64 = 2 };
 // it replaced after arrival) into a ring of registers indexed by the
 // unrolled step, so the wait for a row's data never waits for the rows
 // behind it.
-constexpr int PF = 8;
+constexpr int PF_ROWS = 8;
 
 // One grid row as seen by a lane: the W codes of its columns packed in a
 // dword (byte j = column 4*lane + j of the tile) and the codes just left and
@@ -316,6 +316,9 @@ template <bool UP, int VK, bool CNT, int RAIN, bool VEC, bool BORDER>
 __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* mass, bool* nonfinite) {
   using CT = typename std::conditional<UP, uint32_t, uint64_t>::type;
   using V = Val<CT>;
+  // Rows in flight: fewer in phase A, whose kernel must stay within 128
+  // VGPRs for four wavefronts per SIMD.
+  constexpr int PF = UP ? 6 : PF_ROWS;
   const int lane = threadIdx.x;
   const int k0 = W * lane;  // first tile column of this lane
   const int c = T.c0 + k0;
@@ -518,13 +521,13 @@ __device__ __forceinline__ void root_sweep(const D8Params& P, const Tile& T, boo
 #pragma unroll
   for (int j = 0; j < W; ++j) rp[j] = NONE;
   bool bad = false;
-  // Slot i holds, for step s = i (mod PF), the codes of row r0 + s + 1.
-  CodeIn cq[PF];
+  // Slot i holds, for step s = i (mod PF_ROWS), the codes of row r0 + s + 1.
+  CodeIn cq[PF_ROWS];
 #pragma unroll
-  for (int i = 0; i < PF; ++i) cq[i] = load_codes<VEC>(P, T, T.r0 + i + 1, lane);
-  for (int s0 = 0; s0 < T.th; s0 += PF) {
+  for (int i = 0; i < PF_ROWS; ++i) cq[i] = load_codes<VEC>(P, T, T.r0 + i + 1, lane);
+  for (int s0 = 0; s0 < T.th; s0 += PF_ROWS) {
 #pragma unroll
-    for (int i = 0; i < PF; ++i) {
+    for (int i = 0; i < PF_ROWS; ++i) {
       const int s = s0 + i;
       const int r = T.r0 + s;
       if (s < T.th) {  // uniform
@@ -560,26 +563,30 @@ __device__ __forceinline__ void root_sweep(const D8Params& P, const Tile& T, boo
         below = here;
         here = above;
       }
-      cq[i] = load_codes<VEC>(P, T, r + PF + 1, lane);
+      cq[i] = load_codes<VEC>(P, T, r + PF_ROWS + 1, lane);
     }
   }
   if (bad) *badcode = true;
 }
 
 // ---------------------------------------------------------------------------
-// Phase A.
+// Phase A, as two independent kernels: the root sweep needs few registers
+// and runs at high occupancy; the local sweep carries the values.
+template <bool VEC>
+__global__ __launch_bounds__(64) void k_d8_root(D8Params P) {
+  const Tile T = tile_of(P, blockIdx.x);
+  bool badcode = false;
+  if (T.border) root_sweep<VEC, true>(P, T, &badcode);
+  else root_sweep<VEC, false>(P, T, &badcode);
+  if (badcode) set_status(P.status, FR_ERR_BADCODE);
+}
+
 template <int VK, bool CNT, int RAIN, bool VEC>
 __global__ __launch_bounds__(64) void k_d8_up(D8Params P) {
   const Tile T = tile_of(P, blockIdx.x);
-  bool badcode = false, nonfinite = false;
-  if (T.border) {
-    root_sweep<VEC, true>(P, T, &badcode);
-    sweep<true, VK, CNT, RAIN, VEC, true>(P, T, nullptr, &nonfinite);
-  } else {
-    root_sweep<VEC, false>(P, T, &badcode);
-    sweep<true, VK, CNT, RAIN, VEC, false>(P, T, nullptr, &nonfinite);
-  }
-  if (badcode) set_status(P.status, FR_ERR_BADCODE);
+  bool nonfinite = false;
+  if (T.border) sweep<true, VK, CNT, RAIN, VEC, true>(P, T, nullptr, &nonfinite);
+  else sweep<true, VK, CNT, RAIN, VEC, false>(P, T, nullptr, &nonfinite);
   if (nonfinite) set_status(P.status, FR_ERR_NONFINITE);
 }
 
@@ -759,6 +766,9 @@ void d8_sweep_dispatch(ValKind vk, bool cnt, const D8Params& P, hipStream_t s) {
 }
 
 hipError_t launch_d8_up(ValKind vk, bool cnt, const D8Params& P, hipStream_t s) {
+  const dim3 g((unsigned)((int64_t)P.ntr * P.ntc)), b(64);
+  if ((P.ncols % 4) == 0) hipLaunchKernelGGL(k_d8_root<true>, g, b, 0, s, P);
+  else hipLaunchKernelGGL(k_d8_root<false>, g, b, 0, s, P);
   d8_sweep_dispatch<UpK>(vk, cnt, P, s);
   return hipGetLastError();
 }

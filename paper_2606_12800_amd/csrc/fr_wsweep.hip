@@ -63,6 +63,9 @@ constexpr int LEAD_SPIN = 1 << 14;  // polls before a neighbour counts as absent
 // EDGE_WAIT_MAX_TICKS in all.
 constexpr uint64_t EDGE_STALL_TICKS = 2000;
 constexpr uint64_t EDGE_WAIT_MAX_TICKS = 200000;
+// Waits a strip may start before it must see some of them succeed (each
+// failed wait costs 4, each successful one returns 1).
+constexpr int WAIT_CREDIT = 16;
 // Side cells delivered by the I/O wavefront are taken every ARRIVE_EVERY
 // steps: edge lanes are ghost columns, so their cells may lag a few rows,
 // and taking several deliveries at once retries each affected row once.
@@ -952,7 +955,20 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
     return __ballot(need) != 0;
   };
 
+  // Whether edge cells of row f still wait for side cells.
+  auto edge_missing = [&](int f) -> bool {
+    const int sf = slot(f);
+    const uint32_t m = S.miss[sf][li] & (lane == 0 ? 0x29u : 0x94u);
+    return __ballot(has_side && !(S.st[sf][li] & S_DONE) && m != 0) != 0;
+  };
+
+  // Waiting pays off where the neighbour is about to deliver; where its
+  // side cells cannot finish in this pass (terrain draining against the
+  // sweep) the wait only holds everyone back.  A strip stops waiting once
+  // its waits keep ending without the side cells.
+  int wait_credit = WAIT_CREDIT;
   auto wait_edges = [&](int f, int lo, int t) {
+    if (wait_credit <= 0) return;
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     uint64_t t_last = t0;
     int seen0 = lds_ld(&S.nbp[0]), seen1 = lds_ld(&S.nbp[1]);
@@ -975,6 +991,8 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
         __builtin_amdgcn_s_sleep(1);
       }
     }
+    if (edge_missing(f)) wait_credit -= 4;
+    else if (wait_credit < WAIT_CREDIT) ++wait_credit;
   };
 
   // Writes a row leaving the window to HBM; in the first pass unfinished
@@ -1351,6 +1369,7 @@ __global__ __launch_bounds__(128) void k_batch(BatchParams B) {
     const int64_t ncell = T.nrows * T.ncols;
     int64_t done = 0;
     bool complete = false;
+    uint32_t fin_up = 0, fin_dn = 0;  // cells finished by the last pass each way
     for (int pass = 0; pass < BATCH_MAXPASS; ++pass) {
       WsParams P{};
       P.nrows = T.nrows;
@@ -1387,7 +1406,12 @@ __global__ __launch_bounds__(128) void k_batch(BatchParams B) {
         break;
       }
       if (fin == 0) break;
-      dir = -dir;
+      // After one pass each way, repeat the direction whose last pass
+      // finished more (either direction finishes the highest unfinished cell).
+      if (dir > 0) fin_dn = fin;
+      else fin_up = fin;
+      if (pass == 0 || fin_up == fin_dn) dir = -dir;
+      else dir = fin_dn > fin_up ? 1 : -1;
     }
     // A pass that finished nothing, or too many passes: a cycle (or a tile
     // the sweep cannot finish, reported the same way).
