@@ -34,7 +34,17 @@ ACC_BYTES = 1 + 4 + 4 + 8     # whole accumulate call: code, rain in; q, counts 
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE runs calibrated against a 1 GiB
 # device copy (profiles/d8_43360_hbm_traffic.md).  They describe the kernels
 # as they were when counted; other sizes report null.
-MEASURED_TRAFFIC = {43360: {"receivers": 10.63e9, "d8_up": 11.86e9, "d8_down": 33.35e9}}
+MEASURED_TRAFFIC = {
+    ("d8", 43360, 43360): {"receivers": 10.63e9, "d8_up": 11.86e9, "d8_down": 33.35e9},
+    ("mfd", 16384, 16384): {"sweep": 9.77e9},       # float32 sweep (profiles/sweep_and_batch_hbm_traffic.md)
+    ("adjoint", 4096, 4096): {"sweep": 0.702e9},
+    ("batched", 512): {"batch": 24.87e9},
+}
+# Algorithmic bytes per cell of the secondary workloads' dominant kernel
+# (arrays visible at the C ABI, each touched once): MFD float32 sweep z 4 +
+# mask 1 + q 4; adjoint z 4 + mask 1 + qbar 4 + rbar 4; batched D8 tiles z 4 +
+# counts 8, MFD tiles z 4 + q 4 (codes stay in the batch workspace).
+SWEEP_BYTES = {"mfd": 4 + 1 + 4, "adjoint": 4 + 1 + 4 + 4}
 
 
 def log(msg):
@@ -63,6 +73,34 @@ def cpu_baseline(size: int, seed: int):
         "sample": (f"D8 {size}x{size} DEM seed {seed} (same generator): receivers {t1 - t0:.2f}s, "
                    f"high-to-low sort {t2 - t1:.2f}s, push q+counts {t3 - t2:.2f}s, mass {t4 - t3:.2f}s; "
                    f"host nproc={os.cpu_count()}"),
+    }
+
+
+def cpu_baseline_mfd(size: int, seed: int, adjoint: bool):
+    """The oracle, single-threaded, on a size x size MFD sample of the same
+    generator: high-to-low order, then the push (or the transpose sweep for
+    the adjoint) with fractions computed from z as it goes."""
+    import numpy as np
+    import oracle
+    import synth
+    z = synth.dem(seed, size, size)
+    t0 = t1 = time.perf_counter()
+    order = oracle.order(z)
+    t2 = time.perf_counter()
+    if adjoint:
+        qbar = np.zeros(size * size)
+        cells = synth.distinct_cells(6, synth.STREAM_PICK, 64, size * size)
+        qbar[cells] = synth.normal(6, synth.STREAM_NORMAL, 64)
+        oracle.adjoint_mfd(z, qbar.reshape(size, size), 1.1, order)
+    else:
+        oracle.accumulate_mfd(z, None, 1.1, order)
+    t3 = time.perf_counter()
+    n = size * size
+    what = "transpose sweep" if adjoint else "push"
+    return {
+        "value": n / (t3 - t0), "unit": "cells/s", "cores": 1, "kind": "oracle",
+        "sample": (f"MFD {size}x{size} DEM seed {seed} (same generator): high-to-low sort {t2 - t1:.2f}s, "
+                   f"{what} with fractions {t3 - t2:.2f}s; host nproc={os.cpu_count()}"),
     }
 
 
@@ -132,6 +170,22 @@ def run_secondary(args, workload):
                    "cells": n * n},
         "detail": out,
     }
+    # The sweep is bound by the latency of its row steps, not by HBM; the
+    # roofline below states how far from the HBM bound that leaves it.
+    ms = out["f32"]["phase_ms"].get("sweep", out["f32"]["ms_per_step"])
+    achieved = SWEEP_BYTES[workload] * n * n / (ms * 1e-3) / 1e9
+    line["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS,
+                        "traffic": MEASURED_TRAFFIC.get((workload, n, n), {}).get("sweep"),
+                        "kernel": "k_ws_pass", "bytes_per_cell": SWEEP_BYTES[workload], "ms_per_launch": ms,
+                        "row_step_us": 1e3 * ms / n}
+    if not args.no_cpu_baseline:
+        # MFD: an 8192^2 sample (~15 s on one core); adjoint: the whole 4096^2 workload.
+        size = args.cpu_size if "--cpu-size" in sys.argv else (8192 if workload == "mfd" else n)
+        log(f"cpu baseline: oracle on {size}^2 ...")
+        del z, code
+        torch.cuda.empty_cache()
+        line["cpu_baseline"] = cpu_baseline_mfd(size, seed, workload == "adjoint")
     print(json.dumps(line), flush=True)
 
 
@@ -161,19 +215,71 @@ def run_batched(args):
     log(f"  workspace {b.ws_bytes / 2**30:.2f} GiB; autotuning ...")
     plan = b.autotune(reps=1)
     log(f"  plan: workers {plan.workers} order {plan.order}")
+    b.run(plan=plan)
+    # One batched route captured in a HIP graph (the call allocates nothing,
+    # clears its counters with kernels and never synchronises with the host);
+    # the timed steps are replays of that graph.
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(cap):
+        b.run(check=False, plan=plan)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=cap):
+            b.run(check=False, plan=plan)
+    torch.cuda.current_stream().wait_stream(cap)
     for _ in range(args.warmup):
-        b.run()
+        graph.replay()
     torch.cuda.synchronize()
+    fr._raise_status(b.status, "batched route (graph)")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    ev0.record()
     for _ in range(args.steps):
-        b.run(check=False)
+        graph.replay()
+    ev1.record()
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / args.steps
+    gpu_ms = ev0.elapsed_time(ev1) / args.steps
     fr._raise_status(b.status, "batched route")
-    log(f"  batched float32: {1e3 * t_batch:.2f} ms per batch")
+    log(f"  batched float32 (graph replay): {1e3 * t_batch:.2f} ms per batch, {gpu_ms:.2f} ms on the GPU")
+    # Algorithmic bytes: D8 tiles z + counts, MFD tiles z + q.
+    alg = sum(a * b_ * (4 + 8 if i % 2 == 0 else 4 + 4) for i, (a, b_) in enumerate(shapes))
     # Per-tile float64 launches on the same stream (receivers + accumulate).
-    del b
+    del b, graph
     torch.cuda.empty_cache()
+    if args.no_per_tile:
+        t_tile = float("nan")
+    else:
+        t_tile = per_tile_f64(args, shapes, tiles)
+
+    line = {
+        "metric": "cells routed/sec (D8 & MFD) at 1 MI355X; % HBM peak; batched vs per-tile",
+        "value": ncell / t_batch, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t_batch, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched: {ntiles} tiles, sides U[64,2048] (seed 4), even D8 uint64 counts, "
+                               f"odd MFD float32, unit rain", "cells": ncell},
+        "roofline": {"bound": "hbm", "achieved": alg / (gpu_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": alg / (gpu_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": MEASURED_TRAFFIC.get(("batched", ntiles), {}).get("batch"),
+                     "kernel": "k_batch", "bytes": alg, "ms_per_launch": gpu_ms},
+        "detail": {"plan": {"workers": plan.workers, "order": plan.order}, "timing": "HIP graph replay",
+                   "per_tile_f64_ms": None if t_tile != t_tile else 1e3 * t_tile,
+                   "per_tile_f64_cells_per_s": None if t_tile != t_tile else ncell / t_tile,
+                   "batched_over_per_tile": None if t_tile != t_tile else t_tile / t_batch},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_tiles(shapes)
+    print(json.dumps(line), flush=True)
+
+
+def per_tile_f64(args, shapes, tiles):
+    """Seconds for routing the batch's tiles one by one in float64 (one
+    fr_receivers + fr_accumulate per tile, on the same stream)."""
+    import torch
+    import paper_2606_12800_amd as fr
+    dev = torch.device("cuda:0")
     big = max(a * b_ for a, b_ in shapes)
     q64 = torch.empty(big, dtype=torch.float64, device=dev)
     code = torch.empty(big, dtype=torch.uint8, device=dev)
@@ -200,18 +306,32 @@ def run_batched(args):
     t_tile = time.perf_counter() - t0
     fr._raise_status(status, "per-tile route")
     log(f"  per-tile float64: {1e3 * t_tile:.2f} ms for the batch")
-    line = {
-        "metric": "cells routed/sec (D8 & MFD) at 1 MI355X; % HBM peak; batched vs per-tile",
-        "value": ncell / t_batch, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * t_batch, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"batched: {ntiles} tiles, sides U[64,2048] (seed 4), even D8 uint64 counts, "
-                               f"odd MFD float32, unit rain", "cells": ncell},
-        "detail": {"plan": {"workers": plan.workers, "order": plan.order},
-                   "per_tile_f64_ms": 1e3 * t_tile, "per_tile_f64_cells_per_s": ncell / t_tile,
-                   "batched_over_per_tile": t_tile / t_batch},
-    }
-    print(json.dumps(line), flush=True)
+    return t_tile
+
+
+def cpu_baseline_tiles(shapes, budget_s: float = 15.0):
+    """The oracle, single-threaded, on the batch's tiles in order (same
+    seeds and rules) until about budget_s of CPU work."""
+    import oracle
+    import synth
+    cells, spent, k = 0, 0.0, 0
+    for i, (nr, nc) in enumerate(shapes):
+        z = synth.dem(1000 + i, nr, nc)
+        t0 = time.perf_counter()
+        order = oracle.order(z)
+        if i % 2 == 0:
+            code = oracle.receivers(z)
+            oracle.accumulate_single(code, None, order, q=False, counts=True)
+        else:
+            oracle.accumulate_mfd(z, None, 1.1, order)
+        spent += time.perf_counter() - t0
+        cells += nr * nc
+        k += 1
+        if spent >= budget_s:
+            break
+    return {"value": cells / spent, "unit": "cells/s", "cores": 1, "kind": "oracle",
+            "sample": (f"the first {k} of the batch's tiles ({cells / 1e6:.1f} Mcells; even D8 counts, odd "
+                       f"MFD float64): high-to-low sort + push, {spent:.1f}s; host nproc={os.cpu_count()}")}
 
 
 def main():
@@ -223,9 +343,12 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--size", type=int, default=43360, help="grid side (default: 1.88e9-cell DEM)")
+    ap.add_argument("--rows", type=int, default=0, help="D8: grid rows (with --cols; default: --size)")
+    ap.add_argument("--cols", type=int, default=0, help="D8: grid columns (e.g. the paper's 57345 x 32769)")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--cpu-size", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-tile", action="store_true", help="batched: skip the per-tile float64 comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, run one 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -250,24 +373,25 @@ def main():
 
     lib = fr.load_library()
     dev = torch.device("cuda:0")
-    n = args.size
-    ncell = n * n
+    nr = args.rows or args.size
+    nc = args.cols or args.size
+    ncell = nr * nc
 
-    log(f"generating {n}x{n} DEM (seed {args.seed}) ...")
+    log(f"generating {nr}x{nc} DEM (seed {args.seed}) ...")
     t0 = time.perf_counter()
-    z_h = synth.dem(args.seed, n, n)
-    rain_h = synth.rain(args.seed, n, n)
+    z_h = synth.dem(args.seed, nr, nc)
+    rain_h = synth.rain(args.seed, nr, nc)
     log(f"  generated in {time.perf_counter() - t0:.1f}s; copying to HBM")
     z = torch.from_numpy(z_h).to(dev)
     del z_h
     rain = torch.from_numpy(rain_h).to(dev)
     del rain_h
-    code = torch.empty((n, n), dtype=torch.uint8, device=dev)
-    q = torch.empty((n, n), dtype=torch.float32, device=dev)
-    cnt = torch.empty((n, n), dtype=torch.uint64, device=dev)
+    code = torch.empty((nr, nc), dtype=torch.uint8, device=dev)
+    q = torch.empty((nr, nc), dtype=torch.float32, device=dev)
+    cnt = torch.empty((nr, nc), dtype=torch.uint64, device=dev)
     mass = torch.empty(2, dtype=torch.float64, device=dev)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
-    wsb = fr.workspace_bytes(fr.FN_ACCUMULATE, n, n, fr.D8, fr.F32)
+    wsb = fr.workspace_bytes(fr.FN_ACCUMULATE, nr, nc, fr.D8, fr.F32)
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream(dev)
     sp = ctypes.c_void_p(stream.cuda_stream)
@@ -281,12 +405,12 @@ def main():
 
     def step(record: bool):
         ev[0].record(stream)
-        rc = lib.fr_receivers(P(z), n, n, fr.D8, P(code), P(status), sp)
+        rc = lib.fr_receivers(P(z), nr, nc, fr.D8, P(code), P(status), sp)
         ev[1].record(stream)
         if rc != 0:
             raise fr.FlowRouteError(rc, "fr_receivers")
         ph = fr.timing_last() if record else {}
-        rc = lib.fr_accumulate(None, P(code), n, n, fr.D8, 1.1, P(rain), fr.F32, fr.F32, P(q), P(cnt),
+        rc = lib.fr_accumulate(None, P(code), nr, nc, fr.D8, 1.1, P(rain), fr.F32, fr.F32, P(q), P(cnt),
                                P(mass), P(status), P(ws), wsb, sp)
         ev[2].record(stream)
         if rc != 0:
@@ -348,10 +472,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"D8 {n}x{n} fractal DEM (seed {args.seed}), f32 rain + u64 counts",
+        "config": {"workload": f"D8 {nr}x{nc} fractal DEM (seed {args.seed}), f32 rain + u64 counts",
                    "cells": ncell},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get(n, {}).get(dom),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get(("d8", nr, nc), {}).get(dom),
                      "kernel": PHASE_KERNEL[dom], "bytes_per_cell": PHASE_BYTES[dom],
                      "ms_per_launch": single[dom]},
         "detail": {"receivers_ms": recv_avg, "accumulate_ms": acc_avg,
