@@ -137,8 +137,9 @@ struct Row {
 
 // Raw codes of one row for one lane, as loaded.
 struct CodeIn {
-  uint32_t w;     // own codes
+  uint32_t w;     // own codes (unaligned rows: the first code only)
   uint32_t side;  // lane 0: the column left of the tile; lane 63: right of it
+  uint32_t b[W - 1];  // unaligned rows: codes 1..3, combined only when used
 };
 
 template <bool VEC>
@@ -150,10 +151,9 @@ __device__ __forceinline__ CodeIn load_codes(const D8Params& P, const Tile& T, i
   if (VEC) {
     x.w = *reinterpret_cast<const uint32_t*>(row + min(c, nc - W));
   } else {
-    uint32_t w = 0;
+    x.w = row[min(c, nc - 1)];
 #pragma unroll
-    for (int j = 0; j < W; ++j) w |= (uint32_t)row[min(c + j, nc - 1)] << (8 * j);
-    x.w = w;
+    for (int j = 1; j < W; ++j) x.b[j - 1] = row[min(c + j, nc - 1)];
   }
   const int sc = lane == 0 ? T.c0 - 1 : (lane == 63 ? T.c0 + TW : c);
   x.side = row[min(max(sc, 0), nc - 1)];
@@ -162,9 +162,10 @@ __device__ __forceinline__ CodeIn load_codes(const D8Params& P, const Tile& T, i
 
 // The row at grid row r from its loaded codes.  A tile away from the grid
 // border only ever touches rows and columns inside the grid.
-template <bool BORDER>
+template <bool BORDER, bool VEC>
 __device__ __forceinline__ Row expand_row(const CodeIn& x, const D8Params& P, const Tile& T, int r, int lane) {
   uint32_t w = x.w, side = x.side;
+  if (!VEC) w |= (x.b[0] << 8) | (x.b[1] << 16) | (x.b[2] << 24);
   if (BORDER) {
     const int nr = (int)P.nrows, nc = (int)P.ncols;
     const int c = T.c0 + W * lane;
@@ -313,12 +314,13 @@ __device__ __forceinline__ void acc_ff(float& s, float& e, bool cond, float xh, 
 //                   one tile fit in 32 bits).
 //   DOWN (phase C): write the final water / counts and the mass balance.
 template <bool UP, int VK, bool CNT, int RAIN, bool VEC, bool BORDER>
-__device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* mass, bool* nonfinite) {
+__device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* mass, bool* nonfinite,
+                                      float* xq32 = nullptr, double* xq64 = nullptr, uint64_t* xcnt = nullptr) {
   using CT = typename std::conditional<UP, uint32_t, uint64_t>::type;
   using V = Val<CT>;
   // Rows in flight: fewer in phase A, whose kernel must stay within 128
   // VGPRs for four wavefronts per SIMD.
-  constexpr int PF = UP ? 6 : PF_ROWS;
+  constexpr int PF = !VEC ? 4 : (UP ? 6 : PF_ROWS);
   const int lane = threadIdx.x;
   const int k0 = W * lane;  // first tile column of this lane
   const int c = T.c0 + k0;
@@ -331,8 +333,8 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
   V pv[W];
 #pragma unroll
   for (int j = 0; j < W; ++j) pv[j] = V{};
-  Row above = expand_row<BORDER>(load_codes<VEC>(P, T, rtop + 1, lane), P, T, rtop + 1, lane);
-  Row here = expand_row<BORDER>(load_codes<VEC>(P, T, rtop, lane), P, T, rtop, lane);
+  Row above = expand_row<BORDER, VEC>(load_codes<VEC>(P, T, rtop + 1, lane), P, T, rtop + 1, lane);
+  Row here = expand_row<BORDER, VEC>(load_codes<VEC>(P, T, rtop, lane), P, T, rtop, lane);
   // Slot i of the ring holds, for step s = i (mod PF): the codes of row
   // rtop - s - 1 (the row below) and the rain of row rtop - s.
   CodeIn cq[PF];
@@ -348,7 +350,7 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
       const int s = s0 + i;
       const int r = rtop - s;
       if (s < T.th) {  // uniform
-        const Row below = expand_row<BORDER>(cq[i], P, T, r - 1, lane);
+        const Row below = expand_row<BORDER, VEC>(cq[i], P, T, r - 1, lane);
         const size_t g = (size_t)r * (size_t)nc + (size_t)c;
         const bool top = s == 0;
         const bool bottom = r == T.r0;
@@ -468,15 +470,29 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
               *reinterpret_cast<ulonglong2*>(P.cnt + g) = a;
               *reinterpret_cast<ulonglong2*>(P.cnt + g + 2) = b;
             }
-          } else {
+          }
+        }
+        if (!UP && !VEC) {
+          // Rows not aligned to 4 cells: exchange the row through LDS so
+          // that each store instruction writes 64 consecutive cells.
+          const size_t g0 = (size_t)r * (size_t)nc + (size_t)T.c0;
 #pragma unroll
-            for (int j = 0; j < W; ++j) {
-              if (c + j >= nc) continue;
-              if (VK == VK_FF) P.q32[g + j] = nv[j].f.hi + nv[j].f.lo;
-              if (VK == VK_F64) P.q64[g + j] = nv[j].d;
-              if (CNT) P.cnt[g + j] = nv[j].n;
+          for (int j = 0; j < W; ++j) {
+            if (VK == VK_FF) xq32[k0 + j] = nv[j].f.hi + nv[j].f.lo;
+            if (VK == VK_F64) xq64[k0 + j] = nv[j].d;
+            if (CNT) xcnt[k0 + j] = nv[j].n;
+          }
+          __syncthreads();
+#pragma unroll
+          for (int j = 0; j < W; ++j) {
+            const int kk = 64 * j + lane;
+            if (!BORDER || T.c0 + kk < nc) {
+              if (VK == VK_FF) P.q32[g0 + kk] = xq32[kk];
+              if (VK == VK_F64) P.q64[g0 + kk] = xq64[kk];
+              if (CNT) P.cnt[g0 + kk] = xcnt[kk];
             }
           }
+          __syncthreads();
         }
         if (!UP && VK != VK_NONE) {
 #pragma unroll
@@ -515,8 +531,8 @@ __device__ __forceinline__ void root_sweep(const D8Params& P, const Tile& T, boo
   const int k0 = W * lane;
   const int nc = (int)P.ncols;
   const int tw = BORDER ? T.tw : TW;
-  Row below = expand_row<BORDER>(load_codes<VEC>(P, T, T.r0 - 1, lane), P, T, T.r0 - 1, lane);
-  Row here = expand_row<BORDER>(load_codes<VEC>(P, T, T.r0, lane), P, T, T.r0, lane);
+  Row below = expand_row<BORDER, VEC>(load_codes<VEC>(P, T, T.r0 - 1, lane), P, T, T.r0 - 1, lane);
+  Row here = expand_row<BORDER, VEC>(load_codes<VEC>(P, T, T.r0, lane), P, T, T.r0, lane);
   uint32_t rp[W];  // roots of the row below
 #pragma unroll
   for (int j = 0; j < W; ++j) rp[j] = NONE;
@@ -531,7 +547,7 @@ __device__ __forceinline__ void root_sweep(const D8Params& P, const Tile& T, boo
       const int s = s0 + i;
       const int r = T.r0 + s;
       if (s < T.th) {  // uniform
-        const Row above = expand_row<BORDER>(cq[i], P, T, r + 1, lane);
+        const Row above = expand_row<BORDER, VEC>(cq[i], P, T, r + 1, lane);
         const bool top = s == T.th - 1;
         const bool bottom = s == 0;
         const bool rare = rare_donors(here, below);
@@ -676,12 +692,16 @@ __global__ __launch_bounds__(256) void k_d8_scatter(D8Params P, uint32_t n, int 
 template <int VK, bool CNT, int RAIN, bool VEC>
 __global__ __launch_bounds__(64) void k_d8_down(D8Params P) {
   __shared__ double s_mass[2][64];
+  // Row exchange for grids whose rows are not aligned to 4 cells.
+  __shared__ float s_q32[VEC || VK != VK_FF ? 1 : TW];
+  __shared__ double s_q64[VEC || VK != VK_F64 ? 1 : TW];
+  __shared__ uint64_t s_cnt[VEC || !CNT ? 1 : TW];
   const int lane = threadIdx.x;
   const Tile T = tile_of(P, blockIdx.x);
   double m[2] = {0.0, 0.0};
   bool nonfinite = false;
-  if (T.border) sweep<false, VK, CNT, RAIN, VEC, true>(P, T, m, &nonfinite);
-  else sweep<false, VK, CNT, RAIN, VEC, false>(P, T, m, &nonfinite);
+  if (T.border) sweep<false, VK, CNT, RAIN, VEC, true>(P, T, m, &nonfinite, s_q32, s_q64, s_cnt);
+  else sweep<false, VK, CNT, RAIN, VEC, false>(P, T, m, &nonfinite, s_q32, s_q64, s_cnt);
   if (P.mass_part) {
     s_mass[0][lane] = m[0];
     s_mass[1][lane] = m[1];
