@@ -17,6 +17,9 @@ routing and drainage area determination"):
                           run low-to-high (from eq. linear-system)
 * ``apply_A_*``        -- matrix-free A x (Section 3.1, Appendix A)
 * ``mass_*``           -- sink outflow versus total rain (Section 4)
+* ``block_richardson`` -- the paper's parallel scheme run sequentially: block
+                          Richardson iterations on (I+X) and (I-X)(I+X)
+                          (Section 3.3, Appendix B)
 
 Pins: every function here is checked in ``tests/test_oracle_pins.py`` against
 things other than itself (the paper's 3x3 example, brute force, library
@@ -75,6 +78,7 @@ def _load():
             "or_apply_A_mfd": [vp, i64, i64, dbl, vp, vp],
             "or_mass_single": [vp, i64, vp, vp, vp],
             "or_mass_mfd": [vp, i64, i64, vp, vp, vp],
+            "or_block_richardson": [vp, vp, i64, i64, dbl, vp, vp, i64, i64, ci, ci, vp, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -151,6 +155,28 @@ def accumulate_mfd(z, rain=None, p: float = 1.1, order_=None, frac32: bool = Fal
     _check(_load().or_accumulate_mfd(_p(z), nr, nc, p, int(frac32), _p(order_), _p(r), _p(q)),
            "accumulate_mfd")
     return q
+
+
+def block_richardson(z, block, rule: int = D8, rain=None, scheme: int = 0, p: float = 1.1,
+                     max_iter: int = 100000, order_=None):
+    """The paper's parallel scheme run sequentially (Section 3.3 "I+X"
+    (scheme 0) and "(I-X)(I+X)" (scheme 1) iterations; Appendix B): blocks of
+    block = (rows, cols) cells, per-block high-to-low solves, water passed
+    across block boundaries between iterations.  Returns (q float64,
+    counts uint64 (None for MFD), iterations until the iterate is exact)."""
+    z = _f32(z)
+    nr, nc = z.shape
+    if order_ is None:
+        order_ = order(z)
+    code = receivers(z, rule) if rule != MFD else None
+    r = None if rain is None else _f32(rain)
+    q = np.empty((nr, nc), dtype=np.float64)
+    co = np.empty((nr, nc), dtype=np.uint64) if code is not None else None
+    it = ctypes.c_int(0)
+    _check(_load().or_block_richardson(_p(code), _p(z), nr, nc, p, _p(order_), _p(r), int(block[0]),
+                                       int(block[1]), int(scheme), int(max_iter), _p(q), _p(co),
+                                       ctypes.addressof(it)), "block_richardson")
+    return q, co, it.value
 
 
 def adjoint_single(code, qbar, order_=None, z=None) -> np.ndarray:

@@ -332,3 +332,173 @@ int or_mass_mfd(const float* z, int64_t nr, int64_t nc, const float* rain, const
   out[1] = t;
   return 0;
 }
+
+/* ---------------------------------------------------------------------------
+ * The paper's parallel scheme on one machine: block Richardson iteration
+ * (Section 3.3 "I+X" and "(I-X)(I+X)" schemes; Appendix B iteration).
+ *
+ * The grid is split into blocks of br x bc cells, the paper's per-process
+ * subdomains.  D is the part of A = I - W^T that couples cells of one block;
+ * the routing pairs that cross a block boundary form the transfer rho (the
+ * water a cell passes to a receiver in another block), so A = D - rho and
+ * X = D^{-1} R with R = -rho.  Applying D^{-1} is the per-block high-to-low
+ * push (the global order restricted to pairs inside a block); applying rho
+ * moves each cell's current water across the boundary to its receiver.
+ *
+ *   scheme 0 (I+X):        w <- D^{-1} (r + rho w)        (Appendix B form)
+ *   scheme 1 ((I-X)(I+X)): w <- w + (I - X) (D^{-1} r - (I + X) w)
+ *
+ * from w = 0, alongside the same iteration on integers (see below).  *iters is the first iteration count l >= 1 whose iterate
+ * equals the next one, i.e. the number of iterations after which the
+ * solution is exact.  The error of scheme 0 is multiplied by -X each
+ * iteration and that of scheme 1 by X^2; X^(C+1) = 0 when flow paths cross
+ * block boundaries at most C times, so scheme 0 needs C+1 iterations (the
+ * paper's claim) and scheme 1 ceil((C+1)/2).  code != NULL: single receiver
+ * (D8/D4 codes); code == NULL: MFD fractions from z with exponent p.
+ * q (float64) and counts (exact, unit rain; single receivers only)
+ * receive the final iterate; either may be NULL.  Returns 0, -2 on bad arguments, -3 when max_iter
+ * iterations do not converge.
+ */
+static int pairs_of(const uint8_t* code, const float* z, int64_t nr, int64_t nc, double p, int64_t i,
+                    int64_t nb[8], double f[8]) {
+  if (code) {
+    const int64_t k = code_target(nc, i, code[i]);
+    if (k < 0) return 0;
+    nb[0] = k;
+    f[0] = 1.0;
+    return 1;
+  }
+  return mfd_split(z, nr, nc, i / nc, i % nc, p, 0, nb, f);
+}
+
+static int64_t block_of(int64_t nc, int64_t br, int64_t bc, int64_t i) {
+  const int64_t nbc = (nc + bc - 1) / bc;
+  return (i / nc / br) * nbc + (i % nc) / bc;
+}
+
+/* y = rho x (inside == 0) or y = D^{-1} x (inside == 1), in float64 and in
+ * uint64 (wrap-around arithmetic: the (I-X)(I+X) scheme subtracts). */
+static void block_apply(const uint8_t* code, const float* z, int64_t nr, int64_t nc, double p,
+                        const int64_t* order, int64_t br, int64_t bc, int inside, const double* x,
+                        const uint64_t* xc, double* y, uint64_t* yc) {
+  const int64_t n = nr * nc;
+  int64_t nb[8];
+  double f[8];
+  if (!inside) {
+    for (int64_t i = 0; i < n; ++i) {
+      y[i] = 0.0;
+      yc[i] = 0;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      const int m = pairs_of(code, z, nr, nc, p, i, nb, f);
+      for (int s = 0; s < m; ++s) {
+        if (block_of(nc, br, bc, nb[s]) == block_of(nc, br, bc, i)) continue;
+        y[nb[s]] += f[s] * x[i];
+        yc[nb[s]] += xc[i];
+      }
+    }
+    return;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    y[i] = x[i];
+    yc[i] = xc[i];
+  }
+  for (int64_t t = 0; t < n; ++t) {
+    const int64_t i = order[t];
+    const int m = pairs_of(code, z, nr, nc, p, i, nb, f);
+    for (int s = 0; s < m; ++s) {
+      if (block_of(nc, br, bc, nb[s]) != block_of(nc, br, bc, i)) continue;
+      y[nb[s]] += f[s] * y[i];
+      yc[nb[s]] += yc[i];
+    }
+  }
+}
+
+int or_block_richardson(const uint8_t* code, const float* z, int64_t nr, int64_t nc, double p,
+                        const int64_t* order, const float* rain, int64_t br, int64_t bc, int scheme,
+                        int max_iter, double* q, uint64_t* counts, int* iters) {
+  if ((!code && !z) || !order || !iters || nr < 0 || nc < 0 || br < 1 || bc < 1 || max_iter < 1 ||
+      (scheme != 0 && scheme != 1))
+    return -2;
+  const size_t n = (size_t)(nr * nc) + 1;
+  double* w = (double*)calloc(n, sizeof(double));  /* current iterate */
+  double* b = (double*)malloc(n * sizeof(double));  /* D^{-1} r */
+  double* nx = (double*)malloc(n * sizeof(double)); /* next iterate */
+  double* t1 = (double*)malloc(n * sizeof(double));
+  double* t2 = (double*)malloc(n * sizeof(double));
+  uint64_t* wc = (uint64_t*)calloc(n, sizeof(uint64_t));
+  uint64_t* bcn = (uint64_t*)malloc(n * sizeof(uint64_t));
+  uint64_t* nxc = (uint64_t*)malloc(n * sizeof(uint64_t));
+  uint64_t* u1 = (uint64_t*)malloc(n * sizeof(uint64_t));
+  uint64_t* u2 = (uint64_t*)malloc(n * sizeof(uint64_t));
+  int rc = -3;
+  if (!w || !b || !nx || !t1 || !t2 || !wc || !bcn || !nxc || !u1 || !u2) {
+    rc = -2;
+  } else {
+    const int64_t m = nr * nc;
+    for (int64_t i = 0; i < m; ++i) {
+      t1[i] = rain ? (double)rain[i] : 1.0;
+      u1[i] = 1;
+    }
+    block_apply(code, z, nr, nc, p, order, br, bc, 1, t1, u1, b, bcn); /* b = D^{-1} r */
+    *iters = 0;
+    for (int l = 1; l <= max_iter + 1; ++l) {
+      if (scheme == 0) {
+        /* next = D^{-1} (r + rho w) */
+        block_apply(code, z, nr, nc, p, order, br, bc, 0, w, wc, t1, u1);
+        for (int64_t i = 0; i < m; ++i) {
+          t1[i] += rain ? (double)rain[i] : 1.0;
+          u1[i] += 1;
+        }
+        block_apply(code, z, nr, nc, p, order, br, bc, 1, t1, u1, nx, nxc);
+      } else {
+        /* res = b - (I + X) w = b - w + D^{-1} rho w  (into t1/u1) */
+        block_apply(code, z, nr, nc, p, order, br, bc, 0, w, wc, t2, u2);
+        block_apply(code, z, nr, nc, p, order, br, bc, 1, t2, u2, t1, u1);
+        for (int64_t i = 0; i < m; ++i) {
+          t1[i] = b[i] - w[i] + t1[i];
+          u1[i] = bcn[i] - wc[i] + u1[i];
+        }
+        /* next = w + (I - X) res = w + res + D^{-1} rho res */
+        block_apply(code, z, nr, nc, p, order, br, bc, 0, t1, u1, t2, u2);
+        block_apply(code, z, nr, nc, p, order, br, bc, 1, t2, u2, nx, nxc);
+        for (int64_t i = 0; i < m; ++i) {
+          nx[i] = w[i] + t1[i] + nx[i];
+          nxc[i] = wc[i] + u1[i] + nxc[i];
+        }
+      }
+      /* The iterate is exact once the next one equals it, decided on the
+       * integer iterate: exact cell counts for single receivers; for MFD the
+       * same recurrence with every fraction replaced by 1 counts flow paths
+       * (modulo 2^64), which stops changing exactly when no path with more
+       * crossings is left.  (Comparing the float iterate instead would stop
+       * early wherever the last crossing carries water below the rounding
+       * of its receiver's total.) */
+      int same = l > 1;
+      for (int64_t i = 0; same && i < m; ++i) same = nxc[i] == wc[i];
+      if (same) {
+        *iters = l - 1;
+        rc = 0;
+        break;
+      }
+      memcpy(w, nx, (size_t)m * sizeof(double));
+      memcpy(wc, nxc, (size_t)m * sizeof(uint64_t));
+    }
+    if (rc == 0) {
+      if (q) memcpy(q, w, (size_t)m * sizeof(double));
+      if (counts && code)
+        for (int64_t i = 0; i < m; ++i) counts[i] = (uint64_t)wc[i];
+    }
+  }
+  free(w);
+  free(b);
+  free(nx);
+  free(t1);
+  free(t2);
+  free(wc);
+  free(bcn);
+  free(nxc);
+  free(u1);
+  free(u2);
+  return rc;
+}

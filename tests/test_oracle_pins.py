@@ -394,3 +394,104 @@ def test_fp32_fraction_variant_is_close_to_fp64():
     q64 = oracle.accumulate_mfd(z, None, 1.1)
     q32 = oracle.accumulate_mfd(z, None, 1.1, frac32=True)
     assert np.max(np.abs(q32 - q64) / q64) < 1e-5
+
+
+# ---------------------------------------------------------------------------
+# The paper's parallel scheme (Section 3.3 "I+X" and "(I-X)(I+X)"; Appendix B):
+# block Richardson iterations with per-block high-to-low solves.
+
+def _block(shape, blk, r, c):
+    nbc = (shape[1] + blk[1] - 1) // blk[1]
+    return (r // blk[0]) * nbc + c // blk[1]
+
+
+def _max_crossings_d8(code, blk):
+    """Brute force: follow every cell's flow path to its sink, counting the
+    block boundaries it crosses; the maximum over all paths."""
+    best = 0
+    for r in range(code.shape[0]):
+        for c in range(code.shape[1]):
+            cur, n = (r, c), 0
+            while True:
+                nxt = _target(code, *cur)
+                if nxt is None:
+                    break
+                n += _block(code.shape, blk, *cur) != _block(code.shape, blk, *nxt)
+                cur = nxt
+            best = max(best, n)
+    return best
+
+
+def _max_crossings_mfd(z, blk):
+    """Longest path, counted in block crossings, through the DAG of
+    lower-neighbour edges (cells taken from high to low, plain Python)."""
+    mask, _ = oracle.mfd_fractions(z, 1.1)
+    nr, nc = z.shape
+    cells = sorted(((float(z[r, c]), -(r * nc + c)) for r in range(nr) for c in range(nc)), reverse=True)
+    L = np.zeros(z.shape, dtype=np.int64)
+    for _, neg in cells:
+        i = -neg
+        r, c = divmod(i, nc)
+        for k, (dr, dc) in enumerate(oracle.OFFSETS):
+            if not (mask[r, c] >> k) & 1:
+                continue
+            rr, cc = r + dr, c + dc
+            step = int(_block(z.shape, blk, r, c) != _block(z.shape, blk, rr, cc))
+            L[rr, cc] = max(L[rr, cc], L[r, c] + step)
+    return int(L.max())
+
+
+@pytest.mark.parametrize("rule", [oracle.D8, oracle.D4, oracle.MFD])
+def test_block_richardson_one_block_is_the_sequential_solve(rule):
+    # One process: D = A, R = 0, so one iteration gives the exact solution,
+    # and it is the high-to-low push itself (Section 3.2).
+    z = synth.dem(61, 30, 37)
+    rain = synth.rain(61, 30, 37)
+    if rule == oracle.MFD:
+        ref_q = oracle.accumulate_mfd(z, rain, 1.1)
+        ref_c = None
+    else:
+        ref_q, _ = oracle.accumulate_single(oracle.receivers(z, rule), rain, z=z)
+        _, ref_c = oracle.accumulate_single(oracle.receivers(z, rule), None, z=z)
+    for scheme in (0, 1):
+        q, cnt, it = oracle.block_richardson(z, (30, 37), rule, rain, scheme)
+        assert it == 1
+        assert np.array_equal(q, ref_q)
+        if ref_c is not None:
+            assert np.array_equal(cnt, ref_c)
+
+
+@pytest.mark.parametrize("seed,shape,blk", [(62, (40, 33), (10, 11)), (63, (24, 50), (6, 7)),
+                                            (64, (31, 31), (31, 4)), (65, (20, 20), (1, 1))])
+@pytest.mark.parametrize("rule", [oracle.D8, oracle.D4])
+def test_block_richardson_needs_crossings_plus_one_iterations(seed, shape, blk, rule):
+    # Appendix B: with streams crossing block boundaries at most C times the
+    # I+X iterate is exact after C+1 iterations and not before; the
+    # (I-X)(I+X) scheme squares the iteration's error operator (about half
+    # the iterations, Section 3.3): ceil((C+1)/2).
+    z = synth.dem(seed, *shape)
+    code = oracle.receivers(z, rule)
+    C = _max_crossings_d8(code, blk)
+    ref_q, ref_c = oracle.accumulate_single(code, synth.rain(seed, *shape), z=z)
+    _, ref_c = oracle.accumulate_single(code, None, z=z)
+    q, cnt, it0 = oracle.block_richardson(z, blk, rule, synth.rain(seed, *shape), 0)
+    assert it0 == C + 1
+    assert np.array_equal(cnt, ref_c)
+    assert np.allclose(q, ref_q, rtol=1e-12, atol=0)
+    q1, cnt1, it1 = oracle.block_richardson(z, blk, rule, synth.rain(seed, *shape), 1)
+    assert it1 == (C + 2) // 2
+    assert np.array_equal(cnt1, ref_c)
+    assert np.allclose(q1, ref_q, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("seed,shape,blk", [(66, (21, 18), (7, 6)), (67, (16, 30), (4, 10))])
+def test_block_richardson_mfd_crossings_plus_one(seed, shape, blk):
+    z = synth.dem(seed, *shape)
+    C = _max_crossings_mfd(z, blk)
+    ref = oracle.accumulate_mfd(z, None, 1.1)
+    q, _, it0 = oracle.block_richardson(z, blk, oracle.MFD, None, 0)
+    assert it0 == C + 1
+    assert np.allclose(q, ref, rtol=1e-12, atol=0)
+    q1, _, it1 = oracle.block_richardson(z, blk, oracle.MFD, None, 1)
+    assert it1 == (C + 2) // 2
+    assert np.allclose(q1, ref, rtol=1e-12, atol=0)
