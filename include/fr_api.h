@@ -77,6 +77,7 @@ extern "C" {
 /* Function identifiers for fr_workspace_bytes. */
 #define FR_FN_ACCUMULATE 1
 #define FR_FN_ADJOINT 2
+#define FR_FN_BLOCK_ITER 3
 
 /* Tile orders of fr_batch_plan.order. */
 #define FR_ORDER_GIVEN 0
@@ -171,9 +172,42 @@ int fr_accumulate_adjoint(const float* z, const uint8_t* code, int64_t nrows, in
                           int32_t* dev_status, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
- * fr_workspace_bytes -- workspace size for fn = FR_FN_ACCUMULATE or
- * FR_FN_ADJOINT on an nrows x ncols grid with this rule and dtype (FR_NONE
- * means counts only).  Returns 0 for invalid arguments.
+ * fr_accumulate_block_iterations -- the paper's parallel scheme (Section
+ * 3.3, eq. I+X; Appendix B, eq. richardson-I+X): Richardson iterations
+ * w <- D^-1 (r + R w) with blocks of 256 columns x th rows (th = 512 rows
+ * for grids of 2^28 cells or more, else 256), where D^-1 is the block's own
+ * solve -- here one top-down row sweep, which follows every routing pair
+ * whose receiver lies in the row before inside the block -- and R passes the
+ * previous iterate's water along every other pair (across block boundaries,
+ * within a row, or toward a later row).  Iterates until one equals the
+ * previous one: the exact solution, reached after C + 1 iterations when flow
+ * paths cross those pairs at most C times.  It gives the same water and
+ * counts as fr_accumulate (whose exit forest replaces these C + 1 iterations
+ * by pointer doubling); it exists to measure the paper's scheme.
+ * Single-receiver rules only.
+ *
+ *   code      device uint8 codes (FR_D8 or FR_D4), as for fr_accumulate.
+ *   rain, rain_dtype   as for fr_accumulate (NULL = unit rain).
+ *   q_dtype   FR_F64 (float64 water into q_out) or FR_NONE (counts only).
+ *   counts_out device uint64 cell counts, or NULL.  At least one output.
+ *   max_iter  iteration budget (>= 1); no fixed point within max_iter + 1
+ *             iterations sets FR_ERR_NOTDAG in dev_status.
+ *   iters_out host int32: the number of iterations after which the iterate
+ *             was exact (0 on an empty grid).
+ *   ws, ws_bytes  workspace of fr_workspace_bytes(FR_FN_BLOCK_ITER, ...).
+ * Synchronises with the stream after every iteration (reads the change
+ * flag).  Errors: FR_ERR_ARG, FR_ERR_RULE (not D8/D4), FR_ERR_WORKSPACE,
+ * FR_ERR_TOOLARGE, FR_ERR_HIP; device-detected errors as for fr_accumulate.
+ */
+int fr_accumulate_block_iterations(const uint8_t* code, int64_t nrows, int64_t ncols, int rule,
+                                   const void* rain, int rain_dtype, int q_dtype, void* q_out,
+                                   uint64_t* counts_out, int32_t max_iter, int32_t* iters_out,
+                                   int32_t* dev_status, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * fr_workspace_bytes -- workspace size for fn = FR_FN_ACCUMULATE,
+ * FR_FN_ADJOINT or FR_FN_BLOCK_ITER on an nrows x ncols grid with this rule
+ * and dtype (FR_NONE means counts only).  Returns 0 for invalid arguments.
  */
 size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dtype);
 

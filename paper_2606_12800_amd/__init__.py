@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_PKG, "libflowroute.so")
 D8, MFD, D4 = 0, 1, 2
 NONE, F32, F64 = 0, 1, 2
 SINK = 0xFF
-FN_ACCUMULATE, FN_ADJOINT = 1, 2
+FN_ACCUMULATE, FN_ADJOINT, FN_BLOCK_ITER = 1, 2, 3
 OK = 0
 ERR_ARG, ERR_RULE, ERR_WORKSPACE, ERR_HIP = -1, -2, -3, -4
 ERR_NONFINITE, ERR_NOTDAG, ERR_BADCODE, ERR_TOOLARGE = -5, -6, -7, -8
@@ -33,7 +33,8 @@ ERR_NONFINITE, ERR_NOTDAG, ERR_BADCODE, ERR_TOOLARGE = -5, -6, -7, -8
 RULES = {"d8": D8, "mfd": MFD, "d4": D4}
 EXPORTS = ["fr_receivers", "fr_accumulate", "fr_accumulate_adjoint", "fr_workspace_bytes",
            "fr_status_string", "fr_version", "fr_timing_enable", "fr_timing_last",
-           "fr_batched_workspace_bytes", "fr_accumulate_batched", "fr_batch_autotune"]
+           "fr_batched_workspace_bytes", "fr_accumulate_batched", "fr_batch_autotune",
+           "fr_accumulate_block_iterations"]
 ORDER_GIVEN, ORDER_ROWS_DESC = 0, 1
 
 
@@ -91,6 +92,8 @@ def load_library() -> ctypes.CDLL:
     lib.fr_accumulate_batched.restype = ci
     lib.fr_batch_autotune.argtypes = [vp, i32, vp, vp, sz, ci, vp, vp]
     lib.fr_batch_autotune.restype = ci
+    lib.fr_accumulate_block_iterations.argtypes = [vp, i64, i64, ci, vp, ci, ci, vp, vp, i32, vp, vp, vp, sz, vp]
+    lib.fr_accumulate_block_iterations.restype = ci
     _lib = lib
     return lib
 
@@ -251,6 +254,40 @@ def adjoint(code: torch.Tensor, qbar: torch.Tensor, z: torch.Tensor | None = Non
     if check:
         _raise_status(status, "fr_accumulate_adjoint")
     return rbar
+
+
+def block_iterations(code: torch.Tensor, rain: torch.Tensor | None = None, rule="d8",
+                     dtype=torch.float64, counts: bool = True, max_iter: int = 100000,
+                     ws: Workspace | None = None, check: bool = True):
+    """The paper's I+X block iterations (``fr_accumulate_block_iterations``).
+    Returns (q float64 or None, counts or None, iterations until exact)."""
+    _check_grid(code, torch.uint8, "code")
+    nr, nc = code.shape
+    dev = code.device
+    r = _rule(rule)
+    rdt = F32
+    if rain is not None:
+        if rain.dtype not in (torch.float32, torch.float64):
+            raise TypeError("rain must be float32 or float64")
+        _check_grid(rain, rain.dtype, "rain")
+        rdt = _dtype_code(rain.dtype)
+    if dtype not in (None, torch.float64):
+        raise TypeError("block iterations compute float64 water (or counts only)")
+    dt = _dtype_code(dtype)
+    q = None if dtype is None else torch.empty((nr, nc), dtype=dtype, device=dev)
+    cnt = torch.empty((nr, nc), dtype=torch.uint64, device=dev) if counts else None
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    nbytes = workspace_bytes(FN_BLOCK_ITER, nr, nc, r, dt)
+    buf = (ws or _default_ws).get(nbytes, dev)
+    iters = ctypes.c_int32(0)
+    rc = load_library().fr_accumulate_block_iterations(_ptr(code), nr, nc, r, _ptr(rain), rdt, dt, _ptr(q),
+                                                       _ptr(cnt), int(max_iter), ctypes.byref(iters),
+                                                       _ptr(status), _ptr(buf), buf.numel(), _stream(dev))
+    if rc != OK:
+        raise FlowRouteError(rc, "fr_accumulate_block_iterations")
+    if check:
+        _raise_status(status, "fr_accumulate_block_iterations")
+    return q, cnt, iters.value
 
 
 def route(z: torch.Tensor, rain: torch.Tensor | None = None, rule="d8", dtype=torch.float32,

@@ -478,6 +478,13 @@ const char* fr_status_string(int code) {
   }
 }
 
+// Block iterations: a second float64 value and count per cell (the other
+// iterate) and the change flag.
+size_t block_iter_bytes(int64_t nrows, int64_t ncols) {
+  const size_t n = (size_t)(nrows * ncols);
+  return up(n * sizeof(double)) + up(n * sizeof(uint64_t)) + 2 * kAlign;
+}
+
 size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dtype) {
   if (nrows < 0 || ncols < 0 || !valid_rule(rule)) return 0;
   if (nrows > 0 && ncols > kMaxCells / (nrows > 0 ? nrows : 1)) return 0;
@@ -486,6 +493,9 @@ size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dt
     if (rule == FR_MFD && dtype == FR_NONE) return 0;
   } else if (fn == FR_FN_ADJOINT) {
     if (dtype != FR_F32 && dtype != FR_F64) return 0;
+  } else if (fn == FR_FN_BLOCK_ITER) {
+    if (rule == FR_MFD || (dtype != FR_NONE && dtype != FR_F64)) return 0;
+    return block_iter_bytes(nrows, ncols);
   } else {
     return 0;
   }
@@ -587,6 +597,84 @@ int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t nc
     phase_end(ph, stream);
   }
   return FR_OK;
+}
+
+int fr_accumulate_block_iterations(const uint8_t* code, int64_t nrows, int64_t ncols, int rule,
+                                   const void* rain, int rain_dtype, int q_dtype, void* q_out,
+                                   uint64_t* counts_out, int32_t max_iter, int32_t* iters_out,
+                                   int32_t* dev_status, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (nrows < 0 || ncols < 0 || !iters_out || max_iter < 1) return FR_ERR_ARG;
+  if (rule != FR_D8 && rule != FR_D4) return FR_ERR_RULE;
+  if (rain && rain_dtype != FR_F32 && rain_dtype != FR_F64) return FR_ERR_ARG;
+  if (q_dtype != FR_NONE && q_dtype != FR_F64) return FR_ERR_ARG;
+  *iters_out = 0;
+  if (nrows == 0 || ncols == 0) return FR_OK;
+  if ((q_dtype == FR_NONE) != (q_out == nullptr)) return FR_ERR_ARG;
+  if (q_dtype == FR_NONE && !counts_out) return FR_ERR_ARG;
+  if (ncols > kMaxCells / nrows) return FR_ERR_TOOLARGE;
+  if (!code) return FR_ERR_ARG;
+  if (!ws || ws_bytes < fr_workspace_bytes(FR_FN_BLOCK_ITER, nrows, ncols, rule, q_dtype))
+    return FR_ERR_WORKSPACE;
+  timing_reset();
+  char* base = aligned_base(ws);
+  const size_t n = (size_t)(nrows * ncols);
+  double* wq = reinterpret_cast<double*>(base);
+  uint64_t* wc = reinterpret_cast<uint64_t*>(base + up(n * sizeof(double)));
+  int32_t* flag = reinterpret_cast<int32_t*>(base + up(n * sizeof(double)) + up(n * sizeof(uint64_t)));
+  const ValKind vk = q_dtype == FR_F64 ? VK_F64 : VK_NONE;
+  const bool counts = counts_out != nullptr;
+  D8Params P{};
+  P.nrows = nrows;
+  P.ncols = ncols;
+  P.th = d8_tile_height(nrows, ncols);
+  P.ntr = (int32_t)((nrows + P.th - 1) / P.th);
+  P.ntc = (int32_t)((ncols + D8_TW - 1) / D8_TW);
+  P.code = code;
+  P.rain32 = (rain && rain_dtype == FR_F32) ? static_cast<const float*>(rain) : nullptr;
+  P.rain64 = (rain && rain_dtype == FR_F64) ? static_cast<const double*>(rain) : nullptr;
+  P.status = dev_status;
+  P.it_changed = flag;
+  // The two iterates alternate between the caller's outputs (iterations 2,
+  // 4, ...) and the workspace (1, 3, ...).  Iteration l leaves its result
+  // where iteration l - 1 read from; once an iterate equals the previous one
+  // both buffers hold the solution.
+  double* qbuf[2] = {static_cast<double*>(q_out), vk == VK_F64 ? wq : nullptr};
+  uint64_t* cbuf[2] = {counts_out, counts ? wc : nullptr};
+  const int ph = phase_begin("block_iterations", stream);
+  int rc = FR_OK;
+  for (int32_t l = 1;; ++l) {
+    if (l > max_iter + 1) {
+      // No fixed point within the budget: a cycle in the codes, or too few
+      // iterations allowed for the block crossings of this grid.
+      if (dev_status && launch_set_status(dev_status, FR_ERR_NOTDAG, stream) != hipSuccess) rc = FR_ERR_HIP;
+      break;
+    }
+    const int cur = l & 1, prev = cur ^ 1;
+    P.q64 = qbuf[cur];
+    P.cnt = cbuf[cur];
+    P.it_q64 = qbuf[prev];
+    P.it_cnt = cbuf[prev];
+    P.it_first = l == 1;
+    if (launch_zero_u32(reinterpret_cast<uint32_t*>(flag), 1, stream) != hipSuccess ||
+        launch_d8_iter(vk, counts, P, stream) != hipSuccess) {
+      rc = FR_ERR_HIP;
+      break;
+    }
+    int32_t changed = 0, st = 0;
+    if (hipMemcpyAsync(&changed, flag, sizeof changed, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        (dev_status && hipMemcpyAsync(&st, dev_status, sizeof st, hipMemcpyDeviceToHost, stream) != hipSuccess) ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+      rc = FR_ERR_HIP;
+      break;
+    }
+    if (st != 0) break;
+    if (l > 1 && !changed) {
+      *iters_out = l - 1;
+      break;
+    }
+  }
+  phase_end(ph, stream);
+  return rc;
 }
 
 int fr_accumulate_adjoint(const float* z, const uint8_t* code, int64_t nrows, int64_t ncols, int rule,

@@ -313,9 +313,12 @@ __device__ __forceinline__ void acc_ff(float& s, float& e, bool cond, float xh, 
 //   UP   (phase A): record every exit with its local value (local counts of
 //                   one tile fit in 32 bits).
 //   DOWN (phase C): write the final water / counts and the mass balance.
-template <bool UP, int VK, bool CNT, int RAIN, bool VEC, bool BORDER>
+//   ITER (block iterations, phase C form): cut donors give their water of
+//                   the previous iterate; the tile sweep is the block solve.
+template <bool UP, int VK, bool CNT, int RAIN, bool VEC, bool BORDER, bool ITER = false>
 __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* mass, bool* nonfinite,
-                                      float* xq32 = nullptr, double* xq64 = nullptr, uint64_t* xcnt = nullptr) {
+                                      float* xq32 = nullptr, double* xq64 = nullptr, uint64_t* xcnt = nullptr,
+                                      bool* badcode = nullptr, bool* changed = nullptr) {
   using CT = typename std::conditional<UP, uint32_t, uint64_t>::type;
   using V = Val<CT>;
   // Rows in flight: fewer in phase A, whose kernel must stay within 128
@@ -329,7 +332,7 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
   const int tw = BORDER ? T.tw : TW;
   const bool lane_in = !BORDER || c < nc;
   double m_sink = 0.0, m_rain = 0.0;
-  bool nf = false;
+  bool nf = false, bad = false, chg = false;
   V pv[W];
 #pragma unroll
   for (int j = 0; j < W; ++j) pv[j] = V{};
@@ -385,7 +388,8 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
           const V& a5 = j == 0 ? lv : pv[j == 0 ? 0 : j - 1];
           const V& a7 = j == W - 1 ? rv : pv[j == W - 1 ? 0 : j + 1];
           const auto rain = rq[i].v[j];
-          if (UP && RAIN != RAIN_UNIT) nf |= !isfinite(rain);
+          if ((UP || ITER) && RAIN != RAIN_UNIT) nf |= !isfinite(rain);
+          if (ITER) bad |= (!BORDER || k < tw) && cd != SINK && x.sink;
           V v;
           if (VK == VK_FF) {
             float sh = (float)rain, se = RAIN == RAIN_F64 ? (float)((double)rain - (double)(float)rain) : 0.0f;
@@ -400,7 +404,21 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
           cut[j] = UP ? 0u : cut_donors(above, here, below, j, k, top, rare, tw);
           nv[j] = v;
         }
-        if (!UP && __ballot((cut[0] | cut[1] | cut[2] | cut[3]) != 0u)) {
+        if (ITER && !P.it_first && __ballot((cut[0] | cut[1] | cut[2] | cut[3]) != 0u)) {
+          // Water of the previous iterate across cut edges.
+#pragma unroll
+          for (int j = 0; j < W; ++j) {
+            uint32_t m = cut[j];
+            while (m) {
+              const int n = __builtin_ctz(m);
+              m &= m - 1;
+              const size_t gj = (size_t)((int64_t)(g + j) + (int64_t)nb_dr(n) * nc + nb_dc(n));
+              if (VK == VK_F64) nv[j].d += P.it_q64[gj];
+              if (CNT) nv[j].n += (CT)P.it_cnt[gj];
+            }
+          }
+        }
+        if (!UP && !ITER && __ballot((cut[0] | cut[1] | cut[2] | cut[3]) != 0u)) {
           // Totals of donors across cut edges (sparse: the top row, the
           // outer columns and rare rows).
 #pragma unroll
@@ -494,7 +512,16 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
           }
           __syncthreads();
         }
-        if (!UP && VK != VK_NONE) {
+        if (ITER && !P.it_first) {
+          // Whether this iterate differs from the previous one here.
+#pragma unroll
+          for (int j = 0; j < W; ++j) {
+            if (BORDER && c + j >= nc) continue;
+            if (CNT) chg |= nv[j].n != P.it_cnt[g + j];
+            else if (VK == VK_F64) chg |= __double_as_longlong(nv[j].d) != __double_as_longlong(P.it_q64[g + j]);
+          }
+        }
+        if (!UP && !ITER && VK != VK_NONE) {
 #pragma unroll
           for (int j = 0; j < W; ++j)
             if (!BORDER || c + j < nc) m_rain += (double)rq[i].v[j];
@@ -517,6 +544,8 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
     }
   }
   if (nf) *nonfinite = true;
+  if (ITER && bad) *badcode = true;
+  if (ITER && chg) *changed = true;
   if (mass) {
     mass[0] = m_sink;
     mass[1] = m_rain;
@@ -719,6 +748,29 @@ __global__ __launch_bounds__(64) void k_d8_down(D8Params P) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Block iterations (the paper's I+X scheme, Section 3.3 and Appendix B):
+// w <- D^-1 (r + rho w) with blocks = tiles, D = the pairs a tile's top-down
+// sweep follows (receiver in the row below, inside the tile), rho = every
+// other pair.  One launch is one iteration.
+template <int VK, bool CNT, int RAIN, bool VEC>
+__global__ __launch_bounds__(64) void k_d8_iter(D8Params P) {
+  __shared__ float s_q32[1];
+  __shared__ double s_q64[VEC || VK != VK_F64 ? 1 : TW];
+  __shared__ uint64_t s_cnt[VEC || !CNT ? 1 : TW];
+  const Tile T = tile_of(P, blockIdx.x);
+  bool nonfinite = false, badcode = false, changed = false;
+  if (T.border)
+    sweep<false, VK, CNT, RAIN, VEC, true, true>(P, T, nullptr, &nonfinite, s_q32, s_q64, s_cnt, &badcode,
+                                                  &changed);
+  else
+    sweep<false, VK, CNT, RAIN, VEC, false, true>(P, T, nullptr, &nonfinite, s_q32, s_q64, s_cnt, &badcode,
+                                                   &changed);
+  if (__ballot(changed) && threadIdx.x == 0) *P.it_changed = 1;
+  if (badcode) set_status(P.status, FR_ERR_BADCODE);
+  if (nonfinite) set_status(P.status, FR_ERR_NONFINITE);
+}
+
 int grid_for(uint32_t n) {
   uint32_t b = (n + 255) / 256;
   if (b > 16384) b = 16384;
@@ -772,6 +824,13 @@ struct DownK {
   }
 };
 
+template <int VK, bool CNT, int RAIN, bool VEC>
+struct IterK {
+  static void launch(dim3 g, dim3 b, hipStream_t s, const D8Params& P) {
+    hipLaunchKernelGGL((k_d8_iter<VK, CNT, VK == VK_NONE ? RAIN_UNIT : RAIN, VEC>), g, b, 0, s, P);
+  }
+};
+
 template <template <int, bool, int, bool> class K>
 void d8_sweep_dispatch(ValKind vk, bool cnt, const D8Params& P, hipStream_t s) {
   if (vk == VK_FF) {
@@ -803,6 +862,17 @@ hipError_t launch_d8_round(ValKind vk, bool cnt, const D8Params& P, uint32_t n, 
   if (n == 0) return hipSuccess;
   D8_DISPATCH(k_d8_copy, dim3(grid_for(n)), dim3(256), P, n, b);
   D8_DISPATCH(k_d8_scatter, dim3(grid_for(n)), dim3(256), P, n, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_d8_iter(ValKind vk, bool cnt, const D8Params& P, hipStream_t s) {
+  if (vk == VK_FF) return hipErrorInvalidValue;  // float64 values or counts only
+  if (vk == VK_F64) {
+    if (cnt) d8_sweep_launch<VK_F64, true, IterK>(P, s);
+    else d8_sweep_launch<VK_F64, false, IterK>(P, s);
+  } else {
+    d8_sweep_launch<VK_NONE, true, IterK>(P, s);
+  }
   return hipGetLastError();
 }
 

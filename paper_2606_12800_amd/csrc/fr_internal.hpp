@@ -92,6 +92,12 @@ struct D8Params {
   int32_t* flags;              // [1]: some exit still has an ancestor
   double* mass_part;           // per tile {sum over sinks, sum of rain}, or NULL
   int32_t* status;
+  // Block iterations (the paper's I+X scheme): the previous iterate, read at
+  // cut donors, and a flag set when an iterate differs from the previous one.
+  const double* it_q64;
+  const uint64_t* it_cnt;
+  int32_t* it_changed;
+  int32_t it_first;            // first iteration: no water crosses a cut edge yet
 };
 
 // Launchers (defined in the .hip files).
@@ -99,6 +105,7 @@ hipError_t launch_d8_up(ValKind vk, bool cnt, const D8Params& P, hipStream_t s);
 hipError_t launch_d8_link(const D8Params& P, uint32_t n, hipStream_t s);
 hipError_t launch_d8_round(ValKind vk, bool cnt, const D8Params& P, uint32_t n, int b, hipStream_t s);
 hipError_t launch_d8_down(ValKind vk, bool cnt, const D8Params& P, int fb, hipStream_t s);
+hipError_t launch_d8_iter(ValKind vk, bool cnt, const D8Params& P, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
 hipError_t launch_mass_final(const double* partial, int nblocks, double* out, hipStream_t s);
 hipError_t launch_receivers(const float* z, int64_t nrows, int64_t ncols, int rule, uint8_t* code,

@@ -1,0 +1,89 @@
+"""The paper's block iterations (Section 3.3 "I+X", Appendix B) on the GPU.
+
+fr_accumulate_block_iterations runs w <- D^-1 (r + R w) with one top-down
+sweep per 256 x 256 block as D^-1.  Checks: float64 water against the
+oracle's direct solve (<= 1e-10 per cell, the float64 bar), counts
+bit-exact against the oracle and against fr_accumulate, and the number of
+iterations equal to the oracle's block iteration with the same splitting
+(C + 1, C the most pairs outside D along a flow path).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+fr = pytest.importorskip("paper_2606_12800_amd")
+
+BLOCK = (256, 256)  # tile of grids below 2^28 cells
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fr.load_library()
+    yield
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("seed,shape", [(71, (600, 700)), (72, (513, 259)), (73, (1, 900)), (74, (777, 1)),
+                                        (75, (300, 1031))])
+@pytest.mark.parametrize("rule", ["d8", "d4"])
+def test_block_iterations_match_oracle(seed, shape, rule):
+    print(f"block iterations {rule} seed {seed} shape {shape}", flush=True)
+    r = oracle.D8 if rule == "d8" else oracle.D4
+    z = synth.dem(seed, *shape)
+    rain = synth.rain(seed, *shape)
+    code_h = oracle.receivers(z, r)
+    ref_q, _ = oracle.accumulate_single(code_h, rain, z=z)
+    _, ref_c = oracle.accumulate_single(code_h, None, z=z)
+    _, _, ref_it = oracle.block_richardson(z, BLOCK, r, None, 0, split=1)
+    code = fr.receivers(dev(z), rule)
+    assert np.array_equal(code.cpu().numpy(), code_h)
+    q, cnt, it = fr.block_iterations(code, dev(rain), rule)
+    torch.cuda.synchronize()
+    qh = q.cpu().numpy()
+    assert np.max(np.abs(qh - ref_q) / np.maximum(ref_q, 1e-300)) <= 1e-10
+    assert np.array_equal(cnt.cpu().numpy().astype(np.uint64), ref_c)
+    assert it == ref_it
+    # Same counts as the main path (exit forest instead of iterations).
+    _, c2, _ = fr.accumulate(code, None, None, rule, None, counts=True)
+    assert torch.equal(c2, cnt)
+
+
+def test_block_iterations_counts_only_and_unit_rain():
+    z = synth.dem(76, 520, 300)
+    code = fr.receivers(dev(z), "d8")
+    _, cnt, it = fr.block_iterations(code, None, "d8", dtype=None)
+    q, cnt2, it2 = fr.block_iterations(code, None, "d8")
+    assert it == it2 and torch.equal(cnt, cnt2)
+    # Unit rain: the water is the cell count.
+    assert torch.equal(q, cnt.to(torch.float64))
+
+
+def test_block_iterations_errors():
+    z = synth.dem(77, 64, 64)
+    code = fr.receivers(dev(z), "d8")
+    with pytest.raises(fr.FlowRouteError) as e:
+        fr.block_iterations(fr.receivers(dev(z), "mfd"), None, "mfd")
+    assert e.value.code == fr.ERR_RULE
+    with pytest.raises(TypeError):
+        fr.block_iterations(code, None, "d8", dtype=torch.float32)
+    # An iteration budget below C + 1 leaves no fixed point: reported.
+    big = synth.dem(78, 900, 300)
+    bcode = fr.receivers(dev(big), "d8")
+    _, _, it = fr.block_iterations(bcode, None, "d8")
+    assert it >= 3
+    with pytest.raises(fr.FlowRouteError) as e:
+        fr.block_iterations(bcode, None, "d8", max_iter=it - 2)
+    assert e.value.code == fr.ERR_NOTDAG
+    # Empty grid.
+    q, cnt, it = fr.block_iterations(torch.empty((0, 5), dtype=torch.uint8, device="cuda"), None, "d8")
+    assert it == 0 and q.numel() == 0
