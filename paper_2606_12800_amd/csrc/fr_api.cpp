@@ -626,7 +626,7 @@ int fr_accumulate_block_iterations(const uint8_t* code, int64_t nrows, int64_t n
   D8Params P{};
   P.nrows = nrows;
   P.ncols = ncols;
-  P.th = d8_tile_height(nrows, ncols);
+  P.th = block_iter_height(nrows, ncols);
   P.ntr = (int32_t)((nrows + P.th - 1) / P.th);
   P.ntc = (int32_t)((ncols + D8_TW - 1) / D8_TW);
   P.code = code;

@@ -63,8 +63,18 @@ struct EngineParams {
 // D8_TW columns, one wavefront per tile with 4 columns per lane.
 constexpr int D8_TW = 256;
 // Tile height: taller tiles mean fewer exits (fewer, shallower forest
-// rounds); shorter tiles mean more wavefronts on small grids.
+// rounds); shorter tiles mean more wavefronts, and a tile's rows are swept
+// one after another.  Grids below 2^28 cells get tiles short enough for
+// about 2048 wavefronts (down to 16 rows).
 inline int d8_tile_height(int64_t nrows, int64_t ncols) {
+  if (nrows * ncols >= ((int64_t)1 << 28)) return 512;
+  const int64_t tcols = (ncols + D8_TW - 1) / D8_TW;
+  int th = 256;
+  while (th > 16 && ((nrows + th - 1) / th) * tcols < 2048) th /= 2;
+  return th;
+}
+// Blocks of the block iterations: 256 columns x this many rows.
+inline int block_iter_height(int64_t nrows, int64_t ncols) {
   return nrows * ncols >= ((int64_t)1 << 28) ? 512 : 256;
 }
 
