@@ -358,20 +358,31 @@ def run_blockiter(args):
         raise RuntimeError("fr_receivers")
     del z
     wsb = max(fr.workspace_bytes(fr.FN_ACCUMULATE, nr, nc, fr.D8, fr.NONE),
-              fr.workspace_bytes(fr.FN_BLOCK_ITER, nr, nc, fr.D8, fr.NONE))
+              fr.workspace_bytes(fr.FN_BLOCK_ITER, nr, nc, fr.D8, fr.NONE),
+              fr.workspace_bytes(fr.FN_BLOCK_ITER_PRE, nr, nc, fr.D8, fr.NONE))
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     iters = ctypes.c_int32(0)
+    iters_pre = ctypes.c_int32(0)
 
     def forest():
         return lib.fr_accumulate(None, P(code), nr, nc, fr.D8, 1.1, None, fr.F32, fr.NONE, None, P(cnt2), None,
                                  P(status), P(ws), wsb, sp)
 
     def blocks():
-        return lib.fr_accumulate_block_iterations(P(code), nr, nc, fr.D8, None, fr.F32, fr.NONE, None, P(cnt),
-                                                  100000, ctypes.byref(iters), P(status), P(ws), wsb, sp)
+        return lib.fr_accumulate_block_iterations(P(code), nr, nc, fr.D8, fr.SCHEME_IX, None, fr.F32, fr.NONE,
+                                                  None, P(cnt), 100000, ctypes.byref(iters), P(status), P(ws),
+                                                  wsb, sp)
+
+    def blocks_pre():
+        return lib.fr_accumulate_block_iterations(P(code), nr, nc, fr.D8, fr.SCHEME_IMX_IX, None, fr.F32,
+                                                  fr.NONE, None, P(cnt2), 100000, ctypes.byref(iters_pre),
+                                                  P(status), P(ws), wsb, sp)
 
     times = {}
-    for name, fn in (("forest", forest), ("block_iterations", blocks)):
+    same_pre = None
+    for name, fn in (("forest", forest), ("block_iterations", blocks), ("block_iterations_imx_ix", blocks_pre)):
+        if name == "block_iterations_imx_ix":
+            same = bool(torch.equal(cnt, cnt2))
         for _ in range(args.warmup):
             if fn() != 0:
                 raise RuntimeError(name)
@@ -384,7 +395,7 @@ def run_blockiter(args):
         times[name] = (time.perf_counter() - t0) / args.steps
         log(f"  {name}: {1e3 * times[name]:.2f} ms")
     fr._raise_status(status, "block iterations")
-    same = bool(torch.equal(cnt, cnt2))
+    same_pre = bool(torch.equal(cnt, cnt2))
     ncell = nr * nc
     t_it = times["block_iterations"]
     per_iter_ms = 1e3 * t_it / max(iters.value + 1, 1)
@@ -402,7 +413,10 @@ def run_blockiter(args):
                      "bytes_per_cell": 17, "ms_per_launch": per_iter_ms},
         "detail": {"iterations_until_exact": iters.value, "launches": iters.value + 1,
                    "forest_path_ms": 1e3 * times["forest"], "same_counts_as_forest_path": same,
-                   "block_iterations_over_forest": t_it / times["forest"]},
+                   "block_iterations_over_forest": t_it / times["forest"],
+                   "imx_ix_iterations_until_exact": iters_pre.value,
+                   "imx_ix_ms": 1e3 * times["block_iterations_imx_ix"],
+                   "imx_ix_same_counts": same_pre},
     }
     print(json.dumps(line), flush=True)
 

@@ -77,7 +77,12 @@ extern "C" {
 /* Function identifiers for fr_workspace_bytes. */
 #define FR_FN_ACCUMULATE 1
 #define FR_FN_ADJOINT 2
-#define FR_FN_BLOCK_ITER 3
+#define FR_FN_BLOCK_ITER 3      /* block iterations, scheme FR_SCHEME_IX     */
+#define FR_FN_BLOCK_ITER_PRE 4  /* block iterations, scheme FR_SCHEME_IMX_IX */
+
+/* Iteration schemes of fr_accumulate_block_iterations. */
+#define FR_SCHEME_IX 0      /* Richardson on I + X                         */
+#define FR_SCHEME_IMX_IX 1  /* Richardson on (I - X)(I + X)                */
 
 /* Tile orders of fr_batch_plan.order. */
 #define FR_ORDER_GIVEN 0
@@ -173,41 +178,52 @@ int fr_accumulate_adjoint(const float* z, const uint8_t* code, int64_t nrows, in
 
 /*
  * fr_accumulate_block_iterations -- the paper's parallel scheme (Section
- * 3.3, eq. I+X; Appendix B, eq. richardson-I+X): Richardson iterations
- * w <- D^-1 (r + R w) with blocks of 256 columns x th rows (th = 512 rows
- * for grids of 2^28 cells or more, else 256), where D^-1 is the block's own
- * solve -- here one top-down row sweep, which follows every routing pair
- * whose receiver lies in the row before inside the block -- and R passes the
- * previous iterate's water along every other pair (across block boundaries,
- * within a row, or toward a later row).  Iterates until one equals the
- * previous one: the exact solution, reached after C + 1 iterations when flow
- * paths cross those pairs at most C times.  It gives the same water and
- * counts as fr_accumulate (whose exit forest replaces these C + 1 iterations
- * by pointer doubling); it exists to measure the paper's scheme.
- * Single-receiver rules only.
+ * 3.3; Appendix B): block Richardson iterations with blocks of 256 columns x
+ * th rows (th = 512 rows for grids of 2^28 cells or more, else 256).  Write
+ * the system as (D - R) q = r, where D^-1 is the block's own solve -- here
+ * one top-down row sweep, which follows every routing pair whose receiver
+ * lies in the row before inside the block -- and R passes water along every
+ * other pair (across block boundaries, within a row, or toward a later row);
+ * with X = -D^-1 R the system reads (I + X) q = b, b = D^-1 r.
+ *   FR_SCHEME_IX      w <- D^-1 (r + R w)                      (eq. I+X)
+ *   FR_SCHEME_IMX_IX  w <- w + (I - X)(b - (I + X) w), from w = 0: three
+ *                     block solves per iteration (one for b, once), about
+ *                     half as many iterations            (eq. (I-X)(I+X))
+ * Iterates until one equals the previous one (on the counts where given):
+ * the exact solution, reached after C + 1 (FR_SCHEME_IX) or about
+ * (C + 2) / 2 (FR_SCHEME_IMX_IX) iterations when flow paths cross R's pairs
+ * at most C times.  It gives the same counts as fr_accumulate and the same
+ * water up to rounding (whose exit forest replaces these iterations by
+ * pointer doubling); it exists to measure the paper's scheme.  Single-
+ * receiver rules only.
  *
  *   code      device uint8 codes (FR_D8 or FR_D4), as for fr_accumulate.
+ *   scheme    FR_SCHEME_IX or FR_SCHEME_IMX_IX.
  *   rain, rain_dtype   as for fr_accumulate (NULL = unit rain).
  *   q_dtype   FR_F64 (float64 water into q_out) or FR_NONE (counts only).
- *   counts_out device uint64 cell counts, or NULL.  At least one output.
+ *   counts_out device uint64 cell counts, or NULL (FR_SCHEME_IX with
+ *             q_dtype FR_F64 only: FR_SCHEME_IMX_IX decides convergence on
+ *             the counts).  At least one output.
  *   max_iter  iteration budget (>= 1); no fixed point within max_iter + 1
  *             iterations sets FR_ERR_NOTDAG in dev_status.
  *   iters_out host int32: the number of iterations after which the iterate
  *             was exact (0 on an empty grid).
- *   ws, ws_bytes  workspace of fr_workspace_bytes(FR_FN_BLOCK_ITER, ...).
+ *   ws, ws_bytes  workspace of fr_workspace_bytes(FR_FN_BLOCK_ITER or
+ *             FR_FN_BLOCK_ITER_PRE for the scheme, ...).
  * Synchronises with the stream after every iteration (reads the change
  * flag).  Errors: FR_ERR_ARG, FR_ERR_RULE (not D8/D4), FR_ERR_WORKSPACE,
  * FR_ERR_TOOLARGE, FR_ERR_HIP; device-detected errors as for fr_accumulate.
  */
-int fr_accumulate_block_iterations(const uint8_t* code, int64_t nrows, int64_t ncols, int rule,
+int fr_accumulate_block_iterations(const uint8_t* code, int64_t nrows, int64_t ncols, int rule, int scheme,
                                    const void* rain, int rain_dtype, int q_dtype, void* q_out,
                                    uint64_t* counts_out, int32_t max_iter, int32_t* iters_out,
                                    int32_t* dev_status, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * fr_workspace_bytes -- workspace size for fn = FR_FN_ACCUMULATE,
- * FR_FN_ADJOINT or FR_FN_BLOCK_ITER on an nrows x ncols grid with this rule
- * and dtype (FR_NONE means counts only).  Returns 0 for invalid arguments.
+ * FR_FN_ADJOINT, FR_FN_BLOCK_ITER or FR_FN_BLOCK_ITER_PRE on an nrows x
+ * ncols grid with this rule and dtype (FR_NONE means counts only).  Returns 0
+ * for invalid arguments.
  */
 size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dtype);
 
@@ -221,7 +237,8 @@ size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dt
  * filled; the call is complete when it returns, so reading is synchronous.
  * Phases: "receivers"; "d8_up", "d8_forest", "d8_down", "mass" (row-sweep
  * single-receiver path); "sweep" (wavefront sweep passes); "engine"
- * (peeling engine); "batch" (fr_accumulate_batched).  Not thread-safe.
+ * (peeling engine); "batch" (fr_accumulate_batched); "block_iterations"
+ * (fr_accumulate_block_iterations).  Not thread-safe.
  */
 int fr_timing_enable(int on);
 int fr_timing_last(const char** names, float* ms, int max);

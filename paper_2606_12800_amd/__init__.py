@@ -25,7 +25,8 @@ LIB_PATH = os.path.join(_PKG, "libflowroute.so")
 D8, MFD, D4 = 0, 1, 2
 NONE, F32, F64 = 0, 1, 2
 SINK = 0xFF
-FN_ACCUMULATE, FN_ADJOINT, FN_BLOCK_ITER = 1, 2, 3
+FN_ACCUMULATE, FN_ADJOINT, FN_BLOCK_ITER, FN_BLOCK_ITER_PRE = 1, 2, 3, 4
+SCHEME_IX, SCHEME_IMX_IX = 0, 1
 OK = 0
 ERR_ARG, ERR_RULE, ERR_WORKSPACE, ERR_HIP = -1, -2, -3, -4
 ERR_NONFINITE, ERR_NOTDAG, ERR_BADCODE, ERR_TOOLARGE = -5, -6, -7, -8
@@ -92,7 +93,8 @@ def load_library() -> ctypes.CDLL:
     lib.fr_accumulate_batched.restype = ci
     lib.fr_batch_autotune.argtypes = [vp, i32, vp, vp, sz, ci, vp, vp]
     lib.fr_batch_autotune.restype = ci
-    lib.fr_accumulate_block_iterations.argtypes = [vp, i64, i64, ci, vp, ci, ci, vp, vp, i32, vp, vp, vp, sz, vp]
+    lib.fr_accumulate_block_iterations.argtypes = [vp, i64, i64, ci, ci, vp, ci, ci, vp, vp, i32, vp, vp, vp, sz,
+                                                   vp]
     lib.fr_accumulate_block_iterations.restype = ci
     _lib = lib
     return lib
@@ -258,9 +260,14 @@ def adjoint(code: torch.Tensor, qbar: torch.Tensor, z: torch.Tensor | None = Non
 
 def block_iterations(code: torch.Tensor, rain: torch.Tensor | None = None, rule="d8",
                      dtype=torch.float64, counts: bool = True, max_iter: int = 100000,
-                     ws: Workspace | None = None, check: bool = True):
-    """The paper's I+X block iterations (``fr_accumulate_block_iterations``).
+                     ws: Workspace | None = None, check: bool = True, scheme: str = "ix"):
+    """The paper's block Richardson iterations (``fr_accumulate_block_iterations``):
+    scheme "ix" iterates on I+X, "imx_ix" on (I-X)(I+X).
     Returns (q float64 or None, counts or None, iterations until exact)."""
+    schemes = {"ix": SCHEME_IX, "imx_ix": SCHEME_IMX_IX}
+    if scheme not in schemes:
+        raise ValueError(f"unknown scheme {scheme!r}")
+    sch = schemes[scheme]
     _check_grid(code, torch.uint8, "code")
     nr, nc = code.shape
     dev = code.device
@@ -277,10 +284,10 @@ def block_iterations(code: torch.Tensor, rain: torch.Tensor | None = None, rule=
     q = None if dtype is None else torch.empty((nr, nc), dtype=dtype, device=dev)
     cnt = torch.empty((nr, nc), dtype=torch.uint64, device=dev) if counts else None
     status = torch.zeros(1, dtype=torch.int32, device=dev)
-    nbytes = workspace_bytes(FN_BLOCK_ITER, nr, nc, r, dt)
+    nbytes = workspace_bytes(FN_BLOCK_ITER if sch == SCHEME_IX else FN_BLOCK_ITER_PRE, nr, nc, r, dt)
     buf = (ws or _default_ws).get(nbytes, dev)
     iters = ctypes.c_int32(0)
-    rc = load_library().fr_accumulate_block_iterations(_ptr(code), nr, nc, r, _ptr(rain), rdt, dt, _ptr(q),
+    rc = load_library().fr_accumulate_block_iterations(_ptr(code), nr, nc, r, sch, _ptr(rain), rdt, dt, _ptr(q),
                                                        _ptr(cnt), int(max_iter), ctypes.byref(iters),
                                                        _ptr(status), _ptr(buf), buf.numel(), _stream(dev))
     if rc != OK:

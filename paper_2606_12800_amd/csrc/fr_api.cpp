@@ -281,7 +281,7 @@ int run_d8(const uint8_t* code, int64_t nrows, int64_t ncols, const float* rain3
   }
   phase_end(ph, s);
   ph = phase_begin("d8_down", s);
-  if (launch_d8_down(vk, counts, P, fb, s) != hipSuccess) return FR_ERR_HIP;
+  if (launch_d8_down(vk, counts, P, s) != hipSuccess) return FR_ERR_HIP;
   phase_end(ph, s);
   if (mass_out) {
     const int nt = P.ntr * P.ntc;
@@ -478,11 +478,12 @@ const char* fr_status_string(int code) {
   }
 }
 
-// Block iterations: a second float64 value and count per cell (the other
-// iterate) and the change flag.
-size_t block_iter_bytes(int64_t nrows, int64_t ncols) {
+// Block iterations: `vectors` float64 values and counts per cell (I+X: the
+// other iterate; (I-X)(I+X): also D^-1 r and a temporary) and the change
+// flag.
+size_t block_iter_bytes(int64_t nrows, int64_t ncols, int vectors) {
   const size_t n = (size_t)(nrows * ncols);
-  return up(n * sizeof(double)) + up(n * sizeof(uint64_t)) + 2 * kAlign;
+  return (size_t)vectors * (up(n * sizeof(double)) + up(n * sizeof(uint64_t))) + 2 * kAlign;
 }
 
 size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dtype) {
@@ -493,9 +494,9 @@ size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dt
     if (rule == FR_MFD && dtype == FR_NONE) return 0;
   } else if (fn == FR_FN_ADJOINT) {
     if (dtype != FR_F32 && dtype != FR_F64) return 0;
-  } else if (fn == FR_FN_BLOCK_ITER) {
+  } else if (fn == FR_FN_BLOCK_ITER || fn == FR_FN_BLOCK_ITER_PRE) {
     if (rule == FR_MFD || (dtype != FR_NONE && dtype != FR_F64)) return 0;
-    return block_iter_bytes(nrows, ncols);
+    return block_iter_bytes(nrows, ncols, fn == FR_FN_BLOCK_ITER_PRE ? 3 : 1);
   } else {
     return 0;
   }
@@ -599,30 +600,37 @@ int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t nc
   return FR_OK;
 }
 
-int fr_accumulate_block_iterations(const uint8_t* code, int64_t nrows, int64_t ncols, int rule,
+int fr_accumulate_block_iterations(const uint8_t* code, int64_t nrows, int64_t ncols, int rule, int scheme,
                                    const void* rain, int rain_dtype, int q_dtype, void* q_out,
                                    uint64_t* counts_out, int32_t max_iter, int32_t* iters_out,
                                    int32_t* dev_status, void* ws, size_t ws_bytes, hipStream_t stream) {
   if (nrows < 0 || ncols < 0 || !iters_out || max_iter < 1) return FR_ERR_ARG;
   if (rule != FR_D8 && rule != FR_D4) return FR_ERR_RULE;
+  if (scheme != FR_SCHEME_IX && scheme != FR_SCHEME_IMX_IX) return FR_ERR_ARG;
   if (rain && rain_dtype != FR_F32 && rain_dtype != FR_F64) return FR_ERR_ARG;
   if (q_dtype != FR_NONE && q_dtype != FR_F64) return FR_ERR_ARG;
   *iters_out = 0;
   if (nrows == 0 || ncols == 0) return FR_OK;
   if ((q_dtype == FR_NONE) != (q_out == nullptr)) return FR_ERR_ARG;
-  if (q_dtype == FR_NONE && !counts_out) return FR_ERR_ARG;
+  // Convergence is decided on the exact counts for (I-X)(I+X), whose float
+  // iterate keeps moving in its last bits.
+  if (!counts_out && (q_dtype == FR_NONE || scheme == FR_SCHEME_IMX_IX)) return FR_ERR_ARG;
   if (ncols > kMaxCells / nrows) return FR_ERR_TOOLARGE;
   if (!code) return FR_ERR_ARG;
-  if (!ws || ws_bytes < fr_workspace_bytes(FR_FN_BLOCK_ITER, nrows, ncols, rule, q_dtype))
-    return FR_ERR_WORKSPACE;
+  const int fn = scheme == FR_SCHEME_IX ? FR_FN_BLOCK_ITER : FR_FN_BLOCK_ITER_PRE;
+  if (!ws || ws_bytes < fr_workspace_bytes(fn, nrows, ncols, rule, q_dtype)) return FR_ERR_WORKSPACE;
   timing_reset();
   char* base = aligned_base(ws);
   const size_t n = (size_t)(nrows * ncols);
-  double* wq = reinterpret_cast<double*>(base);
-  uint64_t* wc = reinterpret_cast<uint64_t*>(base + up(n * sizeof(double)));
-  int32_t* flag = reinterpret_cast<int32_t*>(base + up(n * sizeof(double)) + up(n * sizeof(uint64_t)));
+  const size_t vb = up(n * sizeof(double)) + up(n * sizeof(uint64_t));
+  const int nvec = scheme == FR_SCHEME_IX ? 1 : 3;
   const ValKind vk = q_dtype == FR_F64 ? VK_F64 : VK_NONE;
   const bool counts = counts_out != nullptr;
+  auto vq = [&](int v) { return vk == VK_F64 ? reinterpret_cast<double*>(base + v * vb) : nullptr; };
+  auto vc = [&](int v) {
+    return counts ? reinterpret_cast<uint64_t*>(base + v * vb + up(n * sizeof(double))) : nullptr;
+  };
+  int32_t* flag = reinterpret_cast<int32_t*>(base + nvec * vb);
   D8Params P{};
   P.nrows = nrows;
   P.ncols = ncols;
@@ -633,16 +641,36 @@ int fr_accumulate_block_iterations(const uint8_t* code, int64_t nrows, int64_t n
   P.rain32 = (rain && rain_dtype == FR_F32) ? static_cast<const float*>(rain) : nullptr;
   P.rain64 = (rain && rain_dtype == FR_F64) ? static_cast<const double*>(rain) : nullptr;
   P.status = dev_status;
-  P.it_changed = flag;
-  // The two iterates alternate between the caller's outputs (iterations 2,
-  // 4, ...) and the workspace (1, 3, ...).  Iteration l leaves its result
-  // where iteration l - 1 read from; once an iterate equals the previous one
-  // both buffers hold the solution.
-  double* qbuf[2] = {static_cast<double*>(q_out), vk == VK_F64 ? wq : nullptr};
-  uint64_t* cbuf[2] = {counts_out, counts ? wc : nullptr};
+  // The two iterates alternate between the caller's outputs (even
+  // iterations) and workspace vector 0 (odd ones); once an iterate equals
+  // the previous one both hold the solution.
+  double* qbuf[2] = {static_cast<double*>(q_out), vq(0)};
+  uint64_t* cbuf[2] = {counts_out, vc(0)};
+  // One block solve into (oq, oc): D^-1 (src + R prev) -- src is the rain
+  // (unit counts) unless nosrc; prev NULL means no water across cut pairs.
+  auto solve = [&](const double* pq, const uint64_t* pc, bool nosrc, bool detect, double* oq,
+                   uint64_t* oc) -> bool {
+    P.q64 = oq;
+    P.cnt = oc;
+    P.it_q64 = pq;
+    P.it_cnt = pc;
+    P.it_first = (pq == nullptr && pc == nullptr) ? 1 : 0;
+    P.it_nosrc = nosrc ? 1 : 0;
+    P.it_detect = detect ? 1 : 0;
+    P.it_changed = flag;
+    return launch_d8_iter(vk, counts, P, stream) == hipSuccess;
+  };
   const int ph = phase_begin("block_iterations", stream);
   int rc = FR_OK;
-  for (int32_t l = 1;; ++l) {
+  if (scheme == FR_SCHEME_IMX_IX) {
+    // b = D^-1 r (vector 1); the iterate starts at 0 in the slot the first
+    // iteration reads.
+    if (!solve(nullptr, nullptr, false, false, vq(1), vc(1)) ||
+        launch_bi_combine(2, (int64_t)n, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, qbuf[0], cbuf[0],
+                          nullptr, stream) != hipSuccess)
+      rc = FR_ERR_HIP;
+  }
+  for (int32_t l = 1; rc == FR_OK; ++l) {
     if (l > max_iter + 1) {
       // No fixed point within the budget: a cycle in the codes, or too few
       // iterations allowed for the block crossings of this grid.
@@ -650,13 +678,24 @@ int fr_accumulate_block_iterations(const uint8_t* code, int64_t nrows, int64_t n
       break;
     }
     const int cur = l & 1, prev = cur ^ 1;
-    P.q64 = qbuf[cur];
-    P.cnt = cbuf[cur];
-    P.it_q64 = qbuf[prev];
-    P.it_cnt = cbuf[prev];
-    P.it_first = l == 1;
-    if (launch_zero_u32(reinterpret_cast<uint32_t*>(flag), 1, stream) != hipSuccess ||
-        launch_d8_iter(vk, counts, P, stream) != hipSuccess) {
+    bool ok = launch_zero_u32(reinterpret_cast<uint32_t*>(flag), 1, stream) == hipSuccess;
+    if (scheme == FR_SCHEME_IX) {
+      // w <- D^-1 (r + R w); the first iteration has no previous iterate.
+      ok = ok && (l == 1 ? solve(nullptr, nullptr, false, false, qbuf[cur], cbuf[cur])
+                         : solve(qbuf[prev], cbuf[prev], false, true, qbuf[cur], cbuf[cur]));
+    } else {
+      // res = b - (I + X) w = b - w + D^-1 R w   (vector 2)
+      // w  <- w + (I - X) res = w + res + D^-1 R res
+      double* w_q = qbuf[prev];
+      uint64_t* w_c = cbuf[prev];
+      ok = ok && solve(w_q, w_c, true, false, vq(2), vc(2)) &&
+           launch_bi_combine(0, (int64_t)n, vq(1), vc(1), w_q, w_c, vq(2), vc(2), nullptr, nullptr, nullptr,
+                             stream) == hipSuccess &&
+           solve(vq(2), vc(2), true, false, qbuf[cur], cbuf[cur]) &&
+           launch_bi_combine(1, (int64_t)n, nullptr, nullptr, w_q, w_c, vq(2), vc(2), qbuf[cur], cbuf[cur], flag,
+                             stream) == hipSuccess;
+    }
+    if (!ok) {
       rc = FR_ERR_HIP;
       break;
     }

@@ -9,20 +9,24 @@
 // class, and like the paper's per-process solves (Section 2.4, Section 3.3)
 // the grid is cut into blocks whose solves are independent:
 //
-//   A. Each 256 x 64 tile is swept by one wavefront, lane = column.  Edges
-//      from row r+1 to row r inside the tile are followed in registers
-//      (cross-lane shifts); every other edge -- leaving the tile, within a
-//      row, or toward a higher row index -- is "cut".  The sweep yields each
-//      cut cell's (exit's) local upstream sum, and a reverse sweep yields, for
-//      every cell that receives over a cut edge (inlet), the exit or sink
-//      where its in-tile path ends (its root).
+//   A. Each tile (th rows x 256 columns) is swept by one wavefront, four
+//      columns per lane.  Edges from row r+1 to row r inside the tile are
+//      followed in registers (cross-lane shifts); every other edge --
+//      leaving the tile, within a row, or toward a higher row index -- is
+//      "cut".  A top-down sweep yields each cut cell's (exit's) local
+//      upstream sum; a bottom-up sweep (its own kernel) yields, for every
+//      cell that receives over a cut edge (inlet), the exit or sink where its
+//      in-tile path ends (its root).
 //   B. The exits form a forest: exit e drains into exit root(receiver(e)),
 //      or nowhere when that root is a sink.  Subtree sums over this forest are
-//      computed by pointer doubling in ceil(log2(depth)) rounds.  These are
-//      the paper's "C + 1 iterations" across block boundaries (Section 3.3,
-//      Appendix B.1), collapsed to a logarithmic number of rounds.
+//      computed by pointer doubling in ceil(log2(depth)) rounds.  These stand
+//      in for the paper's C + 1 block iterations across block boundaries
+//      (Section 3.3, Appendix B), collapsed to a logarithmic number of rounds.
 //   C. Each tile is swept again with the totals of its cut donors added: the
 //      result is final.  The float64 mass balance is reduced in the same pass.
+//
+// The same top-down sweep, fed the previous iterate's water across cut edges
+// instead of forest totals, is one of the paper's block iterations (k_d8_iter).
 //
 // Numerics: float32 water uses float-float (hi, lo) sums throughout; the
 // exit forest adds hi with float atomics and folds each addition's exact
@@ -398,9 +402,11 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
             acc_ff(sh, se, d7, a7.f.hi, a7.f.lo);
             v.f = ff_fast(sh, se);
           }
+          const bool nosrc = ITER && P.it_nosrc;
           if (VK == VK_F64)
-            v.d = (double)rain + (d5 ? a5.d : 0.0) + (d6 ? pv[j].d : 0.0) + (d7 ? a7.d : 0.0);
-          if (CNT) v.n = (CT)1 + (d5 ? a5.n : (CT)0) + (d6 ? pv[j].n : (CT)0) + (d7 ? a7.n : (CT)0);
+            v.d = (nosrc ? 0.0 : (double)rain) + (d5 ? a5.d : 0.0) + (d6 ? pv[j].d : 0.0) + (d7 ? a7.d : 0.0);
+          if (CNT)
+            v.n = (CT)(nosrc ? 0 : 1) + (d5 ? a5.n : (CT)0) + (d6 ? pv[j].n : (CT)0) + (d7 ? a7.n : (CT)0);
           cut[j] = UP ? 0u : cut_donors(above, here, below, j, k, top, rare, tw);
           nv[j] = v;
         }
@@ -512,7 +518,7 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
           }
           __syncthreads();
         }
-        if (ITER && !P.it_first) {
+        if (ITER && !P.it_first && P.it_detect) {
           // Whether this iterate differs from the previous one here.
 #pragma unroll
           for (int j = 0; j < W; ++j) {
@@ -766,9 +772,33 @@ __global__ __launch_bounds__(64) void k_d8_iter(D8Params P) {
   else
     sweep<false, VK, CNT, RAIN, VEC, false, true>(P, T, nullptr, &nonfinite, s_q32, s_q64, s_cnt, &badcode,
                                                    &changed);
-  if (__ballot(changed) && threadIdx.x == 0) *P.it_changed = 1;
+  if (__ballot(changed) && threadIdx.x == 0 && P.it_changed) *P.it_changed = 1;
   if (badcode) set_status(P.status, FR_ERR_BADCODE);
   if (nonfinite) set_status(P.status, FR_ERR_NONFINITE);
+}
+
+__global__ __launch_bounds__(256) void k_bi_combine(int mode, int64_t n, const double* bq, const uint64_t* bc,
+                                                    const double* wq, const uint64_t* wc, double* tq,
+                                                    uint64_t* tc, double* oq, uint64_t* oc, int32_t* changed) {
+  bool chg = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (mode == 0) {
+      if (tq) tq[i] = bq[i] - wq[i] + tq[i];
+      if (tc) tc[i] = bc[i] - wc[i] + tc[i];
+    } else if (mode == 1) {
+      if (oq) oq[i] = wq[i] + tq[i] + oq[i];
+      if (oc) {
+        const uint64_t v = wc[i] + tc[i] + oc[i];
+        oc[i] = v;
+        chg |= v != wc[i];
+      }
+    } else {
+      if (oq) oq[i] = 0.0;
+      if (oc) oc[i] = 0;
+    }
+  }
+  if (mode == 1 && __ballot(chg) && (threadIdx.x & 63) == 0 && changed && *(volatile int32_t*)changed == 0)
+    *changed = 1;
 }
 
 int grid_for(uint32_t n) {
@@ -865,6 +895,17 @@ hipError_t launch_d8_round(ValKind vk, bool cnt, const D8Params& P, uint32_t n, 
   return hipGetLastError();
 }
 
+hipError_t launch_bi_combine(int mode, int64_t n, const double* bq, const uint64_t* bc, const double* wq,
+                             const uint64_t* wc, double* tq, uint64_t* tc, double* oq, uint64_t* oc,
+                             int32_t* changed, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_bi_combine, dim3((unsigned)blocks), dim3(256), 0, s, mode, n, bq, bc, wq, wc, tq, tc, oq,
+                     oc, changed);
+  return hipGetLastError();
+}
+
 hipError_t launch_d8_iter(ValKind vk, bool cnt, const D8Params& P, hipStream_t s) {
   if (vk == VK_FF) return hipErrorInvalidValue;  // float64 values or counts only
   if (vk == VK_F64) {
@@ -876,8 +917,7 @@ hipError_t launch_d8_iter(ValKind vk, bool cnt, const D8Params& P, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_d8_down(ValKind vk, bool cnt, const D8Params& P, int fb, hipStream_t s) {
-  (void)fb;  // the forest sums are summed in place in slot 0
+hipError_t launch_d8_down(ValKind vk, bool cnt, const D8Params& P, hipStream_t s) {
   d8_sweep_dispatch<DownK>(vk, cnt, P, s);
   return hipGetLastError();
 }

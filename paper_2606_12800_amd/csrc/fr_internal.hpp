@@ -108,14 +108,24 @@ struct D8Params {
   const uint64_t* it_cnt;
   int32_t* it_changed;
   int32_t it_first;            // first iteration: no water crosses a cut edge yet
+  int32_t it_nosrc;            // apply D^-1 R only: no rain, no unit count source
+  int32_t it_detect;           // compare with the previous iterate (set it_changed)
 };
 
 // Launchers (defined in the .hip files).
 hipError_t launch_d8_up(ValKind vk, bool cnt, const D8Params& P, hipStream_t s);
 hipError_t launch_d8_link(const D8Params& P, uint32_t n, hipStream_t s);
 hipError_t launch_d8_round(ValKind vk, bool cnt, const D8Params& P, uint32_t n, int b, hipStream_t s);
-hipError_t launch_d8_down(ValKind vk, bool cnt, const D8Params& P, int fb, hipStream_t s);
+hipError_t launch_d8_down(ValKind vk, bool cnt, const D8Params& P, hipStream_t s);
 hipError_t launch_d8_iter(ValKind vk, bool cnt, const D8Params& P, hipStream_t s);
+// Element-wise steps of the (I - X)(I + X) iteration on float64 values and
+// uint64 (wrap-around) counts; either array pair may be NULL.
+//   mode 0 (residual): t = b - w + t
+//   mode 1 (update):   o = w + t + o, *changed = 1 where o's counts differ from w's
+//   mode 2 (clear):    o = 0
+hipError_t launch_bi_combine(int mode, int64_t n, const double* bq, const uint64_t* bc, const double* wq,
+                             const uint64_t* wc, double* tq, uint64_t* tc, double* oq, uint64_t* oc,
+                             int32_t* changed, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
 hipError_t launch_mass_final(const double* partial, int nblocks, double* out, hipStream_t s);
 hipError_t launch_receivers(const float* z, int64_t nrows, int64_t ncols, int rule, uint8_t* code,

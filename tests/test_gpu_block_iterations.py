@@ -1,11 +1,21 @@
-"""The paper's block iterations (Section 3.3 "I+X", Appendix B) on the GPU.
+"""The paper's block iterations (Section 3.3 "I+X" and "(I-X)(I+X)",
+Appendix B) on the GPU.
 
-fr_accumulate_block_iterations runs w <- D^-1 (r + R w) with one top-down
-sweep per 256 x 256 block as D^-1.  Checks: float64 water against the
-oracle's direct solve (<= 1e-10 per cell, the float64 bar), counts
-bit-exact against the oracle and against fr_accumulate, and the number of
-iterations equal to the oracle's block iteration with the same splitting
-(C + 1, C the most pairs outside D along a flow path).
+fr_accumulate_block_iterations runs w <- D^-1 (r + R w) (scheme "ix") or
+w <- w + (I - X)(b - (I + X) w) (scheme "imx_ix") with one top-down sweep
+per 256 x 256 block as D^-1.  Checks: float64 water against the oracle's
+direct solve, counts bit-exact against the oracle and against fr_accumulate,
+and the number of iterations equal to the oracle's block iteration with the
+same scheme and splitting (C + 1, or about half that, C the most pairs
+outside D along a flow path).
+
+Water tolerance.  Scheme "ix" adds the same positive terms as the direct
+solve in another order: <= 1e-10 per cell, the float64 bar.  Scheme
+"imx_ix" also forms the residual b - w + D^-1 R w, a difference of values
+as large as the cell's own water, whose rounding (a few eps q per
+iteration) is carried downstream by the next solves: at most about
+eps * iterations * A relative to q for a cell draining A cells.  With
+A <= 5.3e3 and <= 15 iterations here that is 9e-12: the same 1e-10 bar.
 """
 import numpy as np
 import pytest
@@ -86,4 +96,48 @@ def test_block_iterations_errors():
     assert e.value.code == fr.ERR_NOTDAG
     # Empty grid.
     q, cnt, it = fr.block_iterations(torch.empty((0, 5), dtype=torch.uint8, device="cuda"), None, "d8")
+    assert it == 0 and q.numel() == 0
+
+
+@pytest.mark.parametrize("seed,shape", [(81, (600, 700)), (82, (513, 259)), (83, (1, 900)), (84, (777, 1)),
+                                        (85, (300, 1031))])
+@pytest.mark.parametrize("rule", ["d8", "d4"])
+def test_preconditioned_block_iterations_match_oracle(seed, shape, rule):
+    print(f"(I-X)(I+X) block iterations {rule} seed {seed} shape {shape}", flush=True)
+    r = oracle.D8 if rule == "d8" else oracle.D4
+    z = synth.dem(seed, *shape)
+    rain = synth.rain(seed, *shape)
+    code_h = oracle.receivers(z, r)
+    ref_q, _ = oracle.accumulate_single(code_h, rain, z=z)
+    _, ref_c = oracle.accumulate_single(code_h, None, z=z)
+    _, _, ref_it = oracle.block_richardson(z, BLOCK, r, None, 1, split=1)
+    _, _, ix_it = oracle.block_richardson(z, BLOCK, r, None, 0, split=1)
+    code = fr.receivers(dev(z), rule)
+    q, cnt, it = fr.block_iterations(code, dev(rain), rule, scheme="imx_ix")
+    torch.cuda.synchronize()
+    qh = q.cpu().numpy()
+    assert np.max(np.abs(qh - ref_q) / np.maximum(ref_q, 1e-300)) <= 1e-10
+    assert np.array_equal(cnt.cpu().numpy().astype(np.uint64), ref_c)
+    assert it == ref_it
+    assert it <= (ix_it + 2) // 2 + 1
+
+
+def test_preconditioned_block_iterations_counts_only_and_errors():
+    z = synth.dem(86, 900, 300)
+    code = fr.receivers(dev(z), "d8")
+    _, cnt, it = fr.block_iterations(code, None, "d8", dtype=None, scheme="imx_ix")
+    _, cnt2, it2 = fr.block_iterations(code, None, "d8", dtype=None)
+    assert torch.equal(cnt, cnt2) and it < it2
+    # Convergence is decided on the counts: they are required.
+    with pytest.raises(fr.FlowRouteError) as e:
+        fr.block_iterations(code, None, "d8", counts=False, scheme="imx_ix")
+    assert e.value.code == fr.ERR_ARG
+    with pytest.raises(ValueError):
+        fr.block_iterations(code, None, "d8", scheme="jacobi")
+    if it >= 3:
+        with pytest.raises(fr.FlowRouteError) as e:
+            fr.block_iterations(code, None, "d8", max_iter=it - 2, scheme="imx_ix")
+        assert e.value.code == fr.ERR_NOTDAG
+    q, cnt, it = fr.block_iterations(torch.empty((3, 0), dtype=torch.uint8, device="cuda"), None, "d8",
+                                     scheme="imx_ix")
     assert it == 0 and q.numel() == 0
