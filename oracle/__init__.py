@@ -20,6 +20,8 @@ routing and drainage area determination"):
 * ``block_richardson`` -- the paper's parallel scheme run sequentially: block
                           Richardson iterations on (I+X) and (I-X)(I+X)
                           (Section 3.3, Appendix B)
+* ``fill_depressions`` -- priority-flood depression filling, plain or with an
+                          epsilon step so every cell drains (Section 4)
 
 Pins: every function here is checked in ``tests/test_oracle_pins.py`` against
 things other than itself (the paper's 3x3 example, brute force, library
@@ -79,6 +81,7 @@ def _load():
             "or_mass_single": [vp, i64, vp, vp, vp],
             "or_mass_mfd": [vp, i64, i64, vp, vp, vp],
             "or_block_richardson": [vp, vp, i64, i64, dbl, vp, vp, i64, i64, ci, ci, ci, vp, vp, vp],
+            "or_fill_depressions": [vp, i64, i64, ci, ci, vp],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -179,6 +182,20 @@ def block_richardson(z, block, rule: int = D8, rain=None, scheme: int = 0, p: fl
                                        int(block[1]), int(split), int(scheme), int(max_iter), _p(q), _p(co),
                                        ctypes.addressof(it)), "block_richardson")
     return q, co, it.value
+
+
+def fill_depressions(z, conn: int = 8, eps: bool = True) -> np.ndarray:
+    """Filled float32 surface: boundary cells keep z; every other cell is
+    raised to the lowest level (plus one float32 step per cell crossed when
+    eps) at which it can drain to the boundary through ``conn``-neighbours."""
+    z = _f32(z)
+    nr, nc = z.shape
+    out = np.empty((nr, nc), dtype=np.float32)
+    rc = _load().or_fill_depressions(_p(z), nr, nc, int(conn), int(bool(eps)), _p(out))
+    if rc == -5:
+        raise ValueError("fill_depressions: non-finite elevation")
+    _check(rc, "fill_depressions")
+    return out
 
 
 def adjoint_single(code, qbar, order_=None, z=None) -> np.ndarray:

@@ -510,3 +510,101 @@ int or_block_richardson(const uint8_t* code, const float* z, int64_t nr, int64_t
   free(u2);
   return rc;
 }
+
+/* ------------------------------------------------------------------------
+ * Depression filling before routing (Section 4, where the DEM is filled by
+ * the priority-flood method of Barnes et al. 2014 so that all water reaches
+ * the domain boundary; Section 5 names this sequential step a bottleneck).
+ *
+ * Definition.  With next(x) the next float32 above x (eps = 1) or x itself
+ * (eps = 0), the filled surface F is the solution of
+ *     F(c) = z(c)                                     on the grid boundary,
+ *     F(c) = max(z(c), min over neighbours n of next(F(n)))   elsewhere,
+ * neighbours being the 8 (conn = 8) or the 4 cardinal (conn = 4) cells.  It
+ * equals the lowest, over paths from c to the boundary, of the path's cost,
+ * the cost growing along the path from the boundary as f <- max(z, next(f)).
+ * With eps = 1 every interior cell then has a strictly lower neighbour, so
+ * the strict-descent rules route every cell to the boundary.
+ *
+ * Method (priority flood): seed all boundary cells with F = z, then pop the
+ * open cell of lowest F (ties by index) and give each neighbour not yet
+ * reached F = max(z, next(F(popped))).  Because the cost is monotone in
+ * F(popped), the first time a cell is reached fixes its value (Dijkstra's
+ * argument).  Elevation -0 is read as +0.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  float v;
+  int64_t i;
+} heap_item;
+
+static int heap_less(heap_item a, heap_item b) { return a.v < b.v || (a.v == b.v && a.i < b.i); }
+
+static void heap_push(heap_item* h, int64_t* n, heap_item x) {
+  int64_t k = (*n)++;
+  while (k > 0) {
+    const int64_t p = (k - 1) / 2;
+    if (!heap_less(x, h[p])) break;
+    h[k] = h[p];
+    k = p;
+  }
+  h[k] = x;
+}
+
+static heap_item heap_pop(heap_item* h, int64_t* n) {
+  const heap_item top = h[0];
+  const heap_item last = h[--(*n)];
+  int64_t k = 0;
+  for (;;) {
+    int64_t c = 2 * k + 1;
+    if (c >= *n) break;
+    if (c + 1 < *n && heap_less(h[c + 1], h[c])) ++c;
+    if (!heap_less(h[c], last)) break;
+    h[k] = h[c];
+    k = c;
+  }
+  if (*n > 0) h[k] = last;
+  return top;
+}
+
+int or_fill_depressions(const float* z, int64_t nr, int64_t nc, int conn, int eps, float* out) {
+  if (!z || !out || nr < 0 || nc < 0 || (conn != 8 && conn != 4) || (eps != 0 && eps != 1)) return -2;
+  const int64_t m = nr * nc;
+  for (int64_t i = 0; i < m; ++i)
+    if (!isfinite(z[i])) return -5;
+  if (m == 0) return 0;
+  uint8_t* done = (uint8_t*)calloc((size_t)m, 1);
+  heap_item* h = (heap_item*)malloc((size_t)m * sizeof(heap_item));
+  if (!done || !h) {
+    free(done);
+    free(h);
+    return -2;
+  }
+  int64_t n = 0;
+  for (int64_t r = 0; r < nr; ++r)
+    for (int64_t c = 0; c < nc; ++c)
+      if (r == 0 || c == 0 || r == nr - 1 || c == nc - 1) {
+        const int64_t i = r * nc + c;
+        out[i] = z[i] + 0.0f; /* -0 -> +0 */
+        done[i] = 1;
+        heap_item x = {out[i], i};
+        heap_push(h, &n, x);
+      }
+  while (n > 0) {
+    const heap_item t = heap_pop(h, &n);
+    const int64_t r = t.i / nc, c = t.i % nc;
+    const float up = eps ? nextafterf(t.v, INFINITY) : t.v;
+    for (int k = 0; k < 8; ++k) {
+      if (conn == 4 && NB_DIAG[k]) continue;
+      const int64_t j = neighbour(nr, nc, r, c, k);
+      if (j < 0 || done[j]) continue;
+      const float zj = z[j] + 0.0f;
+      out[j] = zj > up ? zj : up;
+      done[j] = 1;
+      heap_item x = {out[j], j};
+      heap_push(h, &n, x);
+    }
+  }
+  free(done);
+  free(h);
+  return 0;
+}

@@ -513,3 +513,157 @@ def test_block_richardson_sweep_split_crossings_plus_one(seed, shape, blk):
     _, cnt, it = oracle.block_richardson(z, blk, oracle.D8, None, 0, split=1)
     assert it == C + 1
     assert np.array_equal(cnt, ref_c)
+
+
+# --------------------------------------------------------------------------
+# Depression filling (Section 4: priority flood before routing).
+
+def _fill_relaxation(z, conn, eps):
+    """Independent brute force: start from +inf inside, z on the boundary,
+    and apply F <- max(z, min(F, next(F_n))) to every cell at once until
+    nothing changes (Bellman-Ford order instead of the oracle's heap)."""
+    z = np.asarray(z, dtype=np.float32) + np.float32(0.0)
+    nr, nc = z.shape
+    f = np.full((nr + 2, nc + 2), np.inf, dtype=np.float32)  # padded: off-grid = +inf
+    inner = f[1:-1, 1:-1]
+    inner[...] = np.inf
+    bnd = np.zeros((nr, nc), dtype=bool)
+    bnd[0, :] = bnd[-1, :] = bnd[:, 0] = bnd[:, -1] = True
+    inner[bnd] = z[bnd]
+    offs = [(dr, dc) for dr, dc in OFFS if conn == 8 or dr == 0 or dc == 0]
+    while True:
+        m = np.full((nr, nc), np.inf, dtype=np.float32)
+        for dr, dc in offs:
+            m = np.minimum(m, f[1 + dr:1 + dr + nr, 1 + dc:1 + dc + nc])
+        if eps:
+            m = np.nextafter(m, np.float32(np.inf))
+        new = np.where(bnd, z, np.maximum(z, np.minimum(inner, m)))
+        if np.array_equal(new, inner):
+            return new
+        inner[...] = new
+
+
+def _fill_mst_bottleneck(z, conn):
+    """Plain fill from a library minimum spanning tree: the filled level of
+    a cell is the largest edge on its tree path to a virtual outside node,
+    edges weighted max(z_u, z_v) between neighbours and z_b from each
+    boundary cell (the minimax-path property of spanning trees)."""
+    from scipy.sparse.csgraph import breadth_first_order, minimum_spanning_tree
+    z = np.asarray(z, dtype=np.float64)
+    nr, nc = z.shape
+    n = nr * nc
+    shift = 1.0 - z.min()  # csgraph drops zero weights: make all positive
+    rows, cols, w = [], [], []
+    for r in range(nr):
+        for c in range(nc):
+            i = r * nc + c
+            for dr, dc in OFFS:
+                if conn == 4 and dr != 0 and dc != 0:
+                    continue
+                rr, cc = r + dr, c + dc
+                if 0 <= rr < nr and 0 <= cc < nc and rr * nc + cc > i:
+                    rows.append(i)
+                    cols.append(rr * nc + cc)
+                    w.append(max(z[r, c], z[rr, cc]) + shift)
+            if r in (0, nr - 1) or c in (0, nc - 1):
+                rows.append(i)
+                cols.append(n)
+                w.append(z[r, c] + shift)
+    g = sp.coo_matrix((w, (rows, cols)), shape=(n + 1, n + 1)).tocsr()
+    t = minimum_spanning_tree(g)
+    t = (t + t.T).tocsr()
+    order_, pred = breadth_first_order(t, n, directed=False)
+    level = np.zeros(n + 1)
+    level[n] = -np.inf
+    for v in order_[1:]:
+        level[v] = max(level[pred[v]], t[pred[v], v])
+    return (level[:n] - shift).reshape(nr, nc)
+
+
+def _pit_dem(seed, nr, nc):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 12, size=(nr, nc)).astype(np.float32) * np.float32(0.5)
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+@pytest.mark.parametrize("seed,shape", [(1, (9, 11)), (2, (13, 7)), (3, (3, 20)), (4, (17, 17))])
+def test_fill_plain_matches_spanning_tree_bottleneck(conn, seed, shape):
+    z = _pit_dem(seed, *shape)
+    f = oracle.fill_depressions(z, conn, eps=False)
+    ref = _fill_mst_bottleneck(z, conn)
+    assert np.array_equal(f.astype(np.float64), ref)
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+@pytest.mark.parametrize("seed,shape", [(5, (9, 11)), (6, (16, 23)), (7, (1, 9)), (8, (2, 2)), (9, (30, 4))])
+def test_fill_matches_brute_force_relaxation(conn, seed, shape):
+    z = _pit_dem(seed, *shape)
+    for eps in (False, True):
+        assert np.array_equal(oracle.fill_depressions(z, conn, eps), _fill_relaxation(z, conn, eps))
+    zf = synth.dem(seed, 40, 37)
+    assert np.array_equal(oracle.fill_depressions(zf, conn, True), _fill_relaxation(zf, conn, True))
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_fill_crater_closed_form(conn):
+    # Rim at 10 with one spill cell at 5 on the top edge, flat floor at 0:
+    # the floor fills to 5, and with eps each floor cell sits one float32
+    # step above the cell before it on a shortest hop path to the spill
+    # (Chebyshev distance for 8 neighbours, Manhattan for 4).
+    nr, nc, k = 9, 12, 4
+    z = np.full((nr, nc), 10.0, dtype=np.float32)
+    z[1:-1, 1:-1] = 0.0
+    z[0, k] = 5.0
+    plain = oracle.fill_depressions(z, conn, eps=False)
+    assert np.all(plain[1:-1, 1:-1] == 5.0) and np.array_equal(plain[0], z[0])
+    f = oracle.fill_depressions(z, conn, eps=True)
+    for i in range(1, nr - 1):
+        for j in range(1, nc - 1):
+            d = max(i, abs(j - k)) if conn == 8 else i + abs(j - k)
+            v = np.float32(5.0)
+            for _ in range(d):
+                v = np.nextafter(v, np.float32(np.inf))
+            assert f[i, j] == v, (i, j)
+    assert np.array_equal(f[[0, -1]], z[[0, -1]]) and np.array_equal(f[:, [0, -1]], z[:, [0, -1]])
+
+
+@pytest.mark.parametrize("rule,conn", [(oracle.D8, 8), (oracle.D4, 4)])
+def test_fill_invariants_and_drainage(rule, conn):
+    z = synth.dem(11, 120, 97)
+    f = oracle.fill_depressions(z, conn, True)
+    assert np.all(f >= z)
+    bnd = np.zeros(z.shape, dtype=bool)
+    bnd[0, :] = bnd[-1, :] = bnd[:, 0] = bnd[:, -1] = True
+    assert np.array_equal(f[bnd], z[bnd])
+    # The DEM had interior pits; after filling every interior cell drains.
+    code0 = oracle.receivers(z, rule)
+    assert np.any((code0 == oracle.SINK) & ~bnd)
+    code = oracle.receivers(f, rule)
+    assert not np.any((code == oracle.SINK) & ~bnd)
+    # Idempotent, and a surface that already drains is left alone.
+    assert np.array_equal(oracle.fill_depressions(f, conn, True), f)
+    plain = oracle.fill_depressions(z, conn, False)
+    assert np.array_equal(oracle.fill_depressions(plain, conn, False), plain)
+    assert np.all(f >= plain)
+    rr, cc = np.mgrid[0:50, 0:60]
+    tilt = (rr + 2 * cc).astype(np.float32)
+    assert np.array_equal(oracle.fill_depressions(tilt, conn, True), tilt)
+    # Tight: each raised cell sits one step above its lowest neighbour.
+    pad = np.pad(f, 1, constant_values=np.inf)
+    offs = [(dr, dc) for dr, dc in OFFS if conn == 8 or dr == 0 or dc == 0]
+    m = np.min([pad[1 + dr:1 + dr + f.shape[0], 1 + dc:1 + dc + f.shape[1]] for dr, dc in offs], axis=0)
+    raised = (f > z) & ~bnd
+    assert np.any(raised)
+    assert np.array_equal(f[raised], np.nextafter(m, np.float32(np.inf))[raised])
+    # Section 4 check on the filled DEM: all rain leaves through the boundary.
+    rain = synth.rain(11, *z.shape)
+    q, _ = oracle.accumulate_single(code, rain, z=f)
+    out, total = oracle.mass_single(code, q, rain)
+    assert abs(out - total) <= 1e-12 * total
+
+
+def test_fill_rejects_non_finite():
+    z = np.zeros((4, 4), dtype=np.float32)
+    z[2, 1] = np.nan
+    with pytest.raises(ValueError):
+        oracle.fill_depressions(z)
