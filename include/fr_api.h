@@ -79,6 +79,7 @@ extern "C" {
 #define FR_FN_ADJOINT 2
 #define FR_FN_BLOCK_ITER 3      /* block iterations, scheme FR_SCHEME_IX     */
 #define FR_FN_BLOCK_ITER_PRE 4  /* block iterations, scheme FR_SCHEME_IMX_IX */
+#define FR_FN_FILL 5            /* depression filling (dtype FR_F32)         */
 
 /* Iteration schemes of fr_accumulate_block_iterations. */
 #define FR_SCHEME_IX 0      /* Richardson on I + X                         */
@@ -220,10 +221,39 @@ int fr_accumulate_block_iterations(const uint8_t* code, int64_t nrows, int64_t n
                                    int32_t* dev_status, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * fr_fill_depressions -- depression filling before routing (Section 4: the
+ * DEM is filled by the priority-flood method so that all water reaches the
+ * domain boundary).  Writes the filled surface F: F = z on the grid
+ * boundary, elsewhere F(c) = max(z(c), min over neighbours n of next(F(n))),
+ * next(x) being the next float32 above x when eps = 1 (then every interior
+ * cell has a strictly lower neighbour and the rule routes it to the
+ * boundary) or x itself when eps = 0 (depressions become flats).  This is
+ * the priority-flood result, computed by tiled relaxation; it is exact (no
+ * rounding), bit for bit.
+ *
+ *   z         device float32[nrows*ncols] elevations, all finite; -0 is read
+ *             as +0.
+ *   rule      FR_D8 or FR_MFD: 8 neighbours; FR_D4: the 4 cardinal ones
+ *             (the neighbours the rule can route to).
+ *   eps       1 (epsilon variant) or 0 (plain).
+ *   f_out     device float32[nrows*ncols], written; must not alias z.
+ *   launches_out  host int32 or NULL: tile launches until nothing changed
+ *             (diagnostic).
+ *   dev_status optional device int32: FR_ERR_NONFINITE if z holds NaN or Inf
+ *             (f_out is then unspecified).
+ *   ws, ws_bytes  workspace of fr_workspace_bytes(FR_FN_FILL, nrows, ncols,
+ *             rule, FR_F32), a few bytes per 62 x 62 tile.
+ * Synchronises with the stream every few launches.  Errors: FR_ERR_ARG,
+ * FR_ERR_RULE, FR_ERR_WORKSPACE, FR_ERR_TOOLARGE, FR_ERR_HIP.
+ */
+int fr_fill_depressions(const float* z, int64_t nrows, int64_t ncols, int rule, int eps, float* f_out,
+                        int32_t* launches_out, int32_t* dev_status, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
  * fr_workspace_bytes -- workspace size for fn = FR_FN_ACCUMULATE,
- * FR_FN_ADJOINT, FR_FN_BLOCK_ITER or FR_FN_BLOCK_ITER_PRE on an nrows x
- * ncols grid with this rule and dtype (FR_NONE means counts only).  Returns 0
- * for invalid arguments.
+ * FR_FN_ADJOINT, FR_FN_BLOCK_ITER, FR_FN_BLOCK_ITER_PRE or FR_FN_FILL on an
+ * nrows x ncols grid with this rule and dtype (FR_NONE means counts only).
+ * Returns 0 for invalid arguments.
  */
 size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dtype);
 
@@ -238,7 +268,8 @@ size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dt
  * Phases: "receivers"; "d8_up", "d8_forest", "d8_down", "mass" (row-sweep
  * single-receiver path); "sweep" (wavefront sweep passes); "engine"
  * (peeling engine); "batch" (fr_accumulate_batched); "block_iterations"
- * (fr_accumulate_block_iterations).  Not thread-safe.
+ * (fr_accumulate_block_iterations); "fill" (fr_fill_depressions).  Not
+ * thread-safe.
  */
 int fr_timing_enable(int on);
 int fr_timing_last(const char** names, float* ms, int max);

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_PKG, "libflowroute.so")
 D8, MFD, D4 = 0, 1, 2
 NONE, F32, F64 = 0, 1, 2
 SINK = 0xFF
-FN_ACCUMULATE, FN_ADJOINT, FN_BLOCK_ITER, FN_BLOCK_ITER_PRE = 1, 2, 3, 4
+FN_ACCUMULATE, FN_ADJOINT, FN_BLOCK_ITER, FN_BLOCK_ITER_PRE, FN_FILL = 1, 2, 3, 4, 5
 SCHEME_IX, SCHEME_IMX_IX = 0, 1
 OK = 0
 ERR_ARG, ERR_RULE, ERR_WORKSPACE, ERR_HIP = -1, -2, -3, -4
@@ -35,7 +35,7 @@ RULES = {"d8": D8, "mfd": MFD, "d4": D4}
 EXPORTS = ["fr_receivers", "fr_accumulate", "fr_accumulate_adjoint", "fr_workspace_bytes",
            "fr_status_string", "fr_version", "fr_timing_enable", "fr_timing_last",
            "fr_batched_workspace_bytes", "fr_accumulate_batched", "fr_batch_autotune",
-           "fr_accumulate_block_iterations"]
+           "fr_accumulate_block_iterations", "fr_fill_depressions"]
 ORDER_GIVEN, ORDER_ROWS_DESC = 0, 1
 
 
@@ -96,6 +96,8 @@ def load_library() -> ctypes.CDLL:
     lib.fr_accumulate_block_iterations.argtypes = [vp, i64, i64, ci, ci, vp, ci, ci, vp, vp, i32, vp, vp, vp, sz,
                                                    vp]
     lib.fr_accumulate_block_iterations.restype = ci
+    lib.fr_fill_depressions.argtypes = [vp, i64, i64, ci, ci, vp, vp, vp, vp, sz, vp]
+    lib.fr_fill_depressions.restype = ci
     _lib = lib
     return lib
 
@@ -295,6 +297,30 @@ def block_iterations(code: torch.Tensor, rain: torch.Tensor | None = None, rule=
     if check:
         _raise_status(status, "fr_accumulate_block_iterations")
     return q, cnt, iters.value
+
+
+def fill_depressions(z: torch.Tensor, rule="d8", eps: bool = True, ws: Workspace | None = None,
+                     check: bool = True, launches: bool = False):
+    """Depression filling (``fr_fill_depressions``): the priority-flood
+    surface, with one float32 step per cell crossed when ``eps`` so that the
+    rule routes every cell to the boundary.  Returns the filled float32
+    grid (and the number of tile launches when ``launches``)."""
+    _check_grid(z, torch.float32, "z")
+    nr, nc = z.shape
+    dev = z.device
+    r = _rule(rule)
+    f = torch.empty_like(z)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    nbytes = workspace_bytes(FN_FILL, nr, nc, r, F32)
+    buf = (ws or _default_ws).get(nbytes, dev)
+    n = ctypes.c_int32(0)
+    rc = load_library().fr_fill_depressions(_ptr(z), nr, nc, r, int(bool(eps)), _ptr(f), ctypes.byref(n),
+                                            _ptr(status), _ptr(buf), buf.numel(), _stream(dev))
+    if rc != OK:
+        raise FlowRouteError(rc, "fr_fill_depressions")
+    if check:
+        _raise_status(status, "fr_fill_depressions")
+    return (f, n.value) if launches else f
 
 
 def route(z: torch.Tensor, rain: torch.Tensor | None = None, rule="d8", dtype=torch.float32,

@@ -478,6 +478,13 @@ const char* fr_status_string(int code) {
   }
 }
 
+// Depression filling: one stamp per 62 x 62 tile and the last-change word.
+constexpr int64_t kFillTile = 62;
+size_t fill_bytes(int64_t nrows, int64_t ncols) {
+  const size_t ntiles = (size_t)((nrows + kFillTile - 1) / kFillTile) * (size_t)((ncols + kFillTile - 1) / kFillTile);
+  return up((ntiles + 1) * sizeof(int32_t)) + kAlign;
+}
+
 // Block iterations: `vectors` float64 values and counts per cell (I+X: the
 // other iterate; (I-X)(I+X): also D^-1 r and a temporary) and the change
 // flag.
@@ -497,6 +504,9 @@ size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dt
   } else if (fn == FR_FN_BLOCK_ITER || fn == FR_FN_BLOCK_ITER_PRE) {
     if (rule == FR_MFD || (dtype != FR_NONE && dtype != FR_F64)) return 0;
     return block_iter_bytes(nrows, ncols, fn == FR_FN_BLOCK_ITER_PRE ? 3 : 1);
+  } else if (fn == FR_FN_FILL) {
+    if (dtype != FR_F32) return 0;
+    return fill_bytes(nrows, ncols);
   } else {
     return 0;
   }
@@ -523,6 +533,52 @@ int fr_receivers(const float* z, int64_t nrows, int64_t ncols, int rule, uint8_t
   const hipError_t e = launch_receivers(z, nrows, ncols, rule, code_out, dev_status, stream);
   phase_end(ph, stream);
   return e == hipSuccess ? FR_OK : FR_ERR_HIP;
+}
+
+int fr_fill_depressions(const float* z, int64_t nrows, int64_t ncols, int rule, int eps, float* f_out,
+                        int32_t* launches_out, int32_t* dev_status, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (nrows < 0 || ncols < 0 || (eps != 0 && eps != 1)) return FR_ERR_ARG;
+  if (!valid_rule(rule)) return FR_ERR_RULE;
+  if (launches_out) *launches_out = 0;
+  if (nrows == 0 || ncols == 0) return FR_OK;
+  if (ncols > kMaxCells / nrows) return FR_ERR_TOOLARGE;
+  if (!z || !f_out || static_cast<const void*>(z) == static_cast<const void*>(f_out)) return FR_ERR_ARG;
+  if (!ws || ws_bytes < fill_bytes(nrows, ncols)) return FR_ERR_WORKSPACE;
+  timing_reset();
+  const int32_t ntr = (int32_t)((nrows + kFillTile - 1) / kFillTile);
+  const int32_t ntc = (int32_t)((ncols + kFillTile - 1) / kFillTile);
+  int32_t* stamp = reinterpret_cast<int32_t*>(aligned_base(ws));
+  int32_t* last = stamp + (size_t)ntr * ntc;
+  const bool c8 = rule != FR_D4;
+  const int ph = phase_begin("fill", stream);
+  int rc = FR_OK;
+  if (launch_fill_init(z, f_out, nrows, ncols, stamp, ntr * ntc, last, dev_status, stream) != hipSuccess)
+    rc = FR_ERR_HIP;
+  // Launches go out in batches; after each the host reads the launch index
+  // of the latest change: none in the batch's final launch means no tile
+  // can change any more.  Every launch lowers values or changes nothing, so
+  // this ends.
+  constexpr int32_t kBatch = 8;
+  for (int32_t k = 0; rc == FR_OK; k += kBatch) {
+    for (int32_t j = k; j < k + kBatch && rc == FR_OK; ++j)
+      if (launch_fill_tiles(z, f_out, nrows, ncols, ntr, ntc, eps != 0, c8, stamp, last, j, stream) != hipSuccess)
+        rc = FR_ERR_HIP;
+    int32_t lastk = 0, st = 0;
+    if (rc != FR_OK ||
+        hipMemcpyAsync(&lastk, last, sizeof lastk, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        (dev_status && hipMemcpyAsync(&st, dev_status, sizeof st, hipMemcpyDeviceToHost, stream) != hipSuccess) ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+      rc = FR_ERR_HIP;
+      break;
+    }
+    if (st != 0) break;
+    if (lastk < k + kBatch - 1) {
+      if (launches_out) *launches_out = lastk + 2;  // through the first launch without a change
+      break;
+    }
+  }
+  phase_end(ph, stream);
+  return rc;
 }
 
 int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t ncols, int rule, double mfd_p,

@@ -1,0 +1,172 @@
+"""Depression filling on the GPU (the priority-flood surface the paper fills
+the DEM with before routing, Section 4) against the oracle's priority flood.
+
+Every operation on the path is exact (order-preserving keys, min, max, one
+float32 step), so the filled surface must match bit for bit: D8/MFD (8
+neighbours) and D4 (4), plain and epsilon variants, ragged shapes across
+several 62 x 62 tiles, thin grids that are all boundary, a crater and a
+serpentine channel whose flood path crosses tile boundaries many times.  At
+sizes the oracle cannot take, the fixed-point equation itself is checked at
+every cell: it has exactly one solution, so that check is complete.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+fr = pytest.importorskip("paper_2606_12800_amd")
+
+CONN = {"d8": 8, "d4": 4, "mfd": 8}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fr.load_library()
+    yield
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _bits_equal(a, b):
+    return np.array_equal(np.asarray(a, dtype=np.float32).view(np.uint32), np.asarray(b, dtype=np.float32).view(np.uint32))
+
+
+def _pits(seed, nr, nc):
+    rng = np.random.default_rng(seed)
+    return (rng.integers(0, 40, size=(nr, nc)) * 0.25).astype(np.float32)
+
+
+def _crater(nr, nc, spill_col):
+    z = np.full((nr, nc), 100.0, dtype=np.float32)
+    z[1:-1, 1:-1] = 1.0
+    z[0, spill_col] = 7.0
+    return z
+
+
+def _serpentine(nr, nc, wall=90.0):
+    """Low floor cut into lanes by walls with alternating gaps: the only
+    way out winds through every lane, crossing tile rows many times."""
+    z = np.full((nr, nc), 5.0, dtype=np.float32)
+    for r in range(4, nr - 4, 6):
+        z[r, :] = wall
+        if (r // 6) % 2:
+            z[r, 2:4] = 5.0
+        else:
+            z[r, nc - 4:nc - 2] = 5.0
+    z[:, 0] = z[:, -1] = wall
+    z[-1, :] = wall
+    z[0, :] = wall
+    z[0, 3] = 6.0
+    return z
+
+
+def _check(z, rule, eps):
+    print(f"fill {rule} eps={eps} shape {z.shape}", flush=True)
+    f, n = fr.fill_depressions(dev(z), rule, eps, launches=True)
+    torch.cuda.synchronize()
+    ref = oracle.fill_depressions(z, CONN[rule], eps)
+    assert _bits_equal(f.cpu().numpy(), ref)
+    return n
+
+
+@pytest.mark.parametrize("rule", ["d8", "d4", "mfd"])
+@pytest.mark.parametrize("eps", [True, False])
+@pytest.mark.parametrize("seed,shape", [(1, (1, 1)), (2, (1, 70)), (3, (70, 2)), (4, (3, 3)), (5, (62, 62)),
+                                        (6, (64, 64)), (7, (63, 125)), (8, (200, 300)), (9, (517, 333))])
+def test_fill_matches_oracle(rule, eps, seed, shape):
+    _check(synth.dem(seed, *shape, tilt=0.0), rule, eps)
+
+
+@pytest.mark.parametrize("rule", ["d8", "d4"])
+def test_fill_random_pits_and_crater(rule):
+    for eps in (True, False):
+        _check(_pits(21, 301, 157), rule, eps)
+        _check(_crater(250, 390, 200), rule, eps)
+
+
+@pytest.mark.parametrize("rule", ["d8", "d4"])
+def test_fill_serpentine_many_tile_crossings(rule):
+    z = _serpentine(400, 300)
+    n = _check(z, rule, True)
+    # The flood winds through ~66 lanes: many launches, each reaching the
+    # tiles next to the last change.
+    assert n > 3
+
+
+def test_fill_then_route_drains_to_boundary():
+    z = synth.dem(31, 400, 517, tilt=0.0)
+    zf = fr.fill_depressions(dev(z), "d8", True)
+    code0 = fr.receivers(dev(z), "d8").cpu().numpy()
+    code, q, _, mass = fr.route(zf, dev(synth.rain(31, 400, 517)), "d8", torch.float64, mass=True)
+    c = code.cpu().numpy()
+    inner = np.zeros(z.shape, dtype=bool)
+    inner[1:-1, 1:-1] = True
+    assert np.any((code0 == fr.SINK) & inner)
+    assert not np.any((c == fr.SINK) & inner)
+    out, total = mass.cpu().tolist()
+    assert abs(out - total) <= 1e-12 * total
+
+
+def test_fill_errors_and_empty():
+    z = synth.dem(41, 50, 60)
+    z[10, 20] = np.nan
+    with pytest.raises(fr.FlowRouteError) as e:
+        fr.fill_depressions(dev(z), "d8")
+    assert e.value.code == fr.ERR_NONFINITE
+    e0 = fr.fill_depressions(torch.empty((0, 7), dtype=torch.float32, device="cuda"))
+    assert e0.shape == (0, 7)
+    with pytest.raises(ValueError):
+        fr.fill_depressions(dev(np.zeros(5, dtype=np.float32)))
+    lib = fr.load_library()
+    zz = dev(synth.dem(42, 10, 10))
+    ws = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    import ctypes
+    rc = lib.fr_fill_depressions(zz.data_ptr(), 10, 10, fr.D8, 1, zz.data_ptr(), None, None, ws.data_ptr(), 4096,
+                                 None)
+    assert rc == fr.ERR_ARG  # output aliases the input
+    out = torch.empty_like(zz)
+    rc = lib.fr_fill_depressions(zz.data_ptr(), 10, 10, fr.D8, 2, out.data_ptr(), None, None, ws.data_ptr(), 4096,
+                                 None)
+    assert rc == fr.ERR_ARG  # eps not 0/1
+    rc = lib.fr_fill_depressions(zz.data_ptr(), 10, 10, fr.D8, 1, out.data_ptr(), None, None, ws.data_ptr(), 1,
+                                 None)
+    assert rc == fr.ERR_WORKSPACE
+    del ctypes
+
+
+def _fixed_point_ok(z, f, conn, eps):
+    """F = z on the boundary and F = max(z, min_n next(F_n)) inside, checked
+    with torch on the device in float32 (exact operations)."""
+    inf = torch.tensor(float("inf"), device=f.device)
+    pad = torch.nn.functional.pad(f[None, None], (1, 1, 1, 1), value=float("inf"))[0, 0]
+    nr, nc = f.shape
+    m = torch.full_like(f, float("inf"))
+    for dr in (-1, 0, 1):
+        for dc in (-1, 0, 1):
+            if (dr, dc) == (0, 0) or (conn == 4 and dr != 0 and dc != 0):
+                continue
+            m = torch.minimum(m, pad[1 + dr:1 + dr + nr, 1 + dc:1 + dc + nc])
+    if eps:
+        m = torch.nextafter(m, inf)
+    want = torch.maximum(z, m)
+    ok_in = torch.equal(f[1:-1, 1:-1], want[1:-1, 1:-1])
+    ok_b = (torch.equal(f[0], z[0]) and torch.equal(f[-1], z[-1]) and torch.equal(f[:, 0], z[:, 0])
+            and torch.equal(f[:, -1], z[:, -1]))
+    return ok_in and ok_b
+
+
+@pytest.mark.parametrize("rule,n", [("d8", 4096), ("d4", 2500)])
+def test_fill_fixed_point_large(rule, n):
+    print(f"fill fixed point {rule} {n}x{n}", flush=True)
+    z = dev(synth.dem(51, n, n, tilt=0.0))
+    f = fr.fill_depressions(z, rule, True)
+    assert _fixed_point_ok(z, f, CONN[rule], True)
+    assert bool((f >= z).all())
