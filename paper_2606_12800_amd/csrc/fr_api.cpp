@@ -478,11 +478,12 @@ const char* fr_status_string(int code) {
   }
 }
 
-// Depression filling: one stamp per 62 x 62 tile and the last-change word.
+// Depression filling: per 62 x 62 tile a queue mark and three list slots,
+// plus the list lengths and the last-change word.
 constexpr int64_t kFillTile = 62;
 size_t fill_bytes(int64_t nrows, int64_t ncols) {
   const size_t ntiles = (size_t)((nrows + kFillTile - 1) / kFillTile) * (size_t)((ncols + kFillTile - 1) / kFillTile);
-  return up((ntiles + 1) * sizeof(int32_t)) + kAlign;
+  return up((4 * ntiles + 4) * sizeof(int32_t)) + kAlign;
 }
 
 // Block iterations: `vectors` float64 values and counts per cell (I+X: the
@@ -547,32 +548,38 @@ int fr_fill_depressions(const float* z, int64_t nrows, int64_t ncols, int rule, 
   timing_reset();
   const int32_t ntr = (int32_t)((nrows + kFillTile - 1) / kFillTile);
   const int32_t ntc = (int32_t)((ncols + kFillTile - 1) / kFillTile);
-  int32_t* stamp = reinterpret_cast<int32_t*>(aligned_base(ws));
-  int32_t* last = stamp + (size_t)ntr * ntc;
+  const size_t ntiles = (size_t)ntr * ntc;
+  FillState S;
+  S.ntr = ntr;
+  S.ntc = ntc;
+  S.queued = reinterpret_cast<int32_t*>(aligned_base(ws));
+  S.list = S.queued + ntiles;
+  S.nlist = S.list + 3 * ntiles;
+  S.last = S.nlist + 3;
   const bool c8 = rule != FR_D4;
   const int ph = phase_begin("fill", stream);
   int rc = FR_OK;
-  if (launch_fill_init(z, f_out, nrows, ncols, stamp, ntr * ntc, last, dev_status, stream) != hipSuccess)
-    rc = FR_ERR_HIP;
-  // Launches go out in batches; after each the host reads the launch index
-  // of the latest change: none in the batch's final launch means no tile
-  // can change any more.  Every launch lowers values or changes nothing, so
-  // this ends.
+  if (launch_fill_init(z, f_out, nrows, ncols, S, dev_status, stream) != hipSuccess) rc = FR_ERR_HIP;
+  // Launches go out in batches; after each the host reads the length of the
+  // next work list: empty means no tile changed in the batch's final launch,
+  // so none can change any more.  Every launch lowers values or changes
+  // nothing, so this ends.
   constexpr int32_t kBatch = 8;
   for (int32_t k = 0; rc == FR_OK; k += kBatch) {
     for (int32_t j = k; j < k + kBatch && rc == FR_OK; ++j)
-      if (launch_fill_tiles(z, f_out, nrows, ncols, ntr, ntc, eps != 0, c8, stamp, last, j, stream) != hipSuccess)
-        rc = FR_ERR_HIP;
-    int32_t lastk = 0, st = 0;
+      if (launch_fill_tiles(z, f_out, nrows, ncols, eps != 0, c8, S, j, stream) != hipSuccess) rc = FR_ERR_HIP;
+    int32_t pending = 0, lastk = 0, st = 0;
     if (rc != FR_OK ||
-        hipMemcpyAsync(&lastk, last, sizeof lastk, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipMemcpyAsync(&pending, S.nlist + (k + kBatch) % 3, sizeof pending, hipMemcpyDeviceToHost, stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(&lastk, S.last, sizeof lastk, hipMemcpyDeviceToHost, stream) != hipSuccess ||
         (dev_status && hipMemcpyAsync(&st, dev_status, sizeof st, hipMemcpyDeviceToHost, stream) != hipSuccess) ||
         hipStreamSynchronize(stream) != hipSuccess) {
       rc = FR_ERR_HIP;
       break;
     }
     if (st != 0) break;
-    if (lastk < k + kBatch - 1) {
+    if (pending == 0) {
       if (launches_out) *launches_out = lastk + 2;  // through the first launch without a change
       break;
     }

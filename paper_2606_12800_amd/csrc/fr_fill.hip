@@ -19,9 +19,9 @@
 // read once per launch and never updated, so no lane needs an edge case.
 // Elevations stay in LDS, read in either orientation.  A tile repeats its
 // four sweeps until a round changes nothing (or a round cap is reached),
-// then writes its own cells back.  Launch k runs only the tiles next to a
-// tile that changed in launch k - 1 (per-tile stamps); the host stops after
-// a launch in which no tile changed.
+// then writes its own cells back.  Launch k works through a list of the
+// tiles next to a tile that changed in launch k - 1 (the first list: the
+// tiles on the grid's perimeter); the host stops once a list is empty.
 #include "fr_internal.hpp"
 
 namespace fr {
@@ -90,47 +90,56 @@ __device__ __forceinline__ void transpose(uint32_t (&a)[FT], uint32_t (*sT)[FT +
   for (int s = 0; s < FT; ++s) a[s] = sT[lane][s];
 }
 
-// F = z on the grid boundary, +inf elsewhere; stamps cleared.
+// Position of tile (tr, tc) in the list of tiles on the grid's perimeter,
+// or -1 inside.
+__device__ __forceinline__ int32_t perimeter_slot(int32_t tr, int32_t tc, int32_t ntr, int32_t ntc) {
+  if (ntr == 1) return tc;
+  if (tr == 0) return tc;
+  if (tr == ntr - 1) return ntc + tc;
+  if (ntc == 1) return 2 * ntc + (tr - 1);
+  if (tc == 0) return 2 * ntc + 2 * (tr - 1);
+  if (tc == ntc - 1) return 2 * ntc + 2 * (tr - 1) + 1;
+  return -1;
+}
+
+// F = z on the grid boundary, +inf elsewhere.  The first work list holds the
+// tiles on the grid's perimeter (inside, +inf cells next to +inf cells
+// cannot change).
 __global__ __launch_bounds__(256) void k_fill_init(const float* __restrict__ z, float* __restrict__ F,
-                                                   int64_t nr, int64_t nc, int32_t* stamp, int32_t ntiles,
-                                                   int32_t* last, int32_t* status) {
+                                                   int64_t nr, int64_t nc, FillState S, int32_t* status) {
   bool bad = false;
   const int64_t n = nr * nc;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const float v = z[i];
     bad |= !isfinite(v);
     const int64_t r = i / nc, c = i - r * nc;
     const bool edge = r == 0 || c == 0 || r == nr - 1 || c == nc - 1;
     F[i] = edge ? v + 0.0f : __uint_as_float(0x7F800000u);
   }
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * blockDim.x)
-    stamp[t] = -10;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *last = -1;
+  const int32_t ntiles = S.ntr * S.ntc;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += stride) {
+    const int32_t tr = (int32_t)(t / S.ntc), tc = (int32_t)(t - (int64_t)tr * S.ntc);
+    const int32_t p = perimeter_slot(tr, tc, S.ntr, S.ntc);
+    S.queued[t] = p >= 0 ? 0 : -1;
+    if (p >= 0) S.list[p] = (int32_t)t;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S.nlist[0] = S.ntr == 1 ? S.ntc : (S.ntc == 1 ? S.ntr : 2 * S.ntc + 2 * (S.ntr - 2));
+    S.nlist[1] = 0;
+    S.nlist[2] = 0;
+    *S.last = -1;
+  }
   if (bad && status) atomicCAS(status, 0, FR_ERR_NONFINITE);
 }
 
-// Launch k.  stamp[t] = 2k when tile t changed in launch k and converged,
-// 2k + 1 when it stopped at the round cap (it then runs again itself).
+// Relaxes tile t until a round changes nothing or the round cap is hit and
+// writes its cells back if any changed.  Returns 0 (no change), 1 (changed,
+// converged) or 2 (changed, stopped at the cap).
 template <bool EPS, bool C8>
-__global__ __launch_bounds__(FT) void k_fill_tile(const float* __restrict__ z, float* F, int64_t nr, int64_t nc,
-                                                  int32_t ntr, int32_t ntc, int32_t* stamp, int32_t* last,
-                                                  int32_t k) {
-  __shared__ uint32_t sT[FT][FT + 1];
-  __shared__ uint32_t sZ[FT][FT + 1];  // [window row][window column]
-  const int lane = threadIdx.x;
-  const int32_t t = blockIdx.x;
-  const int32_t tr = t / ntc, tc = t - tr * ntc;
-  if (k > 0) {
-    bool act = false;
-    if (lane < 9) {
-      const int32_t rr = tr + lane / 3 - 1, cc = tc + lane % 3 - 1;
-      if (rr >= 0 && rr < ntr && cc >= 0 && cc < ntc) {
-        const int32_t st = __hip_atomic_load(&stamp[rr * ntc + cc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        act = lane == 4 ? st == 2 * (k - 1) + 1 : (st >> 1) == k - 1;
-      }
-    }
-    if (!__any(act)) return;
-  }
+__device__ __forceinline__ int fill_tile(const float* __restrict__ z, float* F, int64_t nr, int64_t nc,
+                                         int32_t tr, int32_t tc, uint32_t (*sT)[FT + 1], uint32_t (*sZ)[FT + 1],
+                                         int lane) {
   // Window row w is grid row wr0 + w; window column lane is grid column
   // wc0 + lane.  Cells off the grid are +inf with elevation +inf: they never
   // change and lower nothing.
@@ -138,6 +147,7 @@ __global__ __launch_bounds__(FT) void k_fill_tile(const float* __restrict__ z, f
   const int64_t col = wc0 + lane;
   const bool col_in = col >= 0 && col < nc;
   uint32_t f[FT];
+  __syncthreads();  // the previous tile's LDS reads are done
 #pragma unroll
   for (int s = 0; s < FT; ++s) {
     const int64_t row = wr0 + s;
@@ -165,40 +175,74 @@ __global__ __launch_bounds__(FT) void k_fill_tile(const float* __restrict__ z, f
     }
     any = true;
   }
-  if (!any) return;
+  if (!any) return 0;
 #pragma unroll
   for (int s = 1; s < FT - 1; ++s) {
     const int64_t row = wr0 + s;
     if (inner && col_in && row < nr) F[row * nc + col] = fval(f[s]);
   }
-  if (lane == 0) {
-    __hip_atomic_store(&stamp[t], 2 * k + (capped ? 1 : 0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(last, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return capped ? 2 : 1;
+}
+
+// Launch k works through list k (built by launch k - 1) and builds list
+// k + 1: the neighbours of every tile that changed, and the tile itself when
+// it stopped at the round cap, each once (queued[] holds the latest launch
+// a tile was queued for).  List k + 2's length is cleared here: launch k + 1
+// fills it, and list k - 1, which shares its slot, is spent.
+template <bool EPS, bool C8>
+__global__ __launch_bounds__(FT) void k_fill_tile(const float* __restrict__ z, float* F, int64_t nr, int64_t nc,
+                                                  FillState S, int32_t k) {
+  __shared__ uint32_t sT[FT][FT + 1];
+  __shared__ uint32_t sZ[FT][FT + 1];  // [window row][window column]
+  const int lane = threadIdx.x;
+  const int32_t ntiles = S.ntr * S.ntc;
+  const int32_t cur = k % 3, nxt = (k + 1) % 3;
+  if (blockIdx.x == 0 && lane == 0) S.nlist[(k + 2) % 3] = 0;
+  const int32_t n = S.nlist[cur];
+  const int32_t* list = S.list + (size_t)cur * ntiles;
+  int32_t* out = S.list + (size_t)nxt * ntiles;
+  for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const int32_t t = list[i];
+    const int32_t tr = t / S.ntc, tc = t - tr * S.ntc;
+    const int res = fill_tile<EPS, C8>(z, F, nr, nc, tr, tc, sT, sZ, lane);
+    if (res == 0) continue;
+    if (lane < 9 && (lane != 4 || res == 2)) {
+      const int32_t rr = tr + lane / 3 - 1, cc = tc + lane % 3 - 1;
+      if (rr >= 0 && rr < S.ntr && cc >= 0 && cc < S.ntc) {
+        const int32_t u = rr * S.ntc + cc;
+        if (atomicMax(&S.queued[u], k + 1) < k + 1) out[atomicAdd(&S.nlist[nxt], 1)] = u;
+      }
+    }
+    if (lane == 0) __hip_atomic_store(S.last, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
 }  // namespace
 
-hipError_t launch_fill_init(const float* z, float* F, int64_t nr, int64_t nc, int32_t* stamp, int32_t ntiles,
-                            int32_t* last, int32_t* status, hipStream_t s) {
+hipError_t launch_fill_init(const float* z, float* F, int64_t nr, int64_t nc, const FillState& S, int32_t* status,
+                            hipStream_t s) {
+  const int64_t ntiles = (int64_t)S.ntr * S.ntc;
   const int64_t n = nr * nc > ntiles ? nr * nc : ntiles;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 16384) blocks = 16384;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_fill_init, dim3((unsigned)blocks), dim3(256), 0, s, z, F, nr, nc, stamp, ntiles, last,
-                     status);
+  hipLaunchKernelGGL(k_fill_init, dim3((unsigned)blocks), dim3(256), 0, s, z, F, nr, nc, S, status);
   return hipGetLastError();
 }
 
-hipError_t launch_fill_tiles(const float* z, float* F, int64_t nr, int64_t nc, int32_t ntr, int32_t ntc,
-                             bool eps, bool c8, int32_t* stamp, int32_t* last, int32_t k, hipStream_t s) {
-  const dim3 grid((unsigned)(ntr * ntc)), block(FT);
+hipError_t launch_fill_tiles(const float* z, float* F, int64_t nr, int64_t nc, bool eps, bool c8,
+                             const FillState& S, int32_t k, hipStream_t s) {
+  // Enough single-wavefront workgroups for every SIMD of the chip; each
+  // walks the list with a grid stride.
+  int64_t blocks = (int64_t)S.ntr * S.ntc;
+  if (blocks > 2048) blocks = 2048;
+  const dim3 grid((unsigned)blocks), block(FT);
   if (eps) {
-    if (c8) hipLaunchKernelGGL((k_fill_tile<true, true>), grid, block, 0, s, z, F, nr, nc, ntr, ntc, stamp, last, k);
-    else hipLaunchKernelGGL((k_fill_tile<true, false>), grid, block, 0, s, z, F, nr, nc, ntr, ntc, stamp, last, k);
+    if (c8) hipLaunchKernelGGL((k_fill_tile<true, true>), grid, block, 0, s, z, F, nr, nc, S, k);
+    else hipLaunchKernelGGL((k_fill_tile<true, false>), grid, block, 0, s, z, F, nr, nc, S, k);
   } else {
-    if (c8) hipLaunchKernelGGL((k_fill_tile<false, true>), grid, block, 0, s, z, F, nr, nc, ntr, ntc, stamp, last, k);
-    else hipLaunchKernelGGL((k_fill_tile<false, false>), grid, block, 0, s, z, F, nr, nc, ntr, ntc, stamp, last, k);
+    if (c8) hipLaunchKernelGGL((k_fill_tile<false, true>), grid, block, 0, s, z, F, nr, nc, S, k);
+    else hipLaunchKernelGGL((k_fill_tile<false, false>), grid, block, 0, s, z, F, nr, nc, S, k);
   }
   return hipGetLastError();
 }

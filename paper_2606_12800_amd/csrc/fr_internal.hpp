@@ -270,10 +270,18 @@ hipError_t launch_engine_iter(const EngineConfig& cfg, const EngineParams& P, in
 hipError_t launch_mass(RuleKind rk, ValKind vk, const EngineParams& P, double* partial,
                        int nblocks, double* mass_out, hipStream_t s);
 hipError_t launch_set_status(int32_t* status, int32_t code, hipStream_t s);
-hipError_t launch_fill_init(const float* z, float* F, int64_t nr, int64_t nc, int32_t* stamp, int32_t ntiles,
-                            int32_t* last, int32_t* status, hipStream_t s);
-hipError_t launch_fill_tiles(const float* z, float* F, int64_t nr, int64_t nc, int32_t ntr, int32_t ntc,
-                             bool eps, bool c8, int32_t* stamp, int32_t* last, int32_t k, hipStream_t s);
+// Depression filling: tile grid and work lists (workspace).
+struct FillState {
+  int32_t ntr, ntc;  // tiles of 62 x 62 cells
+  int32_t* queued;   // per tile: latest launch it was queued for
+  int32_t* list;     // three lists of ntr * ntc tile indices (ring)
+  int32_t* nlist;    // [3] their lengths
+  int32_t* last;     // latest launch in which a tile changed
+};
+hipError_t launch_fill_init(const float* z, float* F, int64_t nr, int64_t nc, const FillState& S, int32_t* status,
+                            hipStream_t s);
+hipError_t launch_fill_tiles(const float* z, float* F, int64_t nr, int64_t nc, bool eps, bool c8,
+                             const FillState& S, int32_t k, hipStream_t s);
 hipError_t launch_zero_f64(double* p, int n, hipStream_t s);
 
 }  // namespace fr
