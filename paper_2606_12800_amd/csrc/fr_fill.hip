@@ -18,7 +18,7 @@
 // in other lanes arrive by DPP wavefront shifts; the halo lanes and steps are
 // read once per launch and never updated, so no lane needs an edge case.
 // Elevations stay in LDS, read in either orientation.  A tile repeats its
-// four sweeps until a round changes nothing (or a round cap is reached),
+// four sweeps until one sweep changes nothing (or a round cap is reached),
 // then writes its own cells back.  Launch k works through a list of the
 // tiles next to a tile that changed in launch k - 1 (the first list: the
 // tiles on the grid's perimeter); the host stops once a list is empty.
@@ -53,11 +53,19 @@ __device__ __forceinline__ uint32_t from_upper(uint32_t x) {
 __device__ __forceinline__ uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
 __device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
 
+// What one sweep changed in this lane: any cell, the cell at step 1, the
+// cell at step 62.
+struct SweepChange {
+  bool any, lo, hi;
+};
+
 // One sweep over steps 1..62 of the window, forward or backward; lanes 1..62
-// update.  zk(s) is the elevation key of this lane's cell at step s.
-// Returns whether any cell of this lane changed.
+// update.  zk(s) is the elevation key of this lane's cell at step s.  Every
+// cell is evaluated with all its neighbours, so a sweep that changes nothing
+// has found a fixed point of the tile (for its halo).
 template <bool EPS, bool C8, bool FWD, typename ZK>
-__device__ __forceinline__ bool sweep(uint32_t (&f)[FT], bool inner, ZK zk) {
+__device__ __forceinline__ SweepChange sweep(uint32_t (&f)[FT], bool inner, ZK zk) {
+  SweepChange c{false, false, false};
   bool changed = false;
 #pragma unroll
   for (int i = 1; i < FT - 1; ++i) {
@@ -75,10 +83,49 @@ __device__ __forceinline__ bool sweep(uint32_t (&f)[FT], bool inner, ZK zk) {
     const uint32_t nv = umax(zk(s), umin(f[s], cand));
     const bool ch = inner && nv != f[s];
     changed |= ch;
+    if (s == 1) c.lo = ch;
+    if (s == FT - 2) c.hi = ch;
     f[s] = ch ? nv : f[s];
   }
-  return changed;
+  c.any = changed;
+  return c;
 }
+
+// Which owned cells on the tile's sides changed: the neighbour tile on that
+// side reads them as its halo.  Bits: 0 top-left corner, 1 top row, 2
+// top-right corner, 3 left column, 5 right column, 6 bottom-left corner, 7
+// bottom row, 8 bottom-right corner (the neighbour tile at (dr, dc) is bit
+// 3 (dr + 1) + dc + 1); bit 4 (the tile itself) marks a stop at the round
+// cap.
+struct EdgeChange {
+  bool tl = false, t = false, tr = false, l = false, r = false, bl = false, b = false, br = false;
+  // Column orientation: steps = rows, lanes = columns.
+  __device__ void col(const SweepChange& c, int lane) {
+    t |= c.lo;
+    b |= c.hi;
+    l |= lane == 1 && c.any;
+    r |= lane == FT - 2 && c.any;
+    tl |= lane == 1 && c.lo;
+    tr |= lane == FT - 2 && c.lo;
+    bl |= lane == 1 && c.hi;
+    br |= lane == FT - 2 && c.hi;
+  }
+  // Row orientation: steps = columns, lanes = rows.
+  __device__ void row(const SweepChange& c, int lane) {
+    l |= c.lo;
+    r |= c.hi;
+    t |= lane == 1 && c.any;
+    b |= lane == FT - 2 && c.any;
+    tl |= lane == 1 && c.lo;
+    tr |= lane == 1 && c.hi;
+    bl |= lane == FT - 2 && c.lo;
+    br |= lane == FT - 2 && c.hi;
+  }
+  __device__ uint32_t bits() const {
+    return (__any(tl) ? 1u : 0u) | (__any(t) ? 2u : 0u) | (__any(tr) ? 4u : 0u) | (__any(l) ? 8u : 0u) |
+           (__any(r) ? 32u : 0u) | (__any(bl) ? 64u : 0u) | (__any(b) ? 128u : 0u) | (__any(br) ? 256u : 0u);
+  }
+};
 
 // a[s] of lane l becomes a[l] of lane s (64 x 64 transpose through LDS).
 __device__ __forceinline__ void transpose(uint32_t (&a)[FT], uint32_t (*sT)[FT + 1], int lane) {
@@ -133,11 +180,11 @@ __global__ __launch_bounds__(256) void k_fill_init(const float* __restrict__ z, 
   if (bad && status) atomicCAS(status, 0, FR_ERR_NONFINITE);
 }
 
-// Relaxes tile t until a round changes nothing or the round cap is hit and
-// writes its cells back if any changed.  Returns 0 (no change), 1 (changed,
-// converged) or 2 (changed, stopped at the cap).
+// Relaxes tile t until a sweep changes nothing or the round cap is hit and
+// writes its cells back if any changed.  Returns the EdgeChange bits (0: no
+// change on the sides) and whether any cell changed.
 template <bool EPS, bool C8>
-__device__ __forceinline__ int fill_tile(const float* __restrict__ z, float* F, int64_t nr, int64_t nc,
+__device__ __forceinline__ uint32_t fill_tile(const float* __restrict__ z, float* F, int64_t nr, int64_t nc,
                                          int32_t tr, int32_t tc, uint32_t (*sT)[FT + 1], uint32_t (*sZ)[FT + 1],
                                          int lane) {
   // Window row w is grid row wr0 + w; window column lane is grid column
@@ -156,24 +203,37 @@ __device__ __forceinline__ int fill_tile(const float* __restrict__ z, float* F, 
     sZ[s][lane] = in ? fkey(z[row * nc + col]) : KEY_INF;
   }
   const bool inner = lane >= 1 && lane <= FT - 2;
+  const auto zcol = [&](int s) { return sZ[s][lane]; };
+  const auto zrow = [&](int s) { return sZ[lane][s]; };
+  EdgeChange e;
   bool any = false, capped = true;
-  for (int round = 0; round < FILL_ROUNDS; ++round) {
+  for (int round = 0; round < FILL_ROUNDS && capped; ++round) {
     // Column orientation: steps = window rows, lanes = window columns.
     __syncthreads();
-    const auto zcol = [&](int s) { return sZ[s][lane]; };
-    bool ch = sweep<EPS, C8, true>(f, inner, zcol);
-    ch |= sweep<EPS, C8, false>(f, inner, zcol);
-    transpose(f, sT, lane);
-    // Row orientation: steps = window columns, lanes = window rows.
-    const auto zrow = [&](int s) { return sZ[lane][s]; };
-    ch |= sweep<EPS, C8, true>(f, inner, zrow);
-    ch |= sweep<EPS, C8, false>(f, inner, zrow);
-    transpose(f, sT, lane);
-    if (!__any(ch)) {
+    SweepChange c = sweep<EPS, C8, true>(f, inner, zcol);
+    e.col(c, lane);
+    if (!__any(c.any)) {
       capped = false;
       break;
     }
     any = true;
+    c = sweep<EPS, C8, false>(f, inner, zcol);
+    e.col(c, lane);
+    if (!__any(c.any)) {
+      capped = false;
+      break;
+    }
+    transpose(f, sT, lane);
+    // Row orientation: steps = window columns, lanes = window rows.
+    c = sweep<EPS, C8, true>(f, inner, zrow);
+    e.row(c, lane);
+    if (!__any(c.any)) capped = false;
+    if (capped) {
+      c = sweep<EPS, C8, false>(f, inner, zrow);
+      e.row(c, lane);
+      if (!__any(c.any)) capped = false;
+    }
+    transpose(f, sT, lane);
   }
   if (!any) return 0;
 #pragma unroll
@@ -181,12 +241,12 @@ __device__ __forceinline__ int fill_tile(const float* __restrict__ z, float* F, 
     const int64_t row = wr0 + s;
     if (inner && col_in && row < nr) F[row * nc + col] = fval(f[s]);
   }
-  return capped ? 2 : 1;
+  return e.bits() | (capped ? 16u : 0u) | 0x200u;
 }
 
 // Launch k works through list k (built by launch k - 1) and builds list
-// k + 1: the neighbours of every tile that changed, and the tile itself when
-// it stopped at the round cap, each once (queued[] holds the latest launch
+// k + 1: the neighbours of every tile whose cells on the shared side
+// changed, and the tile itself when it stopped at the round cap, each once (queued[] holds the latest launch
 // a tile was queued for).  List k + 2's length is cleared here: launch k + 1
 // fills it, and list k - 1, which shares its slot, is spent.
 template <bool EPS, bool C8>
@@ -204,9 +264,11 @@ __global__ __launch_bounds__(FT) void k_fill_tile(const float* __restrict__ z, f
   for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
     const int32_t t = list[i];
     const int32_t tr = t / S.ntc, tc = t - tr * S.ntc;
-    const int res = fill_tile<EPS, C8>(z, F, nr, nc, tr, tc, sT, sZ, lane);
+    const uint32_t res = fill_tile<EPS, C8>(z, F, nr, nc, tr, tc, sT, sZ, lane);
     if (res == 0) continue;
-    if (lane < 9 && (lane != 4 || res == 2)) {
+    // Queue the neighbours whose halo changed (and the tile itself after a
+    // stop at the round cap).
+    if (lane < 9 && ((res >> lane) & 1u)) {
       const int32_t rr = tr + lane / 3 - 1, cc = tc + lane % 3 - 1;
       if (rr >= 0 && rr < S.ntr && cc >= 0 && cc < S.ntc) {
         const int32_t u = rr * S.ntc + cc;
