@@ -21,21 +21,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per cell of each single-kernel phase (each array the
-# kernel must touch, counted once):
+# Algorithmic bytes per cell of each timed phase (each array its kernels
+# must touch, counted once per kernel):
 PHASE_BYTES = {
     "receivers": 4 + 1,        # z read, code written
-    "d8_up": 1 + 4,            # code, rain read (local sweep; exits are sparse)
+    "d8_up": 1 + 1 + 4,        # phase A: code (root sweep), code + rain (local sweep); exits are sparse
     "d8_down": 1 + 4 + 4 + 8,  # code, rain read; q (f32), counts (u64) written
 }
-PHASE_KERNEL = {"receivers": "k_receivers", "d8_up": "k_d8_up", "d8_down": "k_d8_down"}
+PHASE_KERNEL = {"receivers": "k_receivers", "d8_up": "k_d8_root + k_d8_up", "d8_down": "k_d8_down"}
 ACC_BYTES = 1 + 4 + 4 + 8     # whole accumulate call: code, rain in; q, counts out
-# HBM bytes per launch of the single-kernel phases at the 43360^2 workload,
+# HBM bytes per launch of these phases at the 43360^2 workload,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE runs calibrated against a 1 GiB
 # device copy (profiles/d8_43360_hbm_traffic.md).  They describe the kernels
 # as they were when counted; other sizes report null.
 MEASURED_TRAFFIC = {
-    ("d8", 43360, 43360): {"receivers": 10.63e9, "d8_up": 11.86e9, "d8_down": 33.35e9},
+    ("d8", 43360, 43360): {"receivers": 10.63e9, "d8_up": 2.07e9 + 9.86e9, "d8_down": 33.33e9},
     ("mfd", 16384, 16384): {"sweep": 9.77e9},       # float32 sweep (profiles/sweep_and_batch_hbm_traffic.md)
     ("adjoint", 4096, 4096): {"sweep": 0.702e9},
     ("batched", 512): {"batch": 24.87e9},
@@ -619,7 +619,7 @@ def main():
     acc_avg = sum(acc_ms) / len(acc_ms)
     acc_gbs = ACC_BYTES * ncell / (acc_avg * 1e-3) / 1e9
     phase_avg = {k: sum(v) / len(v) for k, v in phase_ms.items()}
-    # Dominant single-kernel phase: the one with the largest device time.
+    # Dominant phase: the one with the largest device time.
     single = {k: v for k, v in phase_avg.items() if k in PHASE_BYTES}
     dom = max(single, key=single.get)
     achieved = PHASE_BYTES[dom] * ncell / (single[dom] * 1e-3) / 1e9
