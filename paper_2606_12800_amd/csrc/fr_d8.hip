@@ -620,6 +620,91 @@ __device__ __forceinline__ void root_sweep(const D8Params& P, const Tile& T, boo
   if (bad) *badcode = true;
 }
 
+// May a same-row or towards-higher-row donor exist in this wavefront's row?
+// As rare_donors, from one bit per code value: bit (code & 31) of a lane's
+// four codes.  Malformed codes may alias a donor code and answer "yes",
+// which only sends the row through the general donor test.
+__device__ __forceinline__ bool rare_donors_bits(const Row& here, const Row& below) {
+  uint32_t hb = 0, bb = 0;
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    hb |= 1u << ((here.w >> (8 * j)) & 31u);
+    bb |= 1u << ((below.w >> (8 * j)) & 31u);
+  }
+  const bool any = ((hb & 0x18u) | (bb & 0xE0u)) != 0u || here.l == 4u || here.r == 3u || below.l == 7u ||
+                   below.r == 5u;
+  return __ballot(any) != 0;
+}
+
+// root_sweep for a tile away from the grid border, with the per-cell logic
+// in straight-line integer form: a cell's root is its receiver's root when
+// the receiver is in the row below inside the tile, else the cell itself.
+// Outside rows with a rare donor and the tile's top row, only the two outer
+// columns can be inlets (water across the tile's side edges).
+template <bool VEC>
+__device__ __forceinline__ void root_sweep_interior(const D8Params& P, const Tile& T, bool* badcode) {
+  const int lane = threadIdx.x;
+  const int k0 = W * lane;
+  const int nc = (int)P.ncols;
+  Row below = expand_row<false, VEC>(load_codes<VEC>(P, T, T.r0 - 1, lane), P, T, T.r0 - 1, lane);
+  Row here = expand_row<false, VEC>(load_codes<VEC>(P, T, T.r0, lane), P, T, T.r0, lane);
+  uint32_t rp[W];  // roots of the row below
+#pragma unroll
+  for (int j = 0; j < W; ++j) rp[j] = NONE;
+  uint32_t bad = 0;
+  CodeIn cq[PF_ROWS];
+#pragma unroll
+  for (int i = 0; i < PF_ROWS; ++i) cq[i] = load_codes<VEC>(P, T, T.r0 + i + 1, lane);
+  for (int s0 = 0; s0 < T.th; s0 += PF_ROWS) {
+#pragma unroll
+    for (int i = 0; i < PF_ROWS; ++i) {
+      const int s = s0 + i;
+      const int r = T.r0 + s;
+      if (s < T.th) {  // uniform
+        const Row above = expand_row<false, VEC>(cq[i], P, T, r + 1, lane);
+        const bool top = s == T.th - 1;
+        const bool bottom = s == 0;
+        const uint32_t base = (uint32_t)((size_t)r * (size_t)nc + (size_t)(T.c0 + k0));
+        // A code 0 in column 0 or 2 in column TW - 1 leaves the tile: the
+        // cell is its own root, as the DPP edge values say.
+        const uint32_t left = from_left(rp[W - 1], base), right = from_right(rp[0], base + (W - 1));
+        uint32_t nr[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+          const uint32_t cd = here.code(j);
+          bad |= (uint32_t)(((cd + 1u) & 0xFFu) > 8u);  // neither 0..7 nor the sink code
+          const uint32_t rl = j == 0 ? left : rp[j == 0 ? 0 : j - 1];
+          const uint32_t rr = j == W - 1 ? right : rp[j == W - 1 ? 0 : j + 1];
+          uint32_t v = base + j;
+          v = cd == 0u ? rl : v;
+          v = cd == 1u ? rp[j] : v;
+          v = cd == 2u ? rr : v;
+          nr[j] = bottom ? base + j : v;
+        }
+        if (top || rare_donors_bits(here, below)) {  // uniform
+          bool inlet[W];
+#pragma unroll
+          for (int j = 0; j < W; ++j) inlet[j] = cut_donors(above, here, below, j, k0 + j, top, true, TW) != 0u;
+          if (__ballot(inlet[0] || inlet[1] || inlet[2] || inlet[3])) {
+#pragma unroll
+            for (int j = 0; j < W; ++j)
+              if (inlet[j]) P.root_of[base + j] = nr[j];
+          }
+        } else {
+          if (lane == 0 && above.l == 2u) P.root_of[base] = nr[0];
+          if (lane == 63 && above.r == 0u) P.root_of[base + W - 1] = nr[W - 1];
+        }
+#pragma unroll
+        for (int j = 0; j < W; ++j) rp[j] = nr[j];
+        below = here;
+        here = above;
+      }
+      cq[i] = load_codes<VEC>(P, T, r + PF_ROWS + 1, lane);
+    }
+  }
+  if (bad) *badcode = true;
+}
+
 // ---------------------------------------------------------------------------
 // Phase A, as two independent kernels: the root sweep needs few registers
 // and runs at high occupancy; the local sweep carries the values.
@@ -628,7 +713,7 @@ __global__ __launch_bounds__(64) void k_d8_root(D8Params P) {
   const Tile T = tile_of(P, blockIdx.x);
   bool badcode = false;
   if (T.border) root_sweep<VEC, true>(P, T, &badcode);
-  else root_sweep<VEC, false>(P, T, &badcode);
+  else root_sweep_interior<VEC>(P, T, &badcode);
   if (badcode) set_status(P.status, FR_ERR_BADCODE);
 }
 
