@@ -159,7 +159,10 @@ __device__ __forceinline__ CodeIn load_codes(const D8Params& P, const Tile& T, i
 #pragma unroll
     for (int j = 1; j < W; ++j) x.b[j - 1] = row[min(c + j, nc - 1)];
   }
-  const int sc = lane == 0 ? T.c0 - 1 : (lane == 63 ? T.c0 + TW : c);
+  // Lane 0 reads the column left of the tile, lane 63 the one right of it
+  // (c - 1 and c + W); the others re-read their own first column.  Written
+  // as arithmetic so that no lane branches.
+  const int sc = c + (lane == 0 ? -1 : 0) + (lane == 63 ? W : 0);
   x.side = row[min(max(sc, 0), nc - 1)];
   return x;
 }
