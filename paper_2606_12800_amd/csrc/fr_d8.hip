@@ -295,6 +295,15 @@ __device__ __forceinline__ bool rare_donors(const Row& here, const Row& below) {
   return __ballot(any) != 0;
 }
 
+// Exit-list slots reserved per atomic in phase A; unused slots of a chunk
+// are holes (ex_cell = NONE) that the forest skips.
+constexpr uint32_t EXIT_CHUNK = 32;
+
+__device__ __forceinline__ void exit_holes(const D8Params& P, uint32_t from, uint32_t to, int lane) {
+  for (uint32_t h = from + (uint32_t)lane; h < to; h += 64)
+    if (h < P.cap) P.ex_cell[h] = NONE;
+}
+
 // Value carried down a sweep: float-float water, float64 water, count.
 template <typename CT>
 struct Val {
@@ -343,6 +352,7 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
   V pv[W];
 #pragma unroll
   for (int j = 0; j < W; ++j) pv[j] = V{};
+  uint32_t ex_base = 0, ex_used = 0, ex_size = 0;  // the wavefront's exit chunk (uniform)
   Row above = expand_row<BORDER, VEC>(load_codes<VEC>(P, T, rtop + 1, lane), P, T, rtop + 1, lane);
   Row here = expand_row<BORDER, VEC>(load_codes<VEC>(P, T, rtop, lane), P, T, rtop, lane);
   // Slot i of the ring holds, for step s = i (mod PF): the codes of row
@@ -449,17 +459,34 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
           }
         }
         if (UP && __ballot(exits[0] || exits[1] || exits[2] || exits[3])) {
-          // Record exits (wavefront-compacted append).
+          // Record exits in consecutive slots of the wavefront's chunk; a
+          // new chunk (one atomic) when the row does not fit, the rest of
+          // the old one left as holes.
+          uint64_t em[W];
+          uint32_t ne = 0;
+#pragma unroll
+          for (int j = 0; j < W; ++j) {
+            em[j] = __ballot(exits[j]);
+            ne += (uint32_t)__popcll(em[j]);
+          }
+          if (ex_used + ne > ex_size) {  // uniform
+            exit_holes(P, ex_base + ex_used, ex_base + ex_size, lane);
+            const uint32_t want = ne > EXIT_CHUNK ? ne : EXIT_CHUNK;
+            uint32_t nb = 0;
+            if (lane == 0) nb = atomicAdd(P.n_exits, want);
+            ex_base = __shfl(nb, 0, 64);
+            ex_size = want;
+            ex_used = 0;
+          }
+          const uint64_t lower = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+          uint32_t off = ex_base + ex_used;
+          ex_used += ne;
 #pragma unroll
           for (int j = 0; j < W; ++j) {
             const bool ex = exits[j];
-            const uint64_t m = __ballot(ex);
-            if (m) {
-              uint32_t base = 0;
-              if (lane == 0) base = atomicAdd(P.n_exits, (uint32_t)__popcll(m));
-              base = __shfl(base, 0, 64);
+            {
               if (ex) {
-                const uint32_t idx = base + (uint32_t)__popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+                const uint32_t idx = off + (uint32_t)__popcll(em[j] & lower);
                 if (idx < P.cap) {
                   P.node_of[g + j] = idx;
                   P.ex_cell[idx] = (uint32_t)(g + j);
@@ -472,6 +499,7 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
                 }
               }
             }
+            off += (uint32_t)__popcll(em[j]);
           }
         }
         if (!UP && lane_in) {
@@ -552,6 +580,7 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
       rq[i] = load_rain<RAIN, VEC>(P, T, r - PF, lane);
     }
   }
+  if (UP) exit_holes(P, ex_base + ex_used, ex_base + ex_size, lane);
   if (nf) *nonfinite = true;
   if (ITER && bad) *badcode = true;
   if (ITER && chg) *changed = true;
@@ -733,7 +762,12 @@ __global__ __launch_bounds__(64) void k_d8_up(D8Params P) {
 // Phase B: exit forest.
 __global__ __launch_bounds__(256) void k_d8_link(D8Params P, uint32_t n) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int64_t e = P.ex_cell[i];
+    const uint32_t ec = P.ex_cell[i];
+    if (ec == NONE) {  // a hole of a phase-A chunk
+      P.anc[0][i] = NONE;
+      continue;
+    }
+    const int64_t e = ec;
     const int cd = P.code[e];
     const int64_t x = e + (int64_t)nb_dr(cd) * P.ncols + nb_dc(cd);
     const int64_t rt = P.root_of[x];
