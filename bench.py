@@ -39,6 +39,7 @@ MEASURED_TRAFFIC = {
     ("mfd", 16384, 16384): {"sweep": 9.77e9},       # float32 sweep (profiles/sweep_and_batch_hbm_traffic.md)
     ("adjoint", 4096, 4096): {"sweep": 0.702e9},
     ("batched", 512): {"batch": 24.87e9},
+    ("fill", 16384, 16384): {"fill": 37.79e9 + 2.15e9},  # whole fill (profiles/fill_16384_kernel_stats.md)
 }
 # Algorithmic bytes per cell of the secondary workloads' dominant kernel
 # (arrays visible at the C ABI, each touched once): MFD float32 sweep z 4 +
@@ -241,7 +242,9 @@ def run_fill(args):
         "config": {"workload": f"depression filling (epsilon, 8 neighbours) of the {nr}x{nc} untilted fractal "
                                f"DEM (seed {args.seed})", "cells": ncell},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_fill_tile (all launches)",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": MEASURED_TRAFFIC.get(("fill", nr, nc), {}).get("fill"),
+                     "kernel": "k_fill_tile (all launches)",
                      "bytes_per_cell": FILL_BYTES, "ms_per_launch": ms},
         "detail": {"launches": launches.value, "fraction_raised": raised, "device_ms": ms},
     }
