@@ -125,3 +125,68 @@ def test_adjoint_validation(lib):
     assert adj(rule=fr.MFD, p=-1.0) == fr.ERR_ARG
     assert adj(ws=NULL) == fr.ERR_WORKSPACE
     assert adj(nr=0) == fr.OK
+
+
+def test_block_iterations_validation(lib):
+    it = ctypes.c_int32(7)
+
+    def bi(code=FAKE, nr=8, nc=8, rule=fr.D8, scheme=fr.SCHEME_IX, rain=NULL, rdt=fr.F32, qdt=fr.F64, q=FAKE,
+           cnt=FAKE, max_iter=10, iters=ctypes.byref(it), ws=FAKE, wsb=1 << 40):
+        return lib.fr_accumulate_block_iterations(code, nr, nc, rule, scheme, rain, rdt, qdt, q, cnt, max_iter,
+                                                  iters, NULL, ws, wsb, NULL)
+    assert bi(nr=-1) == fr.ERR_ARG
+    assert bi(iters=NULL) == fr.ERR_ARG
+    assert bi(max_iter=0) == fr.ERR_ARG
+    assert bi(rule=fr.MFD) == fr.ERR_RULE
+    assert bi(scheme=2) == fr.ERR_ARG
+    assert bi(rain=FAKE, rdt=fr.NONE) == fr.ERR_ARG
+    assert bi(qdt=fr.F32) == fr.ERR_ARG                      # float64 water or counts only
+    assert bi(q=NULL) == fr.ERR_ARG                          # dtype given but no q_out
+    assert bi(qdt=fr.NONE, q=NULL, cnt=NULL) == fr.ERR_ARG   # nothing to compute
+    assert bi(scheme=fr.SCHEME_IMX_IX, cnt=NULL) == fr.ERR_ARG  # converges on the counts
+    assert bi(code=NULL) == fr.ERR_ARG
+    assert bi(ws=NULL) == fr.ERR_WORKSPACE
+    need = fr.workspace_bytes(fr.FN_BLOCK_ITER_PRE, 8, 8, fr.D8, fr.F64)
+    assert bi(scheme=fr.SCHEME_IMX_IX, wsb=need - 1) == fr.ERR_WORKSPACE
+    assert bi(nr=1 << 16, nc=1 << 16) == fr.ERR_TOOLARGE
+    it.value = 7
+    assert bi(nr=0, code=NULL, ws=NULL) == fr.OK and it.value == 0  # empty grid: no-op
+
+
+def test_fill_validation(lib):
+    n = ctypes.c_int32(5)
+
+    def fill(z=FAKE, nr=8, nc=8, rule=fr.D8, eps=1, out=ctypes.c_void_p(0x2000), ws=FAKE, wsb=1 << 40):
+        return lib.fr_fill_depressions(z, nr, nc, rule, eps, out, ctypes.byref(n), NULL, ws, wsb, NULL)
+    assert fill(nr=-2) == fr.ERR_ARG
+    assert fill(eps=2) == fr.ERR_ARG
+    assert fill(rule=9) == fr.ERR_RULE
+    assert fill(z=NULL) == fr.ERR_ARG
+    assert fill(out=NULL) == fr.ERR_ARG
+    assert fill(out=FAKE) == fr.ERR_ARG  # output aliases the elevations
+    assert fill(ws=NULL) == fr.ERR_WORKSPACE
+    assert fill(wsb=fr.workspace_bytes(fr.FN_FILL, 8, 8, fr.D8, fr.F32) - 1) == fr.ERR_WORKSPACE
+    assert fill(nr=1 << 16, nc=1 << 16) == fr.ERR_TOOLARGE
+    n.value = 5
+    assert fill(nr=0, z=NULL, out=NULL, ws=NULL) == fr.OK and n.value == 0
+
+
+def test_workspace_bytes_next_rows():
+    a = fr.workspace_bytes(fr.FN_BLOCK_ITER, 300, 500, fr.D8, fr.F64)
+    b = fr.workspace_bytes(fr.FN_BLOCK_ITER_PRE, 300, 500, fr.D8, fr.F64)
+    assert a >= 300 * 500 * 16 and b >= 3 * 300 * 500 * 16
+    assert fr.workspace_bytes(fr.FN_BLOCK_ITER, 300, 500, fr.MFD, fr.F64) == 0
+    assert fr.workspace_bytes(fr.FN_BLOCK_ITER, 300, 500, fr.D8, fr.F32) == 0
+    f = fr.workspace_bytes(fr.FN_FILL, 300, 500, fr.D4, fr.F32)
+    tiles = ((300 + 61) // 62) * ((500 + 61) // 62)
+    assert f >= 4 * (4 * tiles + 4)
+    assert fr.workspace_bytes(fr.FN_FILL, 300, 500, fr.D8, fr.F64) == 0
+
+
+def test_scheme_and_fn_constants_match_binding():
+    text = open(HEADER).read()
+    consts = dict((m.group(1), int(m.group(2), 0)) for m in
+                  re.finditer(r"#define\s+(FR_[A-Z_0-9]+)\s+(-?(?:0x)?[0-9A-Fa-f]+)", text))
+    assert consts["FR_SCHEME_IX"] == fr.SCHEME_IX and consts["FR_SCHEME_IMX_IX"] == fr.SCHEME_IMX_IX
+    assert consts["FR_FN_BLOCK_ITER"] == fr.FN_BLOCK_ITER and consts["FR_FN_BLOCK_ITER_PRE"] == fr.FN_BLOCK_ITER_PRE
+    assert consts["FR_FN_FILL"] == fr.FN_FILL
