@@ -264,25 +264,28 @@ int run_d8(const uint8_t* code, int64_t nrows, int64_t ncols, const float* rain3
   if (hipStreamSynchronize(s) != hipSuccess) return FR_ERR_HIP;
   if (n > L.cap) return 1;
   P.n_ex = n;
-  int fb = 0;
+  int round = 0;
   ph = phase_begin("d8_forest", s);
   if (n > 0) {
     if (launch_d8_link(P, n, s) != hipSuccess) return FR_ERR_HIP;
     // A forest of n nodes is at most n deep: 33 rounds always suffice; more
-    // means the exits form a cycle (malformed codes).
-    for (int round = 0;; ++round) {
+    // means the exits form a cycle (malformed codes).  Rounds go out four
+    // at a time (a round after the last one with work returns at once);
+    // the host then reads the flag of the last round queued.
+    constexpr int kRoundBatch = 4;
+    for (;;) {
+      for (int q = 0; q < kRoundBatch; ++q, ++round)
+        if (launch_d8_round(vk, counts, P, n, round, s) != hipSuccess) return FR_ERR_HIP;
+      int32_t flag = 0;
+      if (hipMemcpyAsync(&flag, P.flags + 4 + (round - 1) % 3, sizeof flag, hipMemcpyDeviceToHost, s) !=
+          hipSuccess)
+        return FR_ERR_HIP;
+      if (hipStreamSynchronize(s) != hipSuccess) return FR_ERR_HIP;
+      if (!flag) break;
       if (round > 33) {
         if (status && launch_set_status(status, FR_ERR_NOTDAG, s) != hipSuccess) return FR_ERR_HIP;
         break;
       }
-      if (launch_zero_u32(reinterpret_cast<uint32_t*>(P.flags), 4, s) != hipSuccess) return FR_ERR_HIP;
-      if (launch_d8_round(vk, counts, P, n, fb, s) != hipSuccess) return FR_ERR_HIP;
-      fb ^= 1;
-      int32_t flag = 0;
-      if (hipMemcpyAsync(&flag, P.flags + 1, sizeof flag, hipMemcpyDeviceToHost, s) != hipSuccess)
-        return FR_ERR_HIP;
-      if (hipStreamSynchronize(s) != hipSuccess) return FR_ERR_HIP;
-      if (!flag) break;
     }
   }
   phase_end(ph, s);

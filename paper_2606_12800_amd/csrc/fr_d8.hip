@@ -806,11 +806,20 @@ __global__ __launch_bounds__(256) void k_d8_link(D8Params P, uint32_t n) {
   }
 }
 
-// Round k of pointer doubling (anc[b] = ancestor 2^k exits down, or NONE).
+// Round j sets flag slot j mod 3 when it leaves work for round j + 1, and
+// skips itself when round j - 1 left none (so the host can queue rounds
+// without waiting for each flag); round j's scatter clears slot j + 1.
+__device__ __forceinline__ int32_t* round_flag(const D8Params& P, int j) { return &P.flags[4 + j % 3]; }
+__device__ __forceinline__ bool round_idle(const D8Params& P, int j) {
+  return j > 0 && __hip_atomic_load(round_flag(P, j + 2), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+}
+
+// Round j of pointer doubling (anc[b] = ancestor 2^j exits down, or NONE).
 // Part 1: every exit that still has such an ancestor snapshots its sum (the
-// sum over its subtree within distance < 2^k) and jumps its pointer.
+// sum over its subtree within distance < 2^j) and jumps its pointer.
 template <int VK, bool CNT>
-__global__ __launch_bounds__(256) void k_d8_copy(D8Params P, uint32_t n, int b) {
+__global__ __launch_bounds__(256) void k_d8_copy(D8Params P, uint32_t n, int b, int j) {
+  if (round_idle(P, j)) return;  // uniform
   __shared__ int s_active;
   if (threadIdx.x == 0) s_active = 0;
   __syncthreads();
@@ -834,13 +843,17 @@ __global__ __launch_bounds__(256) void k_d8_copy(D8Params P, uint32_t n, int b) 
   // atomic from every wavefront on one word serialises the whole kernel.
   if (__ballot(active) && (threadIdx.x & 63) == 0) s_active = 1;
   __syncthreads();
-  if (threadIdx.x == 0 && s_active && __hip_atomic_load(&P.flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-    __hip_atomic_store(&P.flags[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0 && s_active &&
+      __hip_atomic_load(round_flag(P, j), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+    __hip_atomic_store(round_flag(P, j), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Part 2: each such exit adds its snapshot to the ancestor's sum in place.
 template <int VK, bool CNT>
-__global__ __launch_bounds__(256) void k_d8_scatter(D8Params P, uint32_t n, int b) {
+__global__ __launch_bounds__(256) void k_d8_scatter(D8Params P, uint32_t n, int b, int j) {
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_store(round_flag(P, j + 1), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (round_idle(P, j)) return;  // uniform
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const uint32_t a = P.anc[b][i];
     if (a == NONE) continue;
@@ -1022,10 +1035,11 @@ hipError_t launch_d8_link(const D8Params& P, uint32_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_d8_round(ValKind vk, bool cnt, const D8Params& P, uint32_t n, int b, hipStream_t s) {
+hipError_t launch_d8_round(ValKind vk, bool cnt, const D8Params& P, uint32_t n, int j, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  D8_DISPATCH(k_d8_copy, dim3(grid_for(n)), dim3(256), P, n, b);
-  D8_DISPATCH(k_d8_scatter, dim3(grid_for(n)), dim3(256), P, n, b);
+  const int b = j & 1;
+  D8_DISPATCH(k_d8_copy, dim3(grid_for(n)), dim3(256), P, n, b, j);
+  D8_DISPATCH(k_d8_scatter, dim3(grid_for(n)), dim3(256), P, n, b, j);
   return hipGetLastError();
 }
 

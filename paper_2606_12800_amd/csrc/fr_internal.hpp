@@ -115,7 +115,7 @@ struct D8Params {
 // Launchers (defined in the .hip files).
 hipError_t launch_d8_up(ValKind vk, bool cnt, const D8Params& P, hipStream_t s);
 hipError_t launch_d8_link(const D8Params& P, uint32_t n, hipStream_t s);
-hipError_t launch_d8_round(ValKind vk, bool cnt, const D8Params& P, uint32_t n, int b, hipStream_t s);
+hipError_t launch_d8_round(ValKind vk, bool cnt, const D8Params& P, uint32_t n, int j, hipStream_t s);
 hipError_t launch_d8_down(ValKind vk, bool cnt, const D8Params& P, hipStream_t s);
 hipError_t launch_d8_iter(ValKind vk, bool cnt, const D8Params& P, hipStream_t s);
 // Element-wise steps of the (I - X)(I + X) iteration on float64 values and
