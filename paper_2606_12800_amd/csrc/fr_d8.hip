@@ -1021,12 +1021,47 @@ void d8_sweep_dispatch(ValKind vk, bool cnt, const D8Params& P, hipStream_t s) {
   }
 }
 
+// A second stream (default priority) per host thread and device, on which
+// the root sweep runs beside the local sweep: the first is bound by its
+// instruction count, the second by HBM, and neither reads what the other
+// writes.
+namespace {
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+hipError_t side_stream(SideStream** out) {
+  constexpr int kMaxDevices = 64;
+  thread_local SideStream per[kMaxDevices];
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  SideStream& ss = per[dev];
+  if (!ss.s) {
+    if ((e = hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&ss.join, hipEventDisableTiming)) != hipSuccess) return e;
+  }
+  *out = &ss;
+  return hipSuccess;
+}
+}  // namespace
+
 hipError_t launch_d8_up(ValKind vk, bool cnt, const D8Params& P, hipStream_t s) {
   const dim3 g((unsigned)((int64_t)P.ntr * P.ntc)), b(64);
-  if ((P.ncols % 4) == 0) hipLaunchKernelGGL(k_d8_root<true>, g, b, 0, s, P);
-  else hipLaunchKernelGGL(k_d8_root<false>, g, b, 0, s, P);
+  SideStream* ss = nullptr;
+  hipError_t e = side_stream(&ss);
+  if (e != hipSuccess) return e;
+  if ((e = hipEventRecord(ss->fork, s)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(ss->s, ss->fork, 0)) != hipSuccess) return e;
+  if ((P.ncols % 4) == 0) hipLaunchKernelGGL(k_d8_root<true>, g, b, 0, ss->s, P);
+  else hipLaunchKernelGGL(k_d8_root<false>, g, b, 0, ss->s, P);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   d8_sweep_dispatch<UpK>(vk, cnt, P, s);
-  return hipGetLastError();
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipEventRecord(ss->join, ss->s)) != hipSuccess) return e;
+  return hipStreamWaitEvent(s, ss->join, 0);
 }
 
 hipError_t launch_d8_link(const D8Params& P, uint32_t n, hipStream_t s) {
