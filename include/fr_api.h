@@ -40,7 +40,11 @@
  * sized by fr_workspace_bytes().  Calls on different streams must use
  * different workspaces.
  *
- * Streams.  All device work is enqueued on the given stream.
+ * Streams.  All device work is ordered on the given stream.  The D8/D4
+ * path of fr_accumulate also runs one kernel on a stream of the library's
+ * own (created once per host thread and device, default priority), forked
+ * from and joined back into the given stream with events, so the call's
+ * work is still complete when the given stream is.
  *
  * Errors.  Return value: FR_OK (0) or a negative FR_ERR_* code from host-side
  * validation of the arguments, or a HIP error seen while enqueueing.
