@@ -61,9 +61,6 @@ uint32_t d8_capacity(int64_t n) {
 }
 
 D8Layout d8_layout(int64_t nrows, int64_t ncols, int vdtype, bool counts) {
-  // Float32 water is computed in float64 on this path (rounded once at the
-  // final store), so its exits carry float64 sums too.
-  if (vdtype == FR_F32) vdtype = FR_F64;
   D8Layout L{};
   const size_t n = (size_t)(nrows * ncols);
   const int th = d8_tile_height(nrows, ncols);
@@ -219,10 +216,7 @@ int run_d8(const uint8_t* code, int64_t nrows, int64_t ncols, const float* rain3
            ValKind vk, float* q32, double* q64, uint64_t* cnt, double* mass_out, int32_t* status, char* base,
            hipStream_t s) {
   const bool counts = cnt != nullptr;
-  // Float32 results: float64 sums throughout (one float64 add per donor
-  // instead of a float-float sum), rounded once when phase C stores them.
-  if (vk == VK_FF) vk = VK_F64;
-  const D8Layout L = d8_layout(nrows, ncols, vk == VK_F64 ? FR_F64 : FR_NONE, counts);
+  const D8Layout L = d8_layout(nrows, ncols, vk == VK_FF ? FR_F32 : (vk == VK_F64 ? FR_F64 : FR_NONE), counts);
   D8Params P{};
   P.nrows = nrows;
   P.ncols = ncols;

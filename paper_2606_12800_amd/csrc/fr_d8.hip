@@ -513,17 +513,8 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
               *reinterpret_cast<float4*>(P.q32 + g) = o;
             }
             if (VK == VK_F64) {
-              if (P.q32) {  // float32 output of a float64 sweep (uniform)
-                float4 o;
-                o.x = (float)nv[0].d;
-                o.y = (float)nv[1].d;
-                o.z = (float)nv[2].d;
-                o.w = (float)nv[3].d;
-                *reinterpret_cast<float4*>(P.q32 + g) = o;
-              } else {
-                *reinterpret_cast<double2*>(P.q64 + g) = make_double2(nv[0].d, nv[1].d);
-                *reinterpret_cast<double2*>(P.q64 + g + 2) = make_double2(nv[2].d, nv[3].d);
-              }
+              *reinterpret_cast<double2*>(P.q64 + g) = make_double2(nv[0].d, nv[1].d);
+              *reinterpret_cast<double2*>(P.q64 + g + 2) = make_double2(nv[2].d, nv[3].d);
             }
             if (CNT) {
               ulonglong2 a, b;
@@ -552,10 +543,7 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
             const int kk = 64 * j + lane;
             if (!BORDER || T.c0 + kk < nc) {
               if (VK == VK_FF) P.q32[g0 + kk] = xq32[kk];
-              if (VK == VK_F64) {
-                if (P.q32) P.q32[g0 + kk] = (float)xq64[kk];
-                else P.q64[g0 + kk] = xq64[kk];
-              }
+              if (VK == VK_F64) P.q64[g0 + kk] = xq64[kk];
               if (CNT) P.cnt[g0 + kk] = xcnt[kk];
             }
           }
