@@ -170,3 +170,39 @@ def test_fill_fixed_point_large(rule, n):
     f = fr.fill_depressions(z, rule, True)
     assert _fixed_point_ok(z, f, CONN[rule], True)
     assert bool((f >= z).all())
+
+
+def test_fill_fixed_point_fullsize():
+    """The bench's fill workload (43360^2 untilted DEM, seed 2, epsilon, 8
+    neighbours), checked band by band against the fixed-point equation, which
+    has exactly one solution."""
+    n = 43360
+    print(f"fill fixed point d8 {n}x{n}", flush=True)
+    z = torch.from_numpy(synth.dem(2, n, n, tilt=0.0)).cuda()
+    f = fr.fill_depressions(z, "d8", True)
+    torch.cuda.synchronize()
+    inf = torch.tensor(float("inf"), device=f.device)
+    for r0 in range(0, n, 4096):
+        r1 = min(r0 + 4096, n)
+        a, b = max(r0 - 1, 0), min(r1 + 1, n)
+        band = torch.nn.functional.pad(f[a:b][None, None], (1, 1, 1 if a == r0 else 0, 1 if b == r1 else 0),
+                                       value=float("inf"))[0, 0]
+        m = torch.full((r1 - r0, n), float("inf"), device=f.device)
+        for dr in (-1, 0, 1):
+            for dc in (-1, 0, 1):
+                if (dr, dc) != (0, 0):
+                    m = torch.minimum(m, band[1 + dr:1 + dr + (r1 - r0), 1 + dc:1 + dc + n])
+        want = torch.maximum(z[r0:r1], torch.nextafter(m, inf))
+        got = f[r0:r1]
+        inner = torch.ones_like(got, dtype=torch.bool)
+        inner[:, 0] = inner[:, -1] = False
+        if r0 == 0:
+            inner[0] = False
+        if r1 == n:
+            inner[-1] = False
+        assert torch.equal(got[inner], want[inner]), r0
+        assert torch.equal(got[~inner], z[r0:r1][~inner]), r0
+        del band, m, want
+    assert bool((f >= z).all())
+    del z, f
+    torch.cuda.empty_cache()
