@@ -141,3 +141,19 @@ def test_preconditioned_block_iterations_counts_only_and_errors():
     q, cnt, it = fr.block_iterations(torch.empty((3, 0), dtype=torch.uint8, device="cuda"), None, "d8",
                                      scheme="imx_ix")
     assert it == 0 and q.numel() == 0
+
+
+def test_block_iterations_fullsize_counts_equal_main_path():
+    """The bench's block-iteration workload: D8 unit-rain counts on the
+    43360^2 DEM (seed 2) by I+X block iterations, bit-exact against the main
+    path's counts (which the full-size tests check cell by cell)."""
+    n = 43360
+    print(f"block iterations d8 {n}x{n}", flush=True)
+    code = fr.receivers(torch.from_numpy(synth.dem(2, n, n)).cuda(), "d8")
+    torch.cuda.synchronize()
+    _, cnt, it = fr.block_iterations(code, None, "d8", dtype=None)
+    _, c2, _ = fr.accumulate(code, None, None, "d8", None, counts=True)
+    assert it > 1 and torch.equal(cnt, c2)
+    del code, cnt, c2
+    fr._default_ws.buf = None
+    torch.cuda.empty_cache()
