@@ -40,6 +40,12 @@
 namespace fr {
 namespace {
 
+// Real-time clock for the sweep's diagnostic counters, read only when they
+// are switched on (each read waits for the scalar memory path).
+__device__ __forceinline__ uint64_t diag_now(const WsParams& P) {
+  return P.debug ? __builtin_amdgcn_s_memrealtime() : 0;
+}
+
 constexpr int LW = 66;         // LDS row: side cell, 64 lanes, side cell
 // Strips overlap: a wavefront computes 64 columns, owns the middle WS_OWN
 // and recomputes GHOST columns of each neighbour (as GHOST columns of its
@@ -558,7 +564,7 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
       const int tc = lds_ld(&S.tcomp);
       bool busy = false;
       ++io_iter;
-      uint64_t q0 = __builtin_amdgcn_s_memrealtime();
+      uint64_t q0 = diag_now(P);
       // Stage a batch once its slots are free: the compute wavefront reads
       // steps tc - WIN .. tc + 1.
       if (y < nr && y + BATCH - 1 <= tc - WIN - 1 + R) {
@@ -582,7 +588,7 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
           }
         }
       }
-      uint64_t q1 = __builtin_amdgcn_s_memrealtime();
+      uint64_t q1 = diag_now(P);
       io_stage += q1 - q0;
       q0 = q1;
       // Poll the neighbours' records for wanted rows still in the ring,
@@ -675,7 +681,7 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
           lds_st(&S.nbp[sd], v);
         }
       }
-      io_poll += __builtin_amdgcn_s_memrealtime() - q0;
+      io_poll += diag_now(P) - q0;
       if (!busy) {
         if (++idle > 4) __builtin_amdgcn_s_sleep(2);
       } else {
@@ -1036,16 +1042,16 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
   };
 
   uint64_t tm_stage = 0, tm_pace = 0, tm_settle = 0, tm_freeze = 0, tm_all = 0;  // diagnostics
-  const uint64_t tm_begin = __builtin_amdgcn_s_memrealtime();
+  const uint64_t tm_begin = diag_now(P);
   for (int t = 0; t < nr && !fail; ++t) {
     lds_st(&S.tcomp, t);
-    uint64_t tm0 = __builtin_amdgcn_s_memrealtime();
+    uint64_t tm0 = diag_now(P);
     if (!wait_staged(t + 2 < nr ? t + 2 : nr)) {
       fail = true;
       break;
     }
     lds_sync();
-    uint64_t tm1 = __builtin_amdgcn_s_memrealtime();
+    uint64_t tm1 = diag_now(P);
     tm_stage += tm1 - tm0;
     tm0 = tm1;
     // Pacing: wait while a neighbour is more than LEAD rows behind.
@@ -1069,7 +1075,7 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
         __builtin_amdgcn_s_sleep(1);
       }
     }
-    tm1 = __builtin_amdgcn_s_memrealtime();
+    tm1 = diag_now(P);
     tm_pace += tm1 - tm0;
     tm0 = tm1;
     const int lo = t - WIN + 1 > 0 ? t - WIN + 1 : 0;
@@ -1081,7 +1087,7 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
     }
     const uint32_t dirty = ((t % ARRIVE_EVERY) == 0 ? take_arrivals(lo, t) : 0u) | (1u << slot(t));
     settle(dirty, lo, t);
-    tm1 = __builtin_amdgcn_s_memrealtime();
+    tm1 = diag_now(P);
     tm_settle += tm1 - tm0;
     tm0 = tm1;
     if (t - WIN + 1 >= 0) {
@@ -1096,10 +1102,10 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
       freeze(f);
     }
     if (lane == 0) prog_put(P.progress + strip, t);
-    tm1 = __builtin_amdgcn_s_memrealtime();
+    tm1 = diag_now(P);
     tm_freeze += tm1 - tm0;
   }
-  tm_all = __builtin_amdgcn_s_memrealtime() - tm_begin;
+  tm_all = diag_now(P) - tm_begin;
 
   // Drain: the last rows wait (bounded) for their side cells, then leave.
   if (!fail) {
