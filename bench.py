@@ -36,9 +36,9 @@ ACC_BYTES = 1 + 4 + 4 + 8     # whole accumulate call: code, rain in; q, counts 
 # as they were when counted; other sizes report null.
 MEASURED_TRAFFIC = {
     ("d8", 43360, 43360): {"receivers": 10.63e9, "d8_up": 2.06e9 + 9.80e9, "d8_down": 33.18e9},
-    ("mfd", 16384, 16384): {"sweep": 9.77e9},       # float32 sweep (profiles/sweep_and_batch_hbm_traffic.md)
-    ("adjoint", 4096, 4096): {"sweep": 0.702e9},
-    ("batched", 512): {"batch": 24.87e9},
+    ("mfd", 16384, 16384): {"sweep": 9.70e9},       # float32 sweep (profiles/sweep_and_batch_hbm_traffic.md)
+    ("adjoint", 4096, 4096): {"sweep": 0.705e9},
+    ("batched", 512): {"batch": 24.70e9},
     ("fill", 16384, 16384): {"fill": 37.79e9 + 2.15e9},  # whole fill (profiles/fill_16384_kernel_stats.md)
 }
 # Algorithmic bytes per cell of the secondary workloads' dominant kernel
