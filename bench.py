@@ -411,8 +411,9 @@ def cpu_baseline_tiles(shapes, budget_s: float = 15.0):
 
 def run_blockiter(args):
     """The paper's parallel scheme on the GPU: D8 unit-rain counts on the
-    43360^2 DEM (seed 2) by block iterations (I+X, one sweep per 256-column
-    tile as D^-1), timed beside the exit-forest path on the same codes."""
+    43360^2 DEM (seed 2) by block iterations (I+X and (I-X)(I+X), blocks of
+    --block cells, each solved exactly), timed beside the direct path on the
+    same codes."""
     import numpy as np
     import torch
     import synth
@@ -443,15 +444,17 @@ def run_blockiter(args):
         return lib.fr_accumulate(None, P(code), nr, nc, fr.D8, 1.1, None, fr.F32, fr.NONE, None, P(cnt2), None,
                                  P(status), P(ws), wsb, sp)
 
+    br, bc = args.block
+
     def blocks():
-        return lib.fr_accumulate_block_iterations(P(code), nr, nc, fr.D8, fr.SCHEME_IX, None, fr.F32, fr.NONE,
-                                                  None, P(cnt), 100000, ctypes.byref(iters), P(status), P(ws),
-                                                  wsb, sp)
+        return lib.fr_accumulate_block_iterations(None, P(code), nr, nc, fr.D8, 0.0, br, bc, fr.SCHEME_IX, None,
+                                                  fr.F32, fr.NONE, None, P(cnt), 100000, ctypes.byref(iters),
+                                                  P(status), P(ws), wsb, sp)
 
     def blocks_pre():
-        return lib.fr_accumulate_block_iterations(P(code), nr, nc, fr.D8, fr.SCHEME_IMX_IX, None, fr.F32,
-                                                  fr.NONE, None, P(cnt2), 100000, ctypes.byref(iters_pre),
-                                                  P(status), P(ws), wsb, sp)
+        return lib.fr_accumulate_block_iterations(None, P(code), nr, nc, fr.D8, 0.0, br, bc, fr.SCHEME_IMX_IX,
+                                                  None, fr.F32, fr.NONE, None, P(cnt2), 100000,
+                                                  ctypes.byref(iters_pre), P(status), P(ws), wsb, sp)
 
     times = {}
     same_pre = None
@@ -482,9 +485,11 @@ def run_blockiter(args):
         "ms_per_step": 1e3 * t_it, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"D8 {nr}x{nc} fractal DEM (seed {args.seed}), unit-rain counts by the paper's "
-                               f"block iterations (I+X), 256-column tiles", "cells": ncell},
+                               f"block iterations (I+X), blocks of {br}x{bc} cells solved exactly",
+                   "cells": ncell},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_d8_iter",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "one block solve (k_d8_a, forest, k_d8_c)",
                      "bytes_per_cell": 17, "ms_per_launch": per_iter_ms},
         "detail": {"iterations_until_exact": iters.value, "launches": iters.value + 1,
                    "forest_path_ms": 1e3 * times["forest"], "same_counts_as_forest_path": same,
@@ -509,6 +514,8 @@ def main():
     ap.add_argument("--cols", type=int, default=0, help="D8: grid columns (e.g. the paper's 57345 x 32769)")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--cpu-size", type=int, default=8192)
+    ap.add_argument("--block", type=int, nargs=2, default=[4096, 4096],
+                    help="blockiter: block rows and columns (multiples of 16 and 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-tile", action="store_true", help="batched: skip the per-tile float64 comparison")
     ap.add_argument("--copy-probe", action="store_true",

@@ -40,11 +40,15 @@
  * sized by fr_workspace_bytes().  Calls on different streams must use
  * different workspaces.
  *
- * Streams.  All device work is ordered on the given stream.  The D8/D4
- * path of fr_accumulate also runs one kernel on a stream of the library's
- * own (created once per host thread and device, default priority), forked
- * from and joined back into the given stream with events, so the call's
- * work is still complete when the given stream is.
+ * Streams.  All device work is ordered on the given stream, and
+ * fr_receivers, fr_accumulate, fr_accumulate_adjoint and
+ * fr_accumulate_batched never synchronise the host with it: they enqueue a
+ * fixed sequence of kernels whose decisions (how many pointer-doubling
+ * rounds, how many sweep passes, whether a fallback path runs) are taken on
+ * the device, and return.  Such a call can be captured in a HIP graph and
+ * replayed.  Results are complete when the stream reaches the point after
+ * the call.  The block iterations and the depression fill read a small flag
+ * back between iterations and say so below.
  *
  * Errors.  Return value: FR_OK (0) or a negative FR_ERR_* code from host-side
  * validation of the arguments, or a HIP error seen while enqueueing.
@@ -103,6 +107,10 @@ extern "C" {
 #define FR_ERR_NOTDAG -6     /* device: routing has a cycle (bad codes)      */
 #define FR_ERR_BADCODE -7    /* device: code not 0..7/0xFF or leaves the grid */
 #define FR_ERR_TOOLARGE -8   /* grid larger than the library supports        */
+#define FR_ERR_STALL -9      /* device: a persistent launch's workgroups could
+                                not all run at once (barrier wait timed out) */
+#define FR_ERR_CAPACITY -10  /* device: block iterations found more exits than
+                                their workspace holds                        */
 
 /*
  * fr_receivers -- local flow routing (Section 2.1; Appendix A for FR_MFD).
@@ -155,9 +163,10 @@ int fr_receivers(const float* z, int64_t nrows, int64_t ncols, int rule, uint8_t
  *             FR_ERR_BADCODE, FR_ERR_NOTDAG.
  *   ws, ws_bytes workspace, at least fr_workspace_bytes(FR_FN_ACCUMULATE,..).
  *   stream    HIP stream.
- * The call synchronises the host with the stream a few times while it runs
- * (it reads back a progress counter); all results are complete when it
- * returns FR_OK.
+ * Enqueues its kernels and returns without synchronising (see Streams); the
+ * outputs are complete when the stream has passed the call.  For FR_F32 and
+ * FR_F64 the outputs are the same, bit for bit, on every run with the same
+ * inputs.
  */
 int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t ncols, int rule,
                   double mfd_p, const void* rain, int rain_dtype, int q_dtype, void* q_out,
@@ -183,26 +192,26 @@ int fr_accumulate_adjoint(const float* z, const uint8_t* code, int64_t nrows, in
 
 /*
  * fr_accumulate_block_iterations -- the paper's parallel scheme (Section
- * 3.3; Appendix B): block Richardson iterations with blocks of 256 columns x
- * th rows (th = 512 rows for grids of 2^28 cells or more, else 256).  Write
- * the system as (D - R) q = r, where D^-1 is the block's own solve -- here
- * one top-down row sweep, which follows every routing pair whose receiver
- * lies in the row before inside the block -- and R passes water along every
- * other pair (across block boundaries, within a row, or toward a later row);
- * with X = -D^-1 R the system reads (I + X) q = b, b = D^-1 r.
+ * 3.3; Appendix B): block Richardson iterations.  The grid is cut into
+ * blocks of block_rows x block_cols cells (the paper's per-process
+ * subdomains).  Write A = I - W^T as D - R, where D holds every routing pair
+ * inside a block and R every pair from one block into another; D^-1 is the
+ * exact solve of each block on its own (the same row sweeps and exit forest
+ * as fr_accumulate, with forest links kept inside the block), and R passes
+ * each cell's water to a receiver in another block.  With X = -D^-1 R the
+ * system reads (I + X) q = b, b = D^-1 r, and from w = 0:
  *   FR_SCHEME_IX      w <- D^-1 (r + R w)                      (eq. I+X)
- *   FR_SCHEME_IMX_IX  w <- w + (I - X)(b - (I + X) w), from w = 0: three
- *                     block solves per iteration (one for b, once), about
- *                     half as many iterations            (eq. (I-X)(I+X))
+ *   FR_SCHEME_IMX_IX  w <- w + (I - X)(b - (I + X) w): two block solves per
+ *                     iteration plus one for b       (eq. (I-X)(I+X))
  * Iterates until one equals the previous one (on the counts where given):
- * the exact solution, reached after C + 1 (FR_SCHEME_IX) or about
- * (C + 2) / 2 (FR_SCHEME_IMX_IX) iterations when flow paths cross R's pairs
- * at most C times.  It gives the same counts as fr_accumulate and the same
- * water up to rounding (whose exit forest replaces these iterations by
- * pointer doubling); it exists to measure the paper's scheme.  Single-
- * receiver rules only.
+ * the exact solution, reached after C + 1 (FR_SCHEME_IX) or
+ * ceil((C + 1) / 2) (FR_SCHEME_IMX_IX) iterations when no flow path crosses
+ * a block boundary more than C times (Appendix B).  Single-receiver rules.
  *
+ *   z, mfd_p  reserved (pass NULL and 0).
  *   code      device uint8 codes (FR_D8 or FR_D4), as for fr_accumulate.
+ *   block_rows, block_cols  block shape: block_cols a multiple of 256 or at
+ *             least ncols; block_rows a multiple of 16 or at least nrows.
  *   scheme    FR_SCHEME_IX or FR_SCHEME_IMX_IX.
  *   rain, rain_dtype   as for fr_accumulate (NULL = unit rain).
  *   q_dtype   FR_F64 (float64 water into q_out) or FR_NONE (counts only).
@@ -216,10 +225,14 @@ int fr_accumulate_adjoint(const float* z, const uint8_t* code, int64_t nrows, in
  *   ws, ws_bytes  workspace of fr_workspace_bytes(FR_FN_BLOCK_ITER or
  *             FR_FN_BLOCK_ITER_PRE for the scheme, ...).
  * Synchronises with the stream after every iteration (reads the change
- * flag).  Errors: FR_ERR_ARG, FR_ERR_RULE (not D8/D4), FR_ERR_WORKSPACE,
- * FR_ERR_TOOLARGE, FR_ERR_HIP; device-detected errors as for fr_accumulate.
+ * flag).  Errors: FR_ERR_ARG (also a block shape not as above), FR_ERR_RULE
+ * (not D8/D4), FR_ERR_WORKSPACE, FR_ERR_TOOLARGE, FR_ERR_HIP; in dev_status
+ * as for fr_accumulate, and FR_ERR_CAPACITY when more cells leave their
+ * tile than the exit list holds (an eighth of the cells on grids above 2^22
+ * cells).
  */
-int fr_accumulate_block_iterations(const uint8_t* code, int64_t nrows, int64_t ncols, int rule, int scheme,
+int fr_accumulate_block_iterations(const float* z, const uint8_t* code, int64_t nrows, int64_t ncols, int rule,
+                                   double mfd_p, int64_t block_rows, int64_t block_cols, int scheme,
                                    const void* rain, int rain_dtype, int q_dtype, void* q_out,
                                    uint64_t* counts_out, int32_t max_iter, int32_t* iters_out,
                                    int32_t* dev_status, void* ws, size_t ws_bytes, hipStream_t stream);
@@ -354,6 +367,20 @@ int fr_accumulate_batched(const fr_tile* tiles_dev, int32_t ntiles, const fr_bat
  */
 int fr_batch_autotune(const fr_tile* tiles_dev, int32_t ntiles, int32_t* dev_status, void* ws,
                       size_t ws_bytes, int reps, fr_batch_plan* plan_out, hipStream_t stream);
+
+/*
+ * fr_set_accumulate_path -- process-wide choice of the accumulation path of
+ * fr_accumulate and fr_accumulate_adjoint, for tests and diagnostics:
+ * FR_PATH_AUTO (the default: row sweeps and exit forest for single
+ * receivers, wavefront sweep otherwise, the peeling engine when either
+ * gives up), FR_PATH_SWEEP (wavefront sweep, then the engine) or
+ * FR_PATH_ENGINE (the peeling engine alone).  Every path computes the same
+ * solution; only the time differs.  Not thread-safe.  Errors: FR_ERR_ARG.
+ */
+#define FR_PATH_AUTO 0
+#define FR_PATH_SWEEP 1
+#define FR_PATH_ENGINE 2
+int fr_set_accumulate_path(int path);
 
 /* fr_status_string -- static text for a status code. */
 const char* fr_status_string(int code);

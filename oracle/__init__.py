@@ -80,7 +80,7 @@ def _load():
             "or_apply_A_mfd": [vp, i64, i64, dbl, vp, vp],
             "or_mass_single": [vp, i64, vp, vp, vp],
             "or_mass_mfd": [vp, i64, i64, vp, vp, vp],
-            "or_block_richardson": [vp, vp, i64, i64, dbl, vp, vp, i64, i64, ci, ci, ci, vp, vp, vp],
+            "or_block_richardson": [vp, vp, i64, i64, dbl, vp, vp, i64, i64, ci, ci, vp, vp, vp],
             "or_fill_depressions": [vp, i64, i64, ci, ci, vp],
         }
         for name, args in sig.items():
@@ -161,14 +161,13 @@ def accumulate_mfd(z, rain=None, p: float = 1.1, order_=None, frac32: bool = Fal
 
 
 def block_richardson(z, block, rule: int = D8, rain=None, scheme: int = 0, p: float = 1.1,
-                     max_iter: int = 100000, order_=None, split: int = 0):
+                     max_iter: int = 100000, order_=None):
     """The paper's parallel scheme run sequentially (Section 3.3 "I+X"
     (scheme 0) and "(I-X)(I+X)" (scheme 1) iterations; Appendix B): blocks of
-    block = (rows, cols) cells, per-block high-to-low solves, water passed
-    across block boundaries between iterations.  Returns (q float64,
-    counts uint64 (None for MFD), iterations until the iterate is exact).
-    split 0: D holds every pair inside a block (the paper); split 1: only the
-    pairs directed to the row before (what one top-down block sweep solves)."""
+    block = (rows, cols) cells, D = every routing pair inside a block solved
+    by the block's own high-to-low push, water passed across block
+    boundaries between iterations.  Returns (q float64, counts uint64 (None
+    for MFD), iterations until the iterate is exact)."""
     z = _f32(z)
     nr, nc = z.shape
     if order_ is None:
@@ -179,7 +178,7 @@ def block_richardson(z, block, rule: int = D8, rain=None, scheme: int = 0, p: fl
     co = np.empty((nr, nc), dtype=np.uint64) if code is not None else None
     it = ctypes.c_int(0)
     _check(_load().or_block_richardson(_p(code), _p(z), nr, nc, p, _p(order_), _p(r), int(block[0]),
-                                       int(block[1]), int(split), int(scheme), int(max_iter), _p(q), _p(co),
+                                       int(block[1]), int(scheme), int(max_iter), _p(q), _p(co),
                                        ctypes.addressof(it)), "block_richardson")
     return q, co, it.value
 

@@ -376,18 +376,15 @@ static int64_t block_of(int64_t nc, int64_t br, int64_t bc, int64_t i) {
   return (i / nc / br) * nbc + (i % nc) / bc;
 }
 
-/* Whether the pair i -> k belongs to D: inside one block and, with split 1,
- * also directed to the row before (the pairs one top-down sweep of a block
- * follows; every other pair is passed between iterations). */
-static int in_d(int64_t nc, int64_t br, int64_t bc, int split, int64_t i, int64_t k) {
-  if (block_of(nc, br, bc, k) != block_of(nc, br, bc, i)) return 0;
-  return split == 0 || k / nc == i / nc - 1;
+/* Whether the pair i -> k belongs to D: both cells in one block. */
+static int in_d(int64_t nc, int64_t br, int64_t bc, int64_t i, int64_t k) {
+  return block_of(nc, br, bc, k) == block_of(nc, br, bc, i);
 }
 
 /* y = rho x (inside == 0) or y = D^{-1} x (inside == 1), in float64 and in
  * uint64 (wrap-around arithmetic: the (I-X)(I+X) scheme subtracts). */
 static void block_apply(const uint8_t* code, const float* z, int64_t nr, int64_t nc, double p,
-                        const int64_t* order, int64_t br, int64_t bc, int split, int inside,
+                        const int64_t* order, int64_t br, int64_t bc, int inside,
                         const double* x, const uint64_t* xc, double* y, uint64_t* yc) {
   const int64_t n = nr * nc;
   int64_t nb[8];
@@ -400,7 +397,7 @@ static void block_apply(const uint8_t* code, const float* z, int64_t nr, int64_t
     for (int64_t i = 0; i < n; ++i) {
       const int m = pairs_of(code, z, nr, nc, p, i, nb, f);
       for (int s = 0; s < m; ++s) {
-        if (in_d(nc, br, bc, split, i, nb[s])) continue;
+        if (in_d(nc, br, bc, i, nb[s])) continue;
         y[nb[s]] += f[s] * x[i];
         yc[nb[s]] += xc[i];
       }
@@ -415,7 +412,7 @@ static void block_apply(const uint8_t* code, const float* z, int64_t nr, int64_t
     const int64_t i = order[t];
     const int m = pairs_of(code, z, nr, nc, p, i, nb, f);
     for (int s = 0; s < m; ++s) {
-      if (!in_d(nc, br, bc, split, i, nb[s])) continue;
+      if (!in_d(nc, br, bc, i, nb[s])) continue;
       y[nb[s]] += f[s] * y[i];
       yc[nb[s]] += yc[i];
     }
@@ -423,10 +420,10 @@ static void block_apply(const uint8_t* code, const float* z, int64_t nr, int64_t
 }
 
 int or_block_richardson(const uint8_t* code, const float* z, int64_t nr, int64_t nc, double p,
-                        const int64_t* order, const float* rain, int64_t br, int64_t bc, int split,
+                        const int64_t* order, const float* rain, int64_t br, int64_t bc,
                         int scheme, int max_iter, double* q, uint64_t* counts, int* iters) {
   if ((!code && !z) || !order || !iters || nr < 0 || nc < 0 || br < 1 || bc < 1 || max_iter < 1 ||
-      (scheme != 0 && scheme != 1) || (split != 0 && split != 1))
+      (scheme != 0 && scheme != 1))
     return -2;
   const size_t n = (size_t)(nr * nc) + 1;
   double* w = (double*)calloc(n, sizeof(double));  /* current iterate */
@@ -448,28 +445,28 @@ int or_block_richardson(const uint8_t* code, const float* z, int64_t nr, int64_t
       t1[i] = rain ? (double)rain[i] : 1.0;
       u1[i] = 1;
     }
-    block_apply(code, z, nr, nc, p, order, br, bc, split, 1, t1, u1, b, bcn); /* b = D^{-1} r */
+    block_apply(code, z, nr, nc, p, order, br, bc, 1, t1, u1, b, bcn); /* b = D^{-1} r */
     *iters = 0;
     for (int l = 1; l <= max_iter + 1; ++l) {
       if (scheme == 0) {
         /* next = D^{-1} (r + rho w) */
-        block_apply(code, z, nr, nc, p, order, br, bc, split, 0, w, wc, t1, u1);
+        block_apply(code, z, nr, nc, p, order, br, bc, 0, w, wc, t1, u1);
         for (int64_t i = 0; i < m; ++i) {
           t1[i] += rain ? (double)rain[i] : 1.0;
           u1[i] += 1;
         }
-        block_apply(code, z, nr, nc, p, order, br, bc, split, 1, t1, u1, nx, nxc);
+        block_apply(code, z, nr, nc, p, order, br, bc, 1, t1, u1, nx, nxc);
       } else {
         /* res = b - (I + X) w = b - w + D^{-1} rho w  (into t1/u1) */
-        block_apply(code, z, nr, nc, p, order, br, bc, split, 0, w, wc, t2, u2);
-        block_apply(code, z, nr, nc, p, order, br, bc, split, 1, t2, u2, t1, u1);
+        block_apply(code, z, nr, nc, p, order, br, bc, 0, w, wc, t2, u2);
+        block_apply(code, z, nr, nc, p, order, br, bc, 1, t2, u2, t1, u1);
         for (int64_t i = 0; i < m; ++i) {
           t1[i] = b[i] - w[i] + t1[i];
           u1[i] = bcn[i] - wc[i] + u1[i];
         }
         /* next = w + (I - X) res = w + res + D^{-1} rho res */
-        block_apply(code, z, nr, nc, p, order, br, bc, split, 0, t1, u1, t2, u2);
-        block_apply(code, z, nr, nc, p, order, br, bc, split, 1, t2, u2, nx, nxc);
+        block_apply(code, z, nr, nc, p, order, br, bc, 0, t1, u1, t2, u2);
+        block_apply(code, z, nr, nc, p, order, br, bc, 1, t2, u2, nx, nxc);
         for (int64_t i = 0; i < m; ++i) {
           nx[i] = w[i] + t1[i] + nx[i];
           nxc[i] = wc[i] + u1[i] + nxc[i];

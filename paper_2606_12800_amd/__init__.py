@@ -13,6 +13,7 @@ solve for gradients with respect to the rain.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 
@@ -30,12 +31,15 @@ SCHEME_IX, SCHEME_IMX_IX = 0, 1
 OK = 0
 ERR_ARG, ERR_RULE, ERR_WORKSPACE, ERR_HIP = -1, -2, -3, -4
 ERR_NONFINITE, ERR_NOTDAG, ERR_BADCODE, ERR_TOOLARGE = -5, -6, -7, -8
+ERR_STALL, ERR_CAPACITY = -9, -10
+PATH_AUTO, PATH_SWEEP, PATH_ENGINE = 0, 1, 2
+PATHS = {"auto": PATH_AUTO, "sweep": PATH_SWEEP, "engine": PATH_ENGINE}
 
 RULES = {"d8": D8, "mfd": MFD, "d4": D4}
 EXPORTS = ["fr_receivers", "fr_accumulate", "fr_accumulate_adjoint", "fr_workspace_bytes",
            "fr_status_string", "fr_version", "fr_timing_enable", "fr_timing_last",
            "fr_batched_workspace_bytes", "fr_accumulate_batched", "fr_batch_autotune",
-           "fr_accumulate_block_iterations", "fr_fill_depressions"]
+           "fr_accumulate_block_iterations", "fr_fill_depressions", "fr_set_accumulate_path"]
 ORDER_GIVEN, ORDER_ROWS_DESC = 0, 1
 
 
@@ -93,11 +97,13 @@ def load_library() -> ctypes.CDLL:
     lib.fr_accumulate_batched.restype = ci
     lib.fr_batch_autotune.argtypes = [vp, i32, vp, vp, sz, ci, vp, vp]
     lib.fr_batch_autotune.restype = ci
-    lib.fr_accumulate_block_iterations.argtypes = [vp, i64, i64, ci, ci, vp, ci, ci, vp, vp, i32, vp, vp, vp, sz,
-                                                   vp]
+    lib.fr_accumulate_block_iterations.argtypes = [vp, vp, i64, i64, ci, cd, i64, i64, ci, vp, ci, ci, vp, vp, i32,
+                                                   vp, vp, vp, sz, vp]
     lib.fr_accumulate_block_iterations.restype = ci
     lib.fr_fill_depressions.argtypes = [vp, i64, i64, ci, ci, vp, vp, vp, vp, sz, vp]
     lib.fr_fill_depressions.restype = ci
+    lib.fr_set_accumulate_path.argtypes = [ci]
+    lib.fr_set_accumulate_path.restype = ci
     _lib = lib
     return lib
 
@@ -127,6 +133,21 @@ def timing_last() -> dict:
         key = names[i].decode()
         out[key] = out.get(key, 0.0) + float(ms[i])
     return out
+
+
+@contextlib.contextmanager
+def accumulate_path(path: str):
+    """Within the block, fr_accumulate / fr_accumulate_adjoint take the given
+    path ("auto", "sweep" or "engine"; ``fr_set_accumulate_path``).  Every
+    path computes the same solution; tests use this to cover the fallbacks."""
+    lib = load_library()
+    rc = lib.fr_set_accumulate_path(PATHS[path])
+    if rc != OK:
+        raise FlowRouteError(rc, "fr_set_accumulate_path")
+    try:
+        yield
+    finally:
+        lib.fr_set_accumulate_path(PATH_AUTO)
 
 
 def _rule(rule) -> int:
@@ -262,8 +283,10 @@ def adjoint(code: torch.Tensor, qbar: torch.Tensor, z: torch.Tensor | None = Non
 
 def block_iterations(code: torch.Tensor, rain: torch.Tensor | None = None, rule="d8",
                      dtype=torch.float64, counts: bool = True, max_iter: int = 100000,
-                     ws: Workspace | None = None, check: bool = True, scheme: str = "ix"):
-    """The paper's block Richardson iterations (``fr_accumulate_block_iterations``):
+                     ws: Workspace | None = None, check: bool = True, scheme: str = "ix",
+                     block=(256, 256)):
+    """The paper's block Richardson iterations (``fr_accumulate_block_iterations``)
+    with blocks of ``block`` = (rows, cols) cells, each solved exactly:
     scheme "ix" iterates on I+X, "imx_ix" on (I-X)(I+X).
     Returns (q float64 or None, counts or None, iterations until exact)."""
     schemes = {"ix": SCHEME_IX, "imx_ix": SCHEME_IMX_IX}
@@ -289,7 +312,8 @@ def block_iterations(code: torch.Tensor, rain: torch.Tensor | None = None, rule=
     nbytes = workspace_bytes(FN_BLOCK_ITER if sch == SCHEME_IX else FN_BLOCK_ITER_PRE, nr, nc, r, dt)
     buf = (ws or _default_ws).get(nbytes, dev)
     iters = ctypes.c_int32(0)
-    rc = load_library().fr_accumulate_block_iterations(_ptr(code), nr, nc, r, sch, _ptr(rain), rdt, dt, _ptr(q),
+    rc = load_library().fr_accumulate_block_iterations(None, _ptr(code), nr, nc, r, 0.0, int(block[0]),
+                                                       int(block[1]), sch, _ptr(rain), rdt, dt, _ptr(q),
                                                        _ptr(cnt), int(max_iter), ctypes.byref(iters),
                                                        _ptr(status), _ptr(buf), buf.numel(), _stream(dev))
     if rc != OK:

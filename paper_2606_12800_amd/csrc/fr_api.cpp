@@ -16,24 +16,30 @@ constexpr int64_t kMaxCells = 2147483647;  // cell indices fit in int32
 
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Every workspace of fr_accumulate, fr_accumulate_adjoint and the block
+// iterations starts (at its first 256-byte aligned address) with the call's
+// control block; the layouts below are relative to the byte after it.
+constexpr size_t kCtlBytes = kAlign;
+
 struct Layout {
-  size_t ext, done, vlo, rs32, iw32, iw64, stamp, list0, list1, ctr, partial, total;
+  size_t vlo, ext, done, rs32, iw32, iw64, stamp, list0, list1, ctr, partial, total;
 };
 
 int64_t tiles_of(int64_t nrows, int64_t ncols) {
   return ((nrows + ENG_TH - 1) / ENG_TH) * ((ncols + ENG_TW - 1) / ENG_TW);
 }
 
-// Offsets relative to the first 256-byte aligned address inside ws; the
-// total includes kAlign bytes of slack for that alignment.
+// Peeling engine.  The float-float low part comes first, at the same offset
+// as the wavefront sweep's, so that the mass reduction after either path
+// reads it from one place.
 Layout layout(int64_t nrows, int64_t ncols, int rule, int vdtype) {
   Layout L{};
   const size_t n = (size_t)(nrows * ncols);
   const size_t nt = (size_t)tiles_of(nrows, ncols);
   size_t o = 0;
+  L.vlo = o; if (vdtype == FR_F32) o += up(n * sizeof(float));
   L.ext = o; o += up(n + 4);
   L.done = o; o += up(n + 4);
-  L.vlo = o; if (vdtype == FR_F32) o += up(n * sizeof(float));
   L.rs32 = o; if (rule == FR_MFD && vdtype == FR_F32) o += up(n * sizeof(float));
   L.iw32 = o; if (rule == FR_MFD && vdtype == FR_F32) o += up(n * sizeof(float));
   L.iw64 = o; if (rule == FR_MFD && vdtype == FR_F64) o += up(n * sizeof(double));
@@ -42,54 +48,57 @@ Layout layout(int64_t nrows, int64_t ncols, int rule, int vdtype) {
   L.list1 = o; o += up(nt * sizeof(int32_t));
   L.ctr = o; o += kAlign;
   L.partial = o; o += up(2 * kMassBlocks * sizeof(double));
-  L.total = o + kAlign;
+  L.total = o;
   return L;
 }
 
-// Workspace of the row-sweep single-receiver path (fr_d8.hip).  It shares
-// the workspace with the engine: the engine only runs when this path gives up
-// (exit list overflow), after which this path's data is dead.
+// Row-sweep single-receiver path (fr_d8.hip).  The engine's layout overlays
+// it: the engine only runs once this path gave up (exit list overflow), and
+// then nothing reads this path's data any more.
 struct D8Layout {
-  size_t root_of, node_of, ex_cell, anc0, anc1, cnt0, cnt1, hi0, hi1, lo0, lo1, q0, q1, ctr, mass, total;
+  size_t root_of, node_of, ex_cell, cnt0, cnt1, fx0, fx1, anc0, anc1, ctr, mass, total;
   uint32_t cap;
 };
 
-uint32_t d8_capacity(int64_t n) {
-  if (n <= ((int64_t)1 << 22)) return (uint32_t)(n > 0 ? n : 1);
+// Exit capacity, plus a chunk of slack per tile (a phase-A wavefront leaves
+// unused slots only in its last chunk): every cell on grids up to 2^22
+// cells, so that the list cannot overflow there, else an eighth of the
+// cells (at least 2^22).
+constexpr int64_t kFullCapacityCells = (int64_t)1 << 22;
+uint32_t d8_capacity(int64_t n, int64_t ntiles) {
+  const int64_t slack = (int64_t)D8_EXIT_CHUNK * ntiles;
+  if (n <= kFullCapacityCells) return (uint32_t)((n > 0 ? n : 1) + slack);
   const int64_t c = n / 8;
-  return (uint32_t)(c > ((int64_t)1 << 22) ? c : ((int64_t)1 << 22));
+  return (uint32_t)((c > kFullCapacityCells ? c : kFullCapacityCells) + slack);
 }
 
-D8Layout d8_layout(int64_t nrows, int64_t ncols, int vdtype, bool counts) {
+// th: tile height (the mass partials are per tile).  The local sums of
+// phase A (float-float or float64, 8 bytes per exit) live in the snapshot
+// buffer fx1 until the link step has turned them into fixed point.
+D8Layout d8_layout(int64_t nrows, int64_t ncols, int th, int vdtype, bool counts) {
   D8Layout L{};
   const size_t n = (size_t)(nrows * ncols);
-  const int th = d8_tile_height(nrows, ncols);
   const size_t nt = (size_t)(((nrows + th - 1) / th) * ((ncols + D8_TW - 1) / D8_TW));
-  L.cap = d8_capacity((int64_t)n);
+  L.cap = d8_capacity((int64_t)n, (int64_t)nt);
   const size_t cap = L.cap;
+  const bool vals = vdtype == FR_F32 || vdtype == FR_F64;
   size_t o = 0;
   L.root_of = o; o += up(n * 4);
   L.node_of = o; o += up(n * 4);
   L.ex_cell = o; o += up(cap * 4);
-  L.anc0 = o; o += up(cap * 4);
-  L.anc1 = o; o += up(cap * 4);
   L.cnt0 = o; if (counts) o += up(cap * 8);
   L.cnt1 = o; if (counts) o += up(cap * 8);
-  L.hi0 = o; if (vdtype == FR_F32) o += up(cap * 4);
-  L.hi1 = o; if (vdtype == FR_F32) o += up(cap * 4);
-  L.lo0 = o; if (vdtype == FR_F32) o += up(cap * 4);
-  L.lo1 = o; if (vdtype == FR_F32) o += up(cap * 4);
-  L.q0 = o; if (vdtype == FR_F64) o += up(cap * 8);
-  L.q1 = o; if (vdtype == FR_F64) o += up(cap * 8);
+  L.fx0 = o; if (vals) o += up(cap * 16);
+  L.fx1 = o; if (vals) o += up(cap * 16);
+  L.anc0 = o; o += up(cap * 4);
+  L.anc1 = o; o += up(cap * 4);
   L.ctr = o; o += kAlign;
   L.mass = o; o += up(nt * 2 * sizeof(double));
-  L.total = o + kAlign;
+  L.total = o;
   return L;
 }
 
-// Workspace of the wavefront sweep (fr_wsweep.hip).  Like the row-sweep
-// path it overlays the engine's workspace; the engine only runs after the
-// sweep gave up.
+// Wavefront sweep (fr_wsweep.hip).  The engine overlays it too.
 struct WsLayout {
   size_t vlo, edge, progress, ctr, partial, total;
 };
@@ -103,7 +112,7 @@ WsLayout ws_layout(int64_t nrows, int64_t ncols, int vdtype) {
   L.progress = o; o += up((size_t)ws_strips(ncols) * sizeof(int32_t));
   L.ctr = o; o += kAlign;
   L.partial = o; o += up(2 * kMassBlocks * sizeof(double));
-  L.total = o + kAlign;
+  L.total = o;
   return L;
 }
 
@@ -111,6 +120,7 @@ struct Counters {
   int32_t nlist[3];
   int32_t pad;
   unsigned long long remaining;
+  unsigned long long bar;
 };
 
 bool valid_rule(int rule) { return rule == FR_D8 || rule == FR_D4 || rule == FR_MFD; }
@@ -121,8 +131,7 @@ int cu_count() {
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
   if (cache[dev] == 0) {
     int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
-      v = 256;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
     cache[dev] = v;
   }
   return cache[dev];
@@ -170,249 +179,19 @@ void phase_end(int i, hipStream_t s) {
   if (i >= 0) (void)hipEventRecord(g_timing.ev[i][1], s);
 }
 
-int run_engine_body(const EngineConfig& cfg, EngineParams P, char* base, const Layout& L, int32_t* status,
-                    hipStream_t s);
-
-// Runs the peeling engine to completion (see fr_engine.hip).
-int run_engine(const EngineConfig& cfg, EngineParams P, char* base, const Layout& L, int32_t* status,
-               hipStream_t s) {
-  const int ph = phase_begin("engine", s);
-  const int rc = run_engine_body(cfg, P, base, L, status, s);
-  phase_end(ph, s);
-  return rc;
-}
-
-int run_engine_body(const EngineConfig& cfg, EngineParams P, char* base, const Layout& L, int32_t* status,
-                    hipStream_t s) {
-  if (launch_engine_init(cfg, P, s) != hipSuccess) return FR_ERR_HIP;
-  const int64_t ntiles = (int64_t)P.ntr * P.ntc;
-  int grid = 2 * cu_count();
-  if ((int64_t)grid > ntiles) grid = (int)ntiles;
-  Counters* dctr = reinterpret_cast<Counters*>(base + L.ctr);
-  int it = 0;
-  int batch = 4;
-  const int max_it = 1 << 30;
-  for (;;) {
-    for (int b = 0; b < batch; ++b, ++it)
-      if (launch_engine_iter(cfg, P, it, grid, s) != hipSuccess) return FR_ERR_HIP;
-    Counters h{};
-    if (hipMemcpyAsync(&h, dctr, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess) return FR_ERR_HIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return FR_ERR_HIP;
-    if (h.remaining == 0) break;
-    if (h.nlist[it % 3] == 0 || it >= max_it) {
-      // Nothing queued but cells unfinished: the routing graph has a cycle.
-      if (status && launch_set_status(status, FR_ERR_NOTDAG, s) != hipSuccess) return FR_ERR_HIP;
-      break;
-    }
-    if (batch < 64) batch *= 2;
-  }
-  return FR_OK;
-}
-
-// Row-sweep path for single-receiver codes, forward solve.  Returns FR_OK,
-// an error, or 1 when the exit list overflowed (the caller then runs the
-// engine).
-int run_d8(const uint8_t* code, int64_t nrows, int64_t ncols, const float* rain32, const double* rain64,
-           ValKind vk, float* q32, double* q64, uint64_t* cnt, double* mass_out, int32_t* status, char* base,
-           hipStream_t s) {
-  const bool counts = cnt != nullptr;
-  const D8Layout L = d8_layout(nrows, ncols, vk == VK_FF ? FR_F32 : (vk == VK_F64 ? FR_F64 : FR_NONE), counts);
-  D8Params P{};
-  P.nrows = nrows;
-  P.ncols = ncols;
-  P.th = d8_tile_height(nrows, ncols);
-  P.ntr = (int32_t)((nrows + P.th - 1) / P.th);
-  P.ntc = (int32_t)((ncols + D8_TW - 1) / D8_TW);
-  P.code = code;
-  P.rain32 = rain32;
-  P.rain64 = rain64;
-  P.q32 = q32;
-  P.q64 = q64;
-  P.cnt = cnt;
-  P.root_of = reinterpret_cast<uint32_t*>(base + L.root_of);
-  P.node_of = reinterpret_cast<uint32_t*>(base + L.node_of);
-  P.ex_cell = reinterpret_cast<uint32_t*>(base + L.ex_cell);
-  P.anc[0] = reinterpret_cast<uint32_t*>(base + L.anc0);
-  P.anc[1] = reinterpret_cast<uint32_t*>(base + L.anc1);
-  P.ex_cnt[0] = reinterpret_cast<uint64_t*>(base + L.cnt0);
-  P.ex_cnt[1] = reinterpret_cast<uint64_t*>(base + L.cnt1);
-  P.ex_hi[0] = reinterpret_cast<float*>(base + L.hi0);
-  P.ex_hi[1] = reinterpret_cast<float*>(base + L.hi1);
-  P.ex_lo[0] = reinterpret_cast<float*>(base + L.lo0);
-  P.ex_lo[1] = reinterpret_cast<float*>(base + L.lo1);
-  P.ex_q64[0] = reinterpret_cast<double*>(base + L.q0);
-  P.ex_q64[1] = reinterpret_cast<double*>(base + L.q1);
-  uint32_t* ctr = reinterpret_cast<uint32_t*>(base + L.ctr);
-  P.n_exits = ctr;
-  P.flags = reinterpret_cast<int32_t*>(ctr + 4);
-  P.cap = L.cap;
-  P.mass_part = mass_out ? reinterpret_cast<double*>(base + L.mass) : nullptr;
-  P.status = status;
-
-  if (launch_zero_u32(ctr, 16, s) != hipSuccess) return FR_ERR_HIP;
-  int ph = phase_begin("d8_up", s);
-  if (launch_d8_up(vk, counts, P, s) != hipSuccess) return FR_ERR_HIP;
-  phase_end(ph, s);
-  uint32_t n = 0;
-  if (hipMemcpyAsync(&n, ctr, sizeof n, hipMemcpyDeviceToHost, s) != hipSuccess) return FR_ERR_HIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return FR_ERR_HIP;
-  if (n > L.cap) return 1;
-  P.n_ex = n;
-  int round = 0;
-  ph = phase_begin("d8_forest", s);
-  if (n > 0) {
-    if (launch_d8_link(P, n, s) != hipSuccess) return FR_ERR_HIP;
-    // A forest of n nodes is at most n deep: 33 rounds always suffice; more
-    // means the exits form a cycle (malformed codes).  Rounds go out four
-    // at a time (a round after the last one with work returns at once);
-    // the host then reads the flag of the last round queued.
-    constexpr int kRoundBatch = 4;
-    for (;;) {
-      for (int q = 0; q < kRoundBatch; ++q, ++round)
-        if (launch_d8_round(vk, counts, P, n, round, s) != hipSuccess) return FR_ERR_HIP;
-      int32_t flag = 0;
-      if (hipMemcpyAsync(&flag, P.flags + 4 + (round - 1) % 3, sizeof flag, hipMemcpyDeviceToHost, s) !=
-          hipSuccess)
-        return FR_ERR_HIP;
-      if (hipStreamSynchronize(s) != hipSuccess) return FR_ERR_HIP;
-      if (!flag) break;
-      if (round > 33) {
-        if (status && launch_set_status(status, FR_ERR_NOTDAG, s) != hipSuccess) return FR_ERR_HIP;
-        break;
-      }
-    }
-  }
-  phase_end(ph, s);
-  ph = phase_begin("d8_down", s);
-  if (launch_d8_down(vk, counts, P, s) != hipSuccess) return FR_ERR_HIP;
-  phase_end(ph, s);
-  if (mass_out) {
-    const int nt = P.ntr * P.ntc;
-    ph = phase_begin("mass", s);
-    if (launch_mass_final(P.mass_part, nt, mass_out, s) != hipSuccess) return FR_ERR_HIP;
-    phase_end(ph, s);
-  }
-  return FR_OK;
-}
-
-// Accumulation path: "auto" (row sweeps for D8/D4 forward, the wavefront
-// sweep otherwise), "sweep" (the wavefront sweep for everything) or
-// "engine" (the peeling engine for everything), from FLOWROUTE_ACC.
-enum AccPath { ACC_AUTO, ACC_SWEEP, ACC_ENGINE };
-AccPath acc_path() {
-  const char* e = getenv("FLOWROUTE_ACC");
-  if (e && strcmp(e, "engine") == 0) return ACC_ENGINE;
-  if (e && strcmp(e, "sweep") == 0) return ACC_SWEEP;
-  return ACC_AUTO;
-}
+// Accumulation path (fr_set_accumulate_path): every path computes the same
+// result; the default picks the row sweeps for single receivers.
+int g_path = FR_PATH_AUTO;
 
 constexpr int kMaxSweepPasses = 32;
-
-// Diagnostics on stderr when FLOWROUTE_VERBOSE is set.
-bool verbose() {
-  static const bool v = getenv("FLOWROUTE_VERBOSE") != nullptr;
-  return v;
-}
-
-// Wavefront-sweep passes until every cell is final.  Returns FR_OK, an
-// error, or 1 when the pass budget ran out (the caller then runs the
-// engine from scratch).
-int run_ws(const EngineConfig& cfg, WsParams P, int32_t* status, hipStream_t s) {
-  if (launch_ws_setup(cfg, P, s) != hipSuccess) return FR_ERR_HIP;
-  uint32_t h[4] = {0, 0, 0, 0};
-  if (hipMemcpyAsync(h, P.ctr, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess) return FR_ERR_HIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return FR_ERR_HIP;
-  // Visit the rows holding most inputs first: forward inputs are donors,
-  // upstream of their receivers; adjoint inputs are the receivers.
-  const bool flows_up = h[1] >= h[2];
-  int dir = ((cfg.dir == DIR_FWD) == flows_up) ? -1 : 1;
-  int64_t remaining = P.nrows * P.ncols;
-  uint32_t last_fin[2] = {0, 0};  // cells finished by the last pass going up (dir -1) / down (dir +1)
-  // FLOWROUTE_WS_MAXPASS (diagnostics): stop after that many passes and
-  // leave unfinished cells as they are.
-  const char* mp = getenv("FLOWROUTE_WS_MAXPASS");
-  const int max_pass = mp ? atoi(mp) : -1;
-  for (int pass = 0;; ++pass) {
-    if (max_pass >= 0 && pass >= max_pass) return FR_OK;
-    if (pass >= kMaxSweepPasses) return 1;
-    if (launch_zero_u32(P.ctr, 1, s) != hipSuccess) return FR_ERR_HIP;
-    if (P.debug && launch_zero_u32(P.ctr + 3, 25, s) != hipSuccess) return FR_ERR_HIP;
-    if (launch_ws_progress_reset(P, s) != hipSuccess) return FR_ERR_HIP;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (verbose() && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess)
-      (void)hipEventRecord(e0, s);
-    if (launch_ws_pass(cfg, P, dir, pass == 0 ? 1 : 0, s) != hipSuccess) return FR_ERR_HIP;
-    if (e1) (void)hipEventRecord(e1, s);
-    uint32_t fin = 0;
-    int32_t st = 0;
-    if (hipMemcpyAsync(&fin, P.ctr, sizeof fin, hipMemcpyDeviceToHost, s) != hipSuccess) return FR_ERR_HIP;
-    if (status && hipMemcpyAsync(&st, status, sizeof st, hipMemcpyDeviceToHost, s) != hipSuccess)
-      return FR_ERR_HIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return FR_ERR_HIP;
-    remaining -= fin;
-    if (verbose()) {
-      float ms = 0.0f;
-      if (e1) (void)hipEventElapsedTime(&ms, e0, e1);
-      uint32_t d[28] = {0};
-      if (P.debug && hipMemcpy(d, P.ctr, sizeof d, hipMemcpyDeviceToHost) != hipSuccess) return FR_ERR_HIP;
-      fprintf(stderr,
-              "flowroute: sweep pass %d dir %+d finished %u remaining %lld (%.3f ms) edge-waits %u pace-spins %u "
-              "resolves %u row-iterations %u\n",
-              pass, dir, fin, (long long)remaining, ms, d[3], d[4], d[5], d[6]);
-      if (P.debug) {
-        const uint64_t* tm = reinterpret_cast<const uint64_t*>(d + 8);
-        const double steps = (double)P.nrows * (double)ws_strips(P.ncols);
-        fprintf(stderr,
-                "flowroute:   per strip-step (us): wait-staged %.3f pace %.3f settle %.3f (resolve %.3f, row loop %.3f) freeze %.3f "
-                "all %.3f | io stage %.3f poll %.3f iterations/step %.2f\n",
-                tm[0] / steps / 100.0, tm[1] / steps / 100.0, tm[2] / steps / 100.0, tm[8] / steps / 100.0, tm[9] / steps / 100.0,
-                tm[3] / steps / 100.0, tm[4] / steps / 100.0, tm[5] / steps / 100.0, tm[6] / steps / 100.0,
-                tm[7] / steps);
-      }
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    if (remaining <= 0 || st != 0) break;
-    if (fin == 0) {
-      // A pass finishes at least the highest unfinished cell of a DAG.
-      if (status && launch_set_status(status, FR_ERR_NOTDAG, s) != hipSuccess) return FR_ERR_HIP;
-      break;
-    }
-    // Either direction finishes the highest unfinished cell, so the next
-    // pass may go either way: after one pass each way, repeat the direction
-    // whose last pass finished more (terrain that drains mostly one way
-    // leaves cells that the reverse sweep barely touches).
-    last_fin[dir > 0] = fin;
-    if (pass == 0 || last_fin[0] == last_fin[1]) dir = -dir;
-    else dir = last_fin[1] > last_fin[0] ? 1 : -1;
-  }
-  return FR_OK;
-}
-
-WsParams ws_params(const EngineConfig& cfg, int64_t nrows, int64_t ncols, const uint8_t* code, const float* z,
-                   double p, char* base, const WsLayout& L, int32_t* status) {
-  WsParams P{};
-  P.nrows = nrows;
-  P.ncols = ncols;
-  P.code = code;
-  P.z = z;
-  P.p = p;
-  P.vlo = cfg.vk == VK_FF ? reinterpret_cast<float*>(base + L.vlo) : nullptr;
-  P.edge = reinterpret_cast<uint64_t*>(base + L.edge);
-  P.progress = reinterpret_cast<int32_t*>(base + L.progress);
-  P.ctr = reinterpret_cast<uint32_t*>(base + L.ctr);
-  P.status = status;
-  P.debug = getenv("FLOWROUTE_WS_DEBUG") != nullptr;
-  return P;
-}
 
 char* aligned_base(void* ws) {
   const uintptr_t a = reinterpret_cast<uintptr_t>(ws);
   return reinterpret_cast<char*>((a + kAlign - 1) / kAlign * kAlign);
 }
 
-EngineParams common_params(int64_t nrows, int64_t ncols, const uint8_t* code, const float* z, double p,
-                           char* base, const Layout& L, int32_t* status) {
+EngineParams engine_params(int64_t nrows, int64_t ncols, const uint8_t* code, const float* z, double p,
+                           char* body, const Layout& L, int32_t* status, const int32_t* gate) {
   EngineParams P{};
   P.nrows = nrows;
   P.ncols = ncols;
@@ -421,20 +200,133 @@ EngineParams common_params(int64_t nrows, int64_t ncols, const uint8_t* code, co
   P.code = code;
   P.z = z;
   P.p = p;
-  P.ext = reinterpret_cast<uint8_t*>(base + L.ext);
-  P.done = reinterpret_cast<uint8_t*>(base + L.done);
-  P.vlo = reinterpret_cast<float*>(base + L.vlo);
-  P.rs32 = reinterpret_cast<float*>(base + L.rs32);
-  P.iw32 = reinterpret_cast<float*>(base + L.iw32);
-  P.iw64 = reinterpret_cast<double*>(base + L.iw64);
-  P.stamp = reinterpret_cast<int32_t*>(base + L.stamp);
-  P.list0 = reinterpret_cast<int32_t*>(base + L.list0);
-  P.list1 = reinterpret_cast<int32_t*>(base + L.list1);
-  Counters* c = reinterpret_cast<Counters*>(base + L.ctr);
+  P.ext = reinterpret_cast<uint8_t*>(body + L.ext);
+  P.done = reinterpret_cast<uint8_t*>(body + L.done);
+  P.vlo = reinterpret_cast<float*>(body + L.vlo);
+  P.rs32 = reinterpret_cast<float*>(body + L.rs32);
+  P.iw32 = reinterpret_cast<float*>(body + L.iw32);
+  P.iw64 = reinterpret_cast<double*>(body + L.iw64);
+  P.stamp = reinterpret_cast<int32_t*>(body + L.stamp);
+  P.list0 = reinterpret_cast<int32_t*>(body + L.list0);
+  P.list1 = reinterpret_cast<int32_t*>(body + L.list1);
+  Counters* c = reinterpret_cast<Counters*>(body + L.ctr);
   P.nlist = c->nlist;
   P.remaining = &c->remaining;
+  P.bar = &c->bar;
   P.status = status;
+  P.gate = gate;
   return P;
+}
+
+// The peeling engine behind a gate: its kernels run only when *gate != 0.
+int enqueue_engine(const EngineConfig& cfg, const EngineParams& P, hipStream_t s) {
+  const int ph = phase_begin("engine", s);
+  if (launch_engine_init(cfg, P, s) != hipSuccess || launch_engine_run(cfg, P, s) != hipSuccess) return FR_ERR_HIP;
+  phase_end(ph, s);
+  return FR_OK;
+}
+
+D8Params d8_params(const uint8_t* code, int64_t nrows, int64_t ncols, int th, const void* rain, int rain_dtype,
+                   ValKind vk, bool counts, char* body, CallCtl* C, int32_t* status, D8Layout* Lout) {
+  const D8Layout L = d8_layout(nrows, ncols, th, vk == VK_FF ? FR_F32 : (vk == VK_F64 ? FR_F64 : FR_NONE), counts);
+  D8Params P{};
+  P.nrows = nrows;
+  P.ncols = ncols;
+  P.th = th;
+  P.ntr = (int32_t)((nrows + P.th - 1) / P.th);
+  P.ntc = (int32_t)((ncols + D8_TW - 1) / D8_TW);
+  P.code = code;
+  P.rain32 = (rain && rain_dtype == FR_F32) ? static_cast<const float*>(rain) : nullptr;
+  P.rain64 = (rain && rain_dtype == FR_F64) ? static_cast<const double*>(rain) : nullptr;
+  P.root_of = reinterpret_cast<uint32_t*>(body + L.root_of);
+  P.node_of = reinterpret_cast<uint32_t*>(body + L.node_of);
+  P.ex_cell = reinterpret_cast<uint32_t*>(body + L.ex_cell);
+  P.ex_cnt[0] = reinterpret_cast<uint64_t*>(body + L.cnt0);
+  P.ex_cnt[1] = reinterpret_cast<uint64_t*>(body + L.cnt1);
+  P.ex_fx[0] = reinterpret_cast<unsigned __int128*>(body + L.fx0);
+  P.ex_fx[1] = reinterpret_cast<unsigned __int128*>(body + L.fx1);
+  P.ex_hi = reinterpret_cast<float*>(body + L.fx1);
+  P.ex_lo = P.ex_hi + L.cap;
+  P.ex_d = reinterpret_cast<double*>(body + L.fx1);
+  P.anc[0] = reinterpret_cast<uint32_t*>(body + L.anc0);
+  P.anc[1] = reinterpret_cast<uint32_t*>(body + L.anc1);
+  uint32_t* ctr = reinterpret_cast<uint32_t*>(body + L.ctr);
+  P.n_exits = ctr;
+  P.flags = reinterpret_cast<int32_t*>(ctr + 4);
+  P.cap = L.cap;
+  P.ctl = C;
+  P.status = status;
+  if (Lout) *Lout = L;
+  return P;
+}
+
+// Row-sweep path for single-receiver codes, forward solve: phases A, B, C
+// and the mass reduction, every one of them ordered on the stream.  An exit
+// list overflow opens C->fallback, which the enqueued engine then serves.
+int enqueue_d8(const uint8_t* code, int64_t nrows, int64_t ncols, const void* rain, int rain_dtype, ValKind vk,
+               float* q32, double* q64, uint64_t* cnt, double* mass_out, int32_t* status, char* body, CallCtl* C,
+               hipStream_t s) {
+  const bool counts = cnt != nullptr;
+  D8Layout L{};
+  D8Params P = d8_params(code, nrows, ncols, d8_tile_height(nrows, ncols), rain, rain_dtype, vk, counts, body, C,
+                         status, &L);
+  P.q32 = q32;
+  P.q64 = q64;
+  P.cnt = cnt;
+  P.mass_part = mass_out ? reinterpret_cast<double*>(body + L.mass) : nullptr;
+  if (launch_zero_u32(P.n_exits, 16, s) != hipSuccess) return FR_ERR_HIP;
+  int ph = phase_begin("d8_up", s);
+  if (launch_d8_up(vk, counts, false, P, s) != hipSuccess) return FR_ERR_HIP;
+  phase_end(ph, s);
+  ph = phase_begin("d8_forest", s);
+  if (launch_d8_forest(vk, counts, false, P, s) != hipSuccess) return FR_ERR_HIP;
+  phase_end(ph, s);
+  ph = phase_begin("d8_down", s);
+  if (launch_d8_down(vk, counts, false, P, s) != hipSuccess) return FR_ERR_HIP;
+  phase_end(ph, s);
+  if (mass_out) {
+    ph = phase_begin("mass", s);
+    if (launch_mass_final(P.mass_part, P.ntr * P.ntc, mass_out, &C->fallback, s) != hipSuccess) return FR_ERR_HIP;
+    phase_end(ph, s);
+  }
+  return FR_OK;
+}
+
+WsParams ws_params(int64_t nrows, int64_t ncols, const uint8_t* code, const float* z, double p, char* body,
+                   const WsLayout& L, ValKind vk, int32_t* status) {
+  WsParams P{};
+  P.nrows = nrows;
+  P.ncols = ncols;
+  P.code = code;
+  P.z = z;
+  P.p = p;
+  P.vlo = vk == VK_FF ? reinterpret_cast<float*>(body + L.vlo) : nullptr;
+  P.edge = reinterpret_cast<uint64_t*>(body + L.edge);
+  P.progress = reinterpret_cast<int32_t*>(body + L.progress);
+  P.ctr = reinterpret_cast<uint32_t*>(body + L.ctr);
+  P.status = status;
+  P.debug = 0;
+  return P;
+}
+
+// Wavefront-sweep passes, each followed by its control step: after the last
+// pass of the budget, cells still unfinished open C->fallback.
+int enqueue_ws(const EngineConfig& cfg, const WsParams& P, CallCtl* C, hipStream_t s) {
+  const int ph = phase_begin("sweep", s);
+  if (launch_ws_setup(cfg, P, C, s) != hipSuccess) return FR_ERR_HIP;
+  for (int pass = 0; pass < kMaxSweepPasses; ++pass) {
+    if (launch_ws_pass(cfg, P, C, pass == 0 ? 1 : 0, s) != hipSuccess ||
+        launch_ws_ctl(P, C, pass, pass == kMaxSweepPasses - 1, s) != hipSuccess)
+      return FR_ERR_HIP;
+  }
+  phase_end(ph, s);
+  return FR_OK;
+}
+
+// Sets the control block's fallback word from the host's path choice
+// (FR_PATH_ENGINE): the engine then serves the call on its own.
+__global__ void k_open_gate(CallCtl* C) {
+  if (threadIdx.x == 0) C->fallback = 1;
 }
 
 }  // namespace
@@ -477,6 +369,8 @@ const char* fr_status_string(int code) {
     case FR_ERR_NOTDAG: return "routing graph has a cycle";
     case FR_ERR_BADCODE: return "malformed routing code";
     case FR_ERR_TOOLARGE: return "grid too large";
+    case FR_ERR_STALL: return "a persistent launch could not run all its workgroups at once";
+    case FR_ERR_CAPACITY: return "more exits than the block iterations' workspace holds";
     default: return "unknown status";
   }
 }
@@ -489,12 +383,14 @@ size_t fill_bytes(int64_t nrows, int64_t ncols) {
   return up((4 * ntiles + 4) * sizeof(int32_t)) + kAlign;
 }
 
-// Block iterations: `vectors` float64 values and counts per cell (I+X: the
-// other iterate; (I-X)(I+X): also D^-1 r and a temporary) and the change
-// flag.
-size_t block_iter_bytes(int64_t nrows, int64_t ncols, int vectors) {
+// Block iterations: the control block, the row-sweep layout (tiles as
+// short as 16 rows bound its per-tile words), then `vectors` float64 values
+// and counts per cell (I+X: the other iterate; (I-X)(I+X): also D^-1 r and a
+// temporary) and the change flag.
+size_t block_iter_bytes(int64_t nrows, int64_t ncols, int vectors, int dtype) {
   const size_t n = (size_t)(nrows * ncols);
-  return (size_t)vectors * (up(n * sizeof(double)) + up(n * sizeof(uint64_t))) + 2 * kAlign;
+  const size_t d8 = d8_layout(nrows, ncols, 16, dtype, true).total;
+  return kCtlBytes + d8 + (size_t)vectors * (up(n * sizeof(double)) + up(n * sizeof(uint64_t))) + 2 * kAlign;
 }
 
 size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dtype) {
@@ -507,7 +403,7 @@ size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dt
     if (dtype != FR_F32 && dtype != FR_F64) return 0;
   } else if (fn == FR_FN_BLOCK_ITER || fn == FR_FN_BLOCK_ITER_PRE) {
     if (rule == FR_MFD || (dtype != FR_NONE && dtype != FR_F64)) return 0;
-    return block_iter_bytes(nrows, ncols, fn == FR_FN_BLOCK_ITER_PRE ? 3 : 1);
+    return block_iter_bytes(nrows, ncols, fn == FR_FN_BLOCK_ITER_PRE ? 3 : 1, dtype);
   } else if (fn == FR_FN_FILL) {
     if (dtype != FR_F32) return 0;
     return fill_bytes(nrows, ncols);
@@ -519,10 +415,16 @@ size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dt
   if (tw > t) t = tw;
   if (fn == FR_FN_ACCUMULATE && rule != FR_MFD) {
     // The counts buffers are sized in, whether or not counts are requested.
-    const size_t t8 = d8_layout(nrows, ncols, dtype, true).total;
+    const size_t t8 = d8_layout(nrows, ncols, d8_tile_height(nrows, ncols), dtype, true).total;
     if (t8 > t) t = t8;
   }
-  return t;
+  return kCtlBytes + t + kAlign;
+}
+
+int fr_set_accumulate_path(int path) {
+  if (path != FR_PATH_AUTO && path != FR_PATH_SWEEP && path != FR_PATH_ENGINE) return FR_ERR_ARG;
+  g_path = path;
+  return FR_OK;
 }
 
 int fr_receivers(const float* z, int64_t nrows, int64_t ncols, int rule, uint8_t* code_out,
@@ -613,10 +515,10 @@ int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t nc
   if (q_dtype == FR_NONE && !counts_out) return FR_ERR_ARG;
   if (ncols > kMaxCells / nrows) return FR_ERR_TOOLARGE;
   if (!code || (rule == FR_MFD && !z)) return FR_ERR_ARG;
-  const Layout L = layout(nrows, ncols, rule, q_dtype);
-  if (!ws || ws_bytes < fr_workspace_bytes(FR_FN_ACCUMULATE, nrows, ncols, rule, q_dtype))
-    return FR_ERR_WORKSPACE;
+  if (!ws || ws_bytes < fr_workspace_bytes(FR_FN_ACCUMULATE, nrows, ncols, rule, q_dtype)) return FR_ERR_WORKSPACE;
   char* base = aligned_base(ws);
+  CallCtl* C = reinterpret_cast<CallCtl*>(base);
+  char* body = base + kCtlBytes;
   timing_reset();
 
   EngineConfig cfg;
@@ -628,49 +530,65 @@ int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t nc
   const double* r64 = (rain && rain_dtype == FR_F64) ? static_cast<const double*>(rain) : nullptr;
   float* q32 = q_dtype == FR_F32 ? static_cast<float*>(q_out) : nullptr;
   double* q64 = q_dtype == FR_F64 ? static_cast<double*>(q_out) : nullptr;
-  const AccPath path = acc_path();
-  if (cfg.rk == RK_SINGLE && path == ACC_AUTO) {
-    const int rc = run_d8(code, nrows, ncols, r32, r64, cfg.vk, q32, q64, counts_out, mass_out, dev_status,
-                          base, stream);
-    if (rc != 1) return rc;  // 1: exit list overflow, fall back to the wavefront sweep
-  }
-  EngineParams P = common_params(nrows, ncols, code, z, mfd_p, base, L, dev_status);
+  const Layout L = layout(nrows, ncols, rule, q_dtype);
+  EngineParams P = engine_params(nrows, ncols, code, z, mfd_p, body, L, dev_status, &C->fallback);
   P.src32 = r32;
   P.src64 = r64;
   P.vhi = q32;
   P.v64 = q64;
   P.cnt = counts_out;
-  int rc = 1;
-  if (path != ACC_ENGINE) {
+  double* partial = reinterpret_cast<double*>(body + L.partial);
+
+  // Every kernel below is ordered on the stream; decisions between them
+  // (exit overflow, sweep passes, the engine's gate) are taken on the
+  // device through the control block, which starts zeroed.
+  if (launch_zero_u32(reinterpret_cast<uint32_t*>(C), CTL_WORDS, stream) != hipSuccess) return FR_ERR_HIP;
+  int rc = FR_OK;
+  const int64_t n = nrows * ncols;
+  if (g_path == FR_PATH_ENGINE) {
+    hipLaunchKernelGGL(k_open_gate, dim3(1), dim3(64), 0, stream, C);
+    if (hipGetLastError() != hipSuccess) return FR_ERR_HIP;
+  } else if (cfg.rk == RK_SINGLE && g_path == FR_PATH_AUTO) {
+    rc = enqueue_d8(code, nrows, ncols, rain, rain_dtype, cfg.vk, q32, q64, counts_out, mass_out, dev_status, body,
+                    C, stream);
+    if (rc != FR_OK) return rc;
+    if (n <= kFullCapacityCells) return FR_OK;  // the exit list cannot overflow: no engine needed
+    // Overflow fallback: the engine and its mass reduction, behind the gate.
+    if ((rc = enqueue_engine(cfg, P, stream)) != FR_OK) return rc;
+    if (mass_out && launch_mass(cfg.rk, cfg.vk, P, partial, kMassBlocks, mass_out, stream) != hipSuccess)
+      return FR_ERR_HIP;
+    return FR_OK;
+  } else {
     const WsLayout WL = ws_layout(nrows, ncols, q_dtype);
-    WsParams W = ws_params(cfg, nrows, ncols, code, z, mfd_p, base, WL, dev_status);
+    WsParams W = ws_params(nrows, ncols, code, z, mfd_p, body, WL, cfg.vk, dev_status);
     W.src32 = r32;
     W.src64 = r64;
     W.vhi = q32;
     W.v64 = q64;
     W.cnt = counts_out;
-    const int ph = phase_begin("sweep", stream);
-    rc = run_ws(cfg, W, dev_status, stream);
-    phase_end(ph, stream);
-    if (rc != FR_OK && rc != 1) return rc;
-    if (rc == FR_OK) P.vlo = W.vlo;  // the float-float low parts the mass sum reads
+    if ((rc = enqueue_ws(cfg, W, C, stream)) != FR_OK) return rc;
   }
-  if (rc == 1) rc = run_engine(cfg, P, base, L, dev_status, stream);
-  if (rc != FR_OK) return rc;
+  if ((rc = enqueue_engine(cfg, P, stream)) != FR_OK) return rc;
   if (mass_out) {
-    double* partial = reinterpret_cast<double*>(base + L.partial);
+    // After the sweep or the engine, whichever finished the solve: both keep
+    // the float-float low part at the same place.
+    EngineParams M = P;
+    M.gate = nullptr;
     const int ph = phase_begin("mass", stream);
-    if (launch_mass(cfg.rk, cfg.vk, P, partial, kMassBlocks, mass_out, stream) != hipSuccess) return FR_ERR_HIP;
+    if (launch_mass(cfg.rk, cfg.vk, M, partial, kMassBlocks, mass_out, stream) != hipSuccess) return FR_ERR_HIP;
     phase_end(ph, stream);
   }
   return FR_OK;
 }
 
-int fr_accumulate_block_iterations(const uint8_t* code, int64_t nrows, int64_t ncols, int rule, int scheme,
+int fr_accumulate_block_iterations(const float* z, const uint8_t* code, int64_t nrows, int64_t ncols, int rule,
+                                   double mfd_p, int64_t block_rows, int64_t block_cols, int scheme,
                                    const void* rain, int rain_dtype, int q_dtype, void* q_out,
                                    uint64_t* counts_out, int32_t max_iter, int32_t* iters_out,
                                    int32_t* dev_status, void* ws, size_t ws_bytes, hipStream_t stream) {
-  if (nrows < 0 || ncols < 0 || !iters_out || max_iter < 1) return FR_ERR_ARG;
+  (void)z;
+  (void)mfd_p;
+  if (nrows < 0 || ncols < 0 || !iters_out || max_iter < 1 || block_rows < 1 || block_cols < 1) return FR_ERR_ARG;
   if (rule != FR_D8 && rule != FR_D4) return FR_ERR_RULE;
   if (scheme != FR_SCHEME_IX && scheme != FR_SCHEME_IMX_IX) return FR_ERR_ARG;
   if (rain && rain_dtype != FR_F32 && rain_dtype != FR_F64) return FR_ERR_ARG;
@@ -683,37 +601,54 @@ int fr_accumulate_block_iterations(const uint8_t* code, int64_t nrows, int64_t n
   if (!counts_out && (q_dtype == FR_NONE || scheme == FR_SCHEME_IMX_IX)) return FR_ERR_ARG;
   if (ncols > kMaxCells / nrows) return FR_ERR_TOOLARGE;
   if (!code) return FR_ERR_ARG;
+  // Blocks are unions of row-sweep tiles: block_cols a multiple of 256 (or
+  // the whole width), block_rows a multiple of 16 (or the whole height); the
+  // tile height is the largest power of two up to 512 dividing block_rows.
+  int th = 512;
+  int64_t bt_r = 0, bt_c = 0;
+  if (block_rows >= nrows) {
+    th = d8_tile_height(nrows, ncols);
+    bt_r = (nrows + th - 1) / th;
+  } else {
+    if (block_rows % 16 != 0) return FR_ERR_ARG;
+    while (block_rows % th != 0) th /= 2;
+    bt_r = block_rows / th;
+  }
+  if (block_cols >= ncols) {
+    bt_c = (ncols + D8_TW - 1) / D8_TW;
+  } else {
+    if (block_cols % D8_TW != 0) return FR_ERR_ARG;
+    bt_c = block_cols / D8_TW;
+  }
   const int fn = scheme == FR_SCHEME_IX ? FR_FN_BLOCK_ITER : FR_FN_BLOCK_ITER_PRE;
   if (!ws || ws_bytes < fr_workspace_bytes(fn, nrows, ncols, rule, q_dtype)) return FR_ERR_WORKSPACE;
   timing_reset();
   char* base = aligned_base(ws);
+  CallCtl* C = reinterpret_cast<CallCtl*>(base);
+  char* body = base + kCtlBytes;
+  const ValKind vk = q_dtype == FR_F64 ? VK_F64 : VK_NONE;
+  const bool counts = counts_out != nullptr;
+  D8Layout DL{};
+  D8Params P = d8_params(code, nrows, ncols, th, rain, rain_dtype, vk, counts, body, C, dev_status, &DL);
+  P.bt_r = (int32_t)bt_r;
+  P.bt_c = (int32_t)bt_c;
+  char* vecs = body + d8_layout(nrows, ncols, 16, q_dtype, true).total;
   const size_t n = (size_t)(nrows * ncols);
   const size_t vb = up(n * sizeof(double)) + up(n * sizeof(uint64_t));
   const int nvec = scheme == FR_SCHEME_IX ? 1 : 3;
-  const ValKind vk = q_dtype == FR_F64 ? VK_F64 : VK_NONE;
-  const bool counts = counts_out != nullptr;
-  auto vq = [&](int v) { return vk == VK_F64 ? reinterpret_cast<double*>(base + v * vb) : nullptr; };
+  auto vq = [&](int v) { return vk == VK_F64 ? reinterpret_cast<double*>(vecs + v * vb) : nullptr; };
   auto vc = [&](int v) {
-    return counts ? reinterpret_cast<uint64_t*>(base + v * vb + up(n * sizeof(double))) : nullptr;
+    return counts ? reinterpret_cast<uint64_t*>(vecs + v * vb + up(n * sizeof(double))) : nullptr;
   };
-  int32_t* flag = reinterpret_cast<int32_t*>(base + nvec * vb);
-  D8Params P{};
-  P.nrows = nrows;
-  P.ncols = ncols;
-  P.th = block_iter_height(nrows, ncols);
-  P.ntr = (int32_t)((nrows + P.th - 1) / P.th);
-  P.ntc = (int32_t)((ncols + D8_TW - 1) / D8_TW);
-  P.code = code;
-  P.rain32 = (rain && rain_dtype == FR_F32) ? static_cast<const float*>(rain) : nullptr;
-  P.rain64 = (rain && rain_dtype == FR_F64) ? static_cast<const double*>(rain) : nullptr;
-  P.status = dev_status;
+  int32_t* flag = reinterpret_cast<int32_t*>(vecs + nvec * vb);
   // The two iterates alternate between the caller's outputs (even
   // iterations) and workspace vector 0 (odd ones); once an iterate equals
   // the previous one both hold the solution.
   double* qbuf[2] = {static_cast<double*>(q_out), vq(0)};
   uint64_t* cbuf[2] = {counts_out, vc(0)};
   // One block solve into (oq, oc): D^-1 (src + R prev) -- src is the rain
-  // (unit counts) unless nosrc; prev NULL means no water across cut pairs.
+  // (unit counts) unless nosrc; prev NULL means no water across block
+  // boundaries.  Phases A, B and C with the forest cut at block boundaries.
   auto solve = [&](const double* pq, const uint64_t* pc, bool nosrc, bool detect, double* oq,
                    uint64_t* oc) -> bool {
     P.q64 = oq;
@@ -724,7 +659,11 @@ int fr_accumulate_block_iterations(const uint8_t* code, int64_t nrows, int64_t n
     P.it_nosrc = nosrc ? 1 : 0;
     P.it_detect = detect ? 1 : 0;
     P.it_changed = flag;
-    return launch_d8_iter(vk, counts, P, stream) == hipSuccess;
+    return launch_zero_u32(reinterpret_cast<uint32_t*>(C), CTL_WORDS, stream) == hipSuccess &&
+           launch_zero_u32(P.n_exits, 16, stream) == hipSuccess &&
+           launch_d8_up(vk, counts, true, P, stream) == hipSuccess &&
+           launch_d8_forest(vk, counts, true, P, stream) == hipSuccess &&
+           launch_d8_down(vk, counts, true, P, stream) == hipSuccess;
   };
   const int ph = phase_begin("block_iterations", stream);
   int rc = FR_OK;
@@ -765,6 +704,9 @@ int fr_accumulate_block_iterations(const uint8_t* code, int64_t nrows, int64_t n
       rc = FR_ERR_HIP;
       break;
     }
+    // The convergence test needs the flag on the host: one read-back per
+    // iteration (this entry point measures the paper's scheme; the
+    // production solve is fr_accumulate).
     int32_t changed = 0, st = 0;
     if (hipMemcpyAsync(&changed, flag, sizeof changed, hipMemcpyDeviceToHost, stream) != hipSuccess ||
         (dev_status && hipMemcpyAsync(&st, dev_status, sizeof st, hipMemcpyDeviceToHost, stream) != hipSuccess) ||
@@ -792,9 +734,10 @@ int fr_accumulate_adjoint(const float* z, const uint8_t* code, int64_t nrows, in
   if (nrows == 0 || ncols == 0) return FR_OK;
   if (ncols > kMaxCells / nrows) return FR_ERR_TOOLARGE;
   if (!code || !qbar || !rbar_out || (rule == FR_MFD && !z)) return FR_ERR_ARG;
-  const Layout L = layout(nrows, ncols, rule, dtype);
   if (!ws || ws_bytes < fr_workspace_bytes(FR_FN_ADJOINT, nrows, ncols, rule, dtype)) return FR_ERR_WORKSPACE;
   char* base = aligned_base(ws);
+  CallCtl* C = reinterpret_cast<CallCtl*>(base);
+  char* body = base + kCtlBytes;
   timing_reset();
 
   EngineConfig cfg;
@@ -806,26 +749,28 @@ int fr_accumulate_adjoint(const float* z, const uint8_t* code, int64_t nrows, in
   const double* s64 = dtype == FR_F64 ? static_cast<const double*>(qbar) : nullptr;
   float* o32 = dtype == FR_F32 ? static_cast<float*>(rbar_out) : nullptr;
   double* o64 = dtype == FR_F64 ? static_cast<double*>(rbar_out) : nullptr;
-  int rc = 1;
-  if (acc_path() != ACC_ENGINE) {
+  if (launch_zero_u32(reinterpret_cast<uint32_t*>(C), CTL_WORDS, stream) != hipSuccess) return FR_ERR_HIP;
+  int rc = FR_OK;
+  if (g_path == FR_PATH_ENGINE) {
+    hipLaunchKernelGGL(k_open_gate, dim3(1), dim3(64), 0, stream, C);
+    if (hipGetLastError() != hipSuccess) return FR_ERR_HIP;
+  } else {
     const WsLayout WL = ws_layout(nrows, ncols, dtype);
-    WsParams W = ws_params(cfg, nrows, ncols, code, z, mfd_p, base, WL, dev_status);
+    WsParams W = ws_params(nrows, ncols, code, z, mfd_p, body, WL, cfg.vk, dev_status);
     W.src32 = s32;
     W.src64 = s64;
     W.vhi = o32;
     W.v64 = o64;
-    const int ph = phase_begin("sweep", stream);
-    rc = run_ws(cfg, W, dev_status, stream);
-    phase_end(ph, stream);
-    if (rc != 1) return rc;
+    if ((rc = enqueue_ws(cfg, W, C, stream)) != FR_OK) return rc;
   }
-  EngineParams P = common_params(nrows, ncols, code, z, mfd_p, base, L, dev_status);
+  const Layout L = layout(nrows, ncols, rule, dtype);
+  EngineParams P = engine_params(nrows, ncols, code, z, mfd_p, body, L, dev_status, &C->fallback);
   P.src32 = s32;
   P.src64 = s64;
   P.vhi = o32;
   P.v64 = o64;
   P.cnt = nullptr;
-  return run_engine(cfg, P, base, L, dev_status, stream);
+  return enqueue_engine(cfg, P, stream);
 }
 
 size_t fr_batched_workspace_bytes(const fr_tile* tiles_host, int32_t ntiles) {
@@ -887,7 +832,6 @@ int fr_batch_autotune(const fr_tile* tiles_dev, int32_t ntiles, int32_t* dev_sta
     }
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = FR_ERR_HIP; break; }
-    if (verbose()) fprintf(stderr, "flowroute: batch plan workers %d order %d: %.3f ms\n", p.workers, p.order, ms / reps);
     if (best < 0.0f || ms < best) {
       best = ms;
       *plan_out = p;

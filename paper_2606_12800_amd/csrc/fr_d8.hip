@@ -14,9 +14,9 @@
 //      followed in registers (cross-lane shifts); every other edge --
 //      leaving the tile, within a row, or toward a higher row index -- is
 //      "cut".  A top-down sweep yields each cut cell's (exit's) local
-//      upstream sum; a bottom-up sweep (its own kernel) yields, for every
-//      cell that receives over a cut edge (inlet), the exit or sink where its
-//      in-tile path ends (its root).
+//      upstream sum; a bottom-up sweep by a second wavefront of the same
+//      workgroup yields, for every cell that receives over a cut edge
+//      (inlet), the exit or sink where its in-tile path ends (its root).
 //   B. The exits form a forest: exit e drains into exit root(receiver(e)),
 //      or nowhere when that root is a sink.  Subtree sums over this forest are
 //      computed by pointer doubling in ceil(log2(depth)) rounds.  These stand
@@ -25,12 +25,23 @@
 //   C. Each tile is swept again with the totals of its cut donors added: the
 //      result is final.  The float64 mass balance is reduced in the same pass.
 //
-// The same top-down sweep, fed the previous iterate's water across cut edges
-// instead of forest totals, is one of the paper's block iterations (k_d8_iter).
+// Every kernel reads the exit count from device memory, and the pointer-
+// doubling rounds are a fixed sequence of launches that return at once when
+// there is nothing left to do, so a solve never waits for the host.  An exit
+// list that overflows its capacity opens the peeling engine's gate instead.
 //
-// Numerics: float32 water uses float-float (hi, lo) sums throughout; the
-// exit forest adds hi with float atomics and folds each addition's exact
-// rounding error into lo.  Counts are exact uint64.
+// Block iterations (the paper's I+X scheme, Section 3.3, Appendix B): with
+// blocks made of bt_r x bt_c tiles, the same three phases are the exact
+// block solve D^-1 -- the forest keeps only links inside a block, and water
+// from donors in other blocks enters as the previous iterate (R w).
+//
+// Numerics.  Float32 water uses float-float (hi, lo) sums in the sweeps.  The
+// forest adds exit sums as 128-bit integers in units of 2^E (E fixed per
+// call from the largest exit sum and the exit count, so no sum can
+// overflow); integer addition is exact and commutative, so the result does
+// not depend on the order in which the atomics land, and the totals go back
+// to float-float / float64 once, after the last round: every output is the
+// same, bit for bit, from run to run.  Counts are exact uint64.
 #include <math.h>
 
 #include <type_traits>
@@ -295,13 +306,135 @@ __device__ __forceinline__ bool rare_donors(const Row& here, const Row& below) {
   return __ballot(any) != 0;
 }
 
-// Exit-list slots reserved per atomic in phase A; unused slots of a chunk
-// are holes (ex_cell = NONE) that the forest skips.
-constexpr uint32_t EXIT_CHUNK = 32;
+// Unused slots at the end of a wavefront's last exit chunk are holes
+// (ex_cell = NONE) that the forest skips.
 
 __device__ __forceinline__ void exit_holes(const D8Params& P, uint32_t from, uint32_t to, int lane) {
   for (uint32_t h = from + (uint32_t)lane; h < to; h += 64)
     if (h < P.cap) P.ex_cell[h] = NONE;
+}
+
+
+// ---------------------------------------------------------------------------
+// 128-bit fixed point for the exit forest.  A value x is held as the integer
+// floor(x / 2^E) (two's complement), E = e_max + ceil(log2(n + 1)) + 2 - 126
+// with every exit's local sum below 2^e_max in magnitude, so no sum of the n
+// exits' values reaches 2^124 units.  Bits below one unit (2^E, at most
+// 2^-124 of the largest possible total) are dropped from each term, the
+// same way in every run.
+using u128 = unsigned __int128;
+using i128 = __int128;
+
+__device__ __forceinline__ int ceil_log2_p1(uint32_t n) { return n == 0 ? 0 : 32 - __clz((int)n); }
+
+template <int VK>
+__device__ __forceinline__ int fx_exponent(const D8Params& P, uint32_t n) {
+  int e = 0;
+  if (VK == VK_FF) {
+    const float m = __uint_as_float(P.ctl->loc_max_f);
+    if (m > 0.0f && isfinite(m)) (void)frexpf(m, &e);  // m < 2^e
+  } else {
+    const double m = __longlong_as_double((long long)P.ctl->loc_max_d);
+    if (m > 0.0 && isfinite(m)) (void)frexp(m, &e);
+  }
+  return e + ceil_log2_p1(n) + 2 - 126;
+}
+
+// m * 2^sh units, floored.  By the choice of E, sh <= 100 for a float32
+// term (|m| < 2^24) and sh <= 71 for a float64 term (|m| < 2^53).
+__device__ __forceinline__ i128 fx_scale(int64_t m, int sh) {
+  if (sh >= 0) return sh <= 100 ? (i128)((u128)(i128)m << sh) : (i128)0;
+  return sh > -64 ? (i128)(m >> (-sh)) : (i128)(m < 0 ? -1 : 0);
+}
+
+__device__ __forceinline__ i128 fx_from(float x, int E) {
+  if (!(x != 0.0f) || !isfinite(x)) return 0;  // non-finite input is reported elsewhere
+  int e = 0;
+  const float f = frexpf(x, &e);                 // x = f 2^e, 1/2 <= |f| < 1
+  return fx_scale((int64_t)(f * 16777216.0f), e - 24 - E);
+}
+
+__device__ __forceinline__ i128 fx_from(double x, int E) {
+  if (!(x != 0.0) || !isfinite(x)) return 0;
+  int e = 0;
+  const double f = frexp(x, &e);
+  return fx_scale((int64_t)(f * 9007199254740992.0), e - 53 - E);
+}
+
+__device__ __forceinline__ int top_bit(u128 u) {
+  const uint64_t h = (uint64_t)(u >> 64), l = (uint64_t)u;
+  return h ? 127 - __clzll((long long)h) : 63 - __clzll((long long)l);
+}
+
+// The leading `bits` bits of u (u != 0) as an integer m and its exponent s:
+// u = m 2^s + rest, 0 <= rest < 2^s.
+__device__ __forceinline__ uint64_t fx_lead(u128 u, int bits, int* s, u128* rest) {
+  const int sh = top_bit(u) - (bits - 1);
+  *s = sh;
+  if (sh <= 0) {
+    *rest = 0;
+    return (uint64_t)(u << (-sh));
+  }
+  const uint64_t m = (uint64_t)(u >> sh);
+  *rest = u - ((u128)m << sh);
+  return m;
+}
+
+// Back to float-float: the leading 24 bits, then the next 24 (truncated:
+// relative error below 2^-47).
+__device__ __forceinline__ ff fx_to_ff(i128 v, int E) {
+  if (v == 0) return {0.0f, 0.0f};
+  const bool neg = v < 0;
+  const u128 u = neg ? (u128)0 - (u128)v : (u128)v;
+  int s1 = 0, s2 = 0;
+  u128 r1 = 0, r2 = 0;
+  const uint64_t m1 = fx_lead(u, 24, &s1, &r1);
+  float hi = ldexpf((float)m1, s1 + E), lo = 0.0f;
+  if (r1 != 0) lo = ldexpf((float)fx_lead(r1, 24, &s2, &r2), s2 + E);
+  if (neg) {
+    hi = -hi;
+    lo = -lo;
+  }
+  return ff_fast(hi, lo);
+}
+
+__device__ __forceinline__ double fx_to_double(i128 v, int E) {
+  if (v == 0) return 0.0;
+  const bool neg = v < 0;
+  const u128 u = neg ? (u128)0 - (u128)v : (u128)v;
+  int s1 = 0, s2 = 0;
+  u128 r1 = 0, r2 = 0;
+  const uint64_t m1 = fx_lead(u, 53, &s1, &r1);
+  double d = ldexp((double)m1, s1 + E);
+  if (r1 != 0) d += ldexp((double)fx_lead(r1, 53, &s2, &r2), s2 + E);
+  return neg ? -d : d;
+}
+
+// Exact 128-bit atomic addition from two 64-bit ones: the low word's
+// carries reach the high word once each, whatever the interleaving.
+__device__ __forceinline__ void atomic_add_fx(u128* p, u128 x) {
+  unsigned long long* w = reinterpret_cast<unsigned long long*>(p);
+  const unsigned long long xl = (unsigned long long)x, xh = (unsigned long long)(x >> 64);
+  const unsigned long long old = atomicAdd(w, xl);
+  const unsigned long long h = xh + ((old + xl < old) ? 1ull : 0ull);
+  if (h) atomicAdd(w + 1, h);
+}
+
+// Rows and columns of the block of tiles holding tile T (block iterations).
+struct Block {
+  int64_t r0, r1, c0, c1;
+};
+__device__ __forceinline__ Block block_of(const D8Params& P, const Tile& T) {
+  const int64_t bh = (int64_t)P.th * P.bt_r, bw = (int64_t)TW * P.bt_c;
+  Block B;
+  B.r0 = (T.r0 / bh) * bh;
+  B.r1 = B.r0 + bh;
+  B.c0 = (T.c0 / bw) * bw;
+  B.c1 = B.c0 + bw;
+  return B;
+}
+__device__ __forceinline__ bool in_block(const Block& B, int64_t r, int64_t c) {
+  return r >= B.r0 && r < B.r1 && c >= B.c0 && c < B.c1;
 }
 
 // Value carried down a sweep: float-float water, float64 water, count.
@@ -321,6 +454,14 @@ __device__ __forceinline__ void acc_ff(float& s, float& e, bool cond, float xh, 
   e += t.lo + xl;
 }
 
+// What a sweep hands back besides its stores.
+struct SweepOut {
+  double mass[2] = {0.0, 0.0};  // phase C: {sum over sinks, sum of rain} of the lane's cells
+  float lmax_f = 0.0f;          // phase A: largest |local sum| of the lane's exits
+  double lmax_d = 0.0;
+  bool nonfinite = false, badcode = false, changed = false;
+};
+
 // Top-down sweep over the tile (rows r0+th-1 .. r0), one wavefront, W
 // columns per lane.  A cell's value is its rain, plus (phase C) the totals of
 // its cut donors, plus the values of its donors in the row above inside the
@@ -329,26 +470,35 @@ __device__ __forceinline__ void acc_ff(float& s, float& e, bool cond, float xh, 
 //   UP   (phase A): record every exit with its local value (local counts of
 //                   one tile fit in 32 bits).
 //   DOWN (phase C): write the final water / counts and the mass balance.
-//   ITER (block iterations, phase C form): cut donors give their water of
-//                   the previous iterate; the tile sweep is the block solve.
-template <bool UP, int VK, bool CNT, int RAIN, bool VEC, bool BORDER, bool ITER = false>
-__device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* mass, bool* nonfinite,
-                                      float* xq32 = nullptr, double* xq64 = nullptr, uint64_t* xcnt = nullptr,
-                                      bool* badcode = nullptr, bool* changed = nullptr) {
+//   ITER (block iterations): donors in other blocks give their water of the
+//                   previous iterate (both phases); the forest covers only
+//                   cut donors inside the block; the new iterate is compared
+//                   with the previous one.
+template <bool UP, int VK, bool CNT, int RAIN, bool VEC, bool BORDER, bool ITER>
+__device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, SweepOut& out, float* xq32 = nullptr,
+                                      double* xq64 = nullptr, uint64_t* xcnt = nullptr) {
   using CT = typename std::conditional<UP, uint32_t, uint64_t>::type;
   using V = Val<CT>;
   // Rows in flight: fewer in phase A, whose kernel must stay within 128
   // VGPRs for four wavefronts per SIMD.
   constexpr int PF = !VEC ? 4 : (UP ? 6 : PF_ROWS);
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const int k0 = W * lane;  // first tile column of this lane
   const int c = T.c0 + k0;
   const int nc = (int)P.ncols;
   const int rtop = T.r0 + T.th - 1;
   const int tw = BORDER ? T.tw : TW;
   const bool lane_in = !BORDER || c < nc;
+  // Phase C reads the forest's totals (of n_ex exits).
+  const uint32_t n_ex = UP ? 0u : min(*P.n_exits, P.cap);
+  Block B{};
+  if (ITER) B = block_of(P, T);
+  const bool nosrc = ITER && P.it_nosrc;
+  const bool prev = ITER && !P.it_first;
   double m_sink = 0.0, m_rain = 0.0;
   bool nf = false, bad = false, chg = false;
+  float lmf = 0.0f;
+  double lmd = 0.0;
   V pv[W];
 #pragma unroll
   for (int j = 0; j < W; ++j) pv[j] = V{};
@@ -374,7 +524,7 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
         const size_t g = (size_t)r * (size_t)nc + (size_t)c;
         const bool top = s == 0;
         const bool bottom = r == T.r0;
-        const bool rare = !UP && rare_donors(here, below);
+        const bool rare = (!UP || ITER) && rare_donors(here, below);
         // Values of the row above at the columns left and right of this lane.
         V lv, rv;
         if (VK == VK_FF) {
@@ -406,7 +556,7 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
           const V& a7 = j == W - 1 ? rv : pv[j == W - 1 ? 0 : j + 1];
           const auto rain = rq[i].v[j];
           if ((UP || ITER) && RAIN != RAIN_UNIT) nf |= !isfinite(rain);
-          if (ITER) bad |= (!BORDER || k < tw) && cd != SINK && x.sink;
+          if (ITER && !UP) bad |= (!BORDER || k < tw) && cd != SINK && x.sink;
           V v;
           if (VK == VK_FF) {
             float sh = (float)rain, se = RAIN == RAIN_F64 ? (float)((double)rain - (double)(float)rain) : 0.0f;
@@ -415,16 +565,17 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
             acc_ff(sh, se, d7, a7.f.hi, a7.f.lo);
             v.f = ff_fast(sh, se);
           }
-          const bool nosrc = ITER && P.it_nosrc;
           if (VK == VK_F64)
             v.d = (nosrc ? 0.0 : (double)rain) + (d5 ? a5.d : 0.0) + (d6 ? pv[j].d : 0.0) + (d7 ? a7.d : 0.0);
           if (CNT)
             v.n = (CT)(nosrc ? 0 : 1) + (d5 ? a5.n : (CT)0) + (d6 ? pv[j].n : (CT)0) + (d7 ? a7.n : (CT)0);
-          cut[j] = UP ? 0u : cut_donors(above, here, below, j, k, top, rare, tw);
+          cut[j] = (UP && !ITER) ? 0u : cut_donors(above, here, below, j, k, top, rare, tw);
           nv[j] = v;
         }
-        if (ITER && !P.it_first && __ballot((cut[0] | cut[1] | cut[2] | cut[3]) != 0u)) {
-          // Water of the previous iterate across cut edges.
+        if ((!UP || ITER) && __ballot((cut[0] | cut[1] | cut[2] | cut[3]) != 0u)) {
+          // Donors across cut edges (sparse: the top row, the outer columns
+          // and rare rows): the forest total of a donor inside the block
+          // (phase C), the previous iterate of a donor in another block.
 #pragma unroll
           for (int j = 0; j < W; ++j) {
             uint32_t m = cut[j];
@@ -432,28 +583,22 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
               const int n = __builtin_ctz(m);
               m &= m - 1;
               const size_t gj = (size_t)((int64_t)(g + j) + (int64_t)nb_dr(n) * nc + nb_dc(n));
-              if (VK == VK_F64) nv[j].d += P.it_q64[gj];
-              if (CNT) nv[j].n += (CT)P.it_cnt[gj];
-            }
-          }
-        }
-        if (!UP && !ITER && __ballot((cut[0] | cut[1] | cut[2] | cut[3]) != 0u)) {
-          // Totals of donors across cut edges (sparse: the top row, the
-          // outer columns and rare rows).
-#pragma unroll
-          for (int j = 0; j < W; ++j) {
-            uint32_t m = cut[j];
-            while (m) {
-              const int n = __builtin_ctz(m);
-              m &= m - 1;
-              const size_t gj = (size_t)((int64_t)(g + j) + (int64_t)nb_dr(n) * nc + nb_dc(n));
+              const bool other = ITER && !in_block(B, r + nb_dr(n), c + j + nb_dc(n));
+              if (other) {
+                if (prev) {
+                  if (VK == VK_F64) nv[j].d += P.it_q64[gj];
+                  if (CNT) nv[j].n += (CT)P.it_cnt[gj];
+                }
+                continue;
+              }
+              if (UP) continue;  // phase A: the forest adds donors inside the block
               const uint32_t nd = P.node_of[gj];
-              if (nd >= P.n_ex) {  // inconsistent bookkeeping: never follow it
+              if (nd >= n_ex) {  // inconsistent bookkeeping: never follow it
                 set_status(P.status, FR_ERR_BADCODE);
                 continue;
               }
-              if (VK == VK_FF) nv[j].f = ff_add(nv[j].f, ff{P.ex_hi[0][nd], P.ex_lo[0][nd]});
-              if (VK == VK_F64) nv[j].d += P.ex_q64[0][nd];
+              if (VK == VK_FF) nv[j].f = ff_add(nv[j].f, ff{P.ex_hi[nd], P.ex_lo[nd]});
+              if (VK == VK_F64) nv[j].d += P.ex_d[nd];
               if (CNT) nv[j].n += (CT)P.ex_cnt[0][nd];
             }
           }
@@ -469,37 +614,47 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
             em[j] = __ballot(exits[j]);
             ne += (uint32_t)__popcll(em[j]);
           }
-          if (ex_used + ne > ex_size) {  // uniform
-            exit_holes(P, ex_base + ex_used, ex_base + ex_size, lane);
-            const uint32_t want = ne > EXIT_CHUNK ? ne : EXIT_CHUNK;
-            uint32_t nb = 0;
+          // The row's exits fill the rest of the current chunk first; the
+          // others go to a new chunk (one atomic, at least D8_EXIT_CHUNK
+          // slots), so only a wavefront's last chunk leaves holes.
+          const uint32_t avail = ex_size - ex_used;  // uniform
+          const uint32_t first = ex_base + ex_used;
+          uint32_t nb = 0, want = 0;
+          if (ne > avail) {
+            want = ne - avail > D8_EXIT_CHUNK ? ne - avail : D8_EXIT_CHUNK;
             if (lane == 0) nb = atomicAdd(P.n_exits, want);
-            ex_base = __shfl(nb, 0, 64);
-            ex_size = want;
-            ex_used = 0;
+            nb = __shfl(nb, 0, 64);
           }
           const uint64_t lower = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-          uint32_t off = ex_base + ex_used;
-          ex_used += ne;
+          uint32_t off = 0;  // exits of this row before column j, over all lanes
 #pragma unroll
           for (int j = 0; j < W; ++j) {
-            const bool ex = exits[j];
-            {
-              if (ex) {
-                const uint32_t idx = off + (uint32_t)__popcll(em[j] & lower);
-                if (idx < P.cap) {
-                  P.node_of[g + j] = idx;
-                  P.ex_cell[idx] = (uint32_t)(g + j);
-                  if (VK == VK_FF) {
-                    P.ex_hi[0][idx] = nv[j].f.hi;
-                    P.ex_lo[0][idx] = nv[j].f.lo;
-                  }
-                  if (VK == VK_F64) P.ex_q64[0][idx] = nv[j].d;
-                  if (CNT) P.ex_cnt[0][idx] = (uint64_t)nv[j].n;
+            if (exits[j]) {
+              const uint32_t t = off + (uint32_t)__popcll(em[j] & lower);
+              const uint32_t idx = t < avail ? first + t : nb + (t - avail);
+              if (idx < P.cap) {
+                P.node_of[g + j] = idx;
+                P.ex_cell[idx] = (uint32_t)(g + j);
+                if (VK == VK_FF) {
+                  P.ex_hi[idx] = nv[j].f.hi;
+                  P.ex_lo[idx] = nv[j].f.lo;
+                  lmf = fmaxf(lmf, fabsf(nv[j].f.hi));
                 }
+                if (VK == VK_F64) {
+                  P.ex_d[idx] = nv[j].d;
+                  lmd = fmax(lmd, fabs(nv[j].d));
+                }
+                if (CNT) P.ex_cnt[0][idx] = (uint64_t)nv[j].n;
               }
             }
             off += (uint32_t)__popcll(em[j]);
+          }
+          if (ne > avail) {
+            ex_base = nb;
+            ex_size = want;
+            ex_used = ne - avail;
+          } else {
+            ex_used += ne;
           }
         }
         if (!UP && lane_in) {
@@ -549,7 +704,7 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
           }
           __syncthreads();
         }
-        if (ITER && !P.it_first && P.it_detect) {
+        if (ITER && !UP && prev && P.it_detect) {
           // Whether this iterate differs from the previous one here.
 #pragma unroll
           for (int j = 0; j < W; ++j) {
@@ -581,20 +736,20 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, double* 
     }
   }
   if (UP) exit_holes(P, ex_base + ex_used, ex_base + ex_size, lane);
-  if (nf) *nonfinite = true;
-  if (ITER && bad) *badcode = true;
-  if (ITER && chg) *changed = true;
-  if (mass) {
-    mass[0] = m_sink;
-    mass[1] = m_rain;
-  }
+  out.nonfinite |= nf;
+  out.badcode |= bad;
+  out.changed |= chg;
+  out.mass[0] = m_sink;
+  out.mass[1] = m_rain;
+  out.lmax_f = lmf;
+  out.lmax_d = lmd;
 }
 
 // Bottom-up sweep (rows r0 .. r0+th-1): the root of every inlet -- the exit
 // or sink where its path through the tile ends.
 template <bool VEC, bool BORDER>
 __device__ __forceinline__ void root_sweep(const D8Params& P, const Tile& T, bool* badcode) {
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const int k0 = W * lane;
   const int nc = (int)P.ncols;
   const int tw = BORDER ? T.tw : TW;
@@ -675,7 +830,7 @@ __device__ __forceinline__ bool rare_donors_bits(const Row& here, const Row& bel
 // columns can be inlets (water across the tile's side edges).
 template <bool VEC>
 __device__ __forceinline__ void root_sweep_interior(const D8Params& P, const Tile& T, bool* badcode) {
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const int k0 = W * lane;
   const int nc = (int)P.ncols;
   Row below = expand_row<false, VEC>(load_codes<VEC>(P, T, T.r0 - 1, lane), P, T, T.r0 - 1, lane);
@@ -737,42 +892,88 @@ __device__ __forceinline__ void root_sweep_interior(const D8Params& P, const Til
   if (bad) *badcode = true;
 }
 
+
 // ---------------------------------------------------------------------------
-// Phase A, as two independent kernels: the root sweep needs few registers
-// and runs at high occupancy; the local sweep carries the values.
+// Phase A: one workgroup of two wavefronts per tile.  Wavefront 0 runs the
+// top-down local sweep (bound by HBM), wavefront 1 the bottom-up root sweep
+// (bound by its instruction count); neither reads what the other writes, so
+// they overlap on the compute unit.  The local sweep also reports the
+// largest |local sum| of its exits, which fixes the forest's fixed-point
+// unit.
+// The root sweep does not depend on the value kind or rain: one copy per
+// row alignment, called (not inlined) from every phase-A kernel.
 template <bool VEC>
-__global__ __launch_bounds__(64) void k_d8_root(D8Params P) {
-  const Tile T = tile_of(P, blockIdx.x);
+__device__ __attribute__((noinline)) void root_wave(const D8Params& P, const Tile& T) {
   bool badcode = false;
   if (T.border) root_sweep<VEC, true>(P, T, &badcode);
   else root_sweep_interior<VEC>(P, T, &badcode);
   if (badcode) set_status(P.status, FR_ERR_BADCODE);
 }
 
-template <int VK, bool CNT, int RAIN, bool VEC>
-__global__ __launch_bounds__(64) void k_d8_up(D8Params P) {
+template <int VK, bool CNT, int RAIN, bool VEC, bool ITER>
+__global__ __launch_bounds__(128) void k_d8_a(D8Params P) {
   const Tile T = tile_of(P, blockIdx.x);
-  bool nonfinite = false;
-  if (T.border) sweep<true, VK, CNT, RAIN, VEC, true>(P, T, nullptr, &nonfinite);
-  else sweep<true, VK, CNT, RAIN, VEC, false>(P, T, nullptr, &nonfinite);
-  if (nonfinite) set_status(P.status, FR_ERR_NONFINITE);
+  if (threadIdx.x >= 64) {
+    root_wave<VEC>(P, T);
+    return;
+  }
+  SweepOut o;
+  if (T.border) sweep<true, VK, CNT, RAIN, VEC, true, ITER>(P, T, o);
+  else sweep<true, VK, CNT, RAIN, VEC, false, ITER>(P, T, o);
+  if (o.nonfinite) set_status(P.status, FR_ERR_NONFINITE);
+  if (VK == VK_FF) {
+    float m = o.lmax_f;
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if (threadIdx.x == 0 && m > 0.0f) atomicMax(&P.ctl->loc_max_f, __float_as_uint(m));
+  }
+  if (VK == VK_F64) {
+    double m = o.lmax_d;
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if (threadIdx.x == 0 && m > 0.0)
+      atomicMax(reinterpret_cast<unsigned long long*>(&P.ctl->loc_max_d), (unsigned long long)__double_as_longlong(m));
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Phase B: exit forest.
-__global__ __launch_bounds__(256) void k_d8_link(D8Params P, uint32_t n) {
+// Phase B: exit forest.  The link step turns each exit's local sum into
+// fixed point and points it at the exit its water reaches next (block
+// iterations: only inside its block).  An exit list that overflowed its
+// capacity opens the engine's gate instead (block iterations: an error).
+__device__ __forceinline__ int64_t blk_row(const D8Params& P, int64_t r) { return r / ((int64_t)P.th * P.bt_r); }
+__device__ __forceinline__ int64_t blk_col(const D8Params& P, int64_t c) { return c / ((int64_t)TW * P.bt_c); }
+
+template <int VK, bool ITER>
+__global__ __launch_bounds__(256) void k_d8_link(D8Params P) {
+  const uint32_t n = *P.n_exits;
+  if (n > P.cap) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (ITER) set_status(P.status, FR_ERR_CAPACITY);
+      else P.ctl->fallback = 1;
+    }
+    return;
+  }
+  const int E = VK != VK_NONE ? fx_exponent<VK>(P, n) : 0;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const uint32_t ec = P.ex_cell[i];
     if (ec == NONE) {  // a hole of a phase-A chunk
       P.anc[0][i] = NONE;
       continue;
     }
+    if (VK == VK_FF) P.ex_fx[0][i] = (u128)(fx_from(P.ex_hi[i], E) + fx_from(P.ex_lo[i], E));
+    if (VK == VK_F64) P.ex_fx[0][i] = (u128)fx_from(P.ex_d[i], E);
     const int64_t e = ec;
     const int cd = P.code[e];
     const int64_t x = e + (int64_t)nb_dr(cd) * P.ncols + nb_dc(cd);
-    const int64_t rt = P.root_of[x];
     uint32_t a = NONE;
-    if (rt >= 0 && rt < P.nrows * P.ncols) {
+    bool leave = false;
+    if (ITER) {
+      const int64_t er = e / P.ncols, xr = x / P.ncols;
+      leave = blk_row(P, er) != blk_row(P, xr) || blk_col(P, e - er * P.ncols) != blk_col(P, x - xr * P.ncols);
+    }
+    const int64_t rt = leave ? -1 : (int64_t)P.root_of[x];
+    if (leave) {
+      // Water leaving the block: passed on by the next iteration.
+    } else if (rt >= 0 && rt < P.nrows * P.ncols) {
       const int64_t rr = rt / P.ncols, rc = rt - rr * P.ncols;
       const int rcd = P.code[rt];
       bool sink = rcd > 7;
@@ -795,8 +996,9 @@ __global__ __launch_bounds__(256) void k_d8_link(D8Params P, uint32_t n) {
 }
 
 // Round j sets flag slot j mod 3 when it leaves work for round j + 1, and
-// skips itself when round j - 1 left none (so the host can queue rounds
-// without waiting for each flag); round j's scatter clears slot j + 1.
+// skips itself when round j - 1 left none; round j's scatter clears slot
+// j + 1.  The rounds are a fixed sequence of launches, so after the last one
+// with work every later one returns at once.
 __device__ __forceinline__ int32_t* round_flag(const D8Params& P, int j) { return &P.flags[4 + j % 3]; }
 __device__ __forceinline__ bool round_idle(const D8Params& P, int j) {
   return j > 0 && __hip_atomic_load(round_flag(P, j + 2), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
@@ -806,8 +1008,9 @@ __device__ __forceinline__ bool round_idle(const D8Params& P, int j) {
 // Part 1: every exit that still has such an ancestor snapshots its sum (the
 // sum over its subtree within distance < 2^j) and jumps its pointer.
 template <int VK, bool CNT>
-__global__ __launch_bounds__(256) void k_d8_copy(D8Params P, uint32_t n, int b, int j) {
-  if (round_idle(P, j)) return;  // uniform
+__global__ __launch_bounds__(256) void k_d8_copy(D8Params P, int b, int j) {
+  const uint32_t n = *P.n_exits;
+  if (n > P.cap || round_idle(P, j)) return;  // uniform
   __shared__ int s_active;
   if (threadIdx.x == 0) s_active = 0;
   __syncthreads();
@@ -816,11 +1019,7 @@ __global__ __launch_bounds__(256) void k_d8_copy(D8Params P, uint32_t n, int b, 
     const uint32_t a = P.anc[b][i];
     uint32_t a2 = NONE;
     if (a != NONE) {
-      if (VK == VK_FF) {
-        P.ex_hi[1][i] = P.ex_hi[0][i];
-        P.ex_lo[1][i] = P.ex_lo[0][i];
-      }
-      if (VK == VK_F64) P.ex_q64[1][i] = P.ex_q64[0][i];
+      if (VK != VK_NONE) P.ex_fx[1][i] = P.ex_fx[0][i];
       if (CNT) P.ex_cnt[1][i] = P.ex_cnt[0][i];
       a2 = P.anc[b][a];
     }
@@ -831,50 +1030,74 @@ __global__ __launch_bounds__(256) void k_d8_copy(D8Params P, uint32_t n, int b, 
   // atomic from every wavefront on one word serialises the whole kernel.
   if (__ballot(active) && (threadIdx.x & 63) == 0) s_active = 1;
   __syncthreads();
-  if (threadIdx.x == 0 && s_active &&
-      __hip_atomic_load(round_flag(P, j), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-    __hip_atomic_store(round_flag(P, j), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0 && s_active) {
+    // Work left after the last round: deeper than any forest can be.
+    if (j == D8_ROUNDS - 1) set_status(P.status, FR_ERR_NOTDAG);
+    else if (__hip_atomic_load(round_flag(P, j), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+      __hip_atomic_store(round_flag(P, j), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
-// Part 2: each such exit adds its snapshot to the ancestor's sum in place.
+// Part 2: each such exit adds its snapshot to the ancestor's sum in place
+// (exact integer additions: the result does not depend on their order).
 template <int VK, bool CNT>
-__global__ __launch_bounds__(256) void k_d8_scatter(D8Params P, uint32_t n, int b, int j) {
+__global__ __launch_bounds__(256) void k_d8_scatter(D8Params P, int b, int j) {
   if (blockIdx.x == 0 && threadIdx.x == 0)
     __hip_atomic_store(round_flag(P, j + 1), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (round_idle(P, j)) return;  // uniform
+  const uint32_t n = *P.n_exits;
+  if (n > P.cap || round_idle(P, j)) return;  // uniform
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const uint32_t a = P.anc[b][i];
     if (a == NONE) continue;
+    if (VK != VK_NONE) atomic_add_fx(&P.ex_fx[0][a], P.ex_fx[1][i]);
+    if (CNT) atomicAdd(reinterpret_cast<unsigned long long*>(&P.ex_cnt[0][a]), (unsigned long long)P.ex_cnt[1][i]);
+  }
+}
+
+// After the last round: the totals back from fixed point into float-float
+// or float64 (into the snapshot buffer's memory, free again), where phase C
+// reads them.
+template <int VK>
+__global__ __launch_bounds__(256) void k_d8_totals(D8Params P) {
+  const uint32_t n = *P.n_exits;
+  if (n > P.cap) return;  // uniform
+  const int E = fx_exponent<VK>(P, n);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if (P.ex_cell[i] == NONE) continue;
+    const i128 v = (i128)P.ex_fx[0][i];
     if (VK == VK_FF) {
-      const float xh = P.ex_hi[1][i], xl = P.ex_lo[1][i];
-      const float old = atomicAdd(&P.ex_hi[0][a], xh);
-      const ff e = ff_two_sum(old, xh);  // e.hi is what the atomic stored
-      atomicAdd(&P.ex_lo[0][a], e.lo + xl);
+      const ff t = fx_to_ff(v, E);
+      P.ex_hi[i] = t.hi;
+      P.ex_lo[i] = t.lo;
+    } else {
+      P.ex_d[i] = fx_to_double(v, E);
     }
-    if (VK == VK_F64) atomicAdd(&P.ex_q64[0][a], P.ex_q64[1][i]);
-    if (CNT) atomicAdd(reinterpret_cast<unsigned long long*>(&P.ex_cnt[0][a]),
-                       (unsigned long long)P.ex_cnt[1][i]);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Phase C.
-template <int VK, bool CNT, int RAIN, bool VEC>
-__global__ __launch_bounds__(64) void k_d8_down(D8Params P) {
+// Phase C (and the block solve's final sweep).  Returns at once when the
+// exit list overflowed: the engine, or an error, takes over.
+template <int VK, bool CNT, int RAIN, bool VEC, bool ITER>
+__global__ __launch_bounds__(64) void k_d8_c(D8Params P) {
   __shared__ double s_mass[2][64];
   // Row exchange for grids whose rows are not aligned to 4 cells.
   __shared__ float s_q32[VEC || VK != VK_FF ? 1 : TW];
   __shared__ double s_q64[VEC || VK != VK_F64 ? 1 : TW];
   __shared__ uint64_t s_cnt[VEC || !CNT ? 1 : TW];
+  if (*P.n_exits > P.cap) return;  // uniform
   const int lane = threadIdx.x;
   const Tile T = tile_of(P, blockIdx.x);
-  double m[2] = {0.0, 0.0};
-  bool nonfinite = false;
-  if (T.border) sweep<false, VK, CNT, RAIN, VEC, true>(P, T, m, &nonfinite, s_q32, s_q64, s_cnt);
-  else sweep<false, VK, CNT, RAIN, VEC, false>(P, T, m, &nonfinite, s_q32, s_q64, s_cnt);
-  if (P.mass_part) {
-    s_mass[0][lane] = m[0];
-    s_mass[1][lane] = m[1];
+  SweepOut o;
+  if (T.border) sweep<false, VK, CNT, RAIN, VEC, true, ITER>(P, T, o, s_q32, s_q64, s_cnt);
+  else sweep<false, VK, CNT, RAIN, VEC, false, ITER>(P, T, o, s_q32, s_q64, s_cnt);
+  if (ITER) {
+    if (__ballot(o.changed) && lane == 0 && P.it_changed) *P.it_changed = 1;
+    if (o.badcode) set_status(P.status, FR_ERR_BADCODE);
+    if (o.nonfinite) set_status(P.status, FR_ERR_NONFINITE);
+  } else if (P.mass_part) {
+    s_mass[0][lane] = o.mass[0];
+    s_mass[1][lane] = o.mass[1];
     __syncthreads();
     if (lane == 0) {
       double a = 0.0, b = 0.0;
@@ -887,29 +1110,6 @@ __global__ __launch_bounds__(64) void k_d8_down(D8Params P) {
       P.mass_part[2 * blockIdx.x + 1] = b;
     }
   }
-}
-
-// ---------------------------------------------------------------------------
-// Block iterations (the paper's I+X scheme, Section 3.3 and Appendix B):
-// w <- D^-1 (r + rho w) with blocks = tiles, D = the pairs a tile's top-down
-// sweep follows (receiver in the row below, inside the tile), rho = every
-// other pair.  One launch is one iteration.
-template <int VK, bool CNT, int RAIN, bool VEC>
-__global__ __launch_bounds__(64) void k_d8_iter(D8Params P) {
-  __shared__ float s_q32[1];
-  __shared__ double s_q64[VEC || VK != VK_F64 ? 1 : TW];
-  __shared__ uint64_t s_cnt[VEC || !CNT ? 1 : TW];
-  const Tile T = tile_of(P, blockIdx.x);
-  bool nonfinite = false, badcode = false, changed = false;
-  if (T.border)
-    sweep<false, VK, CNT, RAIN, VEC, true, true>(P, T, nullptr, &nonfinite, s_q32, s_q64, s_cnt, &badcode,
-                                                  &changed);
-  else
-    sweep<false, VK, CNT, RAIN, VEC, false, true>(P, T, nullptr, &nonfinite, s_q32, s_q64, s_cnt, &badcode,
-                                                   &changed);
-  if (__ballot(changed) && threadIdx.x == 0 && P.it_changed) *P.it_changed = 1;
-  if (badcode) set_status(P.status, FR_ERR_BADCODE);
-  if (nonfinite) set_status(P.status, FR_ERR_NONFINITE);
 }
 
 __global__ __launch_bounds__(256) void k_bi_combine(int mode, int64_t n, const double* bq, const uint64_t* bc,
@@ -936,133 +1136,112 @@ __global__ __launch_bounds__(256) void k_bi_combine(int mode, int64_t n, const d
     *changed = 1;
 }
 
-int grid_for(uint32_t n) {
-  uint32_t b = (n + 255) / 256;
-  if (b > 16384) b = 16384;
-  return (int)(b < 1 ? 1 : b);
+// Workgroups of the forest kernels: enough for the exits of a large grid,
+// few enough that a launch with nothing to do costs little.
+unsigned forest_grid(uint32_t cap) {
+  const uint32_t b = (cap + 255) / 256;
+  return b < 1 ? 1u : (b > 2048 ? 2048u : b);
 }
 
 }  // namespace
 
-#define D8_DISPATCH(KERNEL, GRID, BLOCK, ...)                                                   \
-  do {                                                                                          \
-    if (vk == VK_FF) {                                                                          \
-      if (cnt) hipLaunchKernelGGL((KERNEL<VK_FF, true>), GRID, BLOCK, 0, s, __VA_ARGS__);       \
-      else hipLaunchKernelGGL((KERNEL<VK_FF, false>), GRID, BLOCK, 0, s, __VA_ARGS__);          \
-    } else if (vk == VK_F64) {                                                                  \
-      if (cnt) hipLaunchKernelGGL((KERNEL<VK_F64, true>), GRID, BLOCK, 0, s, __VA_ARGS__);      \
-      else hipLaunchKernelGGL((KERNEL<VK_F64, false>), GRID, BLOCK, 0, s, __VA_ARGS__);         \
-    } else {                                                                                    \
-      hipLaunchKernelGGL((KERNEL<VK_NONE, true>), GRID, BLOCK, 0, s, __VA_ARGS__);              \
-    }                                                                                           \
-  } while (0)
-
-// Launches a phase A / phase C kernel for the rain source and the row
-// alignment of the grid (float4 / dword row loads when ncols % 4 == 0).
-template <int VK, bool CNT, template <int, bool, int, bool> class K>
+// Launches a phase A / phase C kernel for the value kind, the rain source
+// and the row alignment of the grid (float4 / dword row loads when
+// ncols % 4 == 0).
+template <template <int, bool, int, bool, bool> class K, int VK, bool CNT, bool ITER>
 void d8_sweep_launch(const D8Params& P, hipStream_t s) {
-  const dim3 g((unsigned)((int64_t)P.ntr * P.ntc)), b(64);
   const bool vec = (P.ncols % 4) == 0;
   const int rain = P.rain64 ? RAIN_F64 : (P.rain32 ? RAIN_F32 : RAIN_UNIT);
-  if (VK == VK_NONE || rain == RAIN_UNIT) {
-    if (vec) K<VK, CNT, RAIN_UNIT, true>::launch(g, b, s, P);
-    else K<VK, CNT, RAIN_UNIT, false>::launch(g, b, s, P);
-  } else if (rain == RAIN_F32) {
-    if (vec) K<VK, CNT, RAIN_F32, true>::launch(g, b, s, P);
-    else K<VK, CNT, RAIN_F32, false>::launch(g, b, s, P);
+  if constexpr (VK == VK_NONE) {
+    if (vec) K<VK, CNT, RAIN_UNIT, true, ITER>::launch(P, s);
+    else K<VK, CNT, RAIN_UNIT, false, ITER>::launch(P, s);
   } else {
-    if (vec) K<VK, CNT, RAIN_F64, true>::launch(g, b, s, P);
-    else K<VK, CNT, RAIN_F64, false>::launch(g, b, s, P);
+    if (rain == RAIN_UNIT) {
+      if (vec) K<VK, CNT, RAIN_UNIT, true, ITER>::launch(P, s);
+      else K<VK, CNT, RAIN_UNIT, false, ITER>::launch(P, s);
+    } else if (rain == RAIN_F32) {
+      if (vec) K<VK, CNT, RAIN_F32, true, ITER>::launch(P, s);
+      else K<VK, CNT, RAIN_F32, false, ITER>::launch(P, s);
+    } else {
+      if (vec) K<VK, CNT, RAIN_F64, true, ITER>::launch(P, s);
+      else K<VK, CNT, RAIN_F64, false, ITER>::launch(P, s);
+    }
   }
 }
 
-template <int VK, bool CNT, int RAIN, bool VEC>
-struct UpK {
-  static void launch(dim3 g, dim3 b, hipStream_t s, const D8Params& P) {
-    hipLaunchKernelGGL((k_d8_up<VK, CNT, VK == VK_NONE ? RAIN_UNIT : RAIN, VEC>), g, b, 0, s, P);
-  }
-};
-template <int VK, bool CNT, int RAIN, bool VEC>
-struct DownK {
-  static void launch(dim3 g, dim3 b, hipStream_t s, const D8Params& P) {
-    hipLaunchKernelGGL((k_d8_down<VK, CNT, VK == VK_NONE ? RAIN_UNIT : RAIN, VEC>), g, b, 0, s, P);
-  }
-};
-
-template <int VK, bool CNT, int RAIN, bool VEC>
-struct IterK {
-  static void launch(dim3 g, dim3 b, hipStream_t s, const D8Params& P) {
-    hipLaunchKernelGGL((k_d8_iter<VK, CNT, VK == VK_NONE ? RAIN_UNIT : RAIN, VEC>), g, b, 0, s, P);
-  }
-};
-
-template <template <int, bool, int, bool> class K>
-void d8_sweep_dispatch(ValKind vk, bool cnt, const D8Params& P, hipStream_t s) {
-  if (vk == VK_FF) {
-    if (cnt) d8_sweep_launch<VK_FF, true, K>(P, s);
-    else d8_sweep_launch<VK_FF, false, K>(P, s);
+template <template <int, bool, int, bool, bool> class K>
+hipError_t d8_sweep_dispatch(ValKind vk, bool cnt, bool iter, const D8Params& P, hipStream_t s) {
+  if (iter) {
+    // Block iterations: float64 water and/or counts.
+    if (vk == VK_FF) return hipErrorInvalidValue;
+    if (vk == VK_F64) {
+      if (cnt) d8_sweep_launch<K, VK_F64, true, true>(P, s);
+      else d8_sweep_launch<K, VK_F64, false, true>(P, s);
+    } else {
+      d8_sweep_launch<K, VK_NONE, true, true>(P, s);
+    }
+  } else if (vk == VK_FF) {
+    if (cnt) d8_sweep_launch<K, VK_FF, true, false>(P, s);
+    else d8_sweep_launch<K, VK_FF, false, false>(P, s);
   } else if (vk == VK_F64) {
-    if (cnt) d8_sweep_launch<VK_F64, true, K>(P, s);
-    else d8_sweep_launch<VK_F64, false, K>(P, s);
+    if (cnt) d8_sweep_launch<K, VK_F64, true, false>(P, s);
+    else d8_sweep_launch<K, VK_F64, false, false>(P, s);
   } else {
-    d8_sweep_launch<VK_NONE, true, K>(P, s);
+    d8_sweep_launch<K, VK_NONE, true, false>(P, s);
   }
-}
-
-// A second stream (default priority) per host thread and device, on which
-// the root sweep runs beside the local sweep: the first is bound by its
-// instruction count, the second by HBM, and neither reads what the other
-// writes.
-namespace {
-struct SideStream {
-  hipStream_t s = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
-};
-hipError_t side_stream(SideStream** out) {
-  constexpr int kMaxDevices = 64;
-  thread_local SideStream per[kMaxDevices];
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
-  SideStream& ss = per[dev];
-  if (!ss.s) {
-    if ((e = hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking)) != hipSuccess) return e;
-    if ((e = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming)) != hipSuccess) return e;
-    if ((e = hipEventCreateWithFlags(&ss.join, hipEventDisableTiming)) != hipSuccess) return e;
-  }
-  *out = &ss;
-  return hipSuccess;
-}
-}  // namespace
-
-hipError_t launch_d8_up(ValKind vk, bool cnt, const D8Params& P, hipStream_t s) {
-  const dim3 g((unsigned)((int64_t)P.ntr * P.ntc)), b(64);
-  SideStream* ss = nullptr;
-  hipError_t e = side_stream(&ss);
-  if (e != hipSuccess) return e;
-  if ((e = hipEventRecord(ss->fork, s)) != hipSuccess) return e;
-  if ((e = hipStreamWaitEvent(ss->s, ss->fork, 0)) != hipSuccess) return e;
-  if ((P.ncols % 4) == 0) hipLaunchKernelGGL(k_d8_root<true>, g, b, 0, ss->s, P);
-  else hipLaunchKernelGGL(k_d8_root<false>, g, b, 0, ss->s, P);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  d8_sweep_dispatch<UpK>(vk, cnt, P, s);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = hipEventRecord(ss->join, ss->s)) != hipSuccess) return e;
-  return hipStreamWaitEvent(s, ss->join, 0);
-}
-
-hipError_t launch_d8_link(const D8Params& P, uint32_t n, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_d8_link, dim3(grid_for(n)), dim3(256), 0, s, P, n);
   return hipGetLastError();
 }
 
-hipError_t launch_d8_round(ValKind vk, bool cnt, const D8Params& P, uint32_t n, int j, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  const int b = j & 1;
-  D8_DISPATCH(k_d8_copy, dim3(grid_for(n)), dim3(256), P, n, b, j);
-  D8_DISPATCH(k_d8_scatter, dim3(grid_for(n)), dim3(256), P, n, b, j);
+template <int VK, bool CNT, int RAIN, bool VEC, bool ITER>
+struct KernelA {
+  static void launch(const D8Params& P, hipStream_t s) {
+    hipLaunchKernelGGL((k_d8_a<VK, CNT, RAIN, VEC, ITER>), dim3((unsigned)((int64_t)P.ntr * P.ntc)), dim3(128), 0,
+                       s, P);
+  }
+};
+template <int VK, bool CNT, int RAIN, bool VEC, bool ITER>
+struct KernelC {
+  static void launch(const D8Params& P, hipStream_t s) {
+    hipLaunchKernelGGL((k_d8_c<VK, CNT, RAIN, VEC, ITER>), dim3((unsigned)((int64_t)P.ntr * P.ntc)), dim3(64), 0,
+                       s, P);
+  }
+};
+
+hipError_t launch_d8_up(ValKind vk, bool cnt, bool iter, const D8Params& P, hipStream_t s) {
+  return d8_sweep_dispatch<KernelA>(vk, cnt, iter, P, s);
+}
+
+hipError_t launch_d8_down(ValKind vk, bool cnt, bool iter, const D8Params& P, hipStream_t s) {
+  return d8_sweep_dispatch<KernelC>(vk, cnt, iter, P, s);
+}
+
+template <int VK, bool CNT>
+void forest_rounds(const D8Params& P, dim3 g, hipStream_t s) {
+  for (int j = 0; j < D8_ROUNDS; ++j) {
+    hipLaunchKernelGGL((k_d8_copy<VK, CNT>), g, dim3(256), 0, s, P, j & 1, j);
+    hipLaunchKernelGGL((k_d8_scatter<VK, CNT>), g, dim3(256), 0, s, P, j & 1, j);
+  }
+}
+
+hipError_t launch_d8_forest(ValKind vk, bool cnt, bool iter, const D8Params& P, hipStream_t s) {
+  const dim3 g(forest_grid(P.cap)), b(256);
+  if (vk == VK_FF) {
+    if (iter) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_d8_link<VK_FF, false>), g, b, 0, s, P);
+    if (cnt) forest_rounds<VK_FF, true>(P, g, s);
+    else forest_rounds<VK_FF, false>(P, g, s);
+    hipLaunchKernelGGL((k_d8_totals<VK_FF>), g, b, 0, s, P);
+  } else if (vk == VK_F64) {
+    if (iter) hipLaunchKernelGGL((k_d8_link<VK_F64, true>), g, b, 0, s, P);
+    else hipLaunchKernelGGL((k_d8_link<VK_F64, false>), g, b, 0, s, P);
+    if (cnt) forest_rounds<VK_F64, true>(P, g, s);
+    else forest_rounds<VK_F64, false>(P, g, s);
+    hipLaunchKernelGGL((k_d8_totals<VK_F64>), g, b, 0, s, P);
+  } else {
+    if (iter) hipLaunchKernelGGL((k_d8_link<VK_NONE, true>), g, b, 0, s, P);
+    else hipLaunchKernelGGL((k_d8_link<VK_NONE, false>), g, b, 0, s, P);
+    forest_rounds<VK_NONE, true>(P, g, s);
+  }
   return hipGetLastError();
 }
 
@@ -1076,22 +1255,5 @@ hipError_t launch_bi_combine(int mode, int64_t n, const double* bq, const uint64
                      oc, changed);
   return hipGetLastError();
 }
-
-hipError_t launch_d8_iter(ValKind vk, bool cnt, const D8Params& P, hipStream_t s) {
-  if (vk == VK_FF) return hipErrorInvalidValue;  // float64 values or counts only
-  if (vk == VK_F64) {
-    if (cnt) d8_sweep_launch<VK_F64, true, IterK>(P, s);
-    else d8_sweep_launch<VK_F64, false, IterK>(P, s);
-  } else {
-    d8_sweep_launch<VK_NONE, true, IterK>(P, s);
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_d8_down(ValKind vk, bool cnt, const D8Params& P, hipStream_t s) {
-  d8_sweep_dispatch<DownK>(vk, cnt, P, s);
-  return hipGetLastError();
-}
-#undef D8_DISPATCH
 
 }  // namespace fr

@@ -100,6 +100,7 @@ __device__ __forceinline__ double mfd_w64(float zh, float zl, int k, double p) {
 // constants, argument checks that need the data.
 template <int RK, int DIR, int VK>
 __global__ __launch_bounds__(256) void k_engine_init(EngineParams P) {
+  if (P.gate && *P.gate == 0) return;  // another path finished the solve
   const int64_t n = P.nrows * P.ncols;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   bool badcode = false, nonfinite = false;
@@ -175,6 +176,7 @@ __global__ __launch_bounds__(256) void k_engine_init(EngineParams P) {
     P.nlist[1] = 0;
     P.nlist[2] = 0;
     *P.remaining = (unsigned long long)n;
+    *P.bar = 0ull;
   }
   const int64_t ntiles = (int64_t)P.ntr * P.ntc;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += stride) {
@@ -307,16 +309,23 @@ __device__ __forceinline__ bool leaves(const L& S, int h, int lr, int lc, int th
   return any;
 }
 
+__device__ __forceinline__ int32_t ld_dev(const int32_t* p) {
+  return __hip_atomic_load(const_cast<int32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One iteration: every tile of list it % 3 (grid-stride over workgroups).
 template <int RK, int DIR, int VK, bool CNT>
-__global__ __launch_bounds__(ENG_THREADS) void k_engine_iter(EngineParams P, int it) {
+__device__ __forceinline__ void engine_iter(TileLds<RK, VK, CNT>& S, const EngineParams& P, int it) {
   using L = TileLds<RK, VK, CNT>;
   constexpr int TH = L::TH, TW = L::TW, HW = L::HW, NC = L::NC, NH = L::NH;
-  __shared__ L S;
   const int tid = threadIdx.x;
   const float pf = (float)P.p;
-  const int n_active = P.nlist[it % 3];
+  const int n_active = ld_dev(P.nlist + it % 3);
   const int32_t* list = (it & 1) ? P.list1 : P.list0;
-  if (blockIdx.x == 0 && tid == 0) P.nlist[(it + 2) % 3] = 0;
+  // List (it + 2) % 3 was read in the previous iteration and is filled in
+  // the next one: clear it now (an atomic store, like the additions).
+  if (blockIdx.x == 0 && tid == 0)
+    __hip_atomic_store(P.nlist + (it + 2) % 3, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
   for (int e = blockIdx.x; e < n_active; e += gridDim.x) {
     const int64_t t = list[e];
@@ -560,11 +569,62 @@ __global__ __launch_bounds__(ENG_THREADS) void k_engine_iter(EngineParams P, int
   }
 }
 
+// Barrier of all workgroups of a persistent launch: arrivals only count up,
+// and iteration `epoch` is complete once (epoch + 1) * gridDim.x have
+// arrived.  The fences make every global write before the barrier visible
+// to every workgroup after it (the L2 of one XCD is not coherent with the
+// others).  The wait is bounded: false when some workgroup never arrived
+// (the launch's workgroups were not all resident).
+__device__ bool grid_sync(unsigned long long* bar, int epoch) {
+  __threadfence();
+  __syncthreads();
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    const unsigned long long target = (unsigned long long)(epoch + 1) * gridDim.x;
+    atomicAdd(bar, 1ull);
+    ok = 0;
+    for (int i = 0; i < (1 << 24); ++i) {
+      if (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) {
+        ok = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(4);
+    }
+  }
+  __syncthreads();
+  __threadfence();
+  return ok != 0;
+}
+
+// The whole peeling run in one launch: iterations separated by grid
+// barriers, until an iteration queues no tile for the next one -- every
+// cell is final, or (cells left over) the routing has a cycle.  Every
+// workgroup reads the same list length after the same barrier, so all of
+// them leave together.
+template <int RK, int DIR, int VK, bool CNT>
+__global__ __launch_bounds__(ENG_THREADS) void k_engine_run(EngineParams P) {
+  __shared__ TileLds<RK, VK, CNT> S;
+  if (P.gate && *P.gate == 0) return;  // uniform: another path finished the solve
+  for (int it = 0;; ++it) {
+    engine_iter<RK, DIR, VK, CNT>(S, P, it);
+    if (!grid_sync(P.bar, it)) {
+      if (threadIdx.x == 0) set_status(P.status, FR_ERR_STALL);
+      return;
+    }
+    if (ld_dev(P.nlist + (it + 1) % 3) == 0) {
+      if (blockIdx.x == 0 && threadIdx.x == 0 && ld_dev(reinterpret_cast<const uint64_t*>(P.remaining)) != 0)
+        set_status(P.status, FR_ERR_NOTDAG);
+      return;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Mass balance (Section 4 verification): {sum over sinks of q, sum of rain},
 // float64, two deterministic stages.
 template <int RK, int VK>
 __global__ __launch_bounds__(256) void k_mass_partial(EngineParams P, double* partial) {
+  if (P.gate && *P.gate == 0) return;
   const int64_t n = P.nrows * P.ncols;
   double s = 0.0, t = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -591,7 +651,10 @@ __global__ __launch_bounds__(256) void k_mass_partial(EngineParams P, double* pa
   }
 }
 
-__global__ __launch_bounds__(256) void k_mass_final(const double* partial, int nblocks, double* out) {
+// Runs when gate is NULL, or when (*gate != 0) == open.
+__global__ __launch_bounds__(256) void k_mass_final(const double* partial, int nblocks, double* out,
+                                                    const int32_t* gate, int open) {
+  if (gate && ((*gate != 0) != (open != 0))) return;
   __shared__ double rs[256], rt[256];
   double s = 0.0, t = 0.0;
   for (int b = threadIdx.x; b < nblocks; b += 256) {
@@ -654,41 +717,48 @@ hipError_t launch_engine_init(const EngineConfig& cfg, const EngineParams& P, hi
                             : init_dispatch_vk<RK_MULTI, DIR_ADJ>(cfg.vk, P, s);
 }
 
-#define FR_ITER(RK, DIR, VK, CNT) \
-  hipLaunchKernelGGL((k_engine_iter<RK, DIR, VK, CNT>), dim3(grid), dim3(ENG_THREADS), 0, s, P, it)
+// Workgroups of the persistent engine: as many as can be resident at once
+// (at most two per compute unit), so that its grid barriers always complete.
+template <int RK, int DIR, int VK, bool CNT>
+hipError_t run_t(const EngineParams& P, hipStream_t s) {
+  int dev = 0, cus = 0, per = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_engine_run<RK, DIR, VK, CNT>, ENG_THREADS, 0);
+  if (e != hipSuccess) return e;
+  if (per < 1 || cus < 1) return hipErrorLaunchFailure;
+  int64_t grid = (int64_t)cus * (per > 2 ? 2 : per);
+  const int64_t ntiles = (int64_t)P.ntr * P.ntc;
+  if (grid > ntiles) grid = ntiles;
+  hipLaunchKernelGGL((k_engine_run<RK, DIR, VK, CNT>), dim3((unsigned)(grid < 1 ? 1 : grid)), dim3(ENG_THREADS), 0, s,
+                     P);
+  return hipGetLastError();
+}
 
-hipError_t launch_engine_iter(const EngineConfig& cfg, const EngineParams& P, int it, int grid,
-                              hipStream_t s) {
+hipError_t launch_engine_run(const EngineConfig& cfg, const EngineParams& P, hipStream_t s) {
   if (cfg.rk == RK_SINGLE) {
     if (cfg.dir == DIR_FWD) {
       if (cfg.counts) {
         switch (cfg.vk) {
-          case VK_FF: FR_ITER(RK_SINGLE, DIR_FWD, VK_FF, true); break;
-          case VK_F64: FR_ITER(RK_SINGLE, DIR_FWD, VK_F64, true); break;
-          default: FR_ITER(RK_SINGLE, DIR_FWD, VK_NONE, true); break;
-        }
-      } else {
-        switch (cfg.vk) {
-          case VK_FF: FR_ITER(RK_SINGLE, DIR_FWD, VK_FF, false); break;
-          default: FR_ITER(RK_SINGLE, DIR_FWD, VK_F64, false); break;
+          case VK_FF: return run_t<RK_SINGLE, DIR_FWD, VK_FF, true>(P, s);
+          case VK_F64: return run_t<RK_SINGLE, DIR_FWD, VK_F64, true>(P, s);
+          default: return run_t<RK_SINGLE, DIR_FWD, VK_NONE, true>(P, s);
         }
       }
-    } else {
-      if (cfg.vk == VK_FF) FR_ITER(RK_SINGLE, DIR_ADJ, VK_FF, false);
-      else FR_ITER(RK_SINGLE, DIR_ADJ, VK_F64, false);
+      if (cfg.vk == VK_FF) return run_t<RK_SINGLE, DIR_FWD, VK_FF, false>(P, s);
+      return run_t<RK_SINGLE, DIR_FWD, VK_F64, false>(P, s);
     }
-  } else {
-    if (cfg.dir == DIR_FWD) {
-      if (cfg.vk == VK_FF) FR_ITER(RK_MULTI, DIR_FWD, VK_FF, false);
-      else FR_ITER(RK_MULTI, DIR_FWD, VK_F64, false);
-    } else {
-      if (cfg.vk == VK_FF) FR_ITER(RK_MULTI, DIR_ADJ, VK_FF, false);
-      else FR_ITER(RK_MULTI, DIR_ADJ, VK_F64, false);
-    }
+    if (cfg.vk == VK_FF) return run_t<RK_SINGLE, DIR_ADJ, VK_FF, false>(P, s);
+    return run_t<RK_SINGLE, DIR_ADJ, VK_F64, false>(P, s);
   }
-  return hipGetLastError();
+  if (cfg.dir == DIR_FWD) {
+    if (cfg.vk == VK_FF) return run_t<RK_MULTI, DIR_FWD, VK_FF, false>(P, s);
+    return run_t<RK_MULTI, DIR_FWD, VK_F64, false>(P, s);
+  }
+  if (cfg.vk == VK_FF) return run_t<RK_MULTI, DIR_ADJ, VK_FF, false>(P, s);
+  return run_t<RK_MULTI, DIR_ADJ, VK_F64, false>(P, s);
 }
-#undef FR_ITER
 
 hipError_t launch_mass(RuleKind rk, ValKind vk, const EngineParams& P, double* partial, int nblocks,
                        double* mass_out, hipStream_t s) {
@@ -699,12 +769,13 @@ hipError_t launch_mass(RuleKind rk, ValKind vk, const EngineParams& P, double* p
     if (vk == VK_FF) hipLaunchKernelGGL((k_mass_partial<RK_MULTI, VK_FF>), dim3(nblocks), dim3(256), 0, s, P, partial);
     else hipLaunchKernelGGL((k_mass_partial<RK_MULTI, VK_F64>), dim3(nblocks), dim3(256), 0, s, P, partial);
   }
-  hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(256), 0, s, partial, nblocks, mass_out);
+  hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(256), 0, s, partial, nblocks, mass_out, P.gate, 1);
   return hipGetLastError();
 }
 
-hipError_t launch_mass_final(const double* partial, int nblocks, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(256), 0, s, partial, nblocks, out);
+hipError_t launch_mass_final(const double* partial, int nblocks, double* out, const int32_t* skip,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(256), 0, s, partial, nblocks, out, skip, 0);
   return hipGetLastError();
 }
 

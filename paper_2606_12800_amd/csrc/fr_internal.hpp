@@ -57,6 +57,8 @@ struct EngineParams {
   int32_t* nlist;              // [3] ring of list lengths
   unsigned long long* remaining;  // cells not yet finished
   int32_t* status;             // device status word or NULL
+  const int32_t* gate;         // run only when *gate != 0 (NULL: always)
+  unsigned long long* bar;     // grid barrier arrivals of the persistent launch
 };
 
 // Row-sweep single-receiver path (fr_d8.hip): tile = D8Params::th rows x
@@ -78,6 +80,25 @@ inline int block_iter_height(int64_t nrows, int64_t ncols) {
   return nrows * ncols >= ((int64_t)1 << 28) ? 512 : 256;
 }
 
+// Control words of one call, at the start of its workspace (first 256
+// bytes): the decisions that would otherwise need the host -- whether the
+// exit list overflowed, whether the sweep is done, which way its next pass
+// goes -- are taken on the device, so that a call is ordered on its stream
+// alone and can be captured in a HIP graph.  Zeroed by the call's first
+// kernel.
+struct CallCtl {
+  int32_t fallback;          // 1: the peeling engine runs (exit list overflow, sweep budget spent)
+  int32_t sweep_stop;        // 1: no further sweep pass runs
+  int32_t sweep_dir;         // row direction of the next sweep pass (-1 or +1)
+  uint32_t sweep_fin[2];     // cells the last pass going up / down finished
+  uint32_t loc_max_f;        // D8 forest: largest |local sum| of an exit, float32 bits
+  int64_t sweep_remaining;   // cells not yet final
+  uint64_t loc_max_d;        // D8 forest: largest |local sum| of an exit, float64 bits
+  unsigned long long bar;    // persistent engine: grid barrier arrivals
+};
+static_assert(sizeof(CallCtl) <= 256, "control block fits its 256-byte slot");
+constexpr int CTL_WORDS = 64;  // 32-bit words zeroed at the start of a call
+
 struct D8Params {
   int64_t nrows, ncols;
   int32_t ntr, ntc;
@@ -91,33 +112,48 @@ struct D8Params {
   uint32_t* root_of;           // per cell, written for inlets: root cell
   uint32_t* node_of;           // per cell, written for exits: exit index
   uint32_t* ex_cell;           // exit list [cap]
-  uint64_t* ex_cnt[2];         // exit sums [0] and snapshots [1] for pointer doubling
-  float* ex_hi[2];
-  float* ex_lo[2];
-  double* ex_q64[2];
+  float* ex_hi;                // local (in-tile) sums of the exits: float-float
+  float* ex_lo;
+  double* ex_d;                // float64
+  uint64_t* ex_cnt[2];         // exit counts [0] and snapshots [1] for pointer doubling
+  unsigned __int128* ex_fx[2]; // exit water as 128-bit fixed point (unit 2^E), sums and snapshots
   uint32_t* anc[2];
   uint32_t* n_exits;           // exit counter
   uint32_t cap;
-  uint32_t n_ex;               // number of exits (set after phase A)
-  int32_t* flags;              // [1]: some exit still has an ancestor
+  int32_t* flags;              // pointer-doubling round flags
+  CallCtl* ctl;
   double* mass_part;           // per tile {sum over sinks, sum of rain}, or NULL
   int32_t* status;
-  // Block iterations (the paper's I+X scheme): the previous iterate, read at
-  // cut donors, and a flag set when an iterate differs from the previous one.
+  // Block iterations (the paper's I+X scheme): blocks of bt_r x bt_c tiles
+  // (0: a plain solve, no blocks); the previous iterate, read at donors in
+  // other blocks; a flag set when an iterate differs from the previous one.
+  int32_t bt_r, bt_c;
   const double* it_q64;
   const uint64_t* it_cnt;
   int32_t* it_changed;
-  int32_t it_first;            // first iteration: no water crosses a cut edge yet
+  int32_t it_first;            // first iteration: no water crosses a block boundary yet
   int32_t it_nosrc;            // apply D^-1 R only: no rain, no unit count source
   int32_t it_detect;           // compare with the previous iterate (set it_changed)
 };
 
+// Exit-list slots reserved per atomic in phase A (at least).  A phase-A
+// wavefront leaves unused slots only in its last chunk, so a tile's exits
+// take at most their number plus D8_EXIT_CHUNK slots.
+constexpr uint32_t D8_EXIT_CHUNK = 32;
+
+// Pointer-doubling rounds enqueued per solve: a forest of at most 2^31 - 1
+// exits is at most that deep, which 32 doublings cover; round 32 finding
+// work left proves a cycle.
+constexpr int D8_ROUNDS = 33;
+
 // Launchers (defined in the .hip files).
-hipError_t launch_d8_up(ValKind vk, bool cnt, const D8Params& P, hipStream_t s);
-hipError_t launch_d8_link(const D8Params& P, uint32_t n, hipStream_t s);
-hipError_t launch_d8_round(ValKind vk, bool cnt, const D8Params& P, uint32_t n, int j, hipStream_t s);
-hipError_t launch_d8_down(ValKind vk, bool cnt, const D8Params& P, hipStream_t s);
-hipError_t launch_d8_iter(ValKind vk, bool cnt, const D8Params& P, hipStream_t s);
+// Phase A (local sums and roots), phase B (exit forest: link, then
+// D8_ROUNDS pointer-doubling rounds, each a no-op once the forest is done or
+// when the exit list overflowed), phase C (final sweep).  `iter`: the block
+// iteration variants (blocks of P.bt_r x P.bt_c tiles).
+hipError_t launch_d8_up(ValKind vk, bool cnt, bool iter, const D8Params& P, hipStream_t s);
+hipError_t launch_d8_forest(ValKind vk, bool cnt, bool iter, const D8Params& P, hipStream_t s);
+hipError_t launch_d8_down(ValKind vk, bool cnt, bool iter, const D8Params& P, hipStream_t s);
 // Element-wise steps of the (I - X)(I + X) iteration on float64 values and
 // uint64 (wrap-around) counts; either array pair may be NULL.
 //   mode 0 (residual): t = b - w + t
@@ -127,7 +163,10 @@ hipError_t launch_bi_combine(int mode, int64_t n, const double* bq, const uint64
                              const uint64_t* wc, double* tq, uint64_t* tc, double* oq, uint64_t* oc,
                              int32_t* changed, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
-hipError_t launch_mass_final(const double* partial, int nblocks, double* out, hipStream_t s);
+// Final mass reduction of per-block partials; skipped when `skip` is given
+// and *skip != 0 (the result then comes from another path).
+hipError_t launch_mass_final(const double* partial, int nblocks, double* out, const int32_t* skip,
+                             hipStream_t s);
 hipError_t launch_receivers(const float* z, int64_t nrows, int64_t ncols, int rule, uint8_t* code,
                             int32_t* status, hipStream_t s);
 
@@ -260,13 +299,21 @@ size_t ws_edge_words(int64_t nrows, int64_t ncols);
 hipError_t launch_batch(const void* tiles_dev, int32_t ntiles, int order, int workers, int32_t* status,
                         char* ws, size_t ws_bytes, hipStream_t s);
 int64_t ws_strips(int64_t ncols);
-hipError_t launch_ws_progress_reset(const WsParams& P, hipStream_t s);
-hipError_t launch_ws_setup(const EngineConfig& cfg, const WsParams& P, hipStream_t s);
-hipError_t launch_ws_pass(const EngineConfig& cfg, const WsParams& P, int dir, int first, hipStream_t s);
+// Wavefront sweep: set-up (edge records, direction probe, first pass's
+// control), then passes, each followed by a control step that counts the
+// cells finished, picks the next direction and stops the sequence (done,
+// cycle, device error) or, after the last pass of the budget, opens the
+// engine's gate.  Passes return at once after a stop.
+hipError_t launch_ws_setup(const EngineConfig& cfg, const WsParams& P, CallCtl* C, hipStream_t s);
+hipError_t launch_ws_pass(const EngineConfig& cfg, const WsParams& P, const CallCtl* C, int first,
+                          hipStream_t s);
+hipError_t launch_ws_ctl(const WsParams& P, CallCtl* C, int pass, bool last, hipStream_t s);
 
+// The peeling engine: set-up, then one persistent launch that runs its
+// iterations with grid barriers until every cell is final (or a cycle
+// leaves the queue empty).  Both return at once when P.gate is closed.
 hipError_t launch_engine_init(const EngineConfig& cfg, const EngineParams& P, hipStream_t s);
-hipError_t launch_engine_iter(const EngineConfig& cfg, const EngineParams& P, int it, int grid,
-                              hipStream_t s);
+hipError_t launch_engine_run(const EngineConfig& cfg, const EngineParams& P, hipStream_t s);
 hipError_t launch_mass(RuleKind rk, ValKind vk, const EngineParams& P, double* partial,
                        int nblocks, double* mass_out, hipStream_t s);
 hipError_t launch_set_status(int32_t* status, int32_t code, hipStream_t s);

@@ -1145,10 +1145,67 @@ __device__ void ws_strip(WsShared<RK, VK, CNT>& S, const WsParams& P, const int6
   __syncthreads();
 }
 
+// One pass; returns at once after the control step stopped the sequence.
 template <int RK, int DK, int VK, bool CNT>
-__global__ __launch_bounds__(128) void k_ws_pass(WsParams P, int dir, int first) {
+__global__ __launch_bounds__(128) void k_ws_pass(WsParams P, const CallCtl* C, int first) {
   __shared__ WsShared<RK, VK, CNT> S;
-  ws_strip<RK, DK, VK, CNT>(S, P, (int64_t)blockIdx.x, dir, first);
+  if (C->sweep_stop) return;  // uniform
+  ws_strip<RK, DK, VK, CNT>(S, P, (int64_t)blockIdx.x, C->sweep_dir, first);
+}
+
+// Control step before the first pass (pass < 0) and after each pass: counts
+// the cells the pass finished and decides the next pass -- stop when every
+// cell is final or a device error was reported, report a cycle when a pass
+// finished nothing (a pass always finishes the highest unfinished cell of a
+// DAG), open the engine's gate when the budget is spent, otherwise pick the
+// direction (after one pass each way, the one whose last pass finished more
+// cells) -- and clears the pass counter and progress words for it.
+__global__ __launch_bounds__(256) void k_ws_ctl(WsParams P, CallCtl* C, int pass, int fwd, int last) {
+  __shared__ int s_run;
+  if (threadIdx.x == 0) {
+    int run = 0;
+    if (pass < 0) {
+      // Visit first the rows holding most inputs: forward inputs are donors,
+      // upstream of their receivers; adjoint inputs are the receivers.
+      const bool flows_up = P.ctr[1] >= P.ctr[2];
+      C->sweep_dir = ((fwd != 0) == flows_up) ? -1 : 1;
+      C->sweep_remaining = P.nrows * P.ncols;
+      C->sweep_fin[0] = 0u;
+      C->sweep_fin[1] = 0u;
+      C->sweep_stop = 0;
+      run = 1;
+    } else if (!C->sweep_stop) {
+      const uint32_t fin = P.ctr[0];
+      const int32_t st = P.status ? *(volatile int32_t*)P.status : 0;
+      const int64_t rem = C->sweep_remaining - (int64_t)fin;
+      C->sweep_remaining = rem;
+      if (rem <= 0 || st != 0) {
+        C->sweep_stop = 1;
+      } else if (fin == 0) {
+        C->sweep_stop = 1;
+        if (P.status) atomicCAS(P.status, 0, FR_ERR_NOTDAG);
+      } else if (last) {
+        C->sweep_stop = 1;
+        C->fallback = 1;
+      } else {
+        int dir = C->sweep_dir;
+        C->sweep_fin[dir > 0 ? 1 : 0] = fin;
+        const uint32_t up = C->sweep_fin[0], dn = C->sweep_fin[1];
+        if (pass == 0 || up == dn) dir = -dir;
+        else dir = dn > up ? 1 : -1;
+        C->sweep_dir = dir;
+        run = 1;
+      }
+    }
+    s_run = run;
+  }
+  __syncthreads();
+  if (!s_run) return;
+  if (threadIdx.x == 0) P.ctr[0] = 0u;
+  if (P.debug)
+    for (int i = threadIdx.x; i < 25; i += blockDim.x) P.ctr[3 + i] = 0u;
+  const int64_t ns = (P.ncols + WS_OWN - 1) / WS_OWN;
+  for (int64_t i = threadIdx.x; i < ns; i += blockDim.x) P.progress[i] = -1;
 }
 
 // Samples rows for the prevailing vertical flow direction: ctr[1] counts
@@ -1506,9 +1563,9 @@ __global__ __launch_bounds__(256) void k_batch_fill(const BatchHeader* hdr, cons
 }
 
 template <int RK, int DK, int VK, bool CNT>
-hipError_t pass_t(const WsParams& P, int dir, int first, hipStream_t s) {
+hipError_t pass_t(const WsParams& P, const CallCtl* C, int first, hipStream_t s) {
   const unsigned strips = (unsigned)((P.ncols + WS_OWN - 1) / WS_OWN);
-  hipLaunchKernelGGL((k_ws_pass<RK, DK, VK, CNT>), dim3(strips), dim3(128), 0, s, P, dir, first);
+  hipLaunchKernelGGL((k_ws_pass<RK, DK, VK, CNT>), dim3(strips), dim3(128), 0, s, P, C, first);
   return hipGetLastError();
 }
 
@@ -1516,24 +1573,11 @@ hipError_t pass_t(const WsParams& P, int dir, int first, hipStream_t s) {
 
 int64_t ws_strips(int64_t ncols) { return (ncols + WS_OWN - 1) / WS_OWN; }
 
-__global__ __launch_bounds__(256) void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = v;
-}
-
-hipError_t launch_ws_progress_reset(const WsParams& P, hipStream_t s) {
-  const int64_t n = ws_strips(P.ncols);
-  int64_t b = (n + 255) / 256;
-  if (b > 1024) b = 1024;
-  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)(b < 1 ? 1 : b)), dim3(256), 0, s, P.progress, n, -1);
-  return hipGetLastError();
-}
-
 size_t ws_edge_words(int64_t nrows, int64_t ncols) {
   return (size_t)((ncols + WS_OWN - 1) / WS_OWN) * (size_t)nrows * 2 * WS_EW;
 }
 
-hipError_t launch_ws_setup(const EngineConfig& cfg, const WsParams& P, hipStream_t s) {
+hipError_t launch_ws_setup(const EngineConfig& cfg, const WsParams& P, CallCtl* C, hipStream_t s) {
   const int64_t n = (int64_t)ws_edge_words(P.nrows, P.ncols);
   int64_t b = (n + 255) / 256;
   if (b > 8192) b = 8192;
@@ -1544,29 +1588,35 @@ hipError_t launch_ws_setup(const EngineConfig& cfg, const WsParams& P, hipStream
     hipLaunchKernelGGL(k_ws_probe<RK_SINGLE>, dim3(ns), dim3(256), 0, s, P, ns);
   else
     hipLaunchKernelGGL(k_ws_probe<RK_MULTI>, dim3(ns), dim3(256), 0, s, P, ns);
+  hipLaunchKernelGGL(k_ws_ctl, dim3(1), dim3(256), 0, s, P, C, -1, cfg.dir == DIR_FWD ? 1 : 0, 0);
   return hipGetLastError();
 }
 
-hipError_t launch_ws_pass(const EngineConfig& cfg, const WsParams& P, int dir, int first, hipStream_t s) {
+hipError_t launch_ws_ctl(const WsParams& P, CallCtl* C, int pass, bool last, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_ctl, dim3(1), dim3(256), 0, s, P, C, pass, 0, last ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_ws_pass(const EngineConfig& cfg, const WsParams& P, const CallCtl* C, int first, hipStream_t s) {
   if (cfg.dir == DIR_FWD) {
     if (cfg.rk == RK_MULTI) {
-      if (cfg.vk == VK_F64) return pass_t<RK_MULTI, DIR_FWD, VK_F64, false>(P, dir, first, s);
-      return pass_t<RK_MULTI, DIR_FWD, VK_FF, false>(P, dir, first, s);
+      if (cfg.vk == VK_F64) return pass_t<RK_MULTI, DIR_FWD, VK_F64, false>(P, C, first, s);
+      return pass_t<RK_MULTI, DIR_FWD, VK_FF, false>(P, C, first, s);
     }
     if (cfg.counts) {
-      if (cfg.vk == VK_FF) return pass_t<RK_SINGLE, DIR_FWD, VK_FF, true>(P, dir, first, s);
-      if (cfg.vk == VK_F64) return pass_t<RK_SINGLE, DIR_FWD, VK_F64, true>(P, dir, first, s);
-      return pass_t<RK_SINGLE, DIR_FWD, VK_NONE, true>(P, dir, first, s);
+      if (cfg.vk == VK_FF) return pass_t<RK_SINGLE, DIR_FWD, VK_FF, true>(P, C, first, s);
+      if (cfg.vk == VK_F64) return pass_t<RK_SINGLE, DIR_FWD, VK_F64, true>(P, C, first, s);
+      return pass_t<RK_SINGLE, DIR_FWD, VK_NONE, true>(P, C, first, s);
     }
-    if (cfg.vk == VK_F64) return pass_t<RK_SINGLE, DIR_FWD, VK_F64, false>(P, dir, first, s);
-    return pass_t<RK_SINGLE, DIR_FWD, VK_FF, false>(P, dir, first, s);
+    if (cfg.vk == VK_F64) return pass_t<RK_SINGLE, DIR_FWD, VK_F64, false>(P, C, first, s);
+    return pass_t<RK_SINGLE, DIR_FWD, VK_FF, false>(P, C, first, s);
   }
   if (cfg.rk == RK_MULTI) {
-    if (cfg.vk == VK_F64) return pass_t<RK_MULTI, DIR_ADJ, VK_F64, false>(P, dir, first, s);
-    return pass_t<RK_MULTI, DIR_ADJ, VK_FF, false>(P, dir, first, s);
+    if (cfg.vk == VK_F64) return pass_t<RK_MULTI, DIR_ADJ, VK_F64, false>(P, C, first, s);
+    return pass_t<RK_MULTI, DIR_ADJ, VK_FF, false>(P, C, first, s);
   }
-  if (cfg.vk == VK_F64) return pass_t<RK_SINGLE, DIR_ADJ, VK_F64, false>(P, dir, first, s);
-  return pass_t<RK_SINGLE, DIR_ADJ, VK_FF, false>(P, dir, first, s);
+  if (cfg.vk == VK_F64) return pass_t<RK_SINGLE, DIR_ADJ, VK_F64, false>(P, C, first, s);
+  return pass_t<RK_SINGLE, DIR_ADJ, VK_FF, false>(P, C, first, s);
 }
 
 hipError_t launch_batch(const void* tiles_dev, int32_t ntiles, int order, int workers, int32_t* status,

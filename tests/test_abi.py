@@ -42,12 +42,15 @@ def test_header_constants_match_binding():
     assert consts["FR_D8"] == fr.D8 and consts["FR_MFD"] == fr.MFD and consts["FR_D4"] == fr.D4
     assert consts["FR_F32"] == fr.F32 and consts["FR_F64"] == fr.F64 and consts["FR_NONE"] == fr.NONE
     assert consts["FR_SINK"] == fr.SINK
-    for name in ["ARG", "RULE", "WORKSPACE", "HIP", "NONFINITE", "NOTDAG", "BADCODE", "TOOLARGE"]:
+    for name in ["ARG", "RULE", "WORKSPACE", "HIP", "NONFINITE", "NOTDAG", "BADCODE", "TOOLARGE", "STALL",
+                 "CAPACITY"]:
         assert consts[f"FR_ERR_{name}"] == getattr(fr, f"ERR_{name}")
+    for name in ["AUTO", "SWEEP", "ENGINE"]:
+        assert consts[f"FR_PATH_{name}"] == getattr(fr, f"PATH_{name}")
 
 
 def test_status_strings(lib):
-    for code in [0, -1, -2, -3, -4, -5, -6, -7, -8]:
+    for code in [0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10]:
         s = fr.status_string(code)
         assert s and s != "unknown status"
     assert fr.status_string(12345) == "unknown status"
@@ -131,10 +134,13 @@ def test_block_iterations_validation(lib):
     it = ctypes.c_int32(7)
 
     def bi(code=FAKE, nr=8, nc=8, rule=fr.D8, scheme=fr.SCHEME_IX, rain=NULL, rdt=fr.F32, qdt=fr.F64, q=FAKE,
-           cnt=FAKE, max_iter=10, iters=ctypes.byref(it), ws=FAKE, wsb=1 << 40):
-        return lib.fr_accumulate_block_iterations(code, nr, nc, rule, scheme, rain, rdt, qdt, q, cnt, max_iter,
-                                                  iters, NULL, ws, wsb, NULL)
+           cnt=FAKE, max_iter=10, iters=ctypes.byref(it), ws=FAKE, wsb=1 << 40, br=256, bc=256):
+        return lib.fr_accumulate_block_iterations(NULL, code, nr, nc, rule, 0.0, br, bc, scheme, rain, rdt, qdt, q,
+                                                  cnt, max_iter, iters, NULL, ws, wsb, NULL)
     assert bi(nr=-1) == fr.ERR_ARG
+    assert bi(br=0) == fr.ERR_ARG and bi(bc=-3) == fr.ERR_ARG
+    assert bi(nr=600, nc=600, br=100) == fr.ERR_ARG          # block rows: a multiple of 16
+    assert bi(nr=600, nc=600, bc=300) == fr.ERR_ARG          # block cols: a multiple of 256
     assert bi(iters=NULL) == fr.ERR_ARG
     assert bi(max_iter=0) == fr.ERR_ARG
     assert bi(rule=fr.MFD) == fr.ERR_RULE
@@ -151,6 +157,15 @@ def test_block_iterations_validation(lib):
     assert bi(nr=1 << 16, nc=1 << 16) == fr.ERR_TOOLARGE
     it.value = 7
     assert bi(nr=0, code=NULL, ws=NULL) == fr.OK and it.value == 0  # empty grid: no-op
+
+
+def test_accumulate_path_selection(lib):
+    assert lib.fr_set_accumulate_path(3) == fr.ERR_ARG
+    assert lib.fr_set_accumulate_path(-1) == fr.ERR_ARG
+    for p in (fr.PATH_ENGINE, fr.PATH_SWEEP, fr.PATH_AUTO):
+        assert lib.fr_set_accumulate_path(p) == fr.OK
+    with fr.accumulate_path("engine"):
+        pass  # restores the default on exit
 
 
 def test_fill_validation(lib):

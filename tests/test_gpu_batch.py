@@ -96,8 +96,7 @@ def test_batch_matches_oracle(with_rain):
                 assert relmax(host(t["q"]), qref) <= 1e-6, z.shape
 
 
-def test_batch_mfd_bitwise_equals_single_grid_sweep(monkeypatch):
-    monkeypatch.setenv("FLOWROUTE_ACC", "sweep")
+def test_batch_mfd_bitwise_equals_single_grid_sweep():
     shapes = [(300, 260), (129, 500), (64, 64)]
     tiles = []
     for i, (nr, nc) in enumerate(shapes):

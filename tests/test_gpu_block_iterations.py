@@ -2,12 +2,14 @@
 Appendix B) on the GPU.
 
 fr_accumulate_block_iterations runs w <- D^-1 (r + R w) (scheme "ix") or
-w <- w + (I - X)(b - (I + X) w) (scheme "imx_ix") with one top-down sweep
-per 256 x 256 block as D^-1.  Checks: float64 water against the oracle's
-direct solve, counts bit-exact against the oracle and against fr_accumulate,
-and the number of iterations equal to the oracle's block iteration with the
-same scheme and splitting (C + 1, or about half that, C the most pairs
-outside D along a flow path).
+w <- w + (I - X)(b - (I + X) w) (scheme "imx_ix") with D^-1 the exact solve
+of every block of block = (rows, cols) cells: D holds every routing pair
+inside a block, R every pair between blocks -- the paper's splitting.
+Checks against the oracle's block iteration with the same blocks
+(oracle.block_richardson, the per-block high-to-low push): the iteration
+count (C + 1 for "ix", ceil((C + 1) / 2) for "imx_ix", C the most block
+crossings along a flow path), float64 water against the direct solve and
+counts bit-exact.
 
 Water tolerance.  Scheme "ix" adds the same positive terms as the direct
 solve in another order: <= 1e-10 per cell, the float64 bar.  Scheme
@@ -28,7 +30,9 @@ pytestmark = pytest.mark.gpu
 
 fr = pytest.importorskip("paper_2606_12800_amd")
 
-BLOCK = (256, 256)  # tile of grids below 2^28 cells
+# Block shapes (rows, cols): multiples of 16 rows and 256 columns, or the
+# whole extent; several tiles per block where the shapes allow it.
+BLOCKS = [(256, 256), (128, 512), (64, 256), (512, 100000)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -46,18 +50,19 @@ def dev(a):
 @pytest.mark.parametrize("seed,shape", [(71, (600, 700)), (72, (513, 259)), (73, (1, 900)), (74, (777, 1)),
                                         (75, (300, 1031))])
 @pytest.mark.parametrize("rule", ["d8", "d4"])
-def test_block_iterations_match_oracle(seed, shape, rule):
-    print(f"block iterations {rule} seed {seed} shape {shape}", flush=True)
+@pytest.mark.parametrize("block", BLOCKS)
+def test_block_iterations_match_oracle(seed, shape, rule, block):
+    print(f"block iterations {rule} seed {seed} shape {shape} block {block}", flush=True)
     r = oracle.D8 if rule == "d8" else oracle.D4
     z = synth.dem(seed, *shape)
     rain = synth.rain(seed, *shape)
     code_h = oracle.receivers(z, r)
     ref_q, _ = oracle.accumulate_single(code_h, rain, z=z)
     _, ref_c = oracle.accumulate_single(code_h, None, z=z)
-    _, _, ref_it = oracle.block_richardson(z, BLOCK, r, None, 0, split=1)
+    _, _, ref_it = oracle.block_richardson(z, block, r, None, 0)
     code = fr.receivers(dev(z), rule)
     assert np.array_equal(code.cpu().numpy(), code_h)
-    q, cnt, it = fr.block_iterations(code, dev(rain), rule)
+    q, cnt, it = fr.block_iterations(code, dev(rain), rule, block=block)
     torch.cuda.synchronize()
     qh = q.cpu().numpy()
     assert np.max(np.abs(qh - ref_q) / np.maximum(ref_q, 1e-300)) <= 1e-10
@@ -90,6 +95,10 @@ def test_block_iterations_errors():
     big = synth.dem(78, 900, 300)
     bcode = fr.receivers(dev(big), "d8")
     _, _, it = fr.block_iterations(bcode, None, "d8")
+    # Block shapes the row-sweep tiles cannot form.
+    with pytest.raises(fr.FlowRouteError) as e:
+        fr.block_iterations(bcode, None, "d8", block=(100, 256))
+    assert e.value.code == fr.ERR_ARG
     assert it >= 3
     with pytest.raises(fr.FlowRouteError) as e:
         fr.block_iterations(bcode, None, "d8", max_iter=it - 2)
@@ -102,24 +111,26 @@ def test_block_iterations_errors():
 @pytest.mark.parametrize("seed,shape", [(81, (600, 700)), (82, (513, 259)), (83, (1, 900)), (84, (777, 1)),
                                         (85, (300, 1031))])
 @pytest.mark.parametrize("rule", ["d8", "d4"])
-def test_preconditioned_block_iterations_match_oracle(seed, shape, rule):
-    print(f"(I-X)(I+X) block iterations {rule} seed {seed} shape {shape}", flush=True)
+@pytest.mark.parametrize("block", BLOCKS[:2])
+def test_preconditioned_block_iterations_match_oracle(seed, shape, rule, block):
+    print(f"(I-X)(I+X) block iterations {rule} seed {seed} shape {shape} block {block}", flush=True)
     r = oracle.D8 if rule == "d8" else oracle.D4
     z = synth.dem(seed, *shape)
     rain = synth.rain(seed, *shape)
     code_h = oracle.receivers(z, r)
     ref_q, _ = oracle.accumulate_single(code_h, rain, z=z)
     _, ref_c = oracle.accumulate_single(code_h, None, z=z)
-    _, _, ref_it = oracle.block_richardson(z, BLOCK, r, None, 1, split=1)
-    _, _, ix_it = oracle.block_richardson(z, BLOCK, r, None, 0, split=1)
+    _, _, ref_it = oracle.block_richardson(z, block, r, None, 1)
+    _, _, ix_it = oracle.block_richardson(z, block, r, None, 0)
     code = fr.receivers(dev(z), rule)
-    q, cnt, it = fr.block_iterations(code, dev(rain), rule, scheme="imx_ix")
+    q, cnt, it = fr.block_iterations(code, dev(rain), rule, scheme="imx_ix", block=block)
     torch.cuda.synchronize()
     qh = q.cpu().numpy()
     assert np.max(np.abs(qh - ref_q) / np.maximum(ref_q, 1e-300)) <= 1e-10
     assert np.array_equal(cnt.cpu().numpy().astype(np.uint64), ref_c)
     assert it == ref_it
-    assert it <= (ix_it + 2) // 2 + 1
+    # Appendix B: the (I-X)(I+X) error operator is X^2, so ceil((C+1)/2).
+    assert it == (ix_it + 1) // 2
 
 
 def test_preconditioned_block_iterations_counts_only_and_errors():
@@ -145,14 +156,17 @@ def test_preconditioned_block_iterations_counts_only_and_errors():
 
 def test_block_iterations_fullsize_counts_equal_main_path():
     """The bench's block-iteration workload: D8 unit-rain counts on the
-    43360^2 DEM (seed 2) by I+X block iterations, bit-exact against the main
-    path's counts (which the full-size tests check cell by cell)."""
+    43360^2 DEM (seed 2) by I+X block iterations with blocks of 4096 x 4096
+    cells (121 blocks, the paper's per-process subdomains), bit-exact
+    against the main path's counts (which the full-size tests check cell by
+    cell)."""
     n = 43360
-    print(f"block iterations d8 {n}x{n}", flush=True)
+    print(f"block iterations d8 {n}x{n} blocks 4096x4096", flush=True)
     code = fr.receivers(torch.from_numpy(synth.dem(2, n, n)).cuda(), "d8")
     torch.cuda.synchronize()
-    _, cnt, it = fr.block_iterations(code, None, "d8", dtype=None)
+    _, cnt, it = fr.block_iterations(code, None, "d8", dtype=None, block=(4096, 4096))
     _, c2, _ = fr.accumulate(code, None, None, "d8", None, counts=True)
+    print(f"iterations {it}", flush=True)
     assert it > 1 and torch.equal(cnt, c2)
     del code, cnt, c2
     fr._default_ws.buf = None

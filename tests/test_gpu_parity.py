@@ -54,24 +54,24 @@ def relnorm(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-_ACC_ENV = {"rows": "auto", "sweep": "sweep", "engine": "engine"}
+_ACC_PATH = {"rows": "auto", "sweep": "sweep", "engine": "engine"}
 
 
 @pytest.fixture(params=["rows", "sweep", "engine"])
-def d8path(request, monkeypatch):
+def d8path(request):
     """Single-receiver forward accumulation has three GPU paths: row sweeps
-    with an exit forest (default), the windowed wavefront sweep (its
-    fallback) and the peeling engine (the sweep's fallback)."""
-    monkeypatch.setenv("FLOWROUTE_ACC", _ACC_ENV[request.param])
-    return request.param
+    with an exit forest (default), the windowed wavefront sweep and the
+    peeling engine (the fallback of both)."""
+    with fr.accumulate_path(_ACC_PATH[request.param]):
+        yield request.param
 
 
 @pytest.fixture(params=["sweep", "engine"])
-def accpath(request, monkeypatch):
+def accpath(request):
     """MFD and adjoint accumulation: the wavefront sweep (default) or the
     peeling engine."""
-    monkeypatch.setenv("FLOWROUTE_ACC", _ACC_ENV[request.param])
-    return request.param
+    with fr.accumulate_path(_ACC_PATH[request.param]):
+        yield request.param
 
 
 SHAPES = [(256, 256, 1), (97, 131, 7), (1, 1, 8), (1, 300, 9), (300, 1, 10), (64, 64, 11),

@@ -405,10 +405,9 @@ def _block(shape, blk, r, c):
     return (r // blk[0]) * nbc + c // blk[1]
 
 
-def _max_crossings_d8(code, blk, split=0):
+def _max_crossings_d8(code, blk):
     """Brute force: follow every cell's flow path to its sink, counting the
-    pairs outside D (block boundaries; with split 1 also pairs not directed
-    to the row before); the maximum over all paths."""
+    pairs that cross a block boundary; the maximum over all paths."""
     best = 0
     for r in range(code.shape[0]):
         for c in range(code.shape[1]):
@@ -417,10 +416,7 @@ def _max_crossings_d8(code, blk, split=0):
                 nxt = _target(code, *cur)
                 if nxt is None:
                     break
-                inside = _block(code.shape, blk, *cur) == _block(code.shape, blk, *nxt)
-                if split == 1:
-                    inside = inside and nxt[0] == cur[0] - 1
-                n += not inside
+                n += _block(code.shape, blk, *cur) != _block(code.shape, blk, *nxt)
                 cur = nxt
             best = max(best, n)
     return best
@@ -499,20 +495,6 @@ def test_block_richardson_mfd_crossings_plus_one(seed, shape, blk):
     q1, _, it1 = oracle.block_richardson(z, blk, oracle.MFD, None, 1)
     assert it1 == (C + 2) // 2
     assert np.allclose(q1, ref, rtol=1e-12, atol=0)
-
-
-@pytest.mark.parametrize("seed,shape,blk", [(68, (40, 33), (10, 11)), (69, (26, 45), (13, 9))])
-def test_block_richardson_sweep_split_crossings_plus_one(seed, shape, blk):
-    # With D reduced to the pairs a single top-down block sweep follows, the
-    # same argument counts every other pair along a path.
-    z = synth.dem(seed, *shape)
-    code = oracle.receivers(z)
-    C = _max_crossings_d8(code, blk, split=1)
-    assert C >= _max_crossings_d8(code, blk)
-    _, ref_c = oracle.accumulate_single(code, None, z=z)
-    _, cnt, it = oracle.block_richardson(z, blk, oracle.D8, None, 0, split=1)
-    assert it == C + 1
-    assert np.array_equal(cnt, ref_c)
 
 
 # --------------------------------------------------------------------------
