@@ -56,7 +56,7 @@ Layout layout(int64_t nrows, int64_t ncols, int rule, int vdtype) {
 // it: the engine only runs once this path gave up (exit list overflow), and
 // then nothing reads this path's data any more.
 struct D8Layout {
-  size_t root_of, node_of, ex_cell, cnt0, cnt1, fx0, fx1, anc0, anc1, ctr, mass, total;
+  size_t root_of, node_of, ex_cell, cnt[3], fx[3], anc, loc, ctr, mass, total;
   uint32_t cap;
 };
 
@@ -72,9 +72,11 @@ uint32_t d8_capacity(int64_t n, int64_t ntiles) {
   return (uint32_t)((c > kFullCapacityCells ? c : kFullCapacityCells) + slack);
 }
 
-// th: tile height (the mass partials are per tile).  The local sums of
-// phase A (float-float or float64, 8 bytes per exit) live in the snapshot
-// buffer fx1 until the link step has turned them into fixed point.
+// th: tile height (the mass partials are per tile).  Per exit: its cell,
+// the sum and two buffers of pending additions (counts and 128-bit fixed
+// point), two pointers, and the local sum of phase A (float-float or
+// float64); the totals for phase C go into the two pointer buffers
+// (contiguous, 8 bytes per exit) once the rounds are over.
 D8Layout d8_layout(int64_t nrows, int64_t ncols, int th, int vdtype, bool counts) {
   D8Layout L{};
   const size_t n = (size_t)(nrows * ncols);
@@ -86,12 +88,16 @@ D8Layout d8_layout(int64_t nrows, int64_t ncols, int th, int vdtype, bool counts
   L.root_of = o; o += up(n * 4);
   L.node_of = o; o += up(n * 4);
   L.ex_cell = o; o += up(cap * 4);
-  L.cnt0 = o; if (counts) o += up(cap * 8);
-  L.cnt1 = o; if (counts) o += up(cap * 8);
-  L.fx0 = o; if (vals) o += up(cap * 16);
-  L.fx1 = o; if (vals) o += up(cap * 16);
-  L.anc0 = o; o += up(cap * 4);
-  L.anc1 = o; o += up(cap * 4);
+  for (int b = 0; b < 3; ++b) {
+    L.cnt[b] = o;
+    if (counts) o += up(cap * 8);
+  }
+  for (int b = 0; b < 3; ++b) {
+    L.fx[b] = o;
+    if (vals) o += up(cap * 16);
+  }
+  L.anc = o; o += up(cap * 8);
+  L.loc = o; if (vals) o += up(cap * 8);
   L.ctr = o; o += kAlign;
   L.mass = o; o += up(nt * 2 * sizeof(double));
   L.total = o;
@@ -241,15 +247,18 @@ D8Params d8_params(const uint8_t* code, int64_t nrows, int64_t ncols, int th, co
   P.root_of = reinterpret_cast<uint32_t*>(body + L.root_of);
   P.node_of = reinterpret_cast<uint32_t*>(body + L.node_of);
   P.ex_cell = reinterpret_cast<uint32_t*>(body + L.ex_cell);
-  P.ex_cnt[0] = reinterpret_cast<uint64_t*>(body + L.cnt0);
-  P.ex_cnt[1] = reinterpret_cast<uint64_t*>(body + L.cnt1);
-  P.ex_fx[0] = reinterpret_cast<unsigned __int128*>(body + L.fx0);
-  P.ex_fx[1] = reinterpret_cast<unsigned __int128*>(body + L.fx1);
-  P.ex_hi = reinterpret_cast<float*>(body + L.fx1);
+  for (int b = 0; b < 3; ++b) {
+    P.ex_cnt[b] = reinterpret_cast<uint64_t*>(body + L.cnt[b]);
+    P.ex_fx[b] = reinterpret_cast<unsigned __int128*>(body + L.fx[b]);
+  }
+  P.ex_hi = reinterpret_cast<float*>(body + L.loc);
   P.ex_lo = P.ex_hi + L.cap;
-  P.ex_d = reinterpret_cast<double*>(body + L.fx1);
-  P.anc[0] = reinterpret_cast<uint32_t*>(body + L.anc0);
-  P.anc[1] = reinterpret_cast<uint32_t*>(body + L.anc1);
+  P.ex_d = reinterpret_cast<double*>(body + L.loc);
+  P.anc[0] = reinterpret_cast<uint32_t*>(body + L.anc);
+  P.anc[1] = P.anc[0] + L.cap;
+  P.tot_hi = reinterpret_cast<float*>(body + L.anc);
+  P.tot_lo = P.tot_hi + L.cap;
+  P.tot_d = reinterpret_cast<double*>(body + L.anc);
   uint32_t* ctr = reinterpret_cast<uint32_t*>(body + L.ctr);
   P.n_exits = ctr;
   P.flags = reinterpret_cast<int32_t*>(ctr + 4);

@@ -1,47 +1,8 @@
-// Single-receiver (D8 / D4) accumulation by row sweeps plus a reduced exit
-// forest.
-//
-// The water at a cell is its rain plus the water of every cell upstream of it
-// (Section 2.1; the unique solution of (I - W^T) q = r, Section 2.2).  On
-// tilted terrain nearly every receiver lies in the previous row (row - 1), so
-// a sweep over the rows in decreasing index order visits donors before
-// receivers -- it is the paper's high-to-low order restricted to that edge
-// class, and like the paper's per-process solves (Section 2.4, Section 3.3)
-// the grid is cut into blocks whose solves are independent:
-//
-//   A. Each tile (th rows x 256 columns) is swept by one wavefront, four
-//      columns per lane.  Edges from row r+1 to row r inside the tile are
-//      followed in registers (cross-lane shifts); every other edge --
-//      leaving the tile, within a row, or toward a higher row index -- is
-//      "cut".  A top-down sweep yields each cut cell's (exit's) local
-//      upstream sum; a bottom-up sweep by a second wavefront of the same
-//      workgroup yields, for every cell that receives over a cut edge
-//      (inlet), the exit or sink where its in-tile path ends (its root).
-//   B. The exits form a forest: exit e drains into exit root(receiver(e)),
-//      or nowhere when that root is a sink.  Subtree sums over this forest are
-//      computed by pointer doubling in ceil(log2(depth)) rounds.  These stand
-//      in for the paper's C + 1 block iterations across block boundaries
-//      (Section 3.3, Appendix B), collapsed to a logarithmic number of rounds.
-//   C. Each tile is swept again with the totals of its cut donors added: the
-//      result is final.  The float64 mass balance is reduced in the same pass.
-//
-// Every kernel reads the exit count from device memory, and the pointer-
-// doubling rounds are a fixed sequence of launches that return at once when
-// there is nothing left to do, so a solve never waits for the host.  An exit
-// list that overflows its capacity opens the peeling engine's gate instead.
-//
-// Block iterations (the paper's I+X scheme, Section 3.3, Appendix B): with
-// blocks made of bt_r x bt_c tiles, the same three phases are the exact
-// block solve D^-1 -- the forest keeps only links inside a block, and water
-// from donors in other blocks enters as the previous iterate (R w).
-//
-// Numerics.  Float32 water uses float-float (hi, lo) sums in the sweeps.  The
-// forest adds exit sums as 128-bit integers in units of 2^E (E fixed per
-// call from the largest exit sum and the exit count, so no sum can
-// overflow); integer addition is exact and commutative, so the result does
-// not depend on the order in which the atomics land, and the totals go back
-// to float-float / float64 once, after the last round: every output is the
-// same, bit for bit, from run to run.  Counts are exact uint64.
+// Row-sweep single-receiver path: tiles, sweeps and helpers shared by the
+// phase A, phase B (forest) and phase C translation units.  See
+// fr_d8_a.hip for the method.
+#pragma once
+
 #include <math.h>
 
 #include <type_traits>
@@ -597,8 +558,8 @@ __device__ __forceinline__ void sweep(const D8Params& P, const Tile& T, SweepOut
                 set_status(P.status, FR_ERR_BADCODE);
                 continue;
               }
-              if (VK == VK_FF) nv[j].f = ff_add(nv[j].f, ff{P.ex_hi[nd], P.ex_lo[nd]});
-              if (VK == VK_F64) nv[j].d += P.ex_d[nd];
+              if (VK == VK_FF) nv[j].f = ff_add(nv[j].f, ff{P.tot_hi[nd], P.tot_lo[nd]});
+              if (VK == VK_F64) nv[j].d += P.tot_d[nd];
               if (CNT) nv[j].n += (CT)P.ex_cnt[0][nd];
             }
           }
@@ -893,255 +854,6 @@ __device__ __forceinline__ void root_sweep_interior(const D8Params& P, const Til
 }
 
 
-// ---------------------------------------------------------------------------
-// Phase A: one workgroup of two wavefronts per tile.  Wavefront 0 runs the
-// top-down local sweep (bound by HBM), wavefront 1 the bottom-up root sweep
-// (bound by its instruction count); neither reads what the other writes, so
-// they overlap on the compute unit.  The local sweep also reports the
-// largest |local sum| of its exits, which fixes the forest's fixed-point
-// unit.
-// The root sweep does not depend on the value kind or rain: one copy per
-// row alignment, called (not inlined) from every phase-A kernel.
-template <bool VEC>
-__device__ __attribute__((noinline)) void root_wave(const D8Params& P, const Tile& T) {
-  bool badcode = false;
-  if (T.border) root_sweep<VEC, true>(P, T, &badcode);
-  else root_sweep_interior<VEC>(P, T, &badcode);
-  if (badcode) set_status(P.status, FR_ERR_BADCODE);
-}
-
-template <int VK, bool CNT, int RAIN, bool VEC, bool ITER>
-__global__ __launch_bounds__(128) void k_d8_a(D8Params P) {
-  const Tile T = tile_of(P, blockIdx.x);
-  if (threadIdx.x >= 64) {
-    root_wave<VEC>(P, T);
-    return;
-  }
-  SweepOut o;
-  if (T.border) sweep<true, VK, CNT, RAIN, VEC, true, ITER>(P, T, o);
-  else sweep<true, VK, CNT, RAIN, VEC, false, ITER>(P, T, o);
-  if (o.nonfinite) set_status(P.status, FR_ERR_NONFINITE);
-  if (VK == VK_FF) {
-    float m = o.lmax_f;
-    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
-    if (threadIdx.x == 0 && m > 0.0f) atomicMax(&P.ctl->loc_max_f, __float_as_uint(m));
-  }
-  if (VK == VK_F64) {
-    double m = o.lmax_d;
-    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-    if (threadIdx.x == 0 && m > 0.0)
-      atomicMax(reinterpret_cast<unsigned long long*>(&P.ctl->loc_max_d), (unsigned long long)__double_as_longlong(m));
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Phase B: exit forest.  The link step turns each exit's local sum into
-// fixed point and points it at the exit its water reaches next (block
-// iterations: only inside its block).  An exit list that overflowed its
-// capacity opens the engine's gate instead (block iterations: an error).
-__device__ __forceinline__ int64_t blk_row(const D8Params& P, int64_t r) { return r / ((int64_t)P.th * P.bt_r); }
-__device__ __forceinline__ int64_t blk_col(const D8Params& P, int64_t c) { return c / ((int64_t)TW * P.bt_c); }
-
-template <int VK, bool ITER>
-__global__ __launch_bounds__(256) void k_d8_link(D8Params P) {
-  const uint32_t n = *P.n_exits;
-  if (n > P.cap) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      if (ITER) set_status(P.status, FR_ERR_CAPACITY);
-      else P.ctl->fallback = 1;
-    }
-    return;
-  }
-  const int E = VK != VK_NONE ? fx_exponent<VK>(P, n) : 0;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint32_t ec = P.ex_cell[i];
-    if (ec == NONE) {  // a hole of a phase-A chunk
-      P.anc[0][i] = NONE;
-      continue;
-    }
-    if (VK == VK_FF) P.ex_fx[0][i] = (u128)(fx_from(P.ex_hi[i], E) + fx_from(P.ex_lo[i], E));
-    if (VK == VK_F64) P.ex_fx[0][i] = (u128)fx_from(P.ex_d[i], E);
-    const int64_t e = ec;
-    const int cd = P.code[e];
-    const int64_t x = e + (int64_t)nb_dr(cd) * P.ncols + nb_dc(cd);
-    uint32_t a = NONE;
-    bool leave = false;
-    if (ITER) {
-      const int64_t er = e / P.ncols, xr = x / P.ncols;
-      leave = blk_row(P, er) != blk_row(P, xr) || blk_col(P, e - er * P.ncols) != blk_col(P, x - xr * P.ncols);
-    }
-    const int64_t rt = leave ? -1 : (int64_t)P.root_of[x];
-    if (leave) {
-      // Water leaving the block: passed on by the next iteration.
-    } else if (rt >= 0 && rt < P.nrows * P.ncols) {
-      const int64_t rr = rt / P.ncols, rc = rt - rr * P.ncols;
-      const int rcd = P.code[rt];
-      bool sink = rcd > 7;
-      if (!sink) {
-        const int64_t tr = rr + nb_dr(rcd), tc = rc + nb_dc(rcd);
-        sink = tr < 0 || tr >= P.nrows || tc < 0 || tc >= P.ncols;
-      }
-      if (!sink) {
-        a = P.node_of[rt];
-        if (a >= n) {  // inconsistent bookkeeping: never follow it
-          a = NONE;
-          set_status(P.status, FR_ERR_BADCODE);
-        }
-      }
-    } else {
-      set_status(P.status, FR_ERR_BADCODE);
-    }
-    P.anc[0][i] = a;
-  }
-}
-
-// Round j sets flag slot j mod 3 when it leaves work for round j + 1, and
-// skips itself when round j - 1 left none; round j's scatter clears slot
-// j + 1.  The rounds are a fixed sequence of launches, so after the last one
-// with work every later one returns at once.
-__device__ __forceinline__ int32_t* round_flag(const D8Params& P, int j) { return &P.flags[4 + j % 3]; }
-__device__ __forceinline__ bool round_idle(const D8Params& P, int j) {
-  return j > 0 && __hip_atomic_load(round_flag(P, j + 2), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
-}
-
-// Round j of pointer doubling (anc[b] = ancestor 2^j exits down, or NONE).
-// Part 1: every exit that still has such an ancestor snapshots its sum (the
-// sum over its subtree within distance < 2^j) and jumps its pointer.
-template <int VK, bool CNT>
-__global__ __launch_bounds__(256) void k_d8_copy(D8Params P, int b, int j) {
-  const uint32_t n = *P.n_exits;
-  if (n > P.cap || round_idle(P, j)) return;  // uniform
-  __shared__ int s_active;
-  if (threadIdx.x == 0) s_active = 0;
-  __syncthreads();
-  bool active = false;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint32_t a = P.anc[b][i];
-    uint32_t a2 = NONE;
-    if (a != NONE) {
-      if (VK != VK_NONE) P.ex_fx[1][i] = P.ex_fx[0][i];
-      if (CNT) P.ex_cnt[1][i] = P.ex_cnt[0][i];
-      a2 = P.anc[b][a];
-    }
-    P.anc[b ^ 1][i] = a2;
-    active |= (a2 != NONE);
-  }
-  // One store per workgroup, and only while the flag is still clear: an
-  // atomic from every wavefront on one word serialises the whole kernel.
-  if (__ballot(active) && (threadIdx.x & 63) == 0) s_active = 1;
-  __syncthreads();
-  if (threadIdx.x == 0 && s_active) {
-    // Work left after the last round: deeper than any forest can be.
-    if (j == D8_ROUNDS - 1) set_status(P.status, FR_ERR_NOTDAG);
-    else if (__hip_atomic_load(round_flag(P, j), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-      __hip_atomic_store(round_flag(P, j), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
-// Part 2: each such exit adds its snapshot to the ancestor's sum in place
-// (exact integer additions: the result does not depend on their order).
-template <int VK, bool CNT>
-__global__ __launch_bounds__(256) void k_d8_scatter(D8Params P, int b, int j) {
-  if (blockIdx.x == 0 && threadIdx.x == 0)
-    __hip_atomic_store(round_flag(P, j + 1), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const uint32_t n = *P.n_exits;
-  if (n > P.cap || round_idle(P, j)) return;  // uniform
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint32_t a = P.anc[b][i];
-    if (a == NONE) continue;
-    if (VK != VK_NONE) atomic_add_fx(&P.ex_fx[0][a], P.ex_fx[1][i]);
-    if (CNT) atomicAdd(reinterpret_cast<unsigned long long*>(&P.ex_cnt[0][a]), (unsigned long long)P.ex_cnt[1][i]);
-  }
-}
-
-// After the last round: the totals back from fixed point into float-float
-// or float64 (into the snapshot buffer's memory, free again), where phase C
-// reads them.
-template <int VK>
-__global__ __launch_bounds__(256) void k_d8_totals(D8Params P) {
-  const uint32_t n = *P.n_exits;
-  if (n > P.cap) return;  // uniform
-  const int E = fx_exponent<VK>(P, n);
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    if (P.ex_cell[i] == NONE) continue;
-    const i128 v = (i128)P.ex_fx[0][i];
-    if (VK == VK_FF) {
-      const ff t = fx_to_ff(v, E);
-      P.ex_hi[i] = t.hi;
-      P.ex_lo[i] = t.lo;
-    } else {
-      P.ex_d[i] = fx_to_double(v, E);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Phase C (and the block solve's final sweep).  Returns at once when the
-// exit list overflowed: the engine, or an error, takes over.
-template <int VK, bool CNT, int RAIN, bool VEC, bool ITER>
-__global__ __launch_bounds__(64) void k_d8_c(D8Params P) {
-  __shared__ double s_mass[2][64];
-  // Row exchange for grids whose rows are not aligned to 4 cells.
-  __shared__ float s_q32[VEC || VK != VK_FF ? 1 : TW];
-  __shared__ double s_q64[VEC || VK != VK_F64 ? 1 : TW];
-  __shared__ uint64_t s_cnt[VEC || !CNT ? 1 : TW];
-  if (*P.n_exits > P.cap) return;  // uniform
-  const int lane = threadIdx.x;
-  const Tile T = tile_of(P, blockIdx.x);
-  SweepOut o;
-  if (T.border) sweep<false, VK, CNT, RAIN, VEC, true, ITER>(P, T, o, s_q32, s_q64, s_cnt);
-  else sweep<false, VK, CNT, RAIN, VEC, false, ITER>(P, T, o, s_q32, s_q64, s_cnt);
-  if (ITER) {
-    if (__ballot(o.changed) && lane == 0 && P.it_changed) *P.it_changed = 1;
-    if (o.badcode) set_status(P.status, FR_ERR_BADCODE);
-    if (o.nonfinite) set_status(P.status, FR_ERR_NONFINITE);
-  } else if (P.mass_part) {
-    s_mass[0][lane] = o.mass[0];
-    s_mass[1][lane] = o.mass[1];
-    __syncthreads();
-    if (lane == 0) {
-      double a = 0.0, b = 0.0;
-      for (int l = 0; l < 64; ++l) {
-        a += s_mass[0][l];
-        b += s_mass[1][l];
-      }
-      // Indexed by workgroup: the final reduction runs in one fixed order.
-      P.mass_part[2 * blockIdx.x] = a;
-      P.mass_part[2 * blockIdx.x + 1] = b;
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void k_bi_combine(int mode, int64_t n, const double* bq, const uint64_t* bc,
-                                                    const double* wq, const uint64_t* wc, double* tq,
-                                                    uint64_t* tc, double* oq, uint64_t* oc, int32_t* changed) {
-  bool chg = false;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    if (mode == 0) {
-      if (tq) tq[i] = bq[i] - wq[i] + tq[i];
-      if (tc) tc[i] = bc[i] - wc[i] + tc[i];
-    } else if (mode == 1) {
-      if (oq) oq[i] = wq[i] + tq[i] + oq[i];
-      if (oc) {
-        const uint64_t v = wc[i] + tc[i] + oc[i];
-        oc[i] = v;
-        chg |= v != wc[i];
-      }
-    } else {
-      if (oq) oq[i] = 0.0;
-      if (oc) oc[i] = 0;
-    }
-  }
-  if (mode == 1 && __ballot(chg) && (threadIdx.x & 63) == 0 && changed && *(volatile int32_t*)changed == 0)
-    *changed = 1;
-}
-
-// Workgroups of the forest kernels: enough for the exits of a large grid,
-// few enough that a launch with nothing to do costs little.
-unsigned forest_grid(uint32_t cap) {
-  const uint32_t b = (cap + 255) / 256;
-  return b < 1 ? 1u : (b > 2048 ? 2048u : b);
-}
 
 }  // namespace
 
@@ -1189,70 +901,6 @@ hipError_t d8_sweep_dispatch(ValKind vk, bool cnt, bool iter, const D8Params& P,
   } else {
     d8_sweep_launch<K, VK_NONE, true, false>(P, s);
   }
-  return hipGetLastError();
-}
-
-template <int VK, bool CNT, int RAIN, bool VEC, bool ITER>
-struct KernelA {
-  static void launch(const D8Params& P, hipStream_t s) {
-    hipLaunchKernelGGL((k_d8_a<VK, CNT, RAIN, VEC, ITER>), dim3((unsigned)((int64_t)P.ntr * P.ntc)), dim3(128), 0,
-                       s, P);
-  }
-};
-template <int VK, bool CNT, int RAIN, bool VEC, bool ITER>
-struct KernelC {
-  static void launch(const D8Params& P, hipStream_t s) {
-    hipLaunchKernelGGL((k_d8_c<VK, CNT, RAIN, VEC, ITER>), dim3((unsigned)((int64_t)P.ntr * P.ntc)), dim3(64), 0,
-                       s, P);
-  }
-};
-
-hipError_t launch_d8_up(ValKind vk, bool cnt, bool iter, const D8Params& P, hipStream_t s) {
-  return d8_sweep_dispatch<KernelA>(vk, cnt, iter, P, s);
-}
-
-hipError_t launch_d8_down(ValKind vk, bool cnt, bool iter, const D8Params& P, hipStream_t s) {
-  return d8_sweep_dispatch<KernelC>(vk, cnt, iter, P, s);
-}
-
-template <int VK, bool CNT>
-void forest_rounds(const D8Params& P, dim3 g, hipStream_t s) {
-  for (int j = 0; j < D8_ROUNDS; ++j) {
-    hipLaunchKernelGGL((k_d8_copy<VK, CNT>), g, dim3(256), 0, s, P, j & 1, j);
-    hipLaunchKernelGGL((k_d8_scatter<VK, CNT>), g, dim3(256), 0, s, P, j & 1, j);
-  }
-}
-
-hipError_t launch_d8_forest(ValKind vk, bool cnt, bool iter, const D8Params& P, hipStream_t s) {
-  const dim3 g(forest_grid(P.cap)), b(256);
-  if (vk == VK_FF) {
-    if (iter) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_d8_link<VK_FF, false>), g, b, 0, s, P);
-    if (cnt) forest_rounds<VK_FF, true>(P, g, s);
-    else forest_rounds<VK_FF, false>(P, g, s);
-    hipLaunchKernelGGL((k_d8_totals<VK_FF>), g, b, 0, s, P);
-  } else if (vk == VK_F64) {
-    if (iter) hipLaunchKernelGGL((k_d8_link<VK_F64, true>), g, b, 0, s, P);
-    else hipLaunchKernelGGL((k_d8_link<VK_F64, false>), g, b, 0, s, P);
-    if (cnt) forest_rounds<VK_F64, true>(P, g, s);
-    else forest_rounds<VK_F64, false>(P, g, s);
-    hipLaunchKernelGGL((k_d8_totals<VK_F64>), g, b, 0, s, P);
-  } else {
-    if (iter) hipLaunchKernelGGL((k_d8_link<VK_NONE, true>), g, b, 0, s, P);
-    else hipLaunchKernelGGL((k_d8_link<VK_NONE, false>), g, b, 0, s, P);
-    forest_rounds<VK_NONE, true>(P, g, s);
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_bi_combine(int mode, int64_t n, const double* bq, const uint64_t* bc, const double* wq,
-                             const uint64_t* wc, double* tq, uint64_t* tc, double* oq, uint64_t* oc,
-                             int32_t* changed, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_bi_combine, dim3((unsigned)blocks), dim3(256), 0, s, mode, n, bq, bc, wq, wc, tq, tc, oq,
-                     oc, changed);
   return hipGetLastError();
 }
 

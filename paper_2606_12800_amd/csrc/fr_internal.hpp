@@ -95,6 +95,7 @@ struct CallCtl {
   int64_t sweep_remaining;   // cells not yet final
   uint64_t loc_max_d;        // D8 forest: largest |local sum| of an exit, float64 bits
   unsigned long long bar;    // persistent engine: grid barrier arrivals
+  int32_t forest_final;      // D8 forest: the pending-additions buffer of the last round
 };
 static_assert(sizeof(CallCtl) <= 256, "control block fits its 256-byte slot");
 constexpr int CTL_WORDS = 64;  // 32-bit words zeroed at the start of a call
@@ -115,8 +116,11 @@ struct D8Params {
   float* ex_hi;                // local (in-tile) sums of the exits: float-float
   float* ex_lo;
   double* ex_d;                // float64
-  uint64_t* ex_cnt[2];         // exit counts [0] and snapshots [1] for pointer doubling
-  unsigned __int128* ex_fx[2]; // exit water as 128-bit fixed point (unit 2^E), sums and snapshots
+  uint64_t* ex_cnt[3];         // exit counts: sums [0], additions pending [1], [2]
+  unsigned __int128* ex_fx[3]; // exit water as 128-bit fixed point (unit 2^E), likewise
+  float* tot_hi;               // forest totals for phase C: float-float
+  float* tot_lo;
+  double* tot_d;               // float64
   uint32_t* anc[2];
   uint32_t* n_exits;           // exit counter
   uint32_t cap;
@@ -141,15 +145,12 @@ struct D8Params {
 // take at most their number plus D8_EXIT_CHUNK slots.
 constexpr uint32_t D8_EXIT_CHUNK = 32;
 
-// Pointer-doubling rounds enqueued per solve: a forest of at most 2^31 - 1
-// exits is at most that deep, which 32 doublings cover; round 32 finding
-// work left proves a cycle.
-constexpr int D8_ROUNDS = 33;
 
 // Launchers (defined in the .hip files).
-// Phase A (local sums and roots), phase B (exit forest: link, then
-// D8_ROUNDS pointer-doubling rounds, each a no-op once the forest is done or
-// when the exit list overflowed), phase C (final sweep).  `iter`: the block
+// Phase A (local sums and roots), phase B (exit forest: link, then enough
+// pointer-doubling rounds for a forest of P.cap exits -- each a no-op once
+// the forest is done or when the exit list overflowed -- then the totals),
+// phase C (final sweep).  `iter`: the block
 // iteration variants (blocks of P.bt_r x P.bt_c tiles).
 hipError_t launch_d8_up(ValKind vk, bool cnt, bool iter, const D8Params& P, hipStream_t s);
 hipError_t launch_d8_forest(ValKind vk, bool cnt, bool iter, const D8Params& P, hipStream_t s);
