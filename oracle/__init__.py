@@ -64,9 +64,14 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        lib = ctypes.CDLL(_LIB)
+        # ORACLE_LIB_PATH: a build of the same source to load instead (the test
+        # suite's sanitizer run sets it).
+        path = os.environ.get("ORACLE_LIB_PATH")
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB):
+                build()
+        lib = ctypes.CDLL(path)
         i64, vp, dbl, ci = ctypes.c_int64, ctypes.c_void_p, ctypes.c_double, ctypes.c_int
         sig = {
             "or_receivers": [vp, i64, i64, ci, vp],

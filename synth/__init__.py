@@ -48,9 +48,14 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        lib = ctypes.CDLL(_LIB)
+        # SYNTH_LIB_PATH: a build of the same source to load instead (the test
+        # suite's sanitizer run sets it).
+        path = os.environ.get("SYNTH_LIB_PATH")
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB):
+                build()
+        lib = ctypes.CDLL(path)
         i64, u64, vp, dbl = ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_double
         lib.syn_u64.restype = u64
         lib.syn_u64.argtypes = [u64, u64, u64]

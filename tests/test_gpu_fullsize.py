@@ -3,16 +3,24 @@
 paper's own grid shape, 57,345 x 32,769 (Section 4; rows not 4-cell
 aligned, so the unaligned load and store variants run).
 
-The oracle cannot route 1.88e9 cells within a test, so the checks are
-(a) receivers bit-exact against the oracle on sampled row bands (a cell's
-    receiver depends only on its 3x3 neighbourhood, so the oracle routes a
-    3-row slab and its middle row is exact);
+The oracle cannot run its sequential push over 1.88e9 cells within a test,
+so the checks are
+(a) receivers bit-exact against the oracle on every row, band by band (a
+    cell's receiver depends only on its 3x3 neighbourhood, so a band plus
+    one row on each side gives the band's receivers exactly);
 (b) properties that hold at any size and, together, determine the solution:
     every cell's count equals 1 + the counts of its donors (the local
-    balance of (I - W^T) q = r, Section 2.2), the same for the float32
-    water within float tolerance, all cells drain to sinks (sum over sinks =
-    N), and the float64 mass balance of Section 4.
+    balance of (I - W^T) q = r, Section 2.2), all cells drain to sinks (sum
+    over sinks = N), and the float64 mass balance of Section 4;
+(c) the float64 route satisfies the local balance to 1e-12 at every cell.
+    Errors in a triangular system with weights summing to one add up along
+    flow paths, so the float64 water is the exact solution to within
+    1e-12 x (path length) relative -- a few 1e-8 here -- and serves as the
+    reference for the float32 water, gated per cell at 1e-6;
+(d) a second route of the same grid gives the same bits.
 """
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 import torch
@@ -45,17 +53,87 @@ def routed(request):
     torch.cuda.empty_cache()
 
 
-def test_fullsize_receivers_sampled_rows(routed):
+def test_fullsize_receivers_every_row(routed):
     z_h, _, _, _, code, _, _, _ = routed
     N = z_h.shape[0]
-    rows = sorted(set([0, 1, N // 2, N - 2, N - 1] + synth.integers(8, synth.STREAM_PICK, 20, 1, N - 2).tolist()))
-    for r in rows:
-        lo, hi = max(r - 1, 0), min(r + 2, N)
-        ref = oracle.receivers(z_h[lo:hi])[r - lo]
-        got = code[r].cpu().numpy()
-        # The slab has no rows beyond it; only its middle row (or a grid
-        # border row) sees its full neighbourhood.
-        assert np.array_equal(got, ref), r
+    band = 2048
+    starts = list(range(0, N, band))
+
+    def oracle_band(r0):
+        r1 = min(r0 + band, N)
+        lo, hi = max(r0 - 1, 0), min(r1 + 1, N)
+        return r0, oracle.receivers(z_h[lo:hi])[r0 - lo:r0 - lo + (r1 - r0)]
+
+    # The oracle's C routine releases the interpreter lock: bands in parallel.
+    print(f"receivers: oracle on {len(starts)} bands", flush=True)
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        for r0, ref in ex.map(oracle_band, starts):
+            got = code[r0:r0 + ref.shape[0]].cpu().numpy()
+            assert np.array_equal(got, ref), r0
+
+
+def _local_balance(code, q, src, band=4096):
+    """Largest relative residual |q - src - sum of donors' q| / q over the
+    grid, band by band, in float64 (q: float64 or counts)."""
+    N, NC = code.shape
+    worst = 0.0
+    for r0 in range(0, N, band):
+        r1 = min(r0 + band, N)
+        a, b = max(r0 - 1, 0), min(r1 + 1, N)
+        band_code, band_q = code[a:b], q[a:b].double()
+        out = torch.zeros_like(band_q)
+        n_r = b - a
+        for k, (dr, dc) in enumerate(OFFS):
+            src_r = slice(max(-dr, 0), n_r - max(dr, 0))
+            dst_r = slice(max(dr, 0), n_r - max(-dr, 0))
+            src_c = slice(max(-dc, 0), NC - max(dc, 0))
+            dst_c = slice(max(dc, 0), NC - max(-dc, 0))
+            m = band_code[src_r, src_c] == k
+            out[dst_r, dst_c] += torch.where(m, band_q[src_r, src_c],
+                                             torch.zeros((), dtype=torch.float64, device=q.device))
+        inner = slice(r0 - a, r0 - a + (r1 - r0))
+        expect = out[inner] + src(r0, r1)
+        # (a cell with zero rain and no donors holds exactly zero)
+        rel = ((band_q[inner] - expect).abs() / expect.clamp(min=1e-300)).max().item()
+        worst = max(worst, rel)
+        del out, band_q
+    return worst
+
+
+def test_fullsize_float64_reference_and_float32_per_cell(routed):
+    _, _, _, rain, code, q, _, _ = routed
+    N, NC = code.shape
+    print("routing float64", flush=True)
+    q64, _, m64 = fr.accumulate(code, None, rain, "d8", torch.float64, mass=True)
+    torch.cuda.synchronize()
+    res = _local_balance(code, q64, lambda r0, r1: rain[r0:r1].double())
+    print(f"  float64 local balance (relative, max) {res:.3e}", flush=True)
+    assert res <= 1e-12
+    s, t = m64.cpu().tolist()
+    assert abs(s - t) <= 1e-11 * t
+    emax, num, den = 0.0, 0.0, 0.0
+    for r0 in range(0, N, 4096):
+        r1 = min(r0 + 4096, N)
+        d = q[r0:r1].double() - q64[r0:r1]
+        emax = max(emax, (d.abs() / q64[r0:r1].clamp(min=1e-300)).max().item())
+        num += float((d * d).sum().item())
+        den += float((q64[r0:r1] * q64[r0:r1]).sum().item())
+    print(f"  float32 vs float64: max per cell {emax:.3e}, 2-norm {(num / den) ** 0.5:.3e}", flush=True)
+    assert emax <= 1e-6
+    del q64
+    fr._default_ws.buf = None
+    torch.cuda.empty_cache()
+
+
+def test_fullsize_route_repeats_bit_for_bit(routed):
+    _, _, _, rain, code, q, cnt, mass = routed
+    q2, c2, m2 = fr.accumulate(code, None, rain, "d8", torch.float32, counts=True, mass=True)
+    torch.cuda.synchronize()
+    assert torch.equal(q2.view(torch.int32), q.view(torch.int32))
+    assert torch.equal(c2, cnt)
+    assert torch.equal(m2.view(torch.int64), mass.view(torch.int64))
+    del q2, c2
+    torch.cuda.empty_cache()
 
 
 def test_fullsize_counts_local_balance_and_sinks(routed):
@@ -82,26 +160,9 @@ def test_fullsize_counts_local_balance_and_sinks(routed):
 
 def test_fullsize_water_local_balance_and_mass(routed):
     _, rain_h, _, rain, code, q, _, mass = routed
-    N, NC = code.shape
-    for r0 in range(0, N, 4096):
-        r1 = min(r0 + 4096, N)
-        a, b = max(r0 - 1, 0), min(r1 + 1, N)
-        band_code, band_q = code[a:b], q[a:b].double()
-        out = torch.zeros_like(band_q)
-        n_r = b - a
-        for k, (dr, dc) in enumerate(OFFS):
-            src_r = slice(max(-dr, 0), n_r - max(dr, 0))
-            dst_r = slice(max(dr, 0), n_r - max(-dr, 0))
-            src_c = slice(max(-dc, 0), NC - max(dc, 0))
-            dst_c = slice(max(dc, 0), NC - max(-dc, 0))
-            m = band_code[src_r, src_c] == k
-            out[dst_r, dst_c] += torch.where(m, band_q[src_r, src_c], torch.zeros((), dtype=torch.float64, device=q.device))
-        inner = slice(r0 - a, r0 - a + (r1 - r0))
-        expect = out[inner] + rain[r0:r1].double()
-        # (a cell with zero rain and no donors holds exactly zero)
-        rel = ((band_q[inner] - expect).abs() / expect.clamp(min=1e-30)).max().item()
-        # q is float32 rounded from a float-float value; its donors are too.
-        assert rel <= 1e-6, (r0, r1, rel)
+    # q is float32 rounded from a float-float value; its donors are too.
+    res = _local_balance(code, q, lambda r0, r1: rain[r0:r1].double())
+    assert res <= 1e-6
     s, t = mass.cpu().numpy()
     assert abs(s - t) <= 1e-6 * t
     assert t == pytest.approx(float(rain_h.astype(np.float64).sum()), rel=1e-12)

@@ -95,8 +95,12 @@ def test_mfd_config_local_balance_float64(routed):
 def test_mfd_config_float32_and_mass(routed):
     _, q32, q64, m32, m64 = routed
     e = (torch.linalg.vector_norm(q32.double() - q64) / torch.linalg.vector_norm(q64)).item()
-    print(f"  float32 vs float64: relative 2-norm {e:.3e}")
+    emax = ((q32.double() - q64).abs() / q64).max().item()
+    print(f"  float32 vs float64: relative 2-norm {e:.3e}, max per cell {emax:.3e}")
     assert e <= 1e-6
+    # Per cell: the float32 fractions (a few ulp each) compound along flow
+    # paths of ~16k cells; reported, and held to 1e-5.
+    assert emax <= 1e-5
     s64, t64 = m64.cpu().tolist()
     s32, t32 = m32.cpu().tolist()
     assert t64 == float(N * N) and t32 == float(N * N)
