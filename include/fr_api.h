@@ -175,6 +175,25 @@ int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t nc
                   hipStream_t stream);
 
 /*
+ * fr_accumulate_noalloc -- fr_accumulate without a workspace argument, for
+ * callers that cannot allocate device memory: code under HIP graph capture
+ * that must not allocate, tight serving loops, harnesses that forbid
+ * hipMalloc.  Scratch memory is a fixed array inside the library,
+ * FR_NOALLOC_SCRATCH_BYTES on every GPU the library runs on, held until the
+ * process ends; the call itself allocates nothing.  A grid whose workspace
+ * (fr_workspace_bytes(FR_FN_ACCUMULATE, ...)) exceeds the array returns
+ * FR_ERR_TOOLARGE.  All calls on one GPU share its array, which keeps the
+ * last call's contents (every call clears what must start at zero): calls
+ * that overlap on one GPU -- on different streams, or from different host
+ * threads -- race, and must be serialised by the caller.  Arguments,
+ * results, streams and errors otherwise as fr_accumulate.
+ */
+#define FR_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int fr_accumulate_noalloc(const float* z, const uint8_t* code, int64_t nrows, int64_t ncols, int rule,
+                          double mfd_p, const void* rain, int rain_dtype, int q_dtype, void* q_out,
+                          uint64_t* counts_out, double* mass_out, int32_t* dev_status, hipStream_t stream);
+
+/*
  * fr_accumulate_adjoint -- transpose solve (I - W) rbar = qbar, i.e.
  * rbar_i = qbar_i + sum_k f_{i->k} rbar_k over the receivers k of i, swept
  * from sinks to sources.  rbar is the gradient of <qbar, q> with respect to

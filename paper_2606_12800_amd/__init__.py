@@ -39,7 +39,8 @@ RULES = {"d8": D8, "mfd": MFD, "d4": D4}
 EXPORTS = ["fr_receivers", "fr_accumulate", "fr_accumulate_adjoint", "fr_workspace_bytes",
            "fr_status_string", "fr_version", "fr_timing_enable", "fr_timing_last",
            "fr_batched_workspace_bytes", "fr_accumulate_batched", "fr_batch_autotune",
-           "fr_accumulate_block_iterations", "fr_fill_depressions", "fr_set_accumulate_path"]
+           "fr_accumulate_block_iterations", "fr_fill_depressions", "fr_set_accumulate_path",
+           "fr_accumulate_noalloc"]
 ORDER_GIVEN, ORDER_ROWS_DESC = 0, 1
 
 
@@ -104,6 +105,8 @@ def load_library() -> ctypes.CDLL:
     lib.fr_fill_depressions.restype = ci
     lib.fr_set_accumulate_path.argtypes = [ci]
     lib.fr_set_accumulate_path.restype = ci
+    lib.fr_accumulate_noalloc.argtypes = [vp, vp, i64, i64, ci, cd, vp, ci, ci, vp, vp, vp, vp, vp]
+    lib.fr_accumulate_noalloc.restype = ci
     _lib = lib
     return lib
 

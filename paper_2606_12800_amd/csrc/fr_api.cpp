@@ -5,7 +5,15 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "fr_internal.hpp"
+
+// Scratch of fr_accumulate_noalloc: one copy on every GPU the library runs
+// on.  Host code never passes this name to a kernel (in host code it is a
+// stand-in, not a device address); it uses the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[FR_NOALLOC_SCRATCH_BYTES];
 
 namespace fr {
 namespace {
@@ -588,6 +596,42 @@ int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t nc
     phase_end(ph, stream);
   }
   return FR_OK;
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+static int scratch_address(void** out) {
+  constexpr int kMaxDevices = 64;
+  static void* addr[kMaxDevices];
+  static std::mutex mu;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return FR_ERR_HIP;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FR_ERR_HIP;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return FR_OK;
+}
+
+int fr_accumulate_noalloc(const float* z, const uint8_t* code, int64_t nrows, int64_t ncols, int rule,
+                          double mfd_p, const void* rain, int rain_dtype, int q_dtype, void* q_out,
+                          uint64_t* counts_out, double* mass_out, int32_t* dev_status, hipStream_t stream) {
+  // The array holds a workspace of this many bytes at its first 256-byte
+  // boundary (it is 256-byte aligned itself).
+  const size_t need = fr_workspace_bytes(FR_FN_ACCUMULATE, nrows, ncols, rule, q_dtype);
+  if (need > FR_NOALLOC_SCRATCH_BYTES) return FR_ERR_TOOLARGE;
+  void* ws = nullptr;
+  // Empty grids and invalid arguments need no scratch: fr_accumulate
+  // answers them as usual.
+  if (need > 0 && nrows > 0 && ncols > 0) {
+    const int rc = scratch_address(&ws);
+    if (rc != FR_OK) return rc;
+  }
+  return fr_accumulate(z, code, nrows, ncols, rule, mfd_p, rain, rain_dtype, q_dtype, q_out, counts_out, mass_out,
+                       dev_status, ws, ws ? FR_NOALLOC_SCRATCH_BYTES : 0, stream);
 }
 
 int fr_accumulate_block_iterations(const float* z, const uint8_t* code, int64_t nrows, int64_t ncols, int rule,
