@@ -28,19 +28,14 @@ PHASE_BYTES = {
     "d8_up": 1 + 1 + 4,        # phase A: code (root sweep), code + rain (local sweep); exits are sparse
     "d8_down": 1 + 4 + 4 + 8,  # code, rain read; q (f32), counts (u64) written
 }
-PHASE_KERNEL = {"receivers": "k_receivers", "d8_up": "k_d8_root + k_d8_up", "d8_down": "k_d8_down"}
+PHASE_KERNEL = {"receivers": "k_receivers", "d8_up": "k_d8_a (root + local sweep)", "d8_down": "k_d8_c"}
 ACC_BYTES = 1 + 4 + 4 + 8     # whole accumulate call: code, rain in; q, counts out
-# HBM bytes per launch of these phases at the 43360^2 workload,
-# from rocprofv3 FETCH_SIZE / WRITE_SIZE runs calibrated against a 1 GiB
-# device copy (profiles/d8_43360_hbm_traffic.md).  They describe the kernels
-# as they were when counted; other sizes report null.
-MEASURED_TRAFFIC = {
-    ("d8", 43360, 43360): {"receivers": 10.63e9, "d8_up": 2.06e9 + 9.80e9, "d8_down": 33.18e9},
-    ("mfd", 16384, 16384): {"sweep": 9.70e9},       # float32 sweep (profiles/sweep_and_batch_hbm_traffic.md)
-    ("adjoint", 4096, 4096): {"sweep": 0.705e9},
-    ("batched", 512): {"batch": 24.70e9},
-    ("fill", 16384, 16384): {"fill": 37.79e9 + 2.15e9},  # whole fill (profiles/fill_16384_kernel_stats.md)
-}
+ROUTE_BYTES = 4 + 1 + ACC_BYTES  # whole route: receivers (z in, code out) + accumulate
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs calibrated
+# against a device copy, keyed by workload and phase, with the summary they
+# come from.  Only counters taken on the kernels as they are now are listed;
+# a phase without one reports traffic null.
+MEASURED_TRAFFIC = {}
 # Algorithmic bytes per cell of the secondary workloads' dominant kernel
 # (arrays visible at the C ABI, each touched once): MFD float32 sweep z 4 +
 # mask 1 + q 4; adjoint z 4 + mask 1 + qbar 4 + rbar 4; batched D8 tiles z 4 +
@@ -49,6 +44,23 @@ SWEEP_BYTES = {"mfd": 4 + 1 + 4, "adjoint": 4 + 1 + 4 + 4}
 # Depression filling, algorithmic bytes per cell: elevation read, filled
 # surface written.
 FILL_BYTES = 4 + 4
+METRIC = "cells routed/sec (D8 & MFD) at 1 MI355X; % HBM peak; batched vs per-tile"
+
+
+def traffic(key, phase):
+    """(bytes per launch, profile summary) of a counted phase, or (None, None)."""
+    t = MEASURED_TRAFFIC.get(key, {}).get(phase)
+    return (t[0], t[1]) if t else (None, None)
+
+
+def roofline(achieved_gbs, kernel, key, phase, **extra):
+    tb, src = traffic(key, phase)
+    r = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": tb, "kernel": kernel}
+    if src:
+        r["traffic_source"] = src
+    r.update(extra)
+    return r
 
 
 def log(msg):
@@ -165,7 +177,7 @@ def run_secondary(args, workload):
         torch.cuda.empty_cache()
         log(f"  {name}: {1e3 * t:.2f} ms per step")
     line = {
-        "metric": "cells routed/sec (D8 & MFD) at 1 MI355X; % HBM peak; batched vs per-tile",
+        "metric": METRIC,
         "value": out["f32"]["cells_per_s"], "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": out["f32"]["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -178,11 +190,8 @@ def run_secondary(args, workload):
     # roofline below states how far from the HBM bound that leaves it.
     ms = out["f32"]["phase_ms"].get("sweep", out["f32"]["ms_per_step"])
     achieved = SWEEP_BYTES[workload] * n * n / (ms * 1e-3) / 1e9
-    line["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS,
-                        "traffic": MEASURED_TRAFFIC.get((workload, n, n), {}).get("sweep"),
-                        "kernel": "k_ws_pass", "bytes_per_cell": SWEEP_BYTES[workload], "ms_per_launch": ms,
-                        "row_step_us": 1e3 * ms / n}
+    line["roofline"] = roofline(achieved, "k_ws_pass (all passes)", (workload, n, n), "sweep",
+                                bytes_per_cell=SWEEP_BYTES[workload], ms_per_launch=ms, row_step_us=1e3 * ms / n)
     if not args.no_cpu_baseline:
         # MFD: an 8192^2 sample (~15 s on one core); adjoint: the whole 4096^2 workload.
         size = args.cpu_size if "--cpu-size" in sys.argv else (8192 if workload == "mfd" else n)
@@ -190,7 +199,7 @@ def run_secondary(args, workload):
         del z, code
         torch.cuda.empty_cache()
         line["cpu_baseline"] = cpu_baseline_mfd(size, seed, workload == "adjoint")
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def run_fill(args):
@@ -235,17 +244,14 @@ def run_fill(args):
     achieved = FILL_BYTES * ncell / (ms * 1e-3) / 1e9
     log(f"  fill: {1e3 * t_fill:.2f} ms per step ({launches.value} launches, {100 * raised:.2f}% cells raised)")
     line = {
-        "metric": "cells routed/sec (D8 & MFD) at 1 MI355X; % HBM peak; batched vs per-tile",
+        "metric": METRIC,
         "value": ncell / t_fill, "unit": "cells/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * t_fill, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"depression filling (epsilon, 8 neighbours) of the {nr}x{nc} untilted fractal "
                                f"DEM (seed {args.seed})", "cells": ncell},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": MEASURED_TRAFFIC.get(("fill", nr, nc), {}).get("fill"),
-                     "kernel": "k_fill_tile (all launches)",
-                     "bytes_per_cell": FILL_BYTES, "ms_per_launch": ms},
+        "roofline": roofline(achieved, "k_fill_tile (all launches)", ("fill", nr, nc), "fill",
+                             bytes_per_cell=FILL_BYTES, ms_per_launch=ms),
         "detail": {"launches": launches.value, "fraction_raised": raised, "device_ms": ms},
     }
     if not args.no_cpu_baseline:
@@ -268,7 +274,8 @@ def run_batched(args):
     """512 independent tiles, sides uniform in [64, 2048] (seed 4), tile i's DEM
     from seed 1000 + i; even tiles D8 with uint64 counts, odd tiles MFD with
     float32 water, unit rain.  Times the batched float32 route (one persistent
-    launch, autotuned schedule) against per-tile float64 launches."""
+    launch, autotuned schedule, replayed from a HIP graph) against per-tile
+    launches (fr_receivers + fr_accumulate per tile) in float32 and float64."""
     import torch
     import synth
     import paper_2606_12800_amd as fr
@@ -320,50 +327,50 @@ def run_batched(args):
     log(f"  batched float32 (graph replay): {1e3 * t_batch:.2f} ms per batch, {gpu_ms:.2f} ms on the GPU")
     # Algorithmic bytes: D8 tiles z + counts, MFD tiles z + q.
     alg = sum(a * b_ * (4 + 8 if i % 2 == 0 else 4 + 4) for i, (a, b_) in enumerate(shapes))
-    # Per-tile float64 launches on the same stream (receivers + accumulate).
     del b, graph
     torch.cuda.empty_cache()
-    if args.no_per_tile:
-        t_tile = float("nan")
-    else:
-        t_tile = per_tile_f64(args, shapes, tiles)
+    per_tile = {}
+    if not args.no_per_tile:
+        for name, dt in (("f32", fr.F32), ("f64", fr.F64)):
+            per_tile[name] = per_tile_route(shapes, tiles, dt)
 
     line = {
-        "metric": "cells routed/sec (D8 & MFD) at 1 MI355X; % HBM peak; batched vs per-tile",
+        "metric": METRIC,
         "value": ncell / t_batch, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * t_batch, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"batched: {ntiles} tiles, sides U[64,2048] (seed 4), even D8 uint64 counts, "
                                f"odd MFD float32, unit rain", "cells": ncell},
-        "roofline": {"bound": "hbm", "achieved": alg / (gpu_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": alg / (gpu_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": MEASURED_TRAFFIC.get(("batched", ntiles), {}).get("batch"),
-                     "kernel": "k_batch", "bytes": alg, "ms_per_launch": gpu_ms},
-        "detail": {"plan": {"workers": plan.workers, "order": plan.order}, "timing": "HIP graph replay",
-                   "per_tile_f64_ms": None if t_tile != t_tile else 1e3 * t_tile,
-                   "per_tile_f64_cells_per_s": None if t_tile != t_tile else ncell / t_tile,
-                   "batched_over_per_tile": None if t_tile != t_tile else t_tile / t_batch},
+        "roofline": roofline(alg / (gpu_ms * 1e-3) / 1e9, "k_batch", ("batched", ntiles), "batch", bytes=alg,
+                             ms_per_launch=gpu_ms),
+        "detail": {"plan": {"workers": plan.workers, "order": plan.order}, "timing": "HIP graph replay"},
     }
+    for name, t_tile in per_tile.items():
+        line["detail"][f"per_tile_{name}_ms"] = 1e3 * t_tile
+        line["detail"][f"per_tile_{name}_cells_per_s"] = ncell / t_tile
+        line["detail"][f"batched_over_per_tile_{name}"] = t_tile / t_batch
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_tiles(shapes)
-    print(json.dumps(line), flush=True)
+    return line
 
 
-def per_tile_f64(args, shapes, tiles):
-    """Seconds for routing the batch's tiles one by one in float64 (one
-    fr_receivers + fr_accumulate per tile, on the same stream)."""
+def per_tile_route(shapes, tiles, q_dtype):
+    """Seconds for routing the batch's tiles one by one (one fr_receivers +
+    fr_accumulate per tile, on the same stream, a workspace allocated once),
+    with q_dtype water for every tile (D8 tiles also get their counts)."""
     import torch
     import paper_2606_12800_amd as fr
     dev = torch.device("cuda:0")
     big = max(a * b_ for a, b_ in shapes)
-    q64 = torch.empty(big, dtype=torch.float64, device=dev)
+    q = torch.empty(big, dtype=torch.float64 if q_dtype == fr.F64 else torch.float32, device=dev)
+    cnt = torch.empty(big, dtype=torch.uint64, device=dev)
     code = torch.empty(big, dtype=torch.uint8, device=dev)
     ws = fr.Workspace()
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     lib = fr.load_library()
     stream = fr._stream(dev)
     P = lambda t: ctypes.c_void_p(t.data_ptr())
-    wsb_max = max(fr.workspace_bytes(fr.FN_ACCUMULATE, a, b_, fr.MFD if i % 2 else fr.D8, fr.F64)
+    wsb_max = max(fr.workspace_bytes(fr.FN_ACCUMULATE, a, b_, fr.MFD if i % 2 else fr.D8, q_dtype)
                   for i, (a, b_) in enumerate(shapes))
     wbuf = ws.get(wsb_max, dev)
     torch.cuda.synchronize()
@@ -373,14 +380,14 @@ def per_tile_f64(args, shapes, tiles):
         z = tiles[i]["z"]
         if lib.fr_receivers(P(z), nr, nc, rule, P(code), P(status), stream) != 0:
             raise RuntimeError("fr_receivers")
-        rc = lib.fr_accumulate(P(z), P(code), nr, nc, rule, 1.1, None, fr.F32, fr.F64, P(q64), None, None,
-                               P(status), P(wbuf), wsb_max, stream)
+        rc = lib.fr_accumulate(P(z), P(code), nr, nc, rule, 1.1, None, fr.F32, q_dtype, P(q),
+                               P(cnt) if rule == fr.D8 else None, None, P(status), P(wbuf), wsb_max, stream)
         if rc != 0:
             raise fr.FlowRouteError(rc, "per-tile fr_accumulate")
     torch.cuda.synchronize()
     t_tile = time.perf_counter() - t0
     fr._raise_status(status, "per-tile route")
-    log(f"  per-tile float64: {1e3 * t_tile:.2f} ms for the batch")
+    log(f"  per-tile {'float64' if q_dtype == fr.F64 else 'float32'}: {1e3 * t_tile:.2f} ms for the batch")
     return t_tile
 
 
@@ -504,7 +511,7 @@ def run_blockiter(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="d8", choices=["d8", "mfd", "adjoint", "batched", "blockiter", "fill"],
-                    help="d8: the headline 1.88e9-cell route (default); mfd / adjoint / batched: secondary lines")
+                    help="d8: the headline 1.88e9-cell route (default); the others: one line for that workload")
     ap.add_argument("--tiles", type=int, default=512, help="batched workload: number of tiles")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
@@ -517,7 +524,9 @@ def main():
     ap.add_argument("--block", type=int, nargs=2, default=[4096, 4096],
                     help="blockiter: block rows and columns (multiples of 16 and 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-per-tile", action="store_true", help="batched: skip the per-tile float64 comparison")
+    ap.add_argument("--no-per-tile", action="store_true", help="batched: skip the per-tile comparisons")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="d8: time only the headline route (not the MFD and batched workloads in detail)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, run one 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -529,7 +538,7 @@ def main():
         sys.exit(2)
     args.size_given = "--size" in sys.argv
     if args.workload == "batched":
-        run_batched(args)
+        print(json.dumps(run_batched(args)), flush=True)
         return
     if args.workload == "blockiter":
         run_blockiter(args)
@@ -538,9 +547,34 @@ def main():
         run_fill(args)
         return
     if args.workload != "d8":
-        run_secondary(args, args.workload)
+        print(json.dumps(run_secondary(args, args.workload)), flush=True)
         return
+    out = run_d8(args)
+    if not args.headline_only and not args.rows and not args.cols and not args.size_given:
+        # The other configurations of the metric, timed in the same run:
+        # MFD 16384^2 (float32 and float64) and the 512-tile batch (HIP graph
+        # replay against per-tile float32 and float64 launches).  Each keeps
+        # its own roofline; none has a CPU baseline here (bench.py
+        # --workload mfd / batched time the oracle beside them).
+        import torch
+        torch.cuda.empty_cache()
+        sub = argparse.Namespace(**vars(args))
+        sub.no_cpu_baseline = True
+        sub.steps, sub.warmup = 3, 1
+        sub.size_given = False
+        for name, fn in (("mfd_16384", lambda: run_secondary(sub, "mfd")), ("batched_512", lambda: run_batched(sub))):
+            log(f"{name} ...")
+            line = fn()
+            out["detail"][name] = {k: line[k] for k in ("value", "unit", "ms_per_step", "dtype", "config",
+                                                        "roofline", "detail") if k in line}
+            torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
 
+
+def run_d8(args):
+    """The headline route: D8 receivers + accumulation (float32 rain with
+    float-float sums, uint64 counts, float64 mass balance) of the 43360^2
+    DEM (seed 2), inputs resident in HBM."""
     import numpy as np
     import torch
     import synth
@@ -613,6 +647,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     log(f"  timed {args.steps} steps in {wall:.3f}s")
+    fr.timing_enable(False)
 
     if args.copy_probe:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -628,6 +663,7 @@ def main():
     recv_avg = sum(recv_ms) / len(recv_ms)
     acc_avg = sum(acc_ms) / len(acc_ms)
     acc_gbs = ACC_BYTES * ncell / (acc_avg * 1e-3) / 1e9
+    route_gbs = ROUTE_BYTES * ncell / ((recv_avg + acc_avg) * 1e-3) / 1e9
     phase_avg = {k: sum(v) / len(v) for k, v in phase_ms.items()}
     # Dominant phase: the one with the largest device time.
     single = {k: v for k, v in phase_avg.items() if k in PHASE_BYTES}
@@ -635,7 +671,7 @@ def main():
     achieved = PHASE_BYTES[dom] * ncell / (single[dom] * 1e-3) / 1e9
     phase_gbs = {k: PHASE_BYTES[k] * ncell / (single[k] * 1e-3) / 1e9 for k in single}
     out = {
-        "metric": "cells routed/sec (D8 & MFD) at 1 MI355X; % HBM peak; batched vs per-tile",
+        "metric": METRIC,
         "value": value,
         "unit": "cells/s",
         "n_gpus": 1,
@@ -649,23 +685,26 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"D8 {nr}x{nc} fractal DEM (seed {args.seed}), f32 rain + u64 counts",
                    "cells": ncell},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get(("d8", nr, nc), {}).get(dom),
-                     "kernel": PHASE_KERNEL[dom], "bytes_per_cell": PHASE_BYTES[dom],
-                     "ms_per_launch": single[dom]},
+        "roofline": roofline(achieved, PHASE_KERNEL[dom], ("d8", nr, nc), dom, bytes_per_cell=PHASE_BYTES[dom],
+                             ms_per_launch=single[dom]),
         "detail": {"receivers_ms": recv_avg, "accumulate_ms": acc_avg,
                    "accumulate_alg_GBs": acc_gbs,
+                   # The whole route (receivers + accumulate, 22 algorithmic
+                   # bytes per cell) against the HBM peak.
+                   "route_roofline": {"bytes_per_cell": ROUTE_BYTES, "achieved": route_gbs, "unit": "GB/s",
+                                      "frac": route_gbs / HBM_PEAK_GBS, "ms": recv_avg + acc_avg},
                    "phase_ms": phase_avg, "phase_alg_GBs": phase_gbs,
+                   "phase_frac": {k: v / HBM_PEAK_GBS for k, v in phase_gbs.items()},
                    "mass_sinks": float(m[0]), "mass_rain": float(m[1]),
                    "mass_rel_err": abs(float(m[0]) - float(m[1])) / float(m[1]),
                    "sink_counts_total": total_cells_counts},
     }
+    del z, rain, code, q, cnt, ws
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_size}^2 ...")
-        del z, rain, code, q, cnt, ws
-        torch.cuda.empty_cache()
         out["cpu_baseline"] = cpu_baseline(args.cpu_size, args.seed)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":
