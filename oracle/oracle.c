@@ -9,8 +9,9 @@
  *
  *   local flow routing (Section 2.1; Appendix A for multiple receivers)
  *   -> sort all cells high-to-low (Section 2.1, eq. high-to-low-procedure)
- *   -> push each cell's water to its receiver(s) in that order
- *      (Section 2.1 "global flow routing"; Section 3.1 triangular solve)
+ *   -> in that order, each cell's water is its rain plus the shares of its
+ *      donors (a row of (I - W^T) q = r, Section 2.2), every donor being
+ *      higher and so already final
  *   -> mass balance check: water leaving through sinks equals total rain
  *      (Section 4, verification paragraph).
  *
@@ -183,50 +184,81 @@ int or_order(const float* z, int64_t n, int64_t* order /* n entries, output */) 
 }
 
 /* ---------------------------------------------------------------------------
- * Global flow routing, single receiver (Section 2.1 listing; Section 3.1
- * in-place triangular solve): q = r, then in high-to-low order
- * q[dst] += q[src].  rain == NULL means unit rain (drainage area, Section 1).
- * Either output may be NULL; counts are exact cell counts (unit rain).
+ * Global flow routing (Section 2.1; Section 2.2: q solves (I - W^T) q = r).
+ * Row i of that system reads q_i = r_i + sum over donors d of f_{d->i} q_d,
+ * the donors being the neighbours that give i (part of) their water.  Every
+ * donor is strictly higher than i, so taking the cells from high to low
+ * (Section 2.1) finds each donor's value final when it is needed.
+ */
+
+/* Share of donor d's water that goes to cell i (0 when none): D8/D4 codes
+ * (code != NULL) or MFD fractions from z. */
+static double share(const uint8_t* code, const float* z, int64_t nr, int64_t nc, double p, int frac32,
+                    int64_t d, int64_t i) {
+  if (code) return code_target(nc, d, code[d]) == i ? 1.0 : 0.0;
+  int64_t nb[8];
+  double f[8];
+  const int m = mfd_split(z, nr, nc, d / nc, d % nc, p, frac32, nb, f);
+  for (int t = 0; t < m; ++t)
+    if (nb[t] == i) return f[t];
+  return 0.0;
+}
+
+/* Sum over the donors of i of share * x[donor], neighbours taken in order
+ * k = 0..7.  frac != NULL: the MFD fractions of every cell, precomputed
+ * (slot 8 d + j for neighbour j of d; neighbour k of i sees i as its
+ * neighbour 7 - k). */
+static double donor_sum(const uint8_t* code, const float* z, int64_t nr, int64_t nc, double p, int frac32,
+                        const double* frac, const double* x, int64_t i) {
+  double s = 0.0;
+  for (int k = 0; k < 8; ++k) {
+    const int64_t d = neighbour(nr, nc, i / nc, i % nc, k);
+    if (d < 0) continue;
+    const double f = frac ? frac[8 * d + (7 - k)] : share(code, z, nr, nc, p, frac32, d, i);
+    if (f != 0.0) s += f * x[d];
+  }
+  return s;
+}
+
+static uint64_t donor_count(const uint8_t* code, int64_t nr, int64_t nc, const uint64_t* cnt, int64_t i) {
+  uint64_t s = 0;
+  for (int k = 0; k < 8; ++k) {
+    const int64_t d = neighbour(nr, nc, i / nc, i % nc, k);
+    if (d >= 0 && code_target(nc, d, code[d]) == i) s += cnt[d];
+  }
+  return s;
+}
+
+/*
+ * Single receiver (D8/D4 codes): q in float64 and/or exact cell counts
+ * (unit rain); rain == NULL means unit rain (drainage area, Section 1).
  */
 int or_accumulate_single(const uint8_t* code, int64_t nr, int64_t nc, const int64_t* order,
                          const float* rain, double* q, uint64_t* counts) {
   if (!code || !order || nr < 0 || nc < 0) return -2;
   const int64_t n = nr * nc;
-  if (q) {
-    for (int64_t i = 0; i < n; ++i) q[i] = rain ? (double)rain[i] : 1.0;
-    for (int64_t t = 0; t < n; ++t) {
-      const int64_t i = order[t];
-      const int64_t k = code_target(nc, i, code[i]);
-      if (k >= 0) q[k] += q[i];
-    }
-  }
-  if (counts) {
-    for (int64_t i = 0; i < n; ++i) counts[i] = 1;
-    for (int64_t t = 0; t < n; ++t) {
-      const int64_t i = order[t];
-      const int64_t k = code_target(nc, i, code[i]);
-      if (k >= 0) counts[k] += counts[i];
-    }
+  for (int64_t t = 0; t < n; ++t) {
+    const int64_t i = order[t];
+    if (q) q[i] = (rain ? (double)rain[i] : 1.0) + donor_sum(code, NULL, nr, nc, 0.0, 0, NULL, q, i);
+    if (counts) counts[i] = 1 + donor_count(code, nr, nc, counts, i);
   }
   return 0;
 }
 
-/*
- * Global flow routing, multiple receivers (Appendix A): in high-to-low order
- * q[dst_n] += f_n * q[src], fractions recomputed from z for each cell.
- */
+/* Multiple receivers (Appendix A): every cell's fractions computed from z
+ * once, up front. */
 int or_accumulate_mfd(const float* z, int64_t nr, int64_t nc, double p, int frac32,
                       const int64_t* order, const float* rain, double* q) {
   if (!z || !order || !q || nr < 0 || nc < 0) return -2;
   const int64_t n = nr * nc;
-  for (int64_t i = 0; i < n; ++i) q[i] = rain ? (double)rain[i] : 1.0;
+  double* frac = (double*)malloc((size_t)(8 * n + 1) * sizeof(double));
+  if (!frac) return -2;
+  or_mfd_fractions(z, nr, nc, p, frac32, NULL, frac);
   for (int64_t t = 0; t < n; ++t) {
     const int64_t i = order[t];
-    int64_t nb[8];
-    double f[8];
-    const int m = mfd_split(z, nr, nc, i / nc, i % nc, p, frac32, nb, f);
-    for (int s = 0; s < m; ++s) q[nb[s]] += f[s] * q[i];
+    q[i] = (rain ? (double)rain[i] : 1.0) + donor_sum(NULL, z, nr, nc, p, frac32, frac, q, i);
   }
+  free(frac);
   return 0;
 }
 
@@ -267,31 +299,25 @@ int or_adjoint_mfd(const float* z, int64_t nr, int64_t nc, double p, const int64
 }
 
 /*
- * Matrix-free product y = A x with A = I - W^T (Section 3.1, optimized
- * listing; Appendix A for fractions): y = x, then y[dst] -= f * x[src] for
- * every routing pair.  Used for the residual r - A q.
+ * Product y = A x with A = I - W^T (Section 2.2, eq. linear-system; Appendix
+ * A for fractions), row by row: y_i = x_i - sum over donors d of
+ * f_{d->i} x_d.  Used for the residual r - A q.
  */
 int or_apply_A_single(const uint8_t* code, int64_t nr, int64_t nc, const double* x, double* y) {
   if (!code || !x || !y || nr < 0 || nc < 0) return -2;
   const int64_t n = nr * nc;
-  for (int64_t i = 0; i < n; ++i) y[i] = x[i];
-  for (int64_t i = 0; i < n; ++i) {
-    const int64_t k = code_target(nc, i, code[i]);
-    if (k >= 0) y[k] -= x[i];
-  }
+  for (int64_t i = 0; i < n; ++i) y[i] = x[i] - donor_sum(code, NULL, nr, nc, 0.0, 0, NULL, x, i);
   return 0;
 }
 
 int or_apply_A_mfd(const float* z, int64_t nr, int64_t nc, double p, const double* x, double* y) {
   if (!z || !x || !y || nr < 0 || nc < 0) return -2;
   const int64_t n = nr * nc;
-  for (int64_t i = 0; i < n; ++i) y[i] = x[i];
-  for (int64_t i = 0; i < n; ++i) {
-    int64_t nb[8];
-    double f[8];
-    const int m = mfd_split(z, nr, nc, i / nc, i % nc, p, 0, nb, f);
-    for (int s = 0; s < m; ++s) y[nb[s]] -= f[s] * x[i];
-  }
+  double* frac = (double*)malloc((size_t)(8 * n + 1) * sizeof(double));
+  if (!frac) return -2;
+  or_mfd_fractions(z, nr, nc, p, 0, NULL, frac);
+  for (int64_t i = 0; i < n; ++i) y[i] = x[i] - donor_sum(NULL, z, nr, nc, p, 0, frac, x, i);
+  free(frac);
   return 0;
 }
 
@@ -359,18 +385,6 @@ int or_mass_mfd(const float* z, int64_t nr, int64_t nc, const float* rain, const
  * receive the final iterate; either may be NULL.  Returns 0, -2 on bad arguments, -3 when max_iter
  * iterations do not converge.
  */
-static int pairs_of(const uint8_t* code, const float* z, int64_t nr, int64_t nc, double p, int64_t i,
-                    int64_t nb[8], double f[8]) {
-  if (code) {
-    const int64_t k = code_target(nc, i, code[i]);
-    if (k < 0) return 0;
-    nb[0] = k;
-    f[0] = 1.0;
-    return 1;
-  }
-  return mfd_split(z, nr, nc, i / nc, i % nc, p, 0, nb, f);
-}
-
 static int64_t block_of(int64_t nc, int64_t br, int64_t bc, int64_t i) {
   const int64_t nbc = (nc + bc - 1) / bc;
   return (i / nc / br) * nbc + (i % nc) / bc;
@@ -382,40 +396,31 @@ static int in_d(int64_t nc, int64_t br, int64_t bc, int64_t i, int64_t k) {
 }
 
 /* y = rho x (inside == 0) or y = D^{-1} x (inside == 1), in float64 and in
- * uint64 (wrap-around arithmetic: the (I-X)(I+X) scheme subtracts). */
+ * uint64 (wrap-around arithmetic: the (I-X)(I+X) scheme subtracts), row by
+ * row as in the direct solve: (rho x)_i sums the shares of the donors of i
+ * in other blocks; D y = x is solved from high to low with
+ * y_i = x_i + the shares of the donors of i in its own block.  Counts use
+ * share 1 for every pair (for MFD: the number of flow paths). */
 static void block_apply(const uint8_t* code, const float* z, int64_t nr, int64_t nc, double p,
                         const int64_t* order, int64_t br, int64_t bc, int inside,
                         const double* x, const uint64_t* xc, double* y, uint64_t* yc) {
   const int64_t n = nr * nc;
-  int64_t nb[8];
-  double f[8];
-  if (!inside) {
-    for (int64_t i = 0; i < n; ++i) {
-      y[i] = 0.0;
-      yc[i] = 0;
-    }
-    for (int64_t i = 0; i < n; ++i) {
-      const int m = pairs_of(code, z, nr, nc, p, i, nb, f);
-      for (int s = 0; s < m; ++s) {
-        if (in_d(nc, br, bc, i, nb[s])) continue;
-        y[nb[s]] += f[s] * x[i];
-        yc[nb[s]] += xc[i];
-      }
-    }
-    return;
-  }
-  for (int64_t i = 0; i < n; ++i) {
-    y[i] = x[i];
-    yc[i] = xc[i];
-  }
   for (int64_t t = 0; t < n; ++t) {
-    const int64_t i = order[t];
-    const int m = pairs_of(code, z, nr, nc, p, i, nb, f);
-    for (int s = 0; s < m; ++s) {
-      if (!in_d(nc, br, bc, i, nb[s])) continue;
-      y[nb[s]] += f[s] * y[i];
-      yc[nb[s]] += yc[i];
+    const int64_t i = inside ? order[t] : t;
+    const double* src = inside ? y : x;
+    const uint64_t* srcc = inside ? yc : xc;
+    double s = 0.0;
+    uint64_t sc = 0;
+    for (int k = 0; k < 8; ++k) {
+      const int64_t d = neighbour(nr, nc, i / nc, i % nc, k);
+      if (d < 0 || in_d(nc, br, bc, d, i) != inside) continue;
+      const double f = share(code, z, nr, nc, p, 0, d, i);
+      if (f == 0.0) continue;
+      s += f * src[d];
+      sc += srcc[d];
     }
+    y[i] = inside ? x[i] + s : s;
+    yc[i] = inside ? xc[i] + sc : sc;
   }
 }
 
