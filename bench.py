@@ -525,6 +525,8 @@ def main():
                     help="blockiter: block rows and columns (multiples of 16 and 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-tile", action="store_true", help="batched: skip the per-tile comparisons")
+    ap.add_argument("--filled", action="store_true",
+                    help="d8: route the untilted DEM after depression filling (the paper's workflow)")
     ap.add_argument("--headline-only", action="store_true",
                     help="d8: time only the headline route (not the MFD and batched workloads in detail)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -550,7 +552,7 @@ def main():
         print(json.dumps(run_secondary(args, args.workload)), flush=True)
         return
     out = run_d8(args)
-    if not args.headline_only and not args.rows and not args.cols and not args.size_given:
+    if not args.headline_only and not args.rows and not args.cols and not args.size_given and not args.filled:
         # The other configurations of the metric, timed in the same run:
         # MFD 16384^2 (float32 and float64) and the 512-tile batch (HIP graph
         # replay against per-tile float32 and float64 launches).  Each keeps
@@ -588,11 +590,17 @@ def run_d8(args):
 
     log(f"generating {nr}x{nc} DEM (seed {args.seed}) ...")
     t0 = time.perf_counter()
-    z_h = synth.dem(args.seed, nr, nc)
+    z_h = synth.dem(args.seed, nr, nc, tilt=0.0 if args.filled else synth.TILT)
     rain_h = synth.rain(args.seed, nr, nc)
     log(f"  generated in {time.perf_counter() - t0:.1f}s; copying to HBM")
     z = torch.from_numpy(z_h).to(dev)
     del z_h
+    if args.filled:
+        # The paper's workflow (Section 4): the untilted DEM filled first
+        # (not timed), then routed.
+        z = fr.fill_depressions(z, "d8", eps=True)
+        fr._default_ws.buf = None
+        torch.cuda.synchronize()
     rain = torch.from_numpy(rain_h).to(dev)
     del rain_h
     code = torch.empty((nr, nc), dtype=torch.uint8, device=dev)
@@ -683,7 +691,8 @@ def run_d8(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"D8 {nr}x{nc} fractal DEM (seed {args.seed}), f32 rain + u64 counts",
+        "config": {"workload": (f"D8 {nr}x{nc} fractal DEM (seed {args.seed}"
+                                + (", untilted, depression-filled" if args.filled else "") + "), f32 rain + u64 counts"),
                    "cells": ncell},
         "roofline": roofline(achieved, PHASE_KERNEL[dom], ("d8", nr, nc), dom, bytes_per_cell=PHASE_BYTES[dom],
                              ms_per_launch=single[dom]),
@@ -697,7 +706,8 @@ def run_d8(args):
                    "phase_frac": {k: v / HBM_PEAK_GBS for k, v in phase_gbs.items()},
                    "mass_sinks": float(m[0]), "mass_rain": float(m[1]),
                    "mass_rel_err": abs(float(m[0]) - float(m[1])) / float(m[1]),
-                   "sink_counts_total": total_cells_counts},
+                   "sink_counts_total": total_cells_counts,
+                   "cells_leaving_row_sweep": int((code > 2).sum().item()) / ncell},
     }
     del z, rain, code, q, cnt, ws
     torch.cuda.empty_cache()

@@ -95,7 +95,8 @@ extern "C" {
 
 /* Tile orders of fr_batch_plan.order. */
 #define FR_ORDER_GIVEN 0
-#define FR_ORDER_ROWS_DESC 1
+#define FR_ORDER_ROWS_DESC 1   /* tiles with more rows first              */
+#define FR_ORDER_CELLS_DESC 2  /* tiles with more cells first             */
 
 /* Status codes. */
 #define FR_OK 0
@@ -346,7 +347,7 @@ typedef struct fr_tile {
  * (0: two per compute unit; at least ceil(ncols / 48) of the widest tile,
  * whose column strips must all run at once -- a tile that needs more is
  * reported as FR_ERR_ARG in dev_status) and the tile `order`
- * (FR_ORDER_GIVEN, or FR_ORDER_ROWS_DESC: tiles with more rows first).
+ * (FR_ORDER_GIVEN, FR_ORDER_ROWS_DESC or FR_ORDER_CELLS_DESC).
  * fr_batch_autotune picks one by timing candidates.
  */
 typedef struct fr_batch_plan {
@@ -379,13 +380,28 @@ int fr_accumulate_batched(const fr_tile* tiles_dev, int32_t ntiles, const fr_bat
                           int32_t* dev_status, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
- * fr_batch_autotune -- times fr_accumulate_batched on this batch for a few
- * candidate plans (worker counts and tile orders; `reps` timed runs each
- * after one warm-up) and writes the fastest to *plan_out.  Synchronises the
- * stream.  Outputs of the tiles are overwritten.
+ * fr_batch_autotune -- picks a plan for this batch: times
+ * fr_accumulate_batched for every candidate plan -- one, one and a half and
+ * two workgroups per compute unit, times the three tile orders; `reps`
+ * timed runs each after one warm-up -- and writes the fastest to
+ * *plan_out.  Plans are cached by the batch's signature (device, compute
+ * units, and every tile's shape, rule and which of its pointers are NULL):
+ * a batch with a cached signature gets its plan without timing.  The cache
+ * lives in the process, and in the file set by fr_set_autotune_cache when
+ * there is one.  Synchronises the stream; outputs of the tiles are
+ * overwritten when it times.
  */
 int fr_batch_autotune(const fr_tile* tiles_dev, int32_t ntiles, int32_t* dev_status, void* ws,
                       size_t ws_bytes, int reps, fr_batch_plan* plan_out, hipStream_t stream);
+
+/*
+ * fr_set_autotune_cache -- file that keeps fr_batch_autotune's plans across
+ * processes (one "signature workers order" line per batch, read when set and
+ * appended to when a new plan is found), or NULL for the process cache
+ * alone.  Not thread-safe.  Errors: FR_ERR_ARG if the file cannot be read
+ * or created.
+ */
+int fr_set_autotune_cache(const char* path);
 
 /*
  * fr_set_accumulate_path -- process-wide choice of the accumulation path of

@@ -40,8 +40,8 @@ EXPORTS = ["fr_receivers", "fr_accumulate", "fr_accumulate_adjoint", "fr_workspa
            "fr_status_string", "fr_version", "fr_timing_enable", "fr_timing_last",
            "fr_batched_workspace_bytes", "fr_accumulate_batched", "fr_batch_autotune",
            "fr_accumulate_block_iterations", "fr_fill_depressions", "fr_set_accumulate_path",
-           "fr_accumulate_noalloc"]
-ORDER_GIVEN, ORDER_ROWS_DESC = 0, 1
+           "fr_accumulate_noalloc", "fr_set_autotune_cache"]
+ORDER_GIVEN, ORDER_ROWS_DESC, ORDER_CELLS_DESC = 0, 1, 2
 
 
 class Tile(ctypes.Structure):
@@ -107,6 +107,8 @@ def load_library() -> ctypes.CDLL:
     lib.fr_set_accumulate_path.restype = ci
     lib.fr_accumulate_noalloc.argtypes = [vp, vp, i64, i64, ci, cd, vp, ci, ci, vp, vp, vp, vp, vp]
     lib.fr_accumulate_noalloc.restype = ci
+    lib.fr_set_autotune_cache.argtypes = [ctypes.c_char_p]
+    lib.fr_set_autotune_cache.restype = ci
     _lib = lib
     return lib
 
@@ -385,6 +387,13 @@ class FlowAccumulate(torch.autograd.Function):
         return rbar, None, None, None
 
 
+def set_autotune_cache(path: str | None) -> None:
+    """File that keeps autotuned batch plans across processes (or None)."""
+    rc = load_library().fr_set_autotune_cache(None if path is None else os.fsencode(path))
+    if rc != OK:
+        raise FlowRouteError(rc, "fr_set_autotune_cache")
+
+
 class Batch:
     """A batch of independent tiles routed by one persistent launch
     (``fr_accumulate_batched``).  Each tile is given as its elevation tensor,
@@ -439,7 +448,8 @@ class Batch:
             _raise_status(self.status, "fr_accumulate_batched")
 
     def autotune(self, reps: int = 2) -> BatchPlan:
-        """Pick the fastest schedule among the library's candidates."""
+        """Pick the fastest schedule among the library's candidates (cached by
+        the batch's shape signature; see ``set_autotune_cache``)."""
         plan = BatchPlan()
         self.status.zero_()
         rc = load_library().fr_batch_autotune(_ptr(self.table), self.n, _ptr(self.status), _ptr(self.ws),

@@ -5,7 +5,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <map>
 #include <mutex>
+#include <string>
+#include <vector>
 
 #include "fr_internal.hpp"
 
@@ -848,7 +851,8 @@ int fr_accumulate_batched(const fr_tile* tiles_dev, int32_t ntiles, const fr_bat
   timing_reset();
   if (ntiles == 0) return FR_OK;
   if (!tiles_dev) return FR_ERR_ARG;
-  if (plan && (plan->workers < 0 || (plan->order != FR_ORDER_GIVEN && plan->order != FR_ORDER_ROWS_DESC)))
+  if (plan && (plan->workers < 0 || (plan->order != FR_ORDER_GIVEN && plan->order != FR_ORDER_ROWS_DESC &&
+                                     plan->order != FR_ORDER_CELLS_DESC)))
     return FR_ERR_ARG;
   if (!ws || ws_bytes < batch_head_bytes(ntiles) + kAlign) return FR_ERR_WORKSPACE;
   char* base = aligned_base(ws);
@@ -861,15 +865,69 @@ int fr_accumulate_batched(const fr_tile* tiles_dev, int32_t ntiles, const fr_bat
   return e == hipSuccess ? FR_OK : FR_ERR_HIP;
 }
 
+// Autotune cache: batch signature -> plan, in the process and optionally in
+// a file (fr_set_autotune_cache).
+static std::map<uint64_t, fr_batch_plan> g_plans;
+static std::string g_plan_file;
+
+static void fnv(uint64_t& h, uint64_t v) {
+  for (int i = 0; i < 8; ++i) {
+    h ^= (v >> (8 * i)) & 0xFFu;
+    h *= 0x100000001b3ull;
+  }
+}
+
+int fr_set_autotune_cache(const char* path) {
+  g_plan_file = path ? path : "";
+  if (!path) return FR_OK;
+  FILE* f = fopen(path, "a+");
+  if (!f) return FR_ERR_ARG;
+  rewind(f);
+  unsigned long long sig = 0;
+  int w = 0, o = 0;
+  while (fscanf(f, "%llx %d %d", &sig, &w, &o) == 3)
+    if (w > 0 && (o == FR_ORDER_GIVEN || o == FR_ORDER_ROWS_DESC || o == FR_ORDER_CELLS_DESC))
+      g_plans[(uint64_t)sig] = fr_batch_plan{w, o};
+  fclose(f);
+  return FR_OK;
+}
+
 int fr_batch_autotune(const fr_tile* tiles_dev, int32_t ntiles, int32_t* dev_status, void* ws, size_t ws_bytes,
                       int reps, fr_batch_plan* plan_out, hipStream_t stream) {
-  if (!plan_out || reps < 1) return FR_ERR_ARG;
+  if (!plan_out || reps < 1 || ntiles < 0 || (ntiles > 0 && !tiles_dev)) return FR_ERR_ARG;
   const int cu = cu_count();
-  const fr_batch_plan cand[] = {{2 * cu, FR_ORDER_ROWS_DESC}, {2 * cu, FR_ORDER_GIVEN}, {cu, FR_ORDER_ROWS_DESC},
-                                {cu, FR_ORDER_GIVEN}};
+  // Signature of the batch (its tile table, read back from the device).
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return FR_ERR_HIP;
+  std::vector<fr_tile> host((size_t)ntiles);
+  if (ntiles > 0 && (hipMemcpyAsync(host.data(), tiles_dev, sizeof(fr_tile) * (size_t)ntiles,
+                                    hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                     hipStreamSynchronize(stream) != hipSuccess))
+    return FR_ERR_HIP;
+  uint64_t sig = 0xcbf29ce484222325ull;
+  fnv(sig, (uint64_t)dev);
+  fnv(sig, (uint64_t)cu);
+  fnv(sig, (uint64_t)ntiles);
+  for (const fr_tile& t : host) {
+    fnv(sig, (uint64_t)t.nrows);
+    fnv(sig, (uint64_t)t.ncols);
+    fnv(sig, ((uint64_t)t.rule << 8) | ((t.rain != nullptr) << 0) | ((t.q_out != nullptr) << 1) |
+                 ((t.counts_out != nullptr) << 2) | ((t.code_out != nullptr) << 3));
+  }
+  const auto hit = g_plans.find(sig);
+  if (hit != g_plans.end()) {
+    *plan_out = hit->second;
+    return FR_OK;
+  }
+  std::vector<fr_batch_plan> cand;
+  for (int w : {2 * cu, cu + cu / 2, cu})
+    for (int o : {FR_ORDER_ROWS_DESC, FR_ORDER_CELLS_DESC, FR_ORDER_GIVEN}) cand.push_back(fr_batch_plan{w, o});
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return FR_ERR_HIP;
-  if (hipEventCreate(&e1) != hipSuccess) return FR_ERR_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return FR_ERR_HIP;
+  }
   float best = -1.0f;
   int rc = FR_OK;
   for (const fr_batch_plan& p : cand) {
@@ -892,6 +950,16 @@ int fr_batch_autotune(const fr_tile* tiles_dev, int32_t ntiles, int32_t* dev_sta
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (rc == FR_OK && best >= 0.0f) {
+    g_plans[sig] = *plan_out;
+    if (!g_plan_file.empty()) {
+      FILE* f = fopen(g_plan_file.c_str(), "a");
+      if (f) {
+        fprintf(f, "%llx %d %d\n", (unsigned long long)sig, plan_out->workers, plan_out->order);
+        fclose(f);
+      }
+    }
+  }
   return rc;
 }
 

@@ -1492,14 +1492,16 @@ __global__ __launch_bounds__(1024) void k_batch_setup(const fr_tile* tiles, int3
   int32_t* sched = reinterpret_cast<int32_t*>(p);
   p += ws_align((size_t)ntiles * 4);
   int64_t* base = reinterpret_cast<int64_t*>(p);
-  // Schedule: given order, or more rows first (stable), by parallel ranking.
+  // Schedule: given order, or more rows (cells) first, stable, by parallel
+  // ranking.
   for (int i = threadIdx.x; i < ntiles; i += blockDim.x) {
     int rank = i;
-    if (order == FR_ORDER_ROWS_DESC && ntiles <= 16384) {
+    if (order != FR_ORDER_GIVEN && ntiles <= 16384) {
       rank = 0;
-      const int64_t ki = tiles[i].nrows;
+      const bool rows = order == FR_ORDER_ROWS_DESC;
+      const int64_t ki = rows ? tiles[i].nrows : tiles[i].nrows * tiles[i].ncols;
       for (int j = 0; j < ntiles; ++j) {
-        const int64_t kj = tiles[j].nrows;
+        const int64_t kj = rows ? tiles[j].nrows : tiles[j].nrows * tiles[j].ncols;
         rank += (kj > ki || (kj == ki && j < i)) ? 1 : 0;
       }
     }

@@ -156,12 +156,30 @@ def test_batch_errors_and_empty():
         fr.Batch([{"z": dev(synth.dem(3, 8, 8)), "rule": "d8"}])
 
 
-def test_batch_autotune_picks_a_plan():
-    tiles, _ = make_tiles(SHAPES[5:9], 1200, False)
-    b = fr.Batch(tiles)
-    plan = b.autotune(reps=1)
-    assert plan.workers > 0 and plan.order in (fr.ORDER_GIVEN, fr.ORDER_ROWS_DESC)
-    b.run()
+def test_batch_autotune_picks_a_plan_and_caches_it(tmp_path):
+    path = str(tmp_path / "plans.txt")
+    fr.set_autotune_cache(path)
+    try:
+        tiles, _ = make_tiles(SHAPES[5:9], 1200, False)
+        b = fr.Batch(tiles)
+        plan = b.autotune(reps=1)
+        assert plan.workers > 0 and plan.order in (fr.ORDER_GIVEN, fr.ORDER_ROWS_DESC, fr.ORDER_CELLS_DESC)
+        b.run()
+        # The signature is cached: a batch of the same shapes gets the same
+        # plan without timing, also from the file in a fresh cache.
+        tiles2, _ = make_tiles(SHAPES[5:9], 1300, False)
+        p2 = fr.Batch(tiles2).autotune(reps=1)
+        assert (p2.workers, p2.order) == (plan.workers, plan.order)
+        lines = open(path).read().split()
+        assert len(lines) == 3 and int(lines[1]) == plan.workers and int(lines[2]) == plan.order
+        # Every order runs and gives the same results.
+        ref = [t["q"].clone() if "q" in t else t["counts"].clone() for t in tiles]
+        for order in (fr.ORDER_GIVEN, fr.ORDER_ROWS_DESC, fr.ORDER_CELLS_DESC):
+            b.run(plan=fr.BatchPlan(0, order))
+            for t, r in zip(tiles, ref):
+                assert torch.equal(t["q"] if "q" in t else t["counts"], r), order
+    finally:
+        fr.set_autotune_cache(None)
 
 
 def test_batch_fullconfig_equals_single_grid_calls():
