@@ -113,28 +113,25 @@ __global__ __launch_bounds__(256) void k_d8_round(D8Params P, int j, int last) {
   bool active = false;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const uint32_t a = anc[i];
+    // An exit's own sum is read only when it changes or is passed on.
     u128 v = 0;
     unsigned long long c = 0;
     if (VK != VK_NONE) {
-      v = P.ex_fx[0][i];
-      if (j > 0) {
-        const u128 d = P.ex_fx[in][i];
-        if (d != 0) {
-          v += d;
-          P.ex_fx[0][i] = v;
-          P.ex_fx[in][i] = 0;
-        }
+      const u128 d = j > 0 ? P.ex_fx[in][i] : (u128)0;
+      if (d != 0 || a != NONE) v = P.ex_fx[0][i];
+      if (d != 0) {
+        v += d;
+        P.ex_fx[0][i] = v;
+        P.ex_fx[in][i] = 0;
       }
     }
     if (CNT) {
-      c = P.ex_cnt[0][i];
-      if (j > 0) {
-        const unsigned long long d = P.ex_cnt[in][i];
-        if (d != 0) {
-          c += d;
-          P.ex_cnt[0][i] = c;
-          P.ex_cnt[in][i] = 0;
-        }
+      const unsigned long long d = j > 0 ? P.ex_cnt[in][i] : 0ull;
+      if (d != 0 || a != NONE) c = P.ex_cnt[0][i];
+      if (d != 0) {
+        c += d;
+        P.ex_cnt[0][i] = c;
+        P.ex_cnt[in][i] = 0;
       }
     }
     uint32_t a2 = NONE;
