@@ -35,7 +35,13 @@ ROUTE_BYTES = 4 + 1 + ACC_BYTES  # whole route: receivers (z in, code out) + acc
 # against a device copy, keyed by workload and phase, with the summary they
 # come from.  Only counters taken on the kernels as they are now are listed;
 # a phase without one reports traffic null.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    ("d8", 43360, 43360): {
+        "receivers": (1.0632e10, "profiles/d8_43360_hbm_traffic.md"),
+        "d8_up": (1.3366e10, "profiles/d8_43360_hbm_traffic.md"),
+        "d8_down": (3.3176e10, "profiles/d8_43360_hbm_traffic.md"),
+    },
+}
 # Algorithmic bytes per cell of the secondary workloads' dominant kernel
 # (arrays visible at the C ABI, each touched once): MFD float32 sweep z 4 +
 # mask 1 + q 4; adjoint z 4 + mask 1 + qbar 4 + rbar 4; batched D8 tiles z 4 +
@@ -58,6 +64,7 @@ def roofline(achieved_gbs, kernel, key, phase, **extra):
     r = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
          "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": tb, "kernel": kernel}
     if src:
+        r["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
         r["traffic_source"] = src
     r.update(extra)
     return r
