@@ -117,7 +117,7 @@ D8Layout d8_layout(int64_t nrows, int64_t ncols, int th, int vdtype, bool counts
 
 // Wavefront sweep (fr_wsweep.hip).  The engine overlays it too.
 struct WsLayout {
-  size_t vlo, edge, progress, ctr, partial, total;
+  size_t vlo, edge, progress, ctr, partial, ms_ring, ms_progress, ms_partial, ms_junk, total;
 };
 
 WsLayout ws_layout(int64_t nrows, int64_t ncols, int vdtype) {
@@ -129,8 +129,31 @@ WsLayout ws_layout(int64_t nrows, int64_t ncols, int vdtype) {
   L.progress = o; o += up((size_t)ws_strips(ncols) * sizeof(int32_t));
   L.ctr = o; o += kAlign;
   L.partial = o; o += up(2 * kMassBlocks * sizeof(double));
+  // Row sweep (MFD): published rows, progress and mass partials per strip.
+  L.ms_ring = o; o += up(ms_ring_words(ncols) * sizeof(uint64_t));
+  L.ms_progress = o; o += up((size_t)ms_strips(ncols) * sizeof(int32_t));
+  L.ms_partial = o; o += up((size_t)ms_strips(ncols) * 2 * sizeof(double));
+  L.ms_junk = o; o += up((size_t)ms_strips(ncols) * 2 * 64 * sizeof(uint64_t));
   L.total = o;
   return L;
+}
+
+// Row sweep parameters over the sweep's workspace; NULL outputs stay NULL.
+MsParams ms_params(int64_t nrows, int64_t ncols, const uint8_t* code, const float* z, double p, char* body,
+                   const WsLayout& L, int32_t* status) {
+  MsParams M{};
+  M.nrows = nrows;
+  M.ncols = ncols;
+  M.code = code;
+  M.z = z;
+  M.p = p;
+  M.ring = reinterpret_cast<uint64_t*>(body + L.ms_ring);
+  M.progress = reinterpret_cast<int32_t*>(body + L.ms_progress);
+  M.partial = reinterpret_cast<double*>(body + L.ms_partial);
+  M.junk = reinterpret_cast<uint64_t*>(body + L.ms_junk);
+  M.status = status;
+  M.nstrips = (int32_t)ms_strips(ncols);
+  return M;
 }
 
 struct Counters {
@@ -199,6 +222,12 @@ void phase_end(int i, hipStream_t s) {
 // Accumulation path (fr_set_accumulate_path): every path computes the same
 // result; the default picks the row sweeps for single receivers.
 int g_path = FR_PATH_AUTO;
+
+// The row sweep is tried for MFD masks under the automatic path choice when
+// all of its strips can be resident at once.
+bool ms_applicable(RuleKind rk, int64_t ncols) {
+  return rk == RK_MULTI && g_path == FR_PATH_AUTO && ms_strips(ncols) <= ms_max_strips();
+}
 
 constexpr int kMaxSweepPasses = 32;
 
@@ -565,6 +594,9 @@ int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t nc
   if (launch_zero_u32(reinterpret_cast<uint32_t*>(C), CTL_WORDS, stream) != hipSuccess) return FR_ERR_HIP;
   int rc = FR_OK;
   const int64_t n = nrows * ncols;
+  bool ms_on = false;
+  double* ms_partial = nullptr;
+  int32_t ms_nstrips = 0;
   if (g_path == FR_PATH_ENGINE) {
     hipLaunchKernelGGL(k_open_gate, dim3(1), dim3(64), 0, stream, C);
     if (hipGetLastError() != hipSuccess) return FR_ERR_HIP;
@@ -580,6 +612,19 @@ int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t nc
     return FR_OK;
   } else {
     const WsLayout WL = ws_layout(nrows, ncols, q_dtype);
+    if (ms_applicable(cfg.rk, ncols)) {
+      MsParams M = ms_params(nrows, ncols, code, z, mfd_p, body, WL, dev_status);
+      M.src32 = r32;
+      M.src64 = r64;
+      M.vhi = q32;
+      M.v64 = q64;
+      ms_on = true;
+      ms_partial = M.partial;
+      ms_nstrips = M.nstrips;
+      const int ph = phase_begin("row_sweep", stream);
+      if (launch_ms(cfg.vk, false, M, C, stream) != hipSuccess) return FR_ERR_HIP;
+      phase_end(ph, stream);
+    }
     WsParams W = ws_params(nrows, ncols, code, z, mfd_p, body, WL, cfg.vk, dev_status);
     W.src32 = r32;
     W.src64 = r64;
@@ -591,11 +636,14 @@ int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t nc
   if ((rc = enqueue_engine(cfg, P, stream)) != FR_OK) return rc;
   if (mass_out) {
     // After the sweep or the engine, whichever finished the solve: both keep
-    // the float-float low part at the same place.
+    // the float-float low part at the same place.  When the row sweep served
+    // the call, its own partials are summed instead.
     EngineParams M = P;
-    M.gate = nullptr;
+    M.gate = ms_on ? &C->ms_skip : nullptr;
     const int ph = phase_begin("mass", stream);
     if (launch_mass(cfg.rk, cfg.vk, M, partial, kMassBlocks, mass_out, stream) != hipSuccess) return FR_ERR_HIP;
+    if (ms_on && launch_mass_final(ms_partial, ms_nstrips, mass_out, &C->ms_skip, stream) != hipSuccess)
+      return FR_ERR_HIP;
     phase_end(ph, stream);
   }
   return FR_OK;
@@ -812,6 +860,17 @@ int fr_accumulate_adjoint(const float* z, const uint8_t* code, int64_t nrows, in
     if (hipGetLastError() != hipSuccess) return FR_ERR_HIP;
   } else {
     const WsLayout WL = ws_layout(nrows, ncols, dtype);
+    if (ms_applicable(cfg.rk, ncols)) {
+      MsParams M = ms_params(nrows, ncols, code, z, mfd_p, body, WL, dev_status);
+      M.src32 = s32;
+      M.src64 = s64;
+      M.vhi = o32;
+      M.v64 = o64;
+      M.partial = nullptr;
+      const int ph = phase_begin("row_sweep", stream);
+      if (launch_ms(cfg.vk, true, M, C, stream) != hipSuccess) return FR_ERR_HIP;
+      phase_end(ph, stream);
+    }
     WsParams W = ws_params(nrows, ncols, code, z, mfd_p, body, WL, cfg.vk, dev_status);
     W.src32 = s32;
     W.src64 = s64;

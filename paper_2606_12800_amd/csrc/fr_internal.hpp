@@ -96,6 +96,8 @@ struct CallCtl {
   uint64_t loc_max_d;        // D8 forest: largest |local sum| of an exit, float64 bits
   unsigned long long bar;    // persistent engine: grid barrier arrivals
   int32_t forest_final;      // D8 forest: the pending-additions buffer of the last round
+  int32_t ms_flags;          // MFD row sweep: MS_* bits from the check and the decision
+  int32_t ms_skip;           // 1: the row sweep does not serve this call (gate of the general mass)
 };
 static_assert(sizeof(CallCtl) <= 256, "control block fits its 256-byte slot");
 constexpr int CTL_WORDS = 64;  // 32-bit words zeroed at the start of a call
@@ -299,6 +301,42 @@ struct WsParams {
 size_t ws_edge_words(int64_t nrows, int64_t ncols);
 hipError_t launch_batch(const void* tiles_dev, int32_t ntiles, int order, int workers, int32_t* status,
                         char* ws, size_t ws_bytes, hipStream_t s);
+// Row sweep for MFD masks (fr_msweep.hip): one wavefront per strip of
+// MS_OWN columns, computing MS_G ghost columns on each side; owned results
+// published in a ring of MS_RING rows per strip.
+constexpr int MS_G = 16;
+constexpr int MS_OWN = 64 - 2 * MS_G;
+constexpr int MS_NB = (MS_G + MS_OWN - 1) / MS_OWN;  // strips on each side that hold ghost columns
+constexpr int MS_RING = 64;
+enum : int32_t {
+  MS_BAD = 1,       // check: an invalid mask or a non-finite elevation
+  MS_UP = 2,        // check: some cell sends to row r - 1
+  MS_DN = 4,        // check: some cell sends to row r + 1
+  MS_TAKEN = 8,     // decision: the row sweep serves the call
+  MS_FLOW_UP = 16,  // decision: receivers lie in row r - 1
+};
+struct MsParams {
+  int64_t nrows, ncols;
+  const uint8_t* code;     // MFD masks
+  const float* z;
+  double p;
+  const float* src32;      // rain / qbar, float32, or NULL
+  const double* src64;     // float64, or NULL (both NULL: unit)
+  float* vhi;              // float32 output (float-float accumulation), or NULL
+  double* v64;             // float64 output, or NULL
+  uint64_t* ring;          // [strip][MS_RING][MS_OWN] published words
+  int32_t* progress;       // [strip] rows finished
+  double* partial;         // [strip][2] mass partials (forward), or NULL
+  uint64_t* junk;          // [strip][2][64] store slots of lanes that own no column
+  int32_t* status;
+  int32_t nstrips;
+};
+int64_t ms_strips(int64_t ncols);
+size_t ms_ring_words(int64_t ncols);
+int64_t ms_max_strips();
+// Check, decision and the sweep; every kernel after the decision is gated by
+// the control block.
+hipError_t launch_ms(ValKind vk, bool adjoint, const MsParams& P, CallCtl* C, hipStream_t s);
 int64_t ws_strips(int64_t ncols);
 // Wavefront sweep: set-up (edge records, direction probe, first pass's
 // control), then passes, each followed by a control step that counts the

@@ -1164,7 +1164,10 @@ __global__ __launch_bounds__(256) void k_ws_ctl(WsParams P, CallCtl* C, int pass
   __shared__ int s_run;
   if (threadIdx.x == 0) {
     int run = 0;
-    if (pass < 0) {
+    if (pass < 0 && (C->ms_flags & MS_TAKEN)) {
+      // The row sweep has served the call: no pass runs.
+      C->sweep_stop = 1;
+    } else if (pass < 0) {
       // Visit first the rows holding most inputs: forward inputs are donors,
       // upstream of their receivers; adjoint inputs are the receivers.
       const bool flows_up = P.ctr[1] >= P.ctr[2];

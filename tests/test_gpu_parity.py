@@ -66,10 +66,11 @@ def d8path(request):
         yield request.param
 
 
-@pytest.fixture(params=["sweep", "engine"])
+@pytest.fixture(params=["rows", "sweep", "engine"])
 def accpath(request):
-    """MFD and adjoint accumulation: the wavefront sweep (default) or the
-    peeling engine."""
+    """MFD and adjoint accumulation: the automatic choice (the row sweep
+    where no cell sends against a row order, else the wavefront sweep), the
+    wavefront sweep forced, or the peeling engine."""
     with fr.accumulate_path(_ACC_PATH[request.param]):
         yield request.param
 
