@@ -225,8 +225,8 @@ int g_path = FR_PATH_AUTO;
 
 // The row sweep is tried for MFD masks under the automatic path choice when
 // all of its strips can be resident at once.
-bool ms_applicable(RuleKind rk, int64_t ncols) {
-  return rk == RK_MULTI && g_path == FR_PATH_AUTO && ms_strips(ncols) <= ms_max_strips();
+bool ms_applicable(RuleKind rk, ValKind vk, int64_t ncols) {
+  return rk == RK_MULTI && g_path == FR_PATH_AUTO && ms_strips(ncols) <= ms_max_strips(vk);
 }
 
 constexpr int kMaxSweepPasses = 32;
@@ -612,7 +612,7 @@ int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t nc
     return FR_OK;
   } else {
     const WsLayout WL = ws_layout(nrows, ncols, q_dtype);
-    if (ms_applicable(cfg.rk, ncols)) {
+    if (ms_applicable(cfg.rk, cfg.vk, ncols)) {
       MsParams M = ms_params(nrows, ncols, code, z, mfd_p, body, WL, dev_status);
       M.src32 = r32;
       M.src64 = r64;
@@ -860,7 +860,7 @@ int fr_accumulate_adjoint(const float* z, const uint8_t* code, int64_t nrows, in
     if (hipGetLastError() != hipSuccess) return FR_ERR_HIP;
   } else {
     const WsLayout WL = ws_layout(nrows, ncols, dtype);
-    if (ms_applicable(cfg.rk, ncols)) {
+    if (ms_applicable(cfg.rk, cfg.vk, ncols)) {
       MsParams M = ms_params(nrows, ncols, code, z, mfd_p, body, WL, dev_status);
       M.src32 = s32;
       M.src64 = s64;

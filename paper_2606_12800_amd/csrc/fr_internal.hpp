@@ -333,7 +333,7 @@ struct MsParams {
 };
 int64_t ms_strips(int64_t ncols);
 size_t ms_ring_words(int64_t ncols);
-int64_t ms_max_strips();
+int64_t ms_max_strips(ValKind vk);
 // Check, decision and the sweep; every kernel after the decision is gated by
 // the control block.
 hipError_t launch_ms(ValKind vk, bool adjoint, const MsParams& P, CallCtl* C, hipStream_t s);

@@ -326,12 +326,21 @@ __device__ __forceinline__ bool wait_words(const uint64_t* addr, bool need, uint
   }
 }
 
-__device__ __forceinline__ bool wait_progress(const int32_t* p, int32_t target) {
-  for (uint32_t it = 0;; ++it) {
-    if (ld_i32(p) >= target) return true;
-    if (it >= MS_SPIN_LIMIT) return false;
-    __builtin_amdgcn_s_sleep(1);
+// Waits until strips lo..hi other than s have finished `target` rows;
+// returns the smallest progress seen then (below target after the spin
+// limit).
+__device__ __noinline__ int32_t wait_strips(const int32_t* progress, int lo, int hi, int s, int32_t target) {
+  int32_t m = INT32_MAX;
+  for (int k = lo; k <= hi; ++k) {
+    if (k == s) continue;
+    int32_t v = ld_i32(progress + k);
+    for (uint32_t it = 0; v < target && it < MS_SPIN_LIMIT; ++it) {
+      __builtin_amdgcn_s_sleep(1);
+      v = ld_i32(progress + k);
+    }
+    m = min(m, v);
   }
+  return m;
 }
 
 // Kinds of source term (rain, or qbar for the adjoint).
@@ -345,39 +354,147 @@ struct SrcT<SRC_F64> {
   using T = double;
 };
 
-// Inputs of one row step, loaded two steps ahead: the code and source of
-// row y(t), and the elevation the step needs next (forward: row y(t + 1),
-// the receiving row; adjoint: row y(t)).
-template <int SRC>
-struct RowIn {
-  float z;
-  uint32_t code;
-  typename SrcT<SRC>::T src;
+// Producer wavefronts per strip: float64 fractions (two transcendental
+// functions per candidate) cost more than the consumer's row step, so two
+// wavefronts share them (alternate rows).
+template <int VK>
+constexpr int ms_producers() {
+  return VK == VK_F64 ? 2 : 1;
+}
+constexpr int MS_PR = 6;  // staged rows per strip (LDS ring)
+
+// One staged row, per lane: the cell's fractions toward its five candidate
+// receivers (next-row dc -1, 0, +1; left; right), its conservation
+// correction, its source term and its code.
+template <int VK>
+struct Stage {
+  typename Arith<VK>::F nm[MS_LANES], n0[MS_LANES], np[MS_LANES], l[MS_LANES], r[MS_LANES];
+  float d[MS_LANES];
+  typename Arith<VK>::V src[MS_LANES];
+  uint32_t code[MS_LANES];
 };
 
-// One wavefront per strip.  FLOW_UP: receivers lie in row r - 1 (forward
-// sweep visits rows from the last to the first); else in row r + 1.  ADJ:
-// the adjoint, visiting rows the other way and pulling from receivers.
+__device__ __forceinline__ int32_t lds_ld(int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_st(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// LDS operations of one wavefront are performed in issue order; these keep
+// the compiler from moving the staged data across the flag words.
+__device__ __forceinline__ void compiler_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+
+// One workgroup per strip: wavefront 0 is the consumer, which runs the row
+// recurrence for the strip's 64-column window; the others are producers,
+// which load each row's codes, elevations and source terms and compute the
+// fractions into an LDS ring of MS_PR rows ahead of the consumer.
+// FLOW_UP: receivers lie in row r - 1 (the forward sweep visits rows from
+// the last to the first); else in row r + 1.  ADJ: the adjoint, visiting
+// rows the other way and pulling from receivers.
 //
-// Every global load and store of a row step is issued by every lane (loads
-// of columns or rows off the grid read a clamped address and are
-// discarded; stores of lanes that own no column go to a scratch slot), so
-// the compiler can count outstanding memory operations exactly and a step
-// never waits for the loads it issued for a later row.
+// Every global store of a consumer step is issued by every lane (stores of
+// lanes that own no column go to a scratch slot), so the compiler can count
+// outstanding memory operations exactly.
 template <int VK, bool ADJ, bool FLOW_UP, int SRC>
-__global__ __launch_bounds__(64) void k_ms(MsParams P, const CallCtl* C) {
+__global__ __launch_bounds__(64 * (1 + ms_producers<VK>())) void k_ms(MsParams P, const CallCtl* C) {
   using A = Arith<VK>;
   using V = typename A::V;
   using F = typename A::F;
-  using In = RowIn<SRC>;
+  constexpr int NP = ms_producers<VK>();
   const int32_t gate = C->ms_flags;
   if (!(gate & MS_TAKEN) || ((gate & MS_FLOW_UP) != 0) != FLOW_UP) return;
 
-  const int lane = (int)threadIdx.x;
+  __shared__ Stage<VK> stage[MS_PR];
+  __shared__ int32_t slot_row[MS_PR];  // row held by each slot (-1: none yet)
+  __shared__ int32_t cons_row;         // rows the consumer has taken
+  __shared__ int32_t abort_flag;       // set by the consumer when it gives up
+  if (threadIdx.x < MS_PR) slot_row[threadIdx.x] = -1;
+  if (threadIdx.x == 0) {
+    cons_row = -1;
+    abort_flag = 0;
+  }
+  __syncthreads();
+
+  const int wave = (int)threadIdx.x >> 6;
+  const int lane = (int)threadIdx.x & 63;
   const int s = (int)blockIdx.x;
   const int64_t nr = P.nrows, nc = P.ncols;
   const int64_t col = (int64_t)s * MS_OWN - MS_G + lane;
   const bool valid = col >= 0 && col < nc;
+  const int64_t ccol = valid ? col : 0;
+  // Rows in visiting order: step t visits row y(t).
+  const bool rows_down = ADJ ? FLOW_UP : !FLOW_UP;  // true: y = t
+  auto row_of = [&](int64_t t) { return rows_down ? t : nr - 1 - t; };
+
+  if (wave > 0) {
+    // ------------------------------------------------------------ producer
+    // Window-edge lanes do not see the column beyond: that candidate is
+    // dropped from their masks (their fractions are then wrong, and the
+    // consumer treats their values as dirty anyway).
+    uint32_t drop_mask = 0;
+    if (lane == 0) drop_mask |= (1u << 0) | (1u << 3);   // nm, l
+    if (lane == 63) drop_mask |= (1u << 2) | (1u << 4);  // np, r
+    constexpr int kn0 = FLOW_UP ? 0 : 5;
+    const float pf = (float)P.p;
+    // The receiving row of step t: forward the next row visited, adjoint
+    // the previous one.
+    auto recv_step = [&](int64_t t) -> int64_t { return ADJ ? t - 1 : t + 1; };
+    struct Raw {
+      float zc, zo;
+      uint32_t code;
+      typename SrcT<SRC>::T src;
+    };
+    auto load_raw = [&](int64_t t) -> Raw {
+      Raw w;
+      const int64_t tc = t < nr ? t : nr - 1;
+      const int64_t i = row_of(tc) * nc + ccol;
+      w.code = P.code[i];
+      w.zc = P.z[i];
+      int64_t tr = recv_step(tc);
+      tr = tr < 0 ? 0 : (tr >= nr ? nr - 1 : tr);
+      w.zo = P.z[row_of(tr) * nc + ccol];
+      if constexpr (SRC == SRC_F32) w.src = P.src32[i];
+      else if constexpr (SRC == SRC_F64) w.src = P.src64[i];
+      else w.src = 0;
+      return w;
+    };
+    const int k = wave - 1;
+    Raw nx = load_raw(k);
+    for (int64_t t = k; t < nr; t += NP) {
+      const Raw cur = nx;
+      nx = load_raw(t + NP);
+      const int slot = (int)(t % MS_PR);
+      // Wait until the consumer has released the row this slot held (it
+      // keeps its current row and the one before).
+      while (lds_ld(&cons_row) <= t - MS_PR) {
+        if (lds_ld(&abort_flag)) return;
+        __builtin_amdgcn_s_sleep(1);
+      }
+      const int64_t tr = recv_step(t);
+      const float zo = (tr >= 0 && tr < nr) ? cur.zo : 0.0f;
+      uint32_t m = ((cur.code >> kn0) & 7u) | (((cur.code >> 3) & 3u) << 3);
+      m = valid ? (m & ~drop_mask) : 0u;
+      const Frac<VK, FLOW_UP> fr =
+          fractions<VK, FLOW_UP>(cur.zc, sh_l(zo), zo, sh_r(zo), sh_l(cur.zc), sh_r(cur.zc), m, pf, P.p);
+      V sv;
+      if constexpr (SRC == SRC_UNIT) sv = A::one();
+      else sv = A::from_src(cur.src);
+      Stage<VK>& S = stage[slot];
+      S.nm[lane] = fr.nm;
+      S.n0[lane] = fr.n0;
+      S.np[lane] = fr.np;
+      S.l[lane] = fr.l;
+      S.r[lane] = fr.r;
+      S.d[lane] = fr.d;
+      S.src[lane] = sv;
+      S.code[lane] = valid ? cur.code : 0u;
+      compiler_fence();
+      if (lane == 0) lds_st(&slot_row[slot], (int32_t)t);
+    }
+    return;
+  }
+
+  // -------------------------------------------------------------- consumer
   const bool owned = valid && lane >= MS_G && lane < MS_G + MS_OWN;
   const uint64_t vmask = ballot(valid);
   const uint64_t own_mask = kOwn & vmask;
@@ -389,24 +506,6 @@ __global__ __launch_bounds__(64) void k_ms(MsParams P, const CallCtl* C) {
   // Strips whose owned columns are ghost columns here (MS_NB on each side).
   const int nb_lo = s - MS_NB < 0 ? 0 : s - MS_NB;
   const int nb_hi = s + MS_NB > P.nstrips - 1 ? P.nstrips - 1 : s + MS_NB;
-  // Rows in visiting order: step t visits row y(t).
-  const bool rows_down = ADJ ? FLOW_UP : !FLOW_UP;  // true: y = t
-  auto row_of = [&](int64_t t) { return rows_down ? t : nr - 1 - t; };
-  const int64_t ccol = valid ? col : 0;
-  const float pf = (float)P.p;
-
-  // Window-edge lanes do not see the column beyond: that candidate is
-  // dropped from their masks (their fractions are then wrong, and their
-  // values dirty anyway).
-  uint32_t drop_mask = 0;
-  if (lane == 0) drop_mask |= (1u << 0) | (1u << 3);   // nm, l
-  if (lane == 63) drop_mask |= (1u << 2) | (1u << 4);  // np, r
-  // Direction bits of the candidates (nm, n0, np, l, r).
-  constexpr int kn0 = FLOW_UP ? 0 : 5;
-  auto cand = [&](uint32_t code) -> uint32_t {
-    uint32_t m = ((code >> kn0) & 7u) | (((code >> 3) & 3u) << 3);
-    return valid ? (m & ~drop_mask) : 0u;
-  };
 
   // Ring words: a ghost lane reads the owner of its column.
   uint64_t* ring_mine = P.ring + (size_t)s * MS_RING * MS_OWN;
@@ -419,162 +518,165 @@ __global__ __launch_bounds__(64) void k_ms(MsParams P, const CallCtl* C) {
   uint64_t* junk = P.junk + (size_t)s * 2 * MS_LANES + lane;
   uint64_t* pub = owned ? ring_mine + (lane - MS_G) : junk + MS_LANES;
 
-  // Previous row state.
+  // A row's inputs in the form the recurrence takes them: pull weights
+  // toward the previous row's three cells (lane shifts -1, 0, +1), same-row
+  // input fractions from the left / right, with the senders' corrections,
+  // the source term and the masks of lanes taking each input.
+  struct Ctx {
+    F wl, w0, wr, fl, fr;
+    float dwl, dw0, dwr, dfl, dfr;
+    V src;
+    uint32_t code;
+    uint64_t tm, t0, tp, hl, hr;
+  };
+  // The staged rows t - 1 and t stay in the ring while row t is computed.
+  auto load_ctx = [&](int64_t tt) -> Ctx {
+    const Stage<VK>& S = stage[tt % MS_PR];
+    Ctx c;
+    const F nm = S.nm[lane], n0 = S.n0[lane], np = S.np[lane], l = S.l[lane], r = S.r[lane];
+    const float d = S.d[lane];
+    c.src = S.src[lane];
+    c.code = S.code[lane];
+    if (!ADJ) {
+      // Forward: a cell takes a fraction of each upslope neighbour in the
+      // previous row (that cell's own fractions) and of its same-row donors.
+      F pnm = 0, pn0 = 0, pnp = 0;
+      float pd = 0.0f;
+      if (tt > 0) {
+        const Stage<VK>& Q = stage[(tt - 1) % MS_PR];
+        pnm = Q.nm[lane];
+        pn0 = Q.n0[lane];
+        pnp = Q.np[lane];
+        pd = Q.d[lane];
+      }
+      c.wl = sh_l(pnp);
+      c.dwl = sh_l(pd);
+      c.w0 = pn0;
+      c.dw0 = pd;
+      c.wr = sh_r(pnm);
+      c.dwr = sh_r(pd);
+      c.fl = sh_l(r);
+      c.dfl = sh_l(d);
+      c.fr = sh_r(l);
+      c.dfr = sh_r(d);
+    } else {
+      // Adjoint: a cell takes its own fractions of its receivers' values.
+      c.wl = nm;
+      c.w0 = n0;
+      c.wr = np;
+      c.fl = l;
+      c.fr = r;
+      c.dwl = c.dw0 = c.dwr = c.dfl = c.dfr = d;
+    }
+    c.tm = ballot(c.wl != (F)0);
+    c.t0 = ballot(c.w0 != (F)0);
+    c.tp = ballot(c.wr != (F)0);
+    c.hl = ballot(c.fl != (F)0);
+    c.hr = ballot(c.fr != (F)0);
+    return c;
+  };
+  auto pull_prev = [&](const Ctx& c, V vprev) -> V {
+    const V cl = A::contrib_lean(sh_l(vprev), c.wl, c.dwl);
+    const V cm = A::contrib_lean(vprev, c.w0, c.dw0);
+    const V cr = A::contrib_lean(sh_r(vprev), c.wr, c.dwr);
+    return A::norm(A::add_lean(c.src, A::add_lean(A::add_lean(cl, cm), cr)));
+  };
+  auto dirt_prev = [&](const Ctx& c, uint64_t d) -> uint64_t {
+    return ((d << 1) & c.tm) | (d & c.t0) | ((d >> 1) & c.tp);
+  };
+  // One row from the previous row's values and dirt: q and its dirt.
+  auto solve_row = [&](const Ctx& c, V vprev, uint64_t pl, uint64_t pr, V& a, V& q, uint64_t& dl, uint64_t& dr) {
+    a = pull_prev(c, vprev);
+    dl = spread(dirt_prev(c, pl) | edge_l, c.hl, c.hr);
+    dr = spread(dirt_prev(c, pr) | edge_r, c.hl, c.hr);
+    q = lateral<VK>(a, c.fl, c.dfl, c.fr, c.dfr);
+  };
+
+  // Previous row: values and dirt by side of origin.
   V vp = A::zero();
-  F fpm = 0, fp0 = 0, fpp = 0;  // forward: the previous cell's fractions toward this row
-  float dp = 0.0f;
-  uint64_t dpl = 0, dpr = 0;           // dirt of the previous row's values, by side of origin
-  uint64_t spm = 0, sp0 = 0, spp = 0;  // forward: previous-row lanes sending dc -1, 0, +1
-  float z_keep = 0.0f;                 // forward: z of this row; adjoint: z of the previous row
+  uint64_t dpl = 0, dpr = 0;
 
   double msum = 0.0, rsum = 0.0;
   bool nonfinite = false, stalled = false;
 
-  auto load_in = [&](int64_t t) -> In {
-    In in;
-    const int64_t tc = t < nr ? t : nr - 1;
-    const int64_t i = row_of(tc) * nc + ccol;
-    in.code = P.code[i];
-    if constexpr (SRC == SRC_F32) in.src = P.src32[i];
-    else if constexpr (SRC == SRC_F64) in.src = P.src64[i];
-    else in.src = 0;
-    const int64_t tz = ADJ ? tc : (t + 1 < nr ? t + 1 : nr - 1);
-    in.z = P.z[row_of(tz) * nc + ccol];
-    return in;
-  };
-
-  // One row step; false when a wait gave up.
-  auto step = [&](int64_t t, In& in) -> bool {
+  for (int64_t t = 0; t < nr && !stalled; ++t) {
     const int64_t y = row_of(t);
     const int64_t i = y * nc + ccol;
-    // This step's inputs (loaded two steps ago); the loads for the step
-    // after next are issued at once, so the row's work hides their latency.
-    const In cur = in;
-    in = load_in(t + 2);
-    const uint32_t code = cur.code;
-    V srcv;
-    if constexpr (SRC == SRC_UNIT) srcv = A::one();
-    else srcv = A::from_src(cur.src);
-    if (!valid) srcv = A::zero();
-    if (!A::finite(srcv)) {
-      nonfinite = true;
-      srcv = A::zero();
-    }
-    float zc, zo;  // this row; the receiving row
-    if (!ADJ) {
-      zc = z_keep;
-      zo = t + 1 < nr ? cur.z : 0.0f;
-      z_keep = zo;
-    } else {
-      zc = cur.z;
-      zo = z_keep;
-      z_keep = zc;
-    }
-    const uint32_t rcv = cand(code);
-    const Frac<VK, FLOW_UP> fr =
-        fractions<VK, FLOW_UP>(zc, sh_l(zo), zo, sh_r(zo), sh_l(zc), sh_r(zc), rcv, pf, P.p);
-
-    // Same-row inputs: fraction taken from the left / right neighbour.
-    F fin_l, fin_r;
-    float din_l, din_r;
-    if (!ADJ) {
-      fin_l = sh_l(fr.r);
-      din_l = sh_l(fr.d);
-      fin_r = sh_r(fr.l);
-      din_r = sh_r(fr.d);
-    } else {
-      fin_l = fr.l;
-      din_l = fr.d;
-      fin_r = fr.r;
-      din_r = fr.d;
-    }
-    const uint64_t hl = ballot(fin_l != (F)0), hr = ballot(fin_r != (F)0);
-    // Previous-row inputs and their dirt.
-    uint64_t tm, t0, tp;  // lanes taking from the previous row at dc -1, 0, +1 (relative to the taker)
-    if (!ADJ) {
-      tm = spp << 1;
-      t0 = sp0;
-      tp = spm >> 1;
-    } else {
-      tm = ballot(fr.nm != (F)0);
-      t0 = ballot(fr.n0 != (F)0);
-      tp = ballot(fr.np != (F)0);
-    }
-    auto pull_prev = [&](V vprev) -> V {
-      const V vl = sh_l(vprev), vr = sh_r(vprev);
-      V cl, cm, cr;
-      if (!ADJ) {
-        cl = A::contrib_lean(vl, sh_l(fpp), sh_l(dp));
-        cm = A::contrib_lean(vprev, fp0, dp);
-        cr = A::contrib_lean(vr, sh_r(fpm), sh_r(dp));
-      } else {
-        cl = A::contrib_lean(vl, fr.nm, fr.d);
-        cm = A::contrib_lean(vprev, fr.n0, fr.d);
-        cr = A::contrib_lean(vr, fr.np, fr.d);
+    // Before this row is published, the strips reading this one must be
+    // past the row its ring slot holds (they may still read rows from their
+    // own current row - 1 on).  Checked first, before any of the row's work.
+    const int32_t need_prog = (int32_t)(t - MS_RING + 2);
+    if (need_prog > nb_prog && nb_hi > nb_lo) {
+      nb_prog = wait_strips(P.progress, nb_lo, nb_hi, s, need_prog);
+      if (nb_prog < need_prog) {
+        stalled = true;
+        break;
       }
-      return A::norm(A::add_lean(srcv, A::add_lean(A::add_lean(cl, cm), cr)));
-    };
-    auto dirt_prev = [&](uint64_t d) -> uint64_t { return ((d << 1) & tm) | (d & t0) | ((d >> 1) & tp); };
+    }
+    // This row's staged inputs; rows up to t - 2 are released (forward, the
+    // previous row's fractions are read again with this row's).
+    const int slot = (int)(t % MS_PR);
+    while (lds_ld(&slot_row[slot]) != (int32_t)t) __builtin_amdgcn_s_sleep(1);
+    compiler_fence();
+    Ctx cx = load_ctx(t);
+    compiler_fence();
+    if (lane == 0) lds_st(&cons_row, (int32_t)(t - 1));
+    if (!valid) cx.src = A::zero();
+    if (!A::finite(cx.src)) {
+      nonfinite = true;
+      cx.src = A::zero();
+    }
 
-    V a = pull_prev(vp);
-    uint64_t dl = spread(dirt_prev(dpl) | edge_l, hl, hr);
-    uint64_t dr = spread(dirt_prev(dpr) | edge_r, hl, hr);
-    V q = lateral<VK>(a, fin_l, din_l, fin_r, din_r);
+    V a, q;
+    uint64_t dl, dr;
+    solve_row(cx, vp, dpl, dpr, a, q, dl, dr);
 
     if ((dl | dr) & own_mask) {
       // Stage 1: exact previous-row ghost values of the dirty side(s).
-      const bool need_l = (dl & own_mask) != 0, need_r = (dr & own_mask) != 0;
-      if (t > 0) {
-        const uint32_t tag = (uint32_t)((t - 1) & 0xFF);
-        const int slot = (int)((t - 1) % MS_RING);
+      if (t >= 1) {
+        const bool need_l = (dl & own_mask) != 0, need_r = (dr & own_mask) != 0;
         const bool ld = valid && ((need_l && ghost_l) || (need_r && ghost_r));
+        const uint32_t tag = (uint32_t)((t - 1) & 0xFF);
+        const int rs = (int)((t - 1) % MS_RING);
         V got = vp;
-        if (!wait_words<VK>(ld ? ring_ghost + (size_t)slot * MS_OWN : nullptr, ld, tag, got)) return false;
+        if (!wait_words<VK>(ld ? ring_ghost + (size_t)rs * MS_OWN : nullptr, ld, tag, got)) {
+          stalled = true;
+          break;
+        }
         vp = got;
         if (need_l) dpl = edge_l;
         if (need_r) dpr = edge_r;
-        a = pull_prev(vp);
-        dl = spread(dirt_prev(dpl) | edge_l, hl, hr);
-        dr = spread(dirt_prev(dpr) | edge_r, hl, hr);
-        q = lateral<VK>(a, fin_l, din_l, fin_r, din_r);
+        solve_row(cx, vp, dpl, dpr, a, q, dl, dr);
       }
       // Stage 2: a same-row chain from beyond the window -- the
       // neighbour's values of this row for that side's ghost columns.
       const bool need2_l = (dl & own_mask) != 0, need2_r = (dr & own_mask) != 0;
       if (need2_l || need2_r) {
         const uint32_t tag = (uint32_t)(t & 0xFF);
-        const int slot = (int)(t % MS_RING);
+        const int rs = (int)(t % MS_RING);
         const bool ld = valid && ((need2_l && ghost_l) || (need2_r && ghost_r));
         V got = a;
-        if (!wait_words<VK>(ld ? ring_ghost + (size_t)slot * MS_OWN : nullptr, ld, tag, got)) return false;
+        if (!wait_words<VK>(ld ? ring_ghost + (size_t)rs * MS_OWN : nullptr, ld, tag, got)) {
+          stalled = true;
+          break;
+        }
         // Fixed ghost values take no same-row input.
-        F gl = fin_l, gr = fin_r;
+        F gl = cx.fl, gr = cx.fr;
         if (ld) {
           a = got;
           gl = 0;
           gr = 0;
         }
         const uint64_t fixed = ballot(ld);
-        const uint64_t hl2 = hl & ~fixed, hr2 = hr & ~fixed;
-        q = lateral<VK>(a, gl, din_l, gr, din_r);
-        dl = spread((dirt_prev(dpl) | edge_l) & ~fixed, hl2, hr2);
-        dr = spread((dirt_prev(dpr) | edge_r) & ~fixed, hl2, hr2);
-        if ((dl | dr) & own_mask) return false;  // cannot happen: the fixed columns separate the owned ones
+        const uint64_t hl2 = cx.hl & ~fixed, hr2 = cx.hr & ~fixed;
+        q = lateral<VK>(a, gl, cx.dfl, gr, cx.dfr);
+        dl = spread((dirt_prev(cx, dpl) | edge_l) & ~fixed, hl2, hr2);
+        dr = spread((dirt_prev(cx, dpr) | edge_r) & ~fixed, hl2, hr2);
+        if ((dl | dr) & own_mask) {
+          stalled = true;  // cannot happen: the fixed columns separate the owned ones
+          break;
+        }
       }
-    }
-
-    // Before publishing, the strips reading this one must be past the row
-    // the ring slot holds (they may still read rows from their own current
-    // row - 1 on).
-    const int64_t need_prog = t - MS_RING + 2;
-    if (need_prog > nb_prog && nb_hi > nb_lo) {
-      int32_t m = INT32_MAX;
-      for (int k = nb_lo; k <= nb_hi; ++k) {
-        if (k == s) continue;
-        if (!wait_progress(P.progress + k, (int32_t)need_prog)) return false;
-        m = min(m, ld_i32(P.progress + k));
-      }
-      nb_prog = m;
     }
 
     // Results: the owned cells, the ring word, the progress word.
@@ -588,46 +690,25 @@ __global__ __launch_bounds__(64) void k_ms(MsParams P, const CallCtl* C) {
     st_word(pub + (size_t)(t % MS_RING) * (owned ? MS_OWN : 0), A::pack(q, (uint32_t)(t & 0xFF)));
     st_i32(P.progress + s, (int32_t)(t + 1));
     if (owned) {
-      if (!ADJ && code == 0u) msum += A::wide(q);
-      rsum += A::wide(srcv);
+      if (!ADJ && cx.code == 0u) msum += A::wide(q);
+      rsum += A::wide(cx.src);
     }
 
     // This row becomes the previous one.
     vp = q;
     dpl = dl | edge_l;
     dpr = dr | edge_r;
-    if (!ADJ) {
-      fpm = fr.nm;
-      fp0 = fr.n0;
-      fpp = fr.np;
-      dp = fr.d;
-      spm = ballot(fr.nm != (F)0);
-      sp0 = ballot(fr.n0 != (F)0);
-      spp = ballot(fr.np != (F)0);
-    }
-    return true;
-  };
-
-  if (!ADJ) z_keep = P.z[row_of(0) * nc + ccol];
-  In b0 = load_in(0), b1 = load_in(1);
-  for (int64_t t = 0; t < nr; t += 2) {
-    if (!step(t, b0)) {
-      stalled = true;
-      break;
-    }
-    if (t + 1 >= nr) break;
-    if (!step(t + 1, b1)) {
-      stalled = true;
-      break;
-    }
   }
 
   if (ballot(nonfinite && valid) && lane == 0 && P.status) atomicCAS(P.status, 0, FR_ERR_NONFINITE);
   if (ballot(stalled)) {
-    if (lane == 0 && P.status) atomicCAS(P.status, 0, FR_ERR_STALL);
-    // Let the neighbours see this strip as finished, so their waits for it
-    // end too (their results are void, the status says so).
-    if (lane == 0) st_i32(P.progress + s, INT32_MAX);
+    if (lane == 0) {
+      lds_st(&abort_flag, 1);
+      if (P.status) atomicCAS(P.status, 0, FR_ERR_STALL);
+      // Let the neighbours see this strip as finished, so their waits for
+      // it end too (their results are void, the status says so).
+      st_i32(P.progress + s, INT32_MAX);
+    }
     return;
   }
   // Mass balance partials in a fixed order (Section 4 verification).
@@ -693,8 +774,9 @@ template <int VK, bool ADJ, int SRC>
 hipError_t ms_launch_src(const MsParams& P, const CallCtl* C, hipStream_t s) {
   // Both row orientations are launched; the one the check did not pick
   // returns at once.
-  hipLaunchKernelGGL((k_ms<VK, ADJ, true, SRC>), dim3((unsigned)P.nstrips), dim3(64), 0, s, P, C);
-  hipLaunchKernelGGL((k_ms<VK, ADJ, false, SRC>), dim3((unsigned)P.nstrips), dim3(64), 0, s, P, C);
+  const dim3 block(64 * (1 + ms_producers<VK>()));
+  hipLaunchKernelGGL((k_ms<VK, ADJ, true, SRC>), dim3((unsigned)P.nstrips), block, 0, s, P, C);
+  hipLaunchKernelGGL((k_ms<VK, ADJ, false, SRC>), dim3((unsigned)P.nstrips), block, 0, s, P, C);
   return hipGetLastError();
 }
 
@@ -722,24 +804,40 @@ hipError_t launch_ms(ValKind vk, bool adjoint, const MsParams& P, CallCtl* C, hi
   return adjoint ? ms_launch_t<VK_FF, true>(P, C, s) : ms_launch_t<VK_FF, false>(P, C, s);
 }
 
-// Largest number of strips whose wavefronts can all be resident at once
-// (the pass waits between neighbouring strips).
-int64_t ms_max_strips() {
-  static int64_t cached = -1;
-  if (cached >= 0) return cached;
-  int dev = 0, cus = 0, per_cu = 0;
+// Largest number of strips whose workgroups can all be resident at once
+// (the pass waits between neighbouring strips), for the given precision:
+// the smallest occupancy over the kernel variants of that precision.
+int64_t ms_max_strips(ValKind vk) {
+  static int64_t cached[3] = {-1, -1, -1};
+  const int idx = vk == VK_F64 ? 2 : 1;
+  if (cached[idx] >= 0) return cached[idx];
+  int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_ms<VK_F64, true, true, SRC_F64>),
-                                                   64, 0) != hipSuccess)
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  int pc2 = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc2, reinterpret_cast<const void*>(&k_ms<VK_FF, false, true, SRC_F32>), 64,
-                                                   0) == hipSuccess &&
-      pc2 < per_cu)
-    per_cu = pc2;
-  cached = (int64_t)cus * per_cu;
-  return cached;
+  const void* kf[4];
+  int block;
+  if (vk == VK_F64) {
+    kf[0] = reinterpret_cast<const void*>(&k_ms<VK_F64, false, true, SRC_UNIT>);
+    kf[1] = reinterpret_cast<const void*>(&k_ms<VK_F64, false, true, SRC_F64>);
+    kf[2] = reinterpret_cast<const void*>(&k_ms<VK_F64, true, true, SRC_F64>);
+    kf[3] = reinterpret_cast<const void*>(&k_ms<VK_F64, true, false, SRC_F32>);
+    block = 64 * (1 + ms_producers<VK_F64>());
+  } else {
+    kf[0] = reinterpret_cast<const void*>(&k_ms<VK_FF, false, true, SRC_UNIT>);
+    kf[1] = reinterpret_cast<const void*>(&k_ms<VK_FF, false, true, SRC_F64>);
+    kf[2] = reinterpret_cast<const void*>(&k_ms<VK_FF, true, true, SRC_F64>);
+    kf[3] = reinterpret_cast<const void*>(&k_ms<VK_FF, true, false, SRC_F32>);
+    block = 64 * (1 + ms_producers<VK_FF>());
+  }
+  int per_cu = 1 << 30;
+  for (const void* k : kf) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, block, 0) != hipSuccess) return 0;
+    per_cu = n < per_cu ? n : per_cu;
+  }
+  cached[idx] = (int64_t)cus * per_cu;
+  return cached[idx];
 }
 
 }  // namespace fr
