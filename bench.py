@@ -70,6 +70,16 @@ def roofline(achieved_gbs, kernel, key, phase, **extra):
     return r
 
 
+def copy_probe(dev):
+    """One 1 GiB device copy: the reference for HBM byte counters."""
+    import torch
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -193,12 +203,19 @@ def run_secondary(args, workload):
                    "cells": n * n},
         "detail": out,
     }
-    # The sweep is bound by the latency of its row steps, not by HBM; the
-    # roofline below states how far from the HBM bound that leaves it.
-    ms = out["f32"]["phase_ms"].get("sweep", out["f32"]["ms_per_step"])
+    # The sweeps are bound by the latency of their row steps, not by HBM;
+    # the roofline below states how far from the HBM bound that leaves them.
+    # The dominant sweep is the row sweep (k_ms) where no cell sends
+    # against the row order, else the windowed wavefront sweep.
+    ph = out["f32"]["phase_ms"]
+    phase = "row_sweep" if ph.get("row_sweep", 0.0) >= ph.get("sweep", 0.0) else "sweep"
+    ms = ph.get(phase, out["f32"]["ms_per_step"])
+    kernel = "k_ms (row sweep, producer + consumer)" if phase == "row_sweep" else "k_ws_pass (all passes)"
     achieved = SWEEP_BYTES[workload] * n * n / (ms * 1e-3) / 1e9
-    line["roofline"] = roofline(achieved, "k_ws_pass (all passes)", (workload, n, n), "sweep",
+    line["roofline"] = roofline(achieved, kernel, (workload, n, n), phase,
                                 bytes_per_cell=SWEEP_BYTES[workload], ms_per_launch=ms, row_step_us=1e3 * ms / n)
+    if args.copy_probe:
+        copy_probe(torch.device("cuda:0"))
     if not args.no_cpu_baseline:
         # MFD: an 8192^2 sample (~15 s on one core); adjoint: the whole 4096^2 workload.
         size = args.cpu_size if "--cpu-size" in sys.argv else (8192 if workload == "mfd" else n)
@@ -665,11 +682,7 @@ def run_d8(args):
     fr.timing_enable(False)
 
     if args.copy_probe:
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_probe(dev)
 
     m = mass.cpu().numpy()
     total_cells_counts = int(cnt.view(torch.int64)[code == 0xFF].sum().item())

@@ -117,7 +117,7 @@ D8Layout d8_layout(int64_t nrows, int64_t ncols, int th, int vdtype, bool counts
 
 // Wavefront sweep (fr_wsweep.hip).  The engine overlays it too.
 struct WsLayout {
-  size_t vlo, edge, progress, ctr, partial, ms_ring, ms_progress, ms_partial, ms_junk, total;
+  size_t vlo, edge, progress, ctr, partial, ms_ring, ms_progress, ms_partial, total;
 };
 
 WsLayout ws_layout(int64_t nrows, int64_t ncols, int vdtype) {
@@ -133,7 +133,6 @@ WsLayout ws_layout(int64_t nrows, int64_t ncols, int vdtype) {
   L.ms_ring = o; o += up(ms_ring_words(ncols) * sizeof(uint64_t));
   L.ms_progress = o; o += up((size_t)ms_strips(ncols) * sizeof(int32_t));
   L.ms_partial = o; o += up((size_t)ms_strips(ncols) * 2 * sizeof(double));
-  L.ms_junk = o; o += up((size_t)ms_strips(ncols) * 2 * 64 * sizeof(uint64_t));
   L.total = o;
   return L;
 }
@@ -150,7 +149,6 @@ MsParams ms_params(int64_t nrows, int64_t ncols, const uint8_t* code, const floa
   M.ring = reinterpret_cast<uint64_t*>(body + L.ms_ring);
   M.progress = reinterpret_cast<int32_t*>(body + L.ms_progress);
   M.partial = reinterpret_cast<double*>(body + L.ms_partial);
-  M.junk = reinterpret_cast<uint64_t*>(body + L.ms_junk);
   M.status = status;
   M.nstrips = (int32_t)ms_strips(ncols);
   return M;

@@ -309,7 +309,6 @@ constexpr int MS_OWN = 64 - 2 * MS_G;
 constexpr int MS_NB = (MS_G + MS_OWN - 1) / MS_OWN;  // strips on each side that hold ghost columns
 constexpr int MS_RING = 64;
 enum : int32_t {
-  MS_BAD = 1,       // check: an invalid mask or a non-finite elevation
   MS_UP = 2,        // check: some cell sends to row r - 1
   MS_DN = 4,        // check: some cell sends to row r + 1
   MS_TAKEN = 8,     // decision: the row sweep serves the call
@@ -327,7 +326,6 @@ struct MsParams {
   uint64_t* ring;          // [strip][MS_RING][MS_OWN] published words
   int32_t* progress;       // [strip] rows finished
   double* partial;         // [strip][2] mass partials (forward), or NULL
-  uint64_t* junk;          // [strip][2][64] store slots of lanes that own no column
   int32_t* status;
   int32_t nstrips;
 };

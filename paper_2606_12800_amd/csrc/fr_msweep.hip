@@ -10,14 +10,16 @@
 // cells of the previous row and on chains of same-row neighbours, so the
 // grid is solved row by row: every column of a row at once.
 //
-// GPU mapping.  One wavefront owns a strip of MS_OWN columns and computes a
+// GPU mapping.  One workgroup owns a strip of MS_OWN columns and computes a
 // window of 64 columns, lane = column: the owned columns and MS_G columns of
 // each neighbouring strip ("ghost" columns), recomputed from the same
-// inputs.  A row step pulls the previous row's values of the three upslope
-// neighbours through lane shifts (DPP), then resolves same-row chains by
-// repeated lane-shifted pulls until no value changes (chains on this kind of
-// terrain are a few cells long).  No value leaves the wavefront except the
-// owned results.
+// inputs.  Producer wavefronts load each row's codes, elevations and source
+// terms and compute the cells' fractions into a ring of rows in LDS, ahead
+// of the consumer wavefront, which runs the recurrence: a row step pulls
+// the previous row's values of the three upslope neighbours through lane
+// shifts (DPP), then resolves same-row chains by repeated lane-shifted
+// pulls until no value changes (chains on this kind of terrain are a few
+// cells long).  No value leaves the consumer except the owned results.
 //
 // Ghost columns cannot see beyond the window: the two edge columns never
 // know all of their inputs, and what they compute spreads inward along the
@@ -41,12 +43,13 @@
 // passed the row it holds.
 //
 // The pass applies only when the codes admit it: a check before it reads
-// every code and elevation and takes the pass only if the masks are valid
-// (receivers strictly lower, on the grid, elevations finite) and no cell
-// sends to the row before it in one of the two row orders.  Otherwise the
-// general wavefront sweep runs instead.  Results are exact up to rounding
-// and do not depend on timing: which ghost columns are refreshed, and with
-// what, depends only on the data.
+// every code and takes the pass only if no cell sends to the row before it
+// in one of the two row orders; otherwise the general wavefront sweep runs
+// instead.  The pass itself reports masks whose receivers are off the grid
+// or not strictly lower, and non-finite elevations, as the general sweep
+// does.  Results are exact up to rounding and do not depend on timing:
+// which ghost columns are refreshed, and with what, depends only on the
+// data.
 //
 // Precision: float-float accumulation for float32 output (hi written; the
 // low part stays in registers), float64 otherwise; fractions as in the
@@ -384,6 +387,16 @@ __device__ __forceinline__ void lds_st(int32_t* p, int32_t v) {
 // the compiler from moving the staged data across the flag words.
 __device__ __forceinline__ void compiler_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
 
+// Workgroup b runs on XCD b % 8; XCD x takes the x-th contiguous range of
+// strips (the first n % 8 ranges one strip longer), so that only 7 strip
+// boundaries cross XCDs.  A bijection of 0 .. n - 1.
+constexpr int MS_XCDS = 8;
+__device__ __forceinline__ int ms_strip_of_block(int b, int n) {
+  const int x = b % MS_XCDS, k = b / MS_XCDS;
+  const int q = n / MS_XCDS, r = n % MS_XCDS;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // One workgroup per strip: wavefront 0 is the consumer, which runs the row
 // recurrence for the strip's 64-column window; the others are producers,
 // which load each row's codes, elevations and source terms and compute the
@@ -392,9 +405,9 @@ __device__ __forceinline__ void compiler_fence() { __atomic_signal_fence(__ATOMI
 // the last to the first); else in row r + 1.  ADJ: the adjoint, visiting
 // rows the other way and pulling from receivers.
 //
-// Every global store of a consumer step is issued by every lane (stores of
-// lanes that own no column go to a scratch slot), so the compiler can count
-// outstanding memory operations exactly.
+// Strips are numbered so that neighbouring strips run on the same XCD (the
+// hardware deals workgroups to the 8 XCDs in turn): their overlapping
+// columns and exchanged words then meet in one L2.
 template <int VK, bool ADJ, bool FLOW_UP, int SRC>
 __global__ __launch_bounds__(64 * (1 + ms_producers<VK>())) void k_ms(MsParams P, const CallCtl* C) {
   using A = Arith<VK>;
@@ -417,7 +430,7 @@ __global__ __launch_bounds__(64 * (1 + ms_producers<VK>())) void k_ms(MsParams P
 
   const int wave = (int)threadIdx.x >> 6;
   const int lane = (int)threadIdx.x & 63;
-  const int s = (int)blockIdx.x;
+  const int s = ms_strip_of_block((int)blockIdx.x, P.nstrips);
   const int64_t nr = P.nrows, nc = P.ncols;
   const int64_t col = (int64_t)s * MS_OWN - MS_G + lane;
   const bool valid = col >= 0 && col < nc;
@@ -444,25 +457,42 @@ __global__ __launch_bounds__(64 * (1 + ms_producers<VK>())) void k_ms(MsParams P
       uint32_t code;
       typename SrcT<SRC>::T src;
     };
+    // A single producer visits every row and loads each elevation row
+    // once, carrying the other row of a step over from the step before.
+    constexpr bool CARRY = NP == 1;
     auto load_raw = [&](int64_t t) -> Raw {
       Raw w;
       const int64_t tc = t < nr ? t : nr - 1;
       const int64_t i = row_of(tc) * nc + ccol;
       w.code = P.code[i];
-      w.zc = P.z[i];
       int64_t tr = recv_step(tc);
       tr = tr < 0 ? 0 : (tr >= nr ? nr - 1 : tr);
-      w.zo = P.z[row_of(tr) * nc + ccol];
+      // Carrying: forward loads only the receiving (next) row, adjoint only
+      // this row.
+      if (!CARRY || ADJ) w.zc = P.z[i];
+      if (!CARRY || !ADJ) w.zo = P.z[row_of(tr) * nc + ccol];
       if constexpr (SRC == SRC_F32) w.src = P.src32[i];
       else if constexpr (SRC == SRC_F64) w.src = P.src64[i];
       else w.src = 0;
       return w;
     };
     const int k = wave - 1;
+    bool bad = false, nonfin = false;
+    float zcarry = 0.0f;  // forward: this row's z (last step's next row); adjoint: the previous row's z
+    if (CARRY && !ADJ) zcarry = P.z[row_of(0) * nc + ccol];
     Raw nx = load_raw(k);
     for (int64_t t = k; t < nr; t += NP) {
-      const Raw cur = nx;
+      Raw cur = nx;
       nx = load_raw(t + NP);
+      if (CARRY) {
+        if (!ADJ) {
+          cur.zc = zcarry;
+          zcarry = cur.zo;
+        } else {
+          cur.zo = zcarry;
+          zcarry = cur.zc;
+        }
+      }
       const int slot = (int)(t % MS_PR);
       // Wait until the consumer has released the row this slot held (it
       // keeps its current row and the one before).
@@ -471,9 +501,24 @@ __global__ __launch_bounds__(64 * (1 + ms_producers<VK>())) void k_ms(MsParams P
         __builtin_amdgcn_s_sleep(1);
       }
       const int64_t tr = recv_step(t);
-      const float zo = (tr >= 0 && tr < nr) ? cur.zo : 0.0f;
-      uint32_t m = ((cur.code >> kn0) & 7u) | (((cur.code >> 3) & 3u) << 3);
-      m = valid ? (m & ~drop_mask) : 0u;
+      const bool has_recv_row = tr >= 0 && tr < nr;
+      const float zo = has_recv_row ? cur.zo : 0.0f;
+      const uint32_t m_all = ((cur.code >> kn0) & 7u) | (((cur.code >> 3) & 3u) << 3);
+      uint32_t m = valid ? (m_all & ~drop_mask) : 0u;
+      if (valid) {
+        // Each receiver must be a strictly lower cell of the grid (the
+        // general sweep reports the same errors); the window's edge lanes
+        // are checked by the strips that own those columns.
+        const float zr[5] = {sh_l(zo), zo, sh_r(zo), sh_l(cur.zc), sh_r(cur.zc)};
+        const bool on_grid[5] = {has_recv_row && col >= 1, has_recv_row, has_recv_row && col + 1 < nc, col >= 1,
+                                 col + 1 < nc};
+        bool badc = false;
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+          if ((m_all >> j) & 1u) badc |= !on_grid[j] || (((m >> j) & 1u) && !(zr[j] < cur.zc));
+        if (!isfinite(cur.zc)) nonfin = true;
+        if (badc) bad = true;
+      }
       const Frac<VK, FLOW_UP> fr =
           fractions<VK, FLOW_UP>(cur.zc, sh_l(zo), zo, sh_r(zo), sh_l(cur.zc), sh_r(cur.zc), m, pf, P.p);
       V sv;
@@ -490,6 +535,10 @@ __global__ __launch_bounds__(64 * (1 + ms_producers<VK>())) void k_ms(MsParams P
       S.code[lane] = valid ? cur.code : 0u;
       compiler_fence();
       if (lane == 0) lds_st(&slot_row[slot], (int32_t)t);
+    }
+    if (P.status) {
+      if (ballot(bad) && lane == 0) atomicCAS(P.status, 0, FR_ERR_BADCODE);
+      if (ballot(nonfin) && lane == 0) atomicCAS(P.status, 0, FR_ERR_NONFINITE);
     }
     return;
   }
@@ -513,10 +562,7 @@ __global__ __launch_bounds__(64 * (1 + ms_producers<VK>())) void k_ms(MsParams P
   const int64_t owner = valid ? col / MS_OWN : 0;
   const uint64_t* ring_ghost = P.ring + (size_t)owner * MS_RING * MS_OWN + (size_t)(ccol - owner * MS_OWN);
   int32_t nb_prog = 0;  // smallest neighbour progress seen (rows finished)
-  // Store addresses: owned lanes write their cell and ring word, the others
-  // a scratch slot of this strip.
-  uint64_t* junk = P.junk + (size_t)s * 2 * MS_LANES + lane;
-  uint64_t* pub = owned ? ring_mine + (lane - MS_G) : junk + MS_LANES;
+  uint64_t* pub = ring_mine + (owned ? lane - MS_G : 0);
 
   // A row's inputs in the form the recurrence takes them: pull weights
   // toward the previous row's three cells (lane shifts -1, 0, +1), same-row
@@ -679,20 +725,15 @@ __global__ __launch_bounds__(64 * (1 + ms_producers<VK>())) void k_ms(MsParams P
       }
     }
 
-    // Results: the owned cells, the ring word, the progress word.
-    if constexpr (VK == VK_FF) {
-      float* dst = owned ? P.vhi + i : reinterpret_cast<float*>(junk);
-      *dst = q.hi;
-    } else {
-      double* dst = owned ? P.v64 + i : reinterpret_cast<double*>(junk);
-      *dst = q;
-    }
-    st_word(pub + (size_t)(t % MS_RING) * (owned ? MS_OWN : 0), A::pack(q, (uint32_t)(t & 0xFF)));
-    st_i32(P.progress + s, (int32_t)(t + 1));
+    // Results: the owned cells, their ring words, the progress word.
     if (owned) {
+      if constexpr (VK == VK_FF) P.vhi[i] = q.hi;
+      else P.v64[i] = q;
+      st_word(pub + (size_t)(t % MS_RING) * MS_OWN, A::pack(q, (uint32_t)(t & 0xFF)));
       if (!ADJ && cx.code == 0u) msum += A::wide(q);
       rsum += A::wide(cx.src);
     }
+    if (lane == 0) st_i32(P.progress + s, (int32_t)(t + 1));
 
     // This row becomes the previous one.
     vp = q;
@@ -725,31 +766,23 @@ __global__ __launch_bounds__(64 * (1 + ms_producers<VK>())) void k_ms(MsParams P
   }
 }
 
-// Checks the codes and elevations for the row sweep and resets its ring,
-// progress and partial words: MS_BAD for an invalid mask (receiver off the
-// grid or not strictly lower) or a non-finite elevation, MS_UP / MS_DN when
-// some cell sends to row r - 1 / r + 1.
+// Reads the codes for the row sweep and resets its ring, progress and
+// partial words: MS_UP / MS_DN when some cell sends to row r - 1 / r + 1.
+// (The masks' other properties -- receivers on the grid and strictly lower,
+// elevations finite -- are checked by the sweep's producers, which read
+// every candidate receiver's elevation anyway.)
 __global__ __launch_bounds__(256) void k_ms_check(MsParams P, CallCtl* C) {
-  const int64_t nr = P.nrows, nc = P.ncols, n = nr * nc;
+  const int64_t n = P.nrows * P.ncols;
   const int64_t ring_words = (int64_t)P.nstrips * MS_RING * MS_OWN;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  uint32_t fl = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const uint32_t m = P.code[i];
-    const float zi = P.z[i];
-    if (!isfinite(zi)) fl |= MS_BAD;
-    if (m & 0x07u) fl |= MS_UP;
-    if (m & 0xE0u) fl |= MS_DN;
-    if (m) {
-      const int64_t r = i / nc, c = i - r * nc;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        if (!((m >> k) & 1u)) continue;
-        const int64_t rr = r + nb_dr(k), cc = c + nb_dc(k);
-        if (rr < 0 || rr >= nr || cc < 0 || cc >= nc || !(P.z[rr * nc + cc] < zi)) fl |= MS_BAD;
-      }
-    }
-  }
+  uint32_t any = 0;
+  // Four codes per load where the row length allows it.
+  const int64_t n4 = (P.ncols % 4 == 0 && (reinterpret_cast<uintptr_t>(P.code) & 3) == 0) ? n / 4 : 0;
+  const uint32_t* c4 = reinterpret_cast<const uint32_t*>(P.code);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) any |= c4[i];
+  for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) any |= P.code[i];
+  any = any | (any >> 8) | (any >> 16) | (any >> 24);
+  const uint32_t fl = ((any & 0x07u) ? MS_UP : 0u) | ((any & 0xE0u) ? MS_DN : 0u);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ring_words; i += stride) P.ring[i] = MS_EMPTY;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.nstrips; i += stride) P.progress[i] = 0;
   // One atomic per wavefront.
@@ -759,12 +792,12 @@ __global__ __launch_bounds__(256) void k_ms_check(MsParams P, CallCtl* C) {
   if ((threadIdx.x & 63) == 0 && w) atomicOr(reinterpret_cast<uint32_t*>(&C->ms_flags), w);
 }
 
-// The row sweep serves the call when every mask is valid and no cell sends
-// against one of the two row orders.
+// The row sweep serves the call when no cell sends against one of the two
+// row orders.
 __global__ void k_ms_decide(CallCtl* C) {
   if (threadIdx.x != 0) return;
   const int32_t f = C->ms_flags;
-  const bool taken = !(f & MS_BAD) && !((f & MS_UP) && (f & MS_DN));
+  const bool taken = !((f & MS_UP) && (f & MS_DN));
   const bool flow_up = (f & MS_UP) || !(f & MS_DN);
   C->ms_flags = f | (taken ? MS_TAKEN : 0) | (flow_up ? MS_FLOW_UP : 0);
   C->ms_skip = taken ? 0 : 1;

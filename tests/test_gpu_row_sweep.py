@@ -175,3 +175,40 @@ def test_row_sweep_declines_two_way_flow():
     code = fr.receivers(zt, "mfd")
     q64, _, _ = fr.accumulate(code, zt, dev(rain), "mfd", torch.float64)
     assert relmax(host(q64), oracle.accumulate_mfd(z, rain, 1.1)) <= 1e-10
+
+
+@pytest.mark.parametrize("path", ["auto", "sweep"])
+def test_row_sweep_reports_bad_masks_and_nonfinite(path):
+    """Invalid inputs give the same device errors on the row sweep as on
+    the general sweep: a receiver that is not lower or lies off the grid
+    (FR_ERR_BADCODE), a non-finite elevation or rain (FR_ERR_NONFINITE)."""
+    nr, nc = 100, 300
+    z = terrain("fractal", nr, nc, 33)
+    assert _applicable(z)
+    zt = dev(z)
+    code = host(fr.receivers(zt, "mfd"))
+    r = 50
+    j = next(j for j in range(1, nc - 1) if z[r, j + 1] > z[r, j])
+    cases = []
+    c = code.copy()
+    c[r, j] |= 1 << 4  # the higher right neighbour claimed as a receiver
+    cases.append(("higher receiver", c, z, None, fr.ERR_BADCODE))
+    c = code.copy()
+    c[10, 0] |= 1 << 3  # a receiver left of column 0
+    cases.append(("off the grid", c, z, None, fr.ERR_BADCODE))
+    rain = synth.rain(33, nr, nc)
+    rain[20, 30] = np.nan
+    cases.append(("nan rain", code, z, rain, fr.ERR_NONFINITE))
+    # A cell no neighbour sends to (a same-row peak in the highest row), so
+    # that the infinite elevation is the only error.
+    top = nr - 1
+    k = next(k for k in range(1, nc - 1) if z[top, k] > z[top, k - 1] and z[top, k] > z[top, k + 1])
+    z2 = z.copy()
+    z2[top, k] = np.inf
+    cases.append(("inf elevation", code, z2, None, fr.ERR_NONFINITE))
+    with fr.accumulate_path(path):
+        for name, c, zz, rr, err in cases:
+            print(f"  {path}: {name}", flush=True)
+            with pytest.raises(fr.FlowRouteError) as e:
+                fr.accumulate(dev(c), dev(zz), None if rr is None else dev(rr), "mfd", torch.float64)
+            assert e.value.code == err, name
