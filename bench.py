@@ -41,6 +41,9 @@ MEASURED_TRAFFIC = {
         "d8_up": (1.3366e10, "profiles/d8_43360_hbm_traffic.md"),
         "d8_down": (3.3176e10, "profiles/d8_43360_hbm_traffic.md"),
     },
+    ("mfd", 16384, 16384): {"row_sweep": (5.3063e9, "profiles/mfd_16384_row_sweep.md")},
+    ("adjoint", 4096, 4096): {"sweep": (6.987e8, "profiles/sweep_and_batch_hbm_traffic.md")},
+    ("batched", 512): {"batch": (2.472e10, "profiles/sweep_and_batch_hbm_traffic.md")},
 }
 # Algorithmic bytes per cell of the secondary workloads' dominant kernel
 # (arrays visible at the C ABI, each touched once): MFD float32 sweep z 4 +
