@@ -785,11 +785,17 @@ __global__ __launch_bounds__(256) void k_ms_check(MsParams P, CallCtl* C) {
   const uint32_t fl = ((any & 0x07u) ? MS_UP : 0u) | ((any & 0xE0u) ? MS_DN : 0u);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ring_words; i += stride) P.ring[i] = MS_EMPTY;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.nstrips; i += stride) P.progress[i] = 0;
-  // One atomic per wavefront.
-  uint32_t w = fl;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) w |= (uint32_t)__shfl_xor((int)w, off);
-  if ((threadIdx.x & 63) == 0 && w) atomicOr(reinterpret_cast<uint32_t*>(&C->ms_flags), w);
+  // One atomic per workgroup, and only for bits not set yet (every
+  // workgroup of a tilted grid finds the same bit).
+  __shared__ uint32_t blk;
+  if (threadIdx.x == 0) blk = 0u;
+  __syncthreads();
+  if (fl) atomicOr(&blk, fl);
+  __syncthreads();
+  if (threadIdx.x == 0 && blk) {
+    uint32_t* f = reinterpret_cast<uint32_t*>(&C->ms_flags);
+    if ((__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & blk) != blk) atomicOr(f, blk);
+  }
 }
 
 // The row sweep serves the call when no cell sends against one of the two
@@ -830,7 +836,7 @@ hipError_t launch_ms(ValKind vk, bool adjoint, const MsParams& P, CallCtl* C, hi
   const int64_t n = P.nrows * P.ncols;
   const int64_t work = n > (int64_t)ms_ring_words(P.ncols) ? n : (int64_t)ms_ring_words(P.ncols);
   int64_t b = (work + 255) / 256;
-  if (b > 16384) b = 16384;
+  if (b > 2048) b = 2048;
   hipLaunchKernelGGL(k_ms_check, dim3((unsigned)(b < 1 ? 1 : b)), dim3(256), 0, s, P, C);
   hipLaunchKernelGGL(k_ms_decide, dim3(1), dim3(64), 0, s, C);
   if (vk == VK_F64) return adjoint ? ms_launch_t<VK_F64, true>(P, C, s) : ms_launch_t<VK_F64, false>(P, C, s);
