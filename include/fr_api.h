@@ -407,15 +407,46 @@ int fr_set_autotune_cache(const char* path);
  * fr_set_accumulate_path -- process-wide choice of the accumulation path of
  * fr_accumulate and fr_accumulate_adjoint, for tests and diagnostics:
  * FR_PATH_AUTO (the default: row sweeps and exit forest for single
- * receivers, wavefront sweep otherwise, the peeling engine when either
- * gives up), FR_PATH_SWEEP (wavefront sweep, then the engine) or
- * FR_PATH_ENGINE (the peeling engine alone).  Every path computes the same
- * solution; only the time differs.  Not thread-safe.  Errors: FR_ERR_ARG.
+ * receivers -- the tile forest when their exit list overflows --, the row
+ * sweep or the wavefront sweep for MFD, the peeling engine when a sweep
+ * gives up), FR_PATH_SWEEP (wavefront sweep, then the engine),
+ * FR_PATH_ENGINE (the peeling engine alone) or FR_PATH_TILES (the tile
+ * forest for single receivers at once, for terrain known to drain in every
+ * direction such as a depression-filled DEM; MFD as FR_PATH_AUTO).  Every
+ * path computes the same solution; only the time differs.  Not thread-safe.
+ * Errors: FR_ERR_ARG.
  */
 #define FR_PATH_AUTO 0
 #define FR_PATH_SWEEP 1
 #define FR_PATH_ENGINE 2
+#define FR_PATH_TILES 3
 int fr_set_accumulate_path(int path);
+
+/*
+ * fr_served_by -- which solver finished the most recent fr_accumulate or
+ * fr_accumulate_adjoint call that used the workspace `ws` (diagnostics and
+ * tests; the paths are those of fr_set_accumulate_path):
+ *   FR_SERVED_ROWS       row sweeps and exit forest (D8 / D4, Section 2.1)
+ *   FR_SERVED_TILES      tile forest: 32 x 64-cell tiles solved in LDS, joined
+ *                        by the exit forest (D8 / D4 with flow in every
+ *                        direction, when the row sweeps' exit list overflowed)
+ *   FR_SERVED_ROW_SWEEP  MFD row sweep
+ *   FR_SERVED_SWEEP      wavefront sweep
+ *   FR_SERVED_ENGINE     peeling engine
+ *   FR_SERVED_NONE       not known
+ * Reads the workspace's control block with a copy on `stream` and waits for
+ * it, so the answer covers every call enqueued before on that stream (calls
+ * on empty grids use no workspace; a workspace that no call has used yet
+ * gives an unspecified answer).  The workspace stays owned by the caller.  Errors: FR_ERR_ARG (NULL pointer,
+ * ws_bytes below one control block), FR_ERR_HIP.
+ */
+#define FR_SERVED_NONE 0
+#define FR_SERVED_ROWS 1
+#define FR_SERVED_TILES 2
+#define FR_SERVED_ROW_SWEEP 3
+#define FR_SERVED_SWEEP 4
+#define FR_SERVED_ENGINE 5
+int fr_served_by(const void* ws, size_t ws_bytes, int32_t* served_out, hipStream_t stream);
 
 /* fr_status_string -- static text for a status code. */
 const char* fr_status_string(int code);

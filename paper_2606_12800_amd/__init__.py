@@ -32,15 +32,16 @@ OK = 0
 ERR_ARG, ERR_RULE, ERR_WORKSPACE, ERR_HIP = -1, -2, -3, -4
 ERR_NONFINITE, ERR_NOTDAG, ERR_BADCODE, ERR_TOOLARGE = -5, -6, -7, -8
 ERR_STALL, ERR_CAPACITY = -9, -10
-PATH_AUTO, PATH_SWEEP, PATH_ENGINE = 0, 1, 2
-PATHS = {"auto": PATH_AUTO, "sweep": PATH_SWEEP, "engine": PATH_ENGINE}
+PATH_AUTO, PATH_SWEEP, PATH_ENGINE, PATH_TILES = 0, 1, 2, 3
+PATHS = {"auto": PATH_AUTO, "sweep": PATH_SWEEP, "engine": PATH_ENGINE, "tiles": PATH_TILES}
 
 RULES = {"d8": D8, "mfd": MFD, "d4": D4}
 EXPORTS = ["fr_receivers", "fr_accumulate", "fr_accumulate_adjoint", "fr_workspace_bytes",
            "fr_status_string", "fr_version", "fr_timing_enable", "fr_timing_last",
            "fr_batched_workspace_bytes", "fr_accumulate_batched", "fr_batch_autotune",
            "fr_accumulate_block_iterations", "fr_fill_depressions", "fr_set_accumulate_path",
-           "fr_accumulate_noalloc", "fr_set_autotune_cache"]
+           "fr_accumulate_noalloc", "fr_set_autotune_cache", "fr_served_by"]
+SERVED = {0: "none", 1: "rows", 2: "tiles", 3: "row_sweep", 4: "sweep", 5: "engine"}
 ORDER_GIVEN, ORDER_ROWS_DESC, ORDER_CELLS_DESC = 0, 1, 2
 
 
@@ -109,6 +110,8 @@ def load_library() -> ctypes.CDLL:
     lib.fr_accumulate_noalloc.restype = ci
     lib.fr_set_autotune_cache.argtypes = [ctypes.c_char_p]
     lib.fr_set_autotune_cache.restype = ci
+    lib.fr_served_by.argtypes = [vp, sz, vp, vp]
+    lib.fr_served_by.restype = ci
     _lib = lib
     return lib
 
@@ -143,7 +146,7 @@ def timing_last() -> dict:
 @contextlib.contextmanager
 def accumulate_path(path: str):
     """Within the block, fr_accumulate / fr_accumulate_adjoint take the given
-    path ("auto", "sweep" or "engine"; ``fr_set_accumulate_path``).  Every
+    path ("auto", "sweep", "engine" or "tiles"; ``fr_set_accumulate_path``).  Every
     path computes the same solution; tests use this to cover the fallbacks."""
     lib = load_library()
     rc = lib.fr_set_accumulate_path(PATHS[path])
@@ -153,6 +156,21 @@ def accumulate_path(path: str):
         yield
     finally:
         lib.fr_set_accumulate_path(PATH_AUTO)
+
+
+def served_by(ws: "Workspace | None" = None, device=None) -> str:
+    """Which solver finished the most recent accumulate / adjoint call that
+    used the workspace (``fr_served_by``): "rows", "tiles", "row_sweep",
+    "sweep", "engine" or "none"."""
+    w = ws or _default_ws
+    if w.buf is None:
+        return "none"
+    dev = device if device is not None else w.buf.device
+    out = ctypes.c_int32(0)
+    rc = load_library().fr_served_by(_ptr(w.buf), w.buf.numel(), ctypes.byref(out), _stream(dev))
+    if rc != OK:
+        raise FlowRouteError(rc, "fr_served_by")
+    return SERVED.get(out.value, "none")
 
 
 def _rule(rule) -> int:

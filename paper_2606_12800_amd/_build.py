@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libflowroute.so")
 BUILD = os.path.join(PKG, "_build")
 
-SOURCES = ["fr_receivers.hip", "fr_engine.hip", "fr_d8_a.hip", "fr_d8_c.hip", "fr_d8_forest.hip", "fr_wsweep.hip", "fr_msweep.hip", "fr_fill.hip", "fr_api.cpp"]
+SOURCES = ["fr_receivers.hip", "fr_engine.hip", "fr_d8_a.hip", "fr_d8_c.hip", "fr_d8_forest.hip", "fr_d8_tiles.hip", "fr_wsweep.hip", "fr_msweep.hip", "fr_fill.hip", "fr_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -93,6 +93,9 @@ D8Layout d8_layout(int64_t nrows, int64_t ncols, int th, int vdtype, bool counts
   const size_t n = (size_t)(nrows * ncols);
   const size_t nt = (size_t)(((nrows + th - 1) / th) * ((ncols + D8_TW - 1) / D8_TW));
   L.cap = d8_capacity((int64_t)n, (int64_t)nt);
+  // The list also holds the tile-forest path's exits (fr_d8_tiles.hip).
+  const uint64_t tb = d8t_exit_bound(nrows, ncols);
+  if (tb > L.cap) L.cap = (uint32_t)tb;
   const size_t cap = L.cap;
   const bool vals = vdtype == FR_F32 || vdtype == FR_F64;
   size_t o = 0;
@@ -110,7 +113,8 @@ D8Layout d8_layout(int64_t nrows, int64_t ncols, int th, int vdtype, bool counts
   L.anc = o; o += up(cap * 8);
   L.loc = o; if (vals) o += up(cap * 8);
   L.ctr = o; o += kAlign;
-  L.mass = o; o += up(nt * 2 * sizeof(double));
+  const size_t mw = d8t_mass_words(nrows, ncols) > nt * 2 ? d8t_mass_words(nrows, ncols) : nt * 2;
+  L.mass = o; o += up(mw * sizeof(double));
   L.total = o;
   return L;
 }
@@ -224,7 +228,8 @@ int g_path = FR_PATH_AUTO;
 // The row sweep is tried for MFD masks under the automatic path choice when
 // all of its strips can be resident at once.
 bool ms_applicable(RuleKind rk, ValKind vk, int64_t ncols) {
-  return rk == RK_MULTI && g_path == FR_PATH_AUTO && ms_strips(ncols) <= ms_max_strips(vk);
+  return rk == RK_MULTI && (g_path == FR_PATH_AUTO || g_path == FR_PATH_TILES) &&
+         ms_strips(ncols) <= ms_max_strips(vk);
 }
 
 constexpr int kMaxSweepPasses = 32;
@@ -312,7 +317,7 @@ D8Params d8_params(const uint8_t* code, int64_t nrows, int64_t ncols, int th, co
 // list overflow opens C->fallback, which the enqueued engine then serves.
 int enqueue_d8(const uint8_t* code, int64_t nrows, int64_t ncols, const void* rain, int rain_dtype, ValKind vk,
                float* q32, double* q64, uint64_t* cnt, double* mass_out, int32_t* status, char* body, CallCtl* C,
-               hipStream_t s) {
+               bool tiles_only, hipStream_t s) {
   const bool counts = cnt != nullptr;
   D8Layout L{};
   D8Params P = d8_params(code, nrows, ncols, d8_tile_height(nrows, ncols), rain, rain_dtype, vk, counts, body, C,
@@ -321,21 +326,38 @@ int enqueue_d8(const uint8_t* code, int64_t nrows, int64_t ncols, const void* ra
   P.q64 = q64;
   P.cnt = cnt;
   P.mass_part = mass_out ? reinterpret_cast<double*>(body + L.mass) : nullptr;
-  if (launch_zero_u32(P.n_exits, 16, s) != hipSuccess) return FR_ERR_HIP;
-  int ph = phase_begin("d8_up", s);
-  if (launch_d8_up(vk, counts, false, P, s) != hipSuccess) return FR_ERR_HIP;
-  phase_end(ph, s);
-  ph = phase_begin("d8_forest", s);
-  if (launch_d8_forest(vk, counts, false, P, s) != hipSuccess) return FR_ERR_HIP;
-  phase_end(ph, s);
-  ph = phase_begin("d8_down", s);
-  if (launch_d8_down(vk, counts, false, P, s) != hipSuccess) return FR_ERR_HIP;
-  phase_end(ph, s);
-  if (mass_out) {
-    ph = phase_begin("mass", s);
-    if (launch_mass_final(P.mass_part, P.ntr * P.ntc, mass_out, &C->fallback, s) != hipSuccess) return FR_ERR_HIP;
+  if (launch_zero_u32(P.n_exits, 32, s) != hipSuccess) return FR_ERR_HIP;
+  int ph = -1;
+  if (!tiles_only) {
+    ph = phase_begin("d8_up", s);
+    if (launch_d8_up(vk, counts, false, P, s) != hipSuccess) return FR_ERR_HIP;
     phase_end(ph, s);
+    ph = phase_begin("d8_forest", s);
+    if (launch_d8_forest(vk, counts, false, P, s) != hipSuccess) return FR_ERR_HIP;
+    phase_end(ph, s);
+    ph = phase_begin("d8_down", s);
+    if (launch_d8_down(vk, counts, false, P, s) != hipSuccess) return FR_ERR_HIP;
+    phase_end(ph, s);
+    if (mass_out) {
+      ph = phase_begin("mass", s);
+      if (launch_mass_final(P.mass_part, P.ntr * P.ntc, mass_out, &C->fallback, s) != hipSuccess) return FR_ERR_HIP;
+      phase_end(ph, s);
+    }
+    if (nrows * ncols <= kFullCapacityCells) return FR_OK;  // the row sweeps' list cannot overflow
   }
+  // Exit list overflow (flow in every direction), or the path chosen: the
+  // tile-forest path, behind its gate, with an exit count and round flags of
+  // its own.
+  D8Params T = P;
+  T.n_exits = P.n_exits + 16;
+  T.flags = reinterpret_cast<int32_t*>(P.n_exits + 20);
+  ph = phase_begin("d8_tiles", s);
+  if (launch_d8t_gate(C, tiles_only, s) != hipSuccess || launch_d8t(true, vk, counts, T, s) != hipSuccess ||
+      launch_d8_forest(vk, counts, false, T, s) != hipSuccess || launch_d8t(false, vk, counts, T, s) != hipSuccess)
+    return FR_ERR_HIP;
+  if (mass_out && launch_d8t_mass(T.mass_part, d8t_tiles(nrows, ncols), mass_out, C, s) != hipSuccess)
+    return FR_ERR_HIP;
+  phase_end(ph, s);
   return FR_OK;
 }
 
@@ -374,6 +396,20 @@ int enqueue_ws(const EngineConfig& cfg, const WsParams& P, CallCtl* C, hipStream
 // (FR_PATH_ENGINE): the engine then serves the call on its own.
 __global__ void k_open_gate(CallCtl* C) {
   if (threadIdx.x == 0) C->fallback = 1;
+}
+
+// Clears the control block at the start of a call and records the path the
+// host enqueues first.
+__global__ void k_ctl_init(CallCtl* C, int32_t served) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(C);
+  for (int i = threadIdx.x; i < CTL_WORDS; i += blockDim.x) w[i] = 0u;
+  __syncthreads();
+  if (threadIdx.x == 0) C->served = served;
+}
+
+hipError_t launch_ctl_init(CallCtl* C, int32_t served, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, C, served);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -468,8 +504,24 @@ size_t fr_workspace_bytes(int fn, int64_t nrows, int64_t ncols, int rule, int dt
   return kCtlBytes + t + kAlign;
 }
 
+int fr_served_by(const void* ws, size_t ws_bytes, int32_t* served_out, hipStream_t stream) {
+  if (!ws || !served_out || ws_bytes < kCtlBytes + kAlign) return FR_ERR_ARG;
+  CallCtl c{};
+  char* base = aligned_base(const_cast<void*>(ws));
+  if (hipMemcpyAsync(&c, base, sizeof c, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return FR_ERR_HIP;
+  int32_t v = c.served;
+  if (c.fallback) v = FR_SERVED_ENGINE;
+  else if (c.d8_tiles) v = FR_SERVED_TILES;
+  else if (c.ms_flags & MS_TAKEN) v = FR_SERVED_ROW_SWEEP;
+  *served_out = v >= FR_SERVED_NONE && v <= FR_SERVED_ENGINE ? v : FR_SERVED_NONE;
+  return FR_OK;
+}
+
 int fr_set_accumulate_path(int path) {
-  if (path != FR_PATH_AUTO && path != FR_PATH_SWEEP && path != FR_PATH_ENGINE) return FR_ERR_ARG;
+  if (path != FR_PATH_AUTO && path != FR_PATH_SWEEP && path != FR_PATH_ENGINE && path != FR_PATH_TILES)
+    return FR_ERR_ARG;
   g_path = path;
   return FR_OK;
 }
@@ -589,7 +641,12 @@ int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t nc
   // Every kernel below is ordered on the stream; decisions between them
   // (exit overflow, sweep passes, the engine's gate) are taken on the
   // device through the control block, which starts zeroed.
-  if (launch_zero_u32(reinterpret_cast<uint32_t*>(C), CTL_WORDS, stream) != hipSuccess) return FR_ERR_HIP;
+  const bool tiles_only = cfg.rk == RK_SINGLE && g_path == FR_PATH_TILES;
+  const int32_t first = g_path == FR_PATH_ENGINE ? FR_SERVED_ENGINE
+                        : (tiles_only ? FR_SERVED_TILES
+                                      : (cfg.rk == RK_SINGLE && g_path == FR_PATH_AUTO ? FR_SERVED_ROWS
+                                                                                       : FR_SERVED_SWEEP));
+  if (launch_ctl_init(C, first, stream) != hipSuccess) return FR_ERR_HIP;
   int rc = FR_OK;
   const int64_t n = nrows * ncols;
   bool ms_on = false;
@@ -598,11 +655,13 @@ int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t nc
   if (g_path == FR_PATH_ENGINE) {
     hipLaunchKernelGGL(k_open_gate, dim3(1), dim3(64), 0, stream, C);
     if (hipGetLastError() != hipSuccess) return FR_ERR_HIP;
-  } else if (cfg.rk == RK_SINGLE && g_path == FR_PATH_AUTO) {
+  } else if (cfg.rk == RK_SINGLE && (g_path == FR_PATH_AUTO || tiles_only)) {
     rc = enqueue_d8(code, nrows, ncols, rain, rain_dtype, cfg.vk, q32, q64, counts_out, mass_out, dev_status, body,
-                    C, stream);
+                    C, tiles_only, stream);
     if (rc != FR_OK) return rc;
-    if (n <= kFullCapacityCells) return FR_OK;  // the exit list cannot overflow: no engine needed
+    // Neither list can overflow: the row sweeps' holds every cell on grids
+    // up to 2^22 cells, the tile forest's every cell on a tile perimeter.
+    if (n <= kFullCapacityCells || tiles_only) return FR_OK;
     // Overflow fallback: the engine and its mass reduction, behind the gate.
     if ((rc = enqueue_engine(cfg, P, stream)) != FR_OK) return rc;
     if (mass_out && launch_mass(cfg.rk, cfg.vk, P, partial, kMassBlocks, mass_out, stream) != hipSuccess)
@@ -851,7 +910,8 @@ int fr_accumulate_adjoint(const float* z, const uint8_t* code, int64_t nrows, in
   const double* s64 = dtype == FR_F64 ? static_cast<const double*>(qbar) : nullptr;
   float* o32 = dtype == FR_F32 ? static_cast<float*>(rbar_out) : nullptr;
   double* o64 = dtype == FR_F64 ? static_cast<double*>(rbar_out) : nullptr;
-  if (launch_zero_u32(reinterpret_cast<uint32_t*>(C), CTL_WORDS, stream) != hipSuccess) return FR_ERR_HIP;
+  if (launch_ctl_init(C, g_path == FR_PATH_ENGINE ? FR_SERVED_ENGINE : FR_SERVED_SWEEP, stream) != hipSuccess)
+    return FR_ERR_HIP;
   int rc = FR_OK;
   if (g_path == FR_PATH_ENGINE) {
     hipLaunchKernelGGL(k_open_gate, dim3(1), dim3(64), 0, stream, C);

@@ -27,8 +27,9 @@
 //
 // Every kernel reads the exit count from device memory, and the pointer-
 // doubling rounds are a fixed sequence of launches that return at once when
-// there is nothing left to do, so a solve never waits for the host.  An exit
-// list that overflows its capacity opens the peeling engine's gate instead.
+// there is nothing left to do, so a solve never waits for the host.  When the
+// exit list overflows its capacity (flow in every direction, as on filled
+// terrain), the tile-forest path (fr_d8_tiles.hip) serves the call instead.
 //
 // Block iterations (the paper's I+X scheme, Section 3.3, Appendix B): with
 // blocks made of bt_r x bt_c tiles, the same three phases are the exact
@@ -64,6 +65,9 @@ __device__ __forceinline__ void root_wave(const D8Params& P, const Tile& T) {
 
 template <int VK, bool CNT, int RAIN, bool VEC, bool ITER>
 __global__ __launch_bounds__(128) void k_d8_a(D8Params P) {
+  // Once the exit list has overflowed, the rest of the pass is wasted: the
+  // tiles not started yet return at once.
+  if (__hip_atomic_load(P.n_exits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > P.cap) return;  // uniform
   const Tile T = tile_of(P, blockIdx.x);
   if (threadIdx.x >= 64) {
     root_wave<VEC>(P, T);

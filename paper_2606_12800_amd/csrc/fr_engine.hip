@@ -779,6 +779,12 @@ hipError_t launch_mass_final(const double* partial, int nblocks, double* out, co
   return hipGetLastError();
 }
 
+hipError_t launch_mass_final_if(const double* partial, int nblocks, double* out, const int32_t* open,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(256), 0, s, partial, nblocks, out, open, 1);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, p, n);
   return hipGetLastError();

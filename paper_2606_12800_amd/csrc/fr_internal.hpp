@@ -98,6 +98,8 @@ struct CallCtl {
   int32_t forest_final;      // D8 forest: the pending-additions buffer of the last round
   int32_t ms_flags;          // MFD row sweep: MS_* bits from the check and the decision
   int32_t ms_skip;           // 1: the row sweep does not serve this call (gate of the general mass)
+  int32_t d8_tiles;          // 1: the tile-forest path serves this call (the row sweeps' exits overflowed)
+  int32_t served;            // FR_SERVED_* of the path the host enqueued first (device gates may override)
 };
 static_assert(sizeof(CallCtl) <= 256, "control block fits its 256-byte slot");
 constexpr int CTL_WORDS = 64;  // 32-bit words zeroed at the start of a call
@@ -148,6 +150,26 @@ struct D8Params {
 constexpr uint32_t D8_EXIT_CHUNK = 32;
 
 
+// Tile-forest path (fr_d8_tiles.hip): single-receiver solves for flow in
+// every direction, tiles of D8T_ROWS x D8T_COLS cells solved in LDS, joined
+// by the exit forest.  Its exit list never holds more than
+// d8t_exit_bound() entries; its mass partials (d8t_mass_words() doubles) are
+// reduced in runs of D8T_MASS_RUN tiles, then once more.
+constexpr int D8T_ROWS = 32;
+constexpr int D8T_COLS = 64;
+constexpr int D8T_MASS_RUN = 4096;
+int64_t d8t_tiles(int64_t nrows, int64_t ncols);
+uint64_t d8t_exit_bound(int64_t nrows, int64_t ncols);
+size_t d8t_mass_words(int64_t nrows, int64_t ncols);
+// Opens the path's gate (C->d8_tiles) when the row sweeps' exit list
+// overflowed (C->fallback) or `force`, closing the engine's gate again.
+hipError_t launch_d8t_gate(CallCtl* C, bool force, hipStream_t s);
+// Phase A (up) or C (down) of every tile; both return at once while the
+// gate is closed.
+hipError_t launch_d8t(bool up, ValKind vk, bool cnt, const D8Params& P, hipStream_t s);
+// Sums the tiles' mass partials into out[0..1] when the gate is open.
+hipError_t launch_d8t_mass(const double* part, int64_t ntiles, double* out, CallCtl* C, hipStream_t s);
+
 // Launchers (defined in the .hip files).
 // Phase A (local sums and roots), phase B (exit forest: link, then enough
 // pointer-doubling rounds for a forest of P.cap exits -- each a no-op once
@@ -170,6 +192,9 @@ hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
 // and *skip != 0 (the result then comes from another path).
 hipError_t launch_mass_final(const double* partial, int nblocks, double* out, const int32_t* skip,
                              hipStream_t s);
+// As launch_mass_final, but the reduction runs only when *open != 0.
+hipError_t launch_mass_final_if(const double* partial, int nblocks, double* out, const int32_t* open,
+                                hipStream_t s);
 hipError_t launch_receivers(const float* z, int64_t nrows, int64_t ncols, int rule, uint8_t* code,
                             int32_t* status, hipStream_t s);
 

@@ -45,8 +45,11 @@ def test_header_constants_match_binding():
     for name in ["ARG", "RULE", "WORKSPACE", "HIP", "NONFINITE", "NOTDAG", "BADCODE", "TOOLARGE", "STALL",
                  "CAPACITY"]:
         assert consts[f"FR_ERR_{name}"] == getattr(fr, f"ERR_{name}")
-    for name in ["AUTO", "SWEEP", "ENGINE"]:
+    for name in ["AUTO", "SWEEP", "ENGINE", "TILES"]:
         assert consts[f"FR_PATH_{name}"] == getattr(fr, f"PATH_{name}")
+    served = {v: k for k, v in fr.SERVED.items()}
+    for name in ["NONE", "ROWS", "TILES", "ROW_SWEEP", "SWEEP", "ENGINE"]:
+        assert consts[f"FR_SERVED_{name}"] == served[name.lower()]
 
 
 def test_status_strings(lib):
@@ -160,12 +163,20 @@ def test_block_iterations_validation(lib):
 
 
 def test_accumulate_path_selection(lib):
-    assert lib.fr_set_accumulate_path(3) == fr.ERR_ARG
+    assert lib.fr_set_accumulate_path(4) == fr.ERR_ARG
     assert lib.fr_set_accumulate_path(-1) == fr.ERR_ARG
-    for p in (fr.PATH_ENGINE, fr.PATH_SWEEP, fr.PATH_AUTO):
+    for p in (fr.PATH_ENGINE, fr.PATH_SWEEP, fr.PATH_TILES, fr.PATH_AUTO):
         assert lib.fr_set_accumulate_path(p) == fr.OK
     with fr.accumulate_path("engine"):
         pass  # restores the default on exit
+
+
+def test_served_by_validation(lib):
+    out = ctypes.c_int32(7)
+    assert lib.fr_served_by(NULL, 1 << 20, ctypes.byref(out), NULL) == fr.ERR_ARG
+    assert lib.fr_served_by(FAKE, 1 << 20, None, NULL) == fr.ERR_ARG
+    assert lib.fr_served_by(FAKE, 256, ctypes.byref(out), NULL) == fr.ERR_ARG  # below one control block
+    assert out.value == 7
 
 
 def test_fill_validation(lib):

@@ -213,10 +213,9 @@ def test_filled_untilted_dem_routes_like_the_oracle():
     4096^2 fractal DEM (seed 2), filled (epsilon variant, 8 neighbours) on
     the GPU and bit-exact against the oracle's priority flood, then routed
     D8 with float32 rain and counts.  Its flow runs in every direction: more
-    than an eighth of the cells leave their tile, which overflows the row
-    path's exit list at this size, so the call finishes on the peeling
-    engine behind the control block's gate -- counts bit-exact and water
-    within 1e-6 of the oracle either way."""
+    than an eighth of the cells leave their row-sweep tile, which overflows
+    the row sweeps' exit list at this size, so the tile forest serves the
+    call -- counts bit-exact and water within 1e-6 of the oracle."""
     n = 4096
     print(f"fill + route untilted {n}^2", flush=True)
     z_h = synth.dem(2, n, n, tilt=0.0)
@@ -227,6 +226,7 @@ def test_filled_untilted_dem_routes_like_the_oracle():
     assert _bits_equal(f_h, oracle.fill_depressions(z_h, 8, True))
     code, q, cnt, mass = fr.route(f, dev(rain_h), "d8", torch.float32, counts=True, mass=True)
     torch.cuda.synchronize()
+    assert fr.served_by() == "tiles"
     code_h = oracle.receivers(f_h)
     assert np.array_equal(code.cpu().numpy(), code_h)
     # Only boundary cells are sinks after filling.

@@ -54,16 +54,30 @@ def relnorm(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-_ACC_PATH = {"rows": "auto", "sweep": "sweep", "engine": "engine"}
+_ACC_PATH = {"rows": "auto", "sweep": "sweep", "engine": "engine", "tiles": "tiles"}
 
 
-@pytest.fixture(params=["rows", "sweep", "engine"])
+@pytest.fixture(params=["rows", "sweep", "engine", "tiles"])
 def d8path(request):
-    """Single-receiver forward accumulation has three GPU paths: row sweeps
-    with an exit forest (default), the windowed wavefront sweep and the
-    peeling engine (the fallback of both)."""
+    """Single-receiver forward accumulation has four GPU paths: row sweeps
+    with an exit forest (default), the tile forest (where the row sweeps'
+    exit list overflows), the windowed wavefront sweep and the peeling
+    engine (the fallback of the sweeps)."""
     with fr.accumulate_path(_ACC_PATH[request.param]):
         yield request.param
+
+
+_SERVED = {"rows": "rows", "tiles": "tiles", "engine": "engine"}
+
+
+def check_served(d8path):
+    """The chosen single-receiver path served the last forward call (the
+    wavefront sweep may hand over to the engine)."""
+    got = fr.served_by()
+    if d8path == "sweep":
+        assert got in ("sweep", "engine")
+    else:
+        assert got == _SERVED[d8path]
 
 
 @pytest.fixture(params=["rows", "sweep", "engine"])
@@ -129,6 +143,7 @@ def test_counts_bitexact(nr, nc, seed, rule, d8path):
     z = synth.dem(seed, nr, nc)
     code = fr.receivers(dev(z), rule)
     _, cnt, _ = fr.accumulate(code, None, None, rule, dtype=None, counts=True)
+    check_served(d8path)
     _, ref = oracle.accumulate_single(host(code), None, z=z, q=False)
     got = host(cnt)
     assert np.array_equal(got, ref)
@@ -142,6 +157,7 @@ def test_d8_rain_float32_and_counts(nr, nc, seed, d8path):
     rain = synth.rain(seed, nr, nc)
     code = fr.receivers(dev(z), "d8")
     q, cnt, m = fr.accumulate(code, None, dev(rain), "d8", torch.float32, counts=True, mass=True)
+    check_served(d8path)
     qref, cref = oracle.accumulate_single(host(code), rain, z=z)
     assert np.array_equal(host(cnt), cref)
     assert relmax(host(q), qref) <= 1e-6
@@ -156,6 +172,7 @@ def test_d8_float64(nr, nc, seed, d8path):
     rain = synth.rain(seed, nr, nc)
     code = fr.receivers(dev(z), "d8")
     q, _, m = fr.accumulate(code, None, dev(rain), "d8", torch.float64, mass=True)
+    check_served(d8path)
     qref, _ = oracle.accumulate_single(host(code), rain, z=z, counts=False)
     assert relmax(host(q), qref) <= 1e-10
     s, t = host(m)
@@ -188,15 +205,17 @@ def test_d8_terrain_orientations(kind, d8path):
     assert relmax(host(q), qref) <= 1e-6
 
 
-def test_d8_exit_list_overflow_falls_back():
+def test_d8_exit_list_overflow_takes_the_tile_forest():
     # Flow along rows only: every cell is an exit of the row sweep, more than
-    # the exit list holds on a grid above 2^22 cells.
+    # the exit list holds on a grid above 2^22 cells; the tile forest then
+    # serves the call.
     nr, nc = 2100, 2100
     cc = np.arange(nc, dtype=np.float64)[None, :] * np.ones((nr, 1))
     noise = synth.uniform(3, synth.STREAM_NOISE, nr * nc).reshape(nr, nc) * 1e-3
     z = (0.01 * cc + noise).astype(np.float32)
     code = fr.receivers(dev(z), "d8")
     _, cnt, _ = fr.accumulate(code, None, None, "d8", None, counts=True)
+    assert fr.served_by() == "tiles"
     _, cref = oracle.accumulate_single(host(code), None, z=z, q=False)
     assert np.array_equal(host(cnt), cref)
 
