@@ -329,6 +329,9 @@ int enqueue_d8(const uint8_t* code, int64_t nrows, int64_t ncols, const void* ra
   if (launch_zero_u32(P.n_exits, 32, s) != hipSuccess) return FR_ERR_HIP;
   int ph = -1;
   if (!tiles_only) {
+    // Where the list can overflow, a sample of the codes first decides
+    // whether the row sweeps are worth trying.
+    if (nrows * ncols > kFullCapacityCells && launch_d8_probe(P, s) != hipSuccess) return FR_ERR_HIP;
     ph = phase_begin("d8_up", s);
     if (launch_d8_up(vk, counts, false, P, s) != hipSuccess) return FR_ERR_HIP;
     phase_end(ph, s);

@@ -15,14 +15,19 @@
 //
 // Inside a tile (one workgroup of 256 threads, 8 cells each):
 //   1. the codes with a one-cell halo into LDS; each cell's receiver inside
-//      the tile, or none (a sink, or an exit);
+//      the tile, or none (a sink, or an exit); each cell marks itself in its
+//      receiver's donor mask;
 //   2. pointer jumping over those receivers: each cell's root -- the sink or
 //      exit where its in-tile path ends -- and its depth, the number of
 //      in-tile edges to the root, in about log2(depth) rounds;
-//   3. the cells by levels of depth, deepest first.  A cell's donors inside
-//      the tile lie exactly one level deeper, so with one barrier per level
-//      every cell adds its finished donors' values, in neighbour order: a
-//      fixed order, so results repeat bit for bit.
+//   3. a counting sort of the cells with donors inside the tile by depth;
+//   4. the levels of depth, deepest first.  A cell's donors inside the tile
+//      lie exactly one level deeper, so with one barrier per level each cell
+//      of the level reads its finished donors at once and adds them in
+//      neighbour order: a fixed order, so results repeat bit for bit.
+// Global loads that depend on nothing else (codes, rain, the exit indices of
+// the halo) are issued together at the start of a tile, and the halo's
+// forest totals while the tile's own work runs.
 // Phase A (up) stores the local sums of the exits in the exit list and, for
 // every cell receiving water over the tile's edge (inlet), its root.  Phase C
 // (down) starts the inlets from their out-of-tile donors' forest totals;
@@ -124,54 +129,218 @@ __device__ __forceinline__ int wave_max(int x) {
   return x;
 }
 
+// Halo positions (the ring of cells around the tile): top row, bottom row,
+// then the left and right columns.
+constexpr int NHALO = 2 * HW + 2 * HR;
+__device__ __forceinline__ int halo_id(int hr, int hc) {  // frame coordinates, on the ring
+  if (hr == 0) return hc;
+  if (hr == HR + 1) return HW + hc;
+  return 2 * HW + (hc == 0 ? 0 : HR) + (hr - 1);
+}
+__device__ __forceinline__ void halo_pos(int h, int& hr, int& hc) {
+  if (h < HW) {
+    hr = 0;
+    hc = h;
+  } else if (h < 2 * HW) {
+    hr = HR + 1;
+    hc = h - HW;
+  } else {
+    const int k = h - 2 * HW;
+    hr = 1 + (k % HR);
+    hc = k < HR ? 0 : HW - 1;
+  }
+}
+
+// Tile-local offset of the neighbour in direction n (row-major, 64 columns):
+// byte n of the constant holds the offset + 65.
+__device__ __forceinline__ int nb_off(int n) {
+  return (int)((0x8281804240020100ull >> (8 * n)) & 0xFFull) - 65;
+}
+
+// One cell of a level: its value (rain and out-of-tile inflow so far) plus
+// the finished values of its in-tile donors, in neighbour order.  The first
+// four donors are read at once and added without branches (a missing donor
+// adds an exact zero, which changes no bit of the sum); float-float sums are
+// normalised once.  Cells with more donors finish in a loop (rare).
+template <int VK, bool CNT>
+__device__ __forceinline__ void level_cell(typename TV<VK>::T* s_v, uint64_t* s_c, uint32_t ent) {
+  using V = typename TV<VK>::T;
+  const int i = (int)(ent & 0xFFFFu);
+  uint32_t m = ent >> 16;
+  const int kq = __popc(m);
+  int a[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int n = __builtin_ctz(m | 0x100u);  // 8 once no bit is left: the cell itself
+    a[q] = n < 8 ? min(max(i + nb_off(n), 0), HN - 1) : i;
+    m &= m - 1;
+  }
+  V own{}, x[4];
+  uint64_t cown = 0, y[4];
+  if (VK != VK_NONE) {
+    own = s_v[i];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[q] = s_v[a[q]];
+  }
+  if (CNT) {
+    cown = s_c[i];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) y[q] = s_c[a[q]];
+  }
+  if constexpr (VK == VK_FF) {
+    float h = own.hi, e = own.lo;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float xh = q < kq ? x[q].hi : 0.0f, xl = q < kq ? x[q].lo : 0.0f;
+      const ff t = ff_two_sum(h, xh);
+      h = t.hi;
+      e += t.lo + xl;
+    }
+    for (uint32_t r = m; r; r &= r - 1) {
+      const ff xv = s_v[i + nb_off(__builtin_ctz(r))];
+      const ff t = ff_two_sum(h, xv.hi);
+      h = t.hi;
+      e += t.lo + xv.lo;
+    }
+    s_v[i] = ff_fast(h, e);
+  }
+  if constexpr (VK == VK_F64) {
+    double v = own;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v += q < kq ? x[q] : 0.0;
+    for (uint32_t r = m; r; r &= r - 1) v += s_v[i + nb_off(__builtin_ctz(r))];
+    s_v[i] = v;
+  }
+  if (CNT) {
+    uint64_t c = cown;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) c += q < kq ? y[q] : 0ull;
+    for (uint32_t r = m; r; r &= r - 1) c += s_c[i + nb_off(__builtin_ctz(r))];
+    s_c[i] = c;
+  }
+}
+
+template <int RAIN>
+struct RainReg {
+  using T = typename std::conditional<RAIN == RAIN_F64, double, float>::type;
+};
+
 template <bool UP, int VK, bool CNT, int RAIN>
-__global__ __launch_bounds__(HT) void k_d8t(D8Params P, int ntiles) {
+__global__ __launch_bounds__(HT, 3) void k_d8t(D8Params P, int ntiles) {
   if (__hip_atomic_load(&P.ctl->d8_tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;  // uniform
   const uint32_t n_ex = *P.n_exits;
   if (!UP && n_ex > P.cap) return;  // uniform: the engine takes over
   using V = typename TV<VK>::T;
+  using RT = typename RainReg<RAIN>::T;
+  constexpr int NCODE = (HR + 2) * HW;
+  constexpr int NCU = (NCODE + HT - 1) / HT;  // code loads per thread
   constexpr int VB = VK == VK_NONE ? 0 : HN * 8;
   constexpr int CB = CNT ? HN * 8 : 0;
-  constexpr int SB = VB + CB > HN * 4 ? VB + CB : HN * 4;
-  __shared__ __align__(16) unsigned char s_buf[SB];
-  __shared__ uint8_t s_code[(HR + 2) * HW];
+  constexpr int HB = (UP ? 0 : NHALO * ((VK == VK_NONE ? 0 : 8) + (CNT ? 8 : 0)));
+  constexpr int MB = HN * 2 > HB ? HN * 2 : HB;
+  __shared__ __align__(16) unsigned char s_buf[VB + CB];  // values, counts
+  // Donor masks (16 bits per cell: in-tile donors, out-of-tile donors);
+  // once read, the forest totals of the halo cells (phase C).
+  __shared__ __align__(16) unsigned char s_mb[MB];
+  // Pointer jumping (receiver | root flag, depth << 16 per cell), then the
+  // cells with in-tile donors in level order (cell | donor mask << 16).
+  __shared__ uint32_t s_x[HN];
+  __shared__ __align__(16) uint32_t s_lev[HN / 2];  // level histogram, then offsets: 16 bits per level
+  __shared__ uint8_t s_code[NCODE];
   __shared__ int s_int[16];
+  __shared__ int s_open[16];
   __shared__ double s_dbl[8];
   __shared__ float s_flt[4];
   V* s_v = reinterpret_cast<V*>(s_buf);
   uint64_t* s_c = reinterpret_cast<uint64_t*>(s_buf + VB);
-  uint16_t* s_ptr = reinterpret_cast<uint16_t*>(s_buf);  // pointer jumping: aliases the values
-  uint16_t* s_dist = s_ptr + HN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t* s_msk = reinterpret_cast<uint32_t*>(s_mb);
+  V* s_hv = reinterpret_cast<V*>(s_mb);
+  uint64_t* s_hc = reinterpret_cast<uint64_t*>(s_mb + (VK == VK_NONE ? 0 : NHALO * 8));
+  uint16_t* s_off = reinterpret_cast<uint16_t*>(s_lev);
   const int64_t nr = P.nrows, nc = P.ncols;
-
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const TT T = tile_at(P, t, ntiles);
-    // 1. Codes with a one-cell halo; off the grid reads as a sink.
-    for (int e = tid; e < (HR + 2) * HW; e += HT) {
-      const int hr = e / HW, hc = e - hr * HW;
+    // The thread index, opaque to the compiler once per tile: offsets derived
+    // from it are recomputed per tile instead of held in registers (and
+    // spilled) across the loop.
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wave = tid >> 6;
+    // 1. Every global load of the tile that depends on nothing else, issued
+    // together: the codes with a one-cell halo (off the grid: sinks), the
+    // rain of the own cells, and in phase C the exit index of each halo
+    // cell (used only where the halo cell drains into the tile).
+    uint32_t cv[NCU];
+#pragma unroll
+    for (int u = 0; u < NCU; ++u) {
+      const int e = tid + u * HT;
+      const int hr = e / HW, hc = e - (e / HW) * HW;
       const int64_t r = T.r0 + hr - 1, c = T.c0 + hc - 1;
-      uint8_t v = SINK;
-      if (r >= 0 && r < nr && c >= 0 && c < nc) v = P.code[r * nc + c];
-      s_code[e] = v;
+      const bool in = e < NCODE && r >= 0 && r < nr && c >= 0 && c < nc;
+      cv[u] = in ? (uint32_t)P.code[r * nc + c] : (uint32_t)SINK;
     }
+    uint32_t vmask = 0;  // bit k: own cell k lies on the grid
+    RT rq[HK];
+#pragma unroll
+    for (int k = 0; k < HK; ++k) {
+      const int lr = wave + 4 * k;
+      const bool ok = lr < T.h && lane < T.w;
+      vmask |= ok ? 1u << k : 0u;
+      const int64_t g = ok ? (T.r0 + lr) * nc + T.c0 + lane : 0;
+      if (RAIN == RAIN_F32) rq[k] = P.rain32[g];
+      else if (RAIN == RAIN_F64) rq[k] = P.rain64[g];
+      else rq[k] = (RT)1;
+    }
+    int hh_r = 0, hh_c = 0;
+    uint32_t hnd = NONE;
+    if (tid < NHALO) halo_pos(tid, hh_r, hh_c);
+    if (!UP && tid < NHALO) {
+      const int64_t r = T.r0 + hh_r - 1, c = T.c0 + hh_c - 1;
+      if (r >= 0 && r < nr && c >= 0 && c < nc) hnd = P.node_of[r * nc + c];
+    }
+    for (int w = tid; w < HN / 2; w += HT) {
+      s_msk[w] = 0u;
+      s_lev[w] = 0u;
+    }
+    if (tid < 16) s_open[tid] = 0;
+#pragma unroll
+    for (int u = 0; u < NCU; ++u)
+      if (tid + u * HT < NCODE) s_code[tid + u * HT] = (uint8_t)cv[u];
+    // Sources: rain (unit rain: 1) and one cell each.
+    double m_rain = 0.0;
+    bool nonfinite = false;
+#pragma unroll
+    for (int k = 0; k < HK; ++k) {
+      const int i = (wave + 4 * k) * HC + lane;
+      const bool ok = (vmask >> k) & 1u;
+      const double r = (double)rq[k];
+      if (UP) nonfinite |= ok && !isfinite(r);
+      else m_rain += ok ? r : 0.0;
+      if constexpr (VK == VK_FF) {
+        const float hi = (float)rq[k];
+        s_v[i] = ok ? ff{hi, RAIN == RAIN_F64 ? (float)((double)rq[k] - (double)hi) : 0.0f} : ff{0.0f, 0.0f};
+      }
+      if constexpr (VK == VK_F64) s_v[i] = ok ? (double)rq[k] : 0.0;
+      if (CNT) s_c[i] = ok ? 1u : 0u;
+    }
+    if (UP && nonfinite) set_status(P.status, FR_ERR_NONFINITE);
     __syncthreads();
-    // 2. Each own cell: in-tile receiver, donor masks (bit n: the neighbour
-    // in direction n gives this cell water; inside / outside the tile).
-    uint32_t din[HK], dout[HK], ptr[HK], dist[HK];
-    bool sink[HK], valid[HK], ex[HK];
+    // 2. Own cells: receiver inside the tile or not; each cell marks itself
+    // in its receiver's donor mask (bit n: the donor lies in direction n).
+    // Halo cells that drain into the tile mark the out-of-tile bits.
+    uint32_t pd[HK];  // receiver or root (| PT_TERM once it is a root), depth << 16
+    uint32_t smask = 0, xmask = 0;  // bit k: own cell k is a sink / an exit
     bool bad = false;
 #pragma unroll
     for (int k = 0; k < HK; ++k) {
-      const int lr = wave + 4 * k, lc = lane;
-      const int i = lr * HC + lc;
-      valid[k] = lr < T.h && lc < T.w;
-      const uint32_t cd = s_code[(lr + 1) * HW + lc + 1];
+      const int lr = wave + 4 * k;
+      const int i = lr * HC + lane;
+      const uint32_t cd = s_code[(lr + 1) * HW + lane + 1];
       bool sk = true, inside = false;
       int rcv = i;
-      if (valid[k]) {
+      if ((vmask >> k) & 1u) {
         if (cd <= 7u) {
-          const int tr = lr + nb_dr((int)cd), tc = lc + nb_dc((int)cd);
+          const int tr = lr + nb_dr((int)cd), tc = lane + nb_dc((int)cd);
           const int64_t gr = T.r0 + tr, gc = T.c0 + tc;
           if (gr < 0 || gr >= nr || gc < 0 || gc >= nc) {
             bad = true;  // receiver off the grid: malformed, treated as a sink
@@ -183,153 +352,203 @@ __global__ __launch_bounds__(HT) void k_d8t(D8Params P, int ntiles) {
         } else if (cd != SINK) {
           bad = true;
         }
+        smask |= sk ? 1u << k : 0u;
+        xmask |= (!sk && !inside) ? 1u << k : 0u;  // receiver in another tile
       }
-      sink[k] = sk;
-      ex[k] = valid[k] && !sk && !inside;  // receiver in another tile
-      uint32_t mi = 0, mo = 0;
-      if (valid[k]) {
-#pragma unroll
-        for (int n = 0; n < 8; ++n) {
-          const int ar = lr + nb_dr(n), ac = lc + nb_dc(n);
-          if (s_code[(ar + 1) * HW + ac + 1] == (uint8_t)(7 - n)) {
-            if (ar >= 0 && ar < HR && ac >= 0 && ac < HC) mi |= 1u << n;
-            else mo |= 1u << n;
+      if (inside) atomicOr(&s_msk[rcv >> 1], (1u << (7 - cd)) << (16 * (rcv & 1)));
+      pd[k] = inside ? ((uint32_t)rcv | (1u << 16)) : ((uint32_t)i | PT_TERM);
+      s_x[i] = pd[k];
+    }
+    V hv = TV<VK>::zero();
+    uint64_t hcnt = 0;
+    if (tid < NHALO) {
+      const uint32_t cd = s_code[hh_r * HW + hh_c];
+      if (cd <= 7u) {
+        const int tr = hh_r - 1 + nb_dr((int)cd), tc = hh_c - 1 + nb_dc((int)cd);
+        if (tr >= 0 && tr < T.h && tc >= 0 && tc < T.w) {
+          const int rcv = tr * HC + tc;
+          atomicOr(&s_msk[rcv >> 1], (1u << (8 + 7 - cd)) << (16 * (rcv & 1)));
+          if (!UP) {
+            // Its forest total, loaded while the tile's own work goes on.
+            if (hnd < n_ex) {
+              if constexpr (VK == VK_FF) hv = ff{P.tot_hi[hnd], P.tot_lo[hnd]};
+              if constexpr (VK == VK_F64) hv = P.tot_d[hnd];
+              if (CNT) hcnt = P.ex_cnt[0][hnd];
+            } else {
+              set_status(P.status, FR_ERR_BADCODE);  // inconsistent bookkeeping: never follow it
+            }
           }
         }
       }
-      din[k] = mi;
-      dout[k] = mo;
-      ptr[k] = inside ? (uint32_t)rcv : ((uint32_t)i | PT_TERM);
-      dist[k] = inside ? 1u : 0u;
-      s_ptr[i] = (uint16_t)ptr[k];
-      s_dist[i] = (uint16_t)dist[k];
     }
     if (UP && bad) set_status(P.status, FR_ERR_BADCODE);
     __syncthreads();
-    // 3. Pointer jumping: after round j every pointer spans 2^(j+1) edges
-    // or ends at a root; a path inside the tile has fewer than HN edges.
+    uint32_t mk[HK];  // in-tile donors | out-of-tile donors << 8
+#pragma unroll
+    for (int k = 0; k < HK; ++k) {
+      const int i = (wave + 4 * k) * HC + lane;
+      mk[k] = (vmask >> k) & 1u ? (s_msk[i >> 1] >> (16 * (i & 1))) & 0xFFFFu : 0u;
+    }
+    // 3. Pointer jumping: after round j every pointer spans 2^(j+1) edges or
+    // ends at a root; a path inside the tile has fewer than HN edges.
     for (int j = 0; j <= 12; ++j) {
-      uint32_t np[HK], nd[HK];
-      int open = 0;
+      uint32_t np[HK];
+      bool open = false;
 #pragma unroll
       for (int k = 0; k < HK; ++k) {
-        np[k] = ptr[k];
-        nd[k] = dist[k];
-        if (!(ptr[k] & PT_TERM)) {
-          np[k] = s_ptr[ptr[k]];
-          nd[k] = dist[k] + s_dist[ptr[k]];
-          open = 1;
+        np[k] = pd[k];
+        if (!(pd[k] & PT_TERM)) {
+          // Jump to the target's target, adding its depth.
+          const uint32_t w = s_x[pd[k] & 0xFFFFu];
+          np[k] = (w & 0xFFFFu) | ((pd[k] & 0xFFFF0000u) + (w & 0xFFFF0000u));
+          open = true;
         }
       }
-      if (!__syncthreads_or(open) || j == 12) break;  // uniform; every read above is done
+      if (__ballot(open) && lane == 0) s_open[j] = 1;
+      __syncthreads();  // every read above is done (the masks' too)
+      if (!s_open[j] || j == 12) break;  // uniform
 #pragma unroll
       for (int k = 0; k < HK; ++k) {
-        ptr[k] = np[k];
-        dist[k] = nd[k];
-        const int i = (wave + 4 * k) * HC + lane;
-        s_ptr[i] = (uint16_t)np[k];
-        s_dist[i] = (uint16_t)nd[k];
+        pd[k] = np[k];
+        s_x[(wave + 4 * k) * HC + lane] = np[k];
       }
       __syncthreads();
     }
-    // Depths; a cell whose path never reaches a root lies on or above a
-    // cycle (malformed codes).
-    int level[HK];
+    // 4. Depths (a cell whose path never reaches a root lies on or above a
+    // cycle: malformed codes); the level histogram of the cells with
+    // in-tile donors; phase A: the roots of the inlets; phase C: the halo's
+    // totals into LDS (over the masks, which every thread has read).
+    uint32_t ls[HK];  // level | slot << 16 (level NO_LEVEL: nothing to do)
     int dmax = 0;
     bool cyc = false;
 #pragma unroll
     for (int k = 0; k < HK; ++k) {
-      const bool ok = valid[k] && (ptr[k] & PT_TERM);
-      cyc |= valid[k] && !(ptr[k] & PT_TERM);
-      level[k] = ok ? (int)dist[k] : NO_LEVEL;
-      if (ok) dmax = max(dmax, (int)dist[k]);
+      const bool on = (vmask >> k) & 1u;
+      const bool ok = on && (pd[k] & PT_TERM);
+      const int L = (int)(pd[k] >> 16);
+      cyc |= on && !(pd[k] & PT_TERM);
+      if (ok) dmax = max(dmax, L);
+      ls[k] = NO_LEVEL;
+      if (ok && (mk[k] & 0xFFu)) {
+        const uint32_t old = atomicAdd(&s_lev[L >> 1], 1u << (16 * (L & 1)));
+        ls[k] = (uint32_t)L | (((old >> (16 * (L & 1))) & 0xFFFFu) << 16);
+      }
+      if (UP && on && (mk[k] >> 8)) {
+        uint32_t rt = NONE;
+        if (pd[k] & PT_TERM) {
+          const int p = (int)(pd[k] & 0x7FFFu);
+          rt = (uint32_t)((T.r0 + p / HC) * nc + T.c0 + (p % HC));
+        }
+        P.root_of[(T.r0 + wave + 4 * k) * nc + T.c0 + lane] = rt;
+      }
     }
     if (UP && cyc) set_status(P.status, FR_ERR_NOTDAG);
     dmax = wave_max(dmax);
     if (lane == 0) s_int[wave] = dmax;
-    // 4. Sources: rain (unit rain: 1), and in phase C the forest totals of
-    // the out-of-tile donors, in neighbour order.  The pointer arrays are
-    // dead: every thread passed the last barrier after reading them.
-    V val[HK];
-    uint64_t cnt[HK];
-    double m_rain = 0.0;
-    bool nonfinite = false;
-#pragma unroll
-    for (int k = 0; k < HK; ++k) {
-      const int lr = wave + 4 * k;
-      const int64_t g = (T.r0 + lr) * nc + T.c0 + lane;
-      V v = TV<VK>::zero();
-      uint64_t c = 0;
-      if (valid[k]) {
-        if (RAIN != RAIN_UNIT) {
-          const double r = rain_at<RAIN>(P, g);
-          if (UP) nonfinite |= !isfinite(r);
-          else m_rain += r;
-        } else if (!UP) {
-          m_rain += 1.0;
-        }
-        v = src_of<VK, RAIN>(P, g);
-        c = 1;
-        if (!UP && dout[k]) {
-          uint32_t m = dout[k];
-          while (m) {
-            const int n = __builtin_ctz(m);
-            m &= m - 1;
-            const uint32_t nd = P.node_of[g + (int64_t)nb_dr(n) * nc + nb_dc(n)];
-            if (nd >= n_ex) {  // inconsistent bookkeeping: never follow it
-              set_status(P.status, FR_ERR_BADCODE);
-              continue;
-            }
-            if constexpr (VK == VK_FF) v = ff_add(v, ff{P.tot_hi[nd], P.tot_lo[nd]});
-            if constexpr (VK == VK_F64) v += P.tot_d[nd];
-            if (CNT) c += P.ex_cnt[0][nd];
-          }
-        }
-      }
-      val[k] = v;
-      cnt[k] = c;
-      const int i = lr * HC + lane;
-      if (VK != VK_NONE) s_v[i] = v;
-      if (CNT) s_c[i] = c;
+    if (!UP && tid < NHALO) {
+      if (VK != VK_NONE) s_hv[tid] = hv;
+      if (CNT) s_hc[tid] = hcnt;
     }
-    if (UP && nonfinite) set_status(P.status, FR_ERR_NONFINITE);
     __syncthreads();
     const int D = max(max(s_int[0], s_int[1]), max(s_int[2], s_int[3]));
-    // 5. Levels, deepest first: a cell's in-tile donors are one level deeper
-    // and final; each cell adds them in neighbour order.
-    for (int L = D - 1; L >= 0; --L) {
+    // 5. Level offsets (exclusive prefix sums, 8 levels per thread); in
+    // phase C the inlets add their out-of-tile donors' totals in neighbour
+    // order.
+    uint32_t hl[8], run = 0;
+    {
+      const uint4 w4 = reinterpret_cast<const uint4*>(s_lev)[tid];
+      const uint32_t ws[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        hl[2 * q] = run;
+        run += ws[q] & 0xFFFFu;
+        hl[2 * q + 1] = run;
+        run += ws[q] >> 16;
+      }
+    }
+    uint32_t incl = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) s_int[8 + wave] = (int)incl;
+    if (!UP) {
 #pragma unroll
       for (int k = 0; k < HK; ++k) {
-        if (level[k] == L && din[k]) {
-          const int i = (wave + 4 * k) * HC + lane;
-          uint32_t m = din[k];
-          V v = val[k];
-          uint64_t c = cnt[k];
-          while (m) {
-            const int n = __builtin_ctz(m);
-            m &= m - 1;
-            const int a = i + nb_dr(n) * HC + nb_dc(n);
-            if (VK != VK_NONE) v = TV<VK>::add(v, s_v[a]);
-            if (CNT) c += s_c[a];
-          }
-          val[k] = v;
-          cnt[k] = c;
-          if (VK != VK_NONE) s_v[i] = v;
-          if (CNT) s_c[i] = c;
+        if (!(mk[k] >> 8)) continue;
+        const int lr = wave + 4 * k;
+        const int i = lr * HC + lane;
+        V v = TV<VK>::zero();
+        uint64_t c = 0;
+        if (VK != VK_NONE) v = s_v[i];
+        if (CNT) c = s_c[i];
+        uint32_t m = mk[k] >> 8;
+        while (m) {
+          const int n = __builtin_ctz(m);
+          m &= m - 1;
+          const int h = halo_id(lr + 1 + nb_dr(n), lane + 1 + nb_dc(n));
+          if (VK != VK_NONE) v = TV<VK>::add(v, s_hv[h]);
+          if (CNT) c += s_hc[h];
         }
+        if (VK != VK_NONE) s_v[i] = v;
+        if (CNT) s_c[i] = c;
       }
-      __syncthreads();
     }
+    __syncthreads();
+    {
+      uint32_t base = incl - run;
+      for (int w = 0; w < wave; ++w) base += (uint32_t)s_int[8 + w];
+      uint4 o4;
+      o4.x = (base + hl[0]) | ((base + hl[1]) << 16);
+      o4.y = (base + hl[2]) | ((base + hl[3]) << 16);
+      o4.z = (base + hl[4]) | ((base + hl[5]) << 16);
+      o4.w = (base + hl[6]) | ((base + hl[7]) << 16);
+      reinterpret_cast<uint4*>(s_lev)[tid] = o4;  // every histogram read is done
+    }
+    __syncthreads();
+    // 6. The cells with in-tile donors, in level order.
+#pragma unroll
+    for (int k = 0; k < HK; ++k) {
+      if ((ls[k] & 0xFFFFu) != NO_LEVEL) {
+        const int i = (wave + 4 * k) * HC + lane;
+        s_x[s_off[ls[k] & 0xFFFFu] + (ls[k] >> 16)] = (uint32_t)i | ((mk[k] & 0xFFu) << 16);
+      }
+    }
+    __syncthreads();
+    // 7. Levels, deepest first, on wavefront 0 alone: a cell's in-tile
+    // donors are one level deeper and final.  The LDS processes one
+    // wavefront's instructions in order, so a level's reads see the previous
+    // level's writes with no barrier or wait between them (the compiler is
+    // only kept from moving LDS accesses across levels); the next level's
+    // entries are read a level ahead.
+    if (wave == 0 && D > 0) {
+      // Level L spans entries [off[L], off[L + 1]); offsets are read two
+      // levels ahead, entries one.
+      int o1 = s_off[D], o0 = s_off[D - 1], n0 = D >= 2 ? (int)s_off[D - 2] : 0;
+      uint32_t e = lane < o1 - o0 ? s_x[o0 + lane] : 0u;
+      for (int L = D - 1; L >= 0; --L) {
+        const int nn0 = L >= 2 ? (int)s_off[L - 2] : 0;
+        const uint32_t ne = L > 0 && lane < o0 - n0 ? s_x[n0 + lane] : 0u;
+        if (lane < o1 - o0) level_cell<VK, CNT>(s_v, s_c, e);
+        for (int j = o0 + 64 + lane; j < o1; j += 64) level_cell<VK, CNT>(s_v, s_c, s_x[j]);  // wide levels
+        __builtin_amdgcn_wave_barrier();
+        e = ne;
+        o1 = o0;
+        o0 = n0;
+        n0 = nn0;
+      }
+    }
+    __syncthreads();
     if (UP) {
-      // 6a. Exits (a root that is not a sink) into consecutive slots of the
-      // list: one atomic per tile.
+      // 8a. Exits (a root that is not a sink) into consecutive slots of the
+      // list: one atomic per tile.  Slot order inside the wavefront: cell k
+      // of every lane before cell k + 1 of any lane.
       const uint64_t lower = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-      // Slot order inside the wavefront: cell k of every lane before cell
-      // k + 1 of any lane.
       uint32_t off[HK], wtot = 0;
 #pragma unroll
       for (int k = 0; k < HK; ++k) {
-        const uint64_t m = __ballot(ex[k]);
+        const uint64_t m = __ballot((xmask >> k) & 1u);
         off[k] = wtot + (uint32_t)__popcll(m & lower);
         wtot += (uint32_t)__popcll(m);
       }
@@ -337,9 +556,10 @@ __global__ __launch_bounds__(HT) void k_d8t(D8Params P, int ntiles) {
       double lmd = 0.0;
 #pragma unroll
       for (int k = 0; k < HK; ++k) {
-        if (!ex[k]) continue;
-        if constexpr (VK == VK_FF) lmf = fmaxf(lmf, fabsf(val[k].hi));
-        if constexpr (VK == VK_F64) lmd = fmax(lmd, fabs(val[k]));
+        if (!((xmask >> k) & 1u)) continue;
+        const int i = (wave + 4 * k) * HC + lane;
+        if constexpr (VK == VK_FF) lmf = fmaxf(lmf, fabsf(s_v[i].hi));
+        if constexpr (VK == VK_F64) lmd = fmax(lmd, fabs(s_v[i]));
       }
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
@@ -354,7 +574,7 @@ __global__ __launch_bounds__(HT) void k_d8t(D8Params P, int ntiles) {
       __syncthreads();
       if (tid == 0) {
         const uint32_t tot = (uint32_t)(s_int[4] + s_int[5] + s_int[6] + s_int[7]);
-        s_int[8] = tot ? (int)atomicAdd(P.n_exits, tot) : 0;
+        s_int[12] = tot ? (int)atomicAdd(P.n_exits, tot) : 0;
         if constexpr (VK == VK_FF) {
           const float m = fmaxf(fmaxf(s_flt[0], s_flt[1]), fmaxf(s_flt[2], s_flt[3]));
           if (m > 0.0f) atomicMax(&P.ctl->loc_max_f, __float_as_uint(m));
@@ -367,50 +587,45 @@ __global__ __launch_bounds__(HT) void k_d8t(D8Params P, int ntiles) {
         }
       }
       __syncthreads();
-      uint32_t base = (uint32_t)s_int[8];
+      uint32_t base = (uint32_t)s_int[12];
       for (int w = 0; w < wave; ++w) base += (uint32_t)s_int[4 + w];
 #pragma unroll
       for (int k = 0; k < HK; ++k) {
-        const int lr = wave + 4 * k;
-        const int64_t g = (T.r0 + lr) * nc + T.c0 + lane;
-        if (ex[k]) {
-          const uint32_t idx = base + off[k];
-          if (idx < P.cap) {
-            P.node_of[g] = idx;
-            P.ex_cell[idx] = (uint32_t)g;
-            if constexpr (VK == VK_FF) {
-              P.ex_hi[idx] = val[k].hi;
-              P.ex_lo[idx] = val[k].lo;
-            }
-            if constexpr (VK == VK_F64) P.ex_d[idx] = val[k];
-            if (CNT) P.ex_cnt[0][idx] = cnt[k];
+        if (!((xmask >> k) & 1u)) continue;
+        const int i = (wave + 4 * k) * HC + lane;
+        const int64_t g = (T.r0 + wave + 4 * k) * nc + T.c0 + lane;
+        const uint32_t idx = base + off[k];
+        if (idx < P.cap) {
+          P.node_of[g] = idx;
+          P.ex_cell[idx] = (uint32_t)g;
+          if constexpr (VK == VK_FF) {
+            const ff v = s_v[i];
+            P.ex_hi[idx] = v.hi;
+            P.ex_lo[idx] = v.lo;
           }
-        }
-        // 6b. Inlets: the root of their in-tile path (NONE on a cycle).
-        if (valid[k] && dout[k]) {
-          uint32_t rt = NONE;
-          if (ptr[k] & PT_TERM) {
-            const int p = (int)(ptr[k] & 0x7FFFu);
-            rt = (uint32_t)((T.r0 + p / HC) * nc + T.c0 + (p % HC));
-          }
-          P.root_of[g] = rt;
+          if constexpr (VK == VK_F64) P.ex_d[idx] = s_v[i];
+          if (CNT) P.ex_cnt[0][idx] = s_c[i];
         }
       }
     } else {
-      // 6c. Final values and the tile's {sum over sinks, sum of rain}.
+      // 8b. Final values and the tile's {sum over sinks, sum of rain}.
       double m_sink = 0.0;
 #pragma unroll
       for (int k = 0; k < HK; ++k) {
-        if (!valid[k]) continue;
+        if (!((vmask >> k) & 1u)) continue;
+        const int i = (wave + 4 * k) * HC + lane;
         const int64_t g = (T.r0 + wave + 4 * k) * nc + T.c0 + lane;
         if constexpr (VK == VK_FF) {
-          if (P.q32) P.q32[g] = val[k].hi + val[k].lo;
+          const ff v = s_v[i];
+          if (P.q32) P.q32[g] = v.hi + v.lo;
+          if ((smask >> k) & 1u) m_sink += TV<VK>::mass(v);
         }
         if constexpr (VK == VK_F64) {
-          if (P.q64) P.q64[g] = val[k];
+          const double v = s_v[i];
+          if (P.q64) P.q64[g] = v;
+          if ((smask >> k) & 1u) m_sink += v;
         }
-        if (CNT) P.cnt[g] = cnt[k];
-        if (sink[k]) m_sink += TV<VK>::mass(val[k]);
+        if (CNT) P.cnt[g] = s_c[i];
       }
       if (P.mass_part) {
 #pragma unroll
@@ -444,6 +659,37 @@ __global__ void k_d8t_gate(CallCtl* C, int force) {
     C->loc_max_f = 0u;
     C->loc_max_d = 0ull;
   }
+}
+
+// The probe: rows 32, 96, 160, ... (row 0 on grids of fewer rows); every
+// workgroup adds its count once.
+constexpr int PROBE_STRIDE = 64;
+__global__ __launch_bounds__(256) void k_d8_probe(D8Params P) {
+  const int64_t nc = P.ncols;
+  const int64_t nsr = P.nrows > PROBE_STRIDE / 2 ? (P.nrows - PROBE_STRIDE / 2 + PROBE_STRIDE - 1) / PROBE_STRIDE : 1;
+  const int64_t total = nsr * nc;
+  uint32_t cnt = 0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t sr = k / nc;
+    const int64_t r = P.nrows > PROBE_STRIDE / 2 ? PROBE_STRIDE / 2 + sr * PROBE_STRIDE : 0;
+    const uint32_t cd = P.code[r * nc + (k - sr * nc)];
+    cnt += (cd >= 3u && cd <= 7u) ? 1u : 0u;
+  }
+  __shared__ uint32_t s_cnt;
+  if (threadIdx.x == 0) s_cnt = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cnt += (uint32_t)__shfl_xor((int)cnt, o, 64);
+  if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(&s_cnt, cnt);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_cnt) atomicAdd(&P.ctl->probe_cnt, s_cnt);
+}
+
+// Predicted exits above 1.5 x capacity: mark the list overflowed.
+__global__ void k_d8_probe_decide(D8Params P, uint64_t sampled) {
+  if (threadIdx.x != 0) return;
+  const double est = (double)P.ctl->probe_cnt * ((double)(P.nrows * P.ncols) / (double)sampled);
+  if (est > 1.5 * (double)P.cap) *P.n_exits = P.cap + 1u;
 }
 
 // Mass-balance partials of the tiles, first stage: each workgroup sums a
@@ -545,6 +791,16 @@ uint64_t d8t_exit_bound(int64_t nrows, int64_t ncols) {
 size_t d8t_mass_words(int64_t nrows, int64_t ncols) {
   const int64_t nt = d8t_tiles(nrows, ncols);
   return (size_t)(2 * (nt + (nt + D8T_MASS_RUN - 1) / D8T_MASS_RUN));
+}
+
+hipError_t launch_d8_probe(const D8Params& P, hipStream_t s) {
+  const int64_t nsr = P.nrows > PROBE_STRIDE / 2 ? (P.nrows - PROBE_STRIDE / 2 + PROBE_STRIDE - 1) / PROBE_STRIDE : 1;
+  const int64_t total = nsr * P.ncols;
+  int64_t b = (total + 255) / 256;
+  if (b > 1024) b = 1024;
+  hipLaunchKernelGGL(k_d8_probe, dim3((unsigned)(b < 1 ? 1 : b)), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(k_d8_probe_decide, dim3(1), dim3(64), 0, s, P, (uint64_t)(total > 0 ? total : 1));
+  return hipGetLastError();
 }
 
 hipError_t launch_d8t_gate(CallCtl* C, bool force, hipStream_t s) {

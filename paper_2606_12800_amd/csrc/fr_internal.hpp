@@ -100,6 +100,7 @@ struct CallCtl {
   int32_t ms_skip;           // 1: the row sweep does not serve this call (gate of the general mass)
   int32_t d8_tiles;          // 1: the tile-forest path serves this call (the row sweeps' exits overflowed)
   int32_t served;            // FR_SERVED_* of the path the host enqueued first (device gates may override)
+  uint32_t probe_cnt;        // D8 probe: sampled cells that drain sideways or to the next row
 };
 static_assert(sizeof(CallCtl) <= 256, "control block fits its 256-byte slot");
 constexpr int CTL_WORDS = 64;  // 32-bit words zeroed at the start of a call
@@ -167,6 +168,12 @@ hipError_t launch_d8t_gate(CallCtl* C, bool force, hipStream_t s);
 // Phase A (up) or C (down) of every tile; both return at once while the
 // gate is closed.
 hipError_t launch_d8t(bool up, ValKind vk, bool cnt, const D8Params& P, hipStream_t s);
+// Samples every 64th row of the codes before the row sweeps: when the cells
+// that drain sideways or to the next row predict an overflow of the row
+// sweeps' exit list, the list is marked overflowed at once (its count set
+// above capacity), so that the row sweeps return at once and the tile
+// forest serves the call.
+hipError_t launch_d8_probe(const D8Params& P, hipStream_t s);
 // Sums the tiles' mass partials into out[0..1] when the gate is open.
 hipError_t launch_d8t_mass(const double* part, int64_t ntiles, double* out, CallCtl* C, hipStream_t s);
 
