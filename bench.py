@@ -27,8 +27,13 @@ PHASE_BYTES = {
     "receivers": 4 + 1,        # z read, code written
     "d8_up": 1 + 1 + 4,        # phase A: code (root sweep), code + rain (local sweep); exits are sparse
     "d8_down": 1 + 4 + 4 + 8,  # code, rain read; q (f32), counts (u64) written
+    # Tile forest (flow in every direction): its phase A reads code + rain,
+    # its phase C code + rain and writes q + counts; the exit forest between
+    # them is not counted (exits are a few per cent of the cells).
+    "d8_tiles": (1 + 4) + (1 + 4 + 4 + 8),
 }
-PHASE_KERNEL = {"receivers": "k_receivers", "d8_up": "k_d8_a (root + local sweep)", "d8_down": "k_d8_c"}
+PHASE_KERNEL = {"receivers": "k_receivers", "d8_up": "k_d8_a (root + local sweep)", "d8_down": "k_d8_c",
+                "d8_tiles": "k_d8t (tile forest, phases A and C) + exit forest rounds"}
 ACC_BYTES = 1 + 4 + 4 + 8     # whole accumulate call: code, rain in; q, counts out
 ROUTE_BYTES = 4 + 1 + ACC_BYTES  # whole route: receivers (z in, code out) + accumulate
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs calibrated
@@ -41,6 +46,9 @@ MEASURED_TRAFFIC = {
         "d8_up": (1.3366e10, "profiles/d8_43360_hbm_traffic.md"),
         "d8_down": (3.3176e10, "profiles/d8_43360_hbm_traffic.md"),
     },
+    # The tile phase of the filled route: both tile kernels, link, rounds
+    # and totals.
+    ("d8_filled", 43360, 43360): {"d8_tiles": (1.5990e11, "profiles/d8_43360_filled_tile_forest.md")},
     ("mfd", 16384, 16384): {"row_sweep": (5.3063e9, "profiles/mfd_16384_row_sweep.md")},
     ("adjoint", 4096, 4096): {"sweep": (6.987e8, "profiles/sweep_and_batch_hbm_traffic.md")},
     ("batched", 512): {"batch": (2.472e10, "profiles/sweep_and_batch_hbm_traffic.md")},
@@ -581,17 +589,23 @@ def main():
     out = run_d8(args)
     if not args.headline_only and not args.rows and not args.cols and not args.size_given and not args.filled:
         # The other configurations of the metric, timed in the same run:
-        # MFD 16384^2 (float32 and float64) and the 512-tile batch (HIP graph
-        # replay against per-tile float32 and float64 launches).  Each keeps
-        # its own roofline; none has a CPU baseline here (bench.py
-        # --workload mfd / batched time the oracle beside them).
+        # MFD 16384^2 (float32 and float64), the 512-tile batch (HIP graph
+        # replay against per-tile float32 and float64 launches) and the
+        # paper's workflow -- the untilted 43360^2 DEM depression-filled
+        # (not timed), then routed D8.  Each keeps its own roofline; none has
+        # a CPU baseline here (bench.py --workload mfd / batched time the
+        # oracle beside them).
         import torch
         torch.cuda.empty_cache()
         sub = argparse.Namespace(**vars(args))
         sub.no_cpu_baseline = True
         sub.steps, sub.warmup = 3, 1
         sub.size_given = False
-        for name, fn in (("mfd_16384", lambda: run_secondary(sub, "mfd")), ("batched_512", lambda: run_batched(sub))):
+        filled = argparse.Namespace(**vars(sub))
+        filled.filled = True
+        filled.headline_only = True
+        for name, fn in (("mfd_16384", lambda: run_secondary(sub, "mfd")), ("batched_512", lambda: run_batched(sub)),
+                         ("d8_filled_43360", lambda: run_d8(filled))):
             log(f"{name} ...")
             line = fn()
             out["detail"][name] = {k: line[k] for k in ("value", "unit", "ms_per_step", "dtype", "config",
@@ -717,7 +731,8 @@ def run_d8(args):
         "config": {"workload": (f"D8 {nr}x{nc} fractal DEM (seed {args.seed}"
                                 + (", untilted, depression-filled" if args.filled else "") + "), f32 rain + u64 counts"),
                    "cells": ncell},
-        "roofline": roofline(achieved, PHASE_KERNEL[dom], ("d8", nr, nc), dom, bytes_per_cell=PHASE_BYTES[dom],
+        "roofline": roofline(achieved, PHASE_KERNEL[dom], ("d8_filled" if args.filled else "d8", nr, nc), dom,
+                             bytes_per_cell=PHASE_BYTES[dom],
                              ms_per_launch=single[dom]),
         "detail": {"receivers_ms": recv_avg, "accumulate_ms": acc_avg,
                    "accumulate_alg_GBs": acc_gbs,
