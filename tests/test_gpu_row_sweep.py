@@ -114,6 +114,10 @@ def test_row_sweep_forward(kind, nr, nc, seed, path):
         q32, _, m32 = fr.accumulate(code, zt, dev(rain), "mfd", torch.float32, mass=True)
         q64, _, m64 = fr.accumulate(code, zt, dev(rain), "mfd", torch.float64, mass=True)
         qu, _, _ = fr.accumulate(code, zt, None, "mfd", torch.float64)
+        # The automatic choice takes the row sweep here; the forced wavefront
+        # sweep finishes the call itself (or hands it to the engine).
+        served = fr.served_by()
+        assert served == "row_sweep" if path == "auto" else served in ("sweep", "engine")
     e32, e64 = relmax(host(q32), qref), relmax(host(q64), qref)
     print(f"  e_max32={e32:.2e} e_norm32={relnorm(host(q32), qref):.2e} e_max64={e64:.2e}", flush=True)
     assert e32 <= 1e-6
@@ -174,6 +178,7 @@ def test_row_sweep_declines_two_way_flow():
     zt = dev(z)
     code = fr.receivers(zt, "mfd")
     q64, _, _ = fr.accumulate(code, zt, dev(rain), "mfd", torch.float64)
+    assert fr.served_by() in ("sweep", "engine")
     assert relmax(host(q64), oracle.accumulate_mfd(z, rain, 1.1)) <= 1e-10
 
 
