@@ -1,7 +1,9 @@
 """Full-size checks at the benchmark's launch configuration: the 43,360 x
-43,360 (1.88e9-cell) D8 route with float32 rain and uint64 counts, and the
+43,360 (1.88e9-cell) D8 route with float32 rain and uint64 counts, the
 paper's own grid shape, 57,345 x 32,769 (Section 4; rows not 4-cell
-aligned, so the unaligned load and store variants run).
+aligned, so the unaligned load and store variants run), and the paper's
+workflow at 43,360 x 43,360: the untilted DEM depression-filled on the
+GPU, then routed (flow in every direction: the tile forest serves it).
 
 The oracle cannot run its sequential push over 1.88e9 cells within a test,
 so the checks are
@@ -35,21 +37,30 @@ fr = pytest.importorskip("paper_2606_12800_amd")
 OFFS = oracle.OFFSETS
 
 
-@pytest.fixture(scope="module", params=[(43360, 43360), (57345, 32769)], ids=["43360sq", "paper_shape"])
+@pytest.fixture(scope="module", params=[(43360, 43360, False), (57345, 32769, False), (43360, 43360, True)],
+                ids=["43360sq", "paper_shape", "43360sq_filled"])
 def routed(request):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    nr, nc = request.param
-    print(f"generating {nr}x{nc} DEM", flush=True)
-    z_h = synth.dem(2, nr, nc)
+    nr, nc, filled = request.param
+    print(f"generating {nr}x{nc} DEM" + (" (untilted, to be filled)" if filled else ""), flush=True)
+    z_h = synth.dem(2, nr, nc, tilt=0.0 if filled else synth.TILT)
     rain_h = synth.rain(2, nr, nc)
     z = torch.from_numpy(z_h).cuda()
+    if filled:
+        # The surface routed is the filled one; the receivers check reads it.
+        z = fr.fill_depressions(z, "d8", eps=True)
+        fr._default_ws.buf = None
+        torch.cuda.synchronize()
+        z_h = z.cpu().numpy()
     rain = torch.from_numpy(rain_h).cuda()
     print(f"routing {nr}x{nc}", flush=True)
     code, q, cnt, mass = fr.route(z, rain, "d8", torch.float32, counts=True, mass=True)
     torch.cuda.synchronize()
+    assert fr.served_by() == ("tiles" if filled else "rows")
     yield z_h, rain_h, z, rain, code, q, cnt, mass
     del z, rain, code, q, cnt
+    fr._default_ws.buf = None
     torch.cuda.empty_cache()
 
 
