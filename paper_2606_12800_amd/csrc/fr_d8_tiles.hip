@@ -21,10 +21,15 @@
 //      exit where its in-tile path ends -- and its depth, the number of
 //      in-tile edges to the root, in about log2(depth) rounds;
 //   3. a counting sort of the cells with donors inside the tile by depth;
-//   4. the levels of depth, deepest first.  A cell's donors inside the tile
-//      lie exactly one level deeper, so with one barrier per level each cell
-//      of the level reads its finished donors at once and adds them in
-//      neighbour order: a fixed order, so results repeat bit for bit.
+//   4. the levels of depth, deepest first, on one wavefront.  A cell's
+//      donors inside the tile lie exactly one level deeper, so each cell of
+//      the level reads its finished donors at once (the LDS serves one
+//      wavefront's accesses in order: no barrier between levels) and adds
+//      them in neighbour order: a fixed order, so results repeat bit for
+//      bit.
+// Counts live in LDS as 16 bits in phase A (local counts, at most 2048) and
+// 32 bits in phase C (at most the grid's cell count, below 2^31), so that
+// four workgroups fit on a compute unit.
 // Global loads that depend on nothing else (codes, rain, the exit indices of
 // the halo) are issued together at the start of a tile, and the halo's
 // forest totals while the tile's own work runs.
@@ -33,9 +38,9 @@
 // (down) starts the inlets from their out-of-tile donors' forest totals;
 // its values are final and go out with the tile's mass-balance partial.
 //
-// The path runs only after the row sweeps' exit list overflowed: every
-// launch first reads the control block's gate and returns at once when it is
-// closed, and each workgroup walks a stride of tiles, so that a closed gate
+// The path runs only after the row sweeps' exit list overflowed, or when the
+// caller chose it: every launch first reads the control block's gate and
+// returns at once when it is closed, and each workgroup walks a stride of tiles, so that a closed gate
 // costs a few thousand short workgroups.
 #include "fr_d8.hpp"
 
@@ -162,8 +167,8 @@ __device__ __forceinline__ int nb_off(int n) {
 // four donors are read at once and added without branches (a missing donor
 // adds an exact zero, which changes no bit of the sum); float-float sums are
 // normalised once.  Cells with more donors finish in a loop (rare).
-template <int VK, bool CNT>
-__device__ __forceinline__ void level_cell(typename TV<VK>::T* s_v, uint64_t* s_c, uint32_t ent) {
+template <int VK, bool CNT, class CT>
+__device__ __forceinline__ void level_cell(typename TV<VK>::T* s_v, CT* s_c, uint32_t ent) {
   using V = typename TV<VK>::T;
   const int i = (int)(ent & 0xFFFFu);
   uint32_t m = ent >> 16;
@@ -216,7 +221,7 @@ __device__ __forceinline__ void level_cell(typename TV<VK>::T* s_v, uint64_t* s_
 #pragma unroll
     for (int q = 0; q < 4; ++q) c += q < kq ? y[q] : 0ull;
     for (uint32_t r = m; r; r &= r - 1) c += s_c[i + nb_off(__builtin_ctz(r))];
-    s_c[i] = c;
+    s_c[i] = (CT)c;
   }
 }
 
@@ -226,7 +231,7 @@ struct RainReg {
 };
 
 template <bool UP, int VK, bool CNT, int RAIN>
-__global__ __launch_bounds__(HT, 3) void k_d8t(D8Params P, int ntiles) {
+__global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
   if (__hip_atomic_load(&P.ctl->d8_tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;  // uniform
   const uint32_t n_ex = *P.n_exits;
   if (!UP && n_ex > P.cap) return;  // uniform: the engine takes over
@@ -235,27 +240,35 @@ __global__ __launch_bounds__(HT, 3) void k_d8t(D8Params P, int ntiles) {
   constexpr int NCODE = (HR + 2) * HW;
   constexpr int NCU = (NCODE + HT - 1) / HT;  // code loads per thread
   constexpr int VB = VK == VK_NONE ? 0 : HN * 8;
-  constexpr int CB = CNT ? HN * 8 : 0;
-  constexpr int HB = (UP ? 0 : NHALO * ((VK == VK_NONE ? 0 : 8) + (CNT ? 8 : 0)));
+  // Counts in LDS: phase A holds local counts (at most the tile's 2048
+  // cells: 16 bits), phase C final counts (at most the grid's cell count,
+  // below 2^31: 32 bits).  With the level histogram over the donor masks in
+  // phase C, either phase's LDS stays within a quarter of a compute unit's.
+  using CT = typename std::conditional<UP, uint16_t, uint32_t>::type;
+  constexpr int CB = CNT ? HN * (int)sizeof(CT) : 0;
+  constexpr int HB = (UP ? 0 : NHALO * ((VK == VK_NONE ? 0 : 8) + (CNT ? 4 : 0)));
   constexpr int MB = HN * 2 > HB ? HN * 2 : HB;
   __shared__ __align__(16) unsigned char s_buf[VB + CB];  // values, counts
   // Donor masks (16 bits per cell: in-tile donors, out-of-tile donors);
-  // once read, the forest totals of the halo cells (phase C).
+  // once read, the forest totals of the halo cells, and once those are
+  // added, the level histogram (phase C).
   __shared__ __align__(16) unsigned char s_mb[MB];
   // Pointer jumping (receiver | root flag, depth << 16 per cell), then the
   // cells with in-tile donors in level order (cell | donor mask << 16).
   __shared__ uint32_t s_x[HN];
-  __shared__ __align__(16) uint32_t s_lev[HN / 2];  // level histogram, then offsets: 16 bits per level
+  __shared__ __align__(16) uint32_t s_lev_a[UP ? HN / 2 : 4];  // phase A's level histogram
   __shared__ uint8_t s_code[NCODE];
   __shared__ int s_int[16];
   __shared__ int s_open[16];
   __shared__ double s_dbl[8];
   __shared__ float s_flt[4];
   V* s_v = reinterpret_cast<V*>(s_buf);
-  uint64_t* s_c = reinterpret_cast<uint64_t*>(s_buf + VB);
+  CT* s_c = reinterpret_cast<CT*>(s_buf + VB);
   uint32_t* s_msk = reinterpret_cast<uint32_t*>(s_mb);
   V* s_hv = reinterpret_cast<V*>(s_mb);
-  uint64_t* s_hc = reinterpret_cast<uint64_t*>(s_mb + (VK == VK_NONE ? 0 : NHALO * 8));
+  CT* s_hc = reinterpret_cast<CT*>(s_mb + (VK == VK_NONE ? 0 : NHALO * 8));
+  // Level histogram, then level offsets: 16 bits per level.
+  uint32_t* s_lev = UP ? s_lev_a : reinterpret_cast<uint32_t*>(s_mb);
   uint16_t* s_off = reinterpret_cast<uint16_t*>(s_lev);
   const int64_t nr = P.nrows, nc = P.ncols;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -300,7 +313,7 @@ __global__ __launch_bounds__(HT, 3) void k_d8t(D8Params P, int ntiles) {
     }
     for (int w = tid; w < HN / 2; w += HT) {
       s_msk[w] = 0u;
-      s_lev[w] = 0u;
+      if (UP) s_lev[w] = 0u;
     }
     if (tid < 16) s_open[tid] = 0;
 #pragma unroll
@@ -321,7 +334,7 @@ __global__ __launch_bounds__(HT, 3) void k_d8t(D8Params P, int ntiles) {
         s_v[i] = ok ? ff{hi, RAIN == RAIN_F64 ? (float)((double)rq[k] - (double)hi) : 0.0f} : ff{0.0f, 0.0f};
       }
       if constexpr (VK == VK_F64) s_v[i] = ok ? (double)rq[k] : 0.0;
-      if (CNT) s_c[i] = ok ? 1u : 0u;
+      if (CNT) s_c[i] = ok ? (CT)1 : (CT)0;
     }
     if (UP && nonfinite) set_status(P.status, FR_ERR_NONFINITE);
     __syncthreads();
@@ -389,6 +402,40 @@ __global__ __launch_bounds__(HT, 3) void k_d8t(D8Params P, int ntiles) {
       const int i = (wave + 4 * k) * HC + lane;
       mk[k] = (vmask >> k) & 1u ? (s_msk[i >> 1] >> (16 * (i & 1))) & 0xFFFFu : 0u;
     }
+    if (!UP) {
+      // Phase C: the halo's forest totals into LDS over the masks (every
+      // thread has read its own), then the inlets add their out-of-tile
+      // donors' totals in neighbour order; the level histogram then takes
+      // the masks' place.
+      __syncthreads();
+      if (tid < NHALO) {
+        if (VK != VK_NONE) s_hv[tid] = hv;
+        if (CNT) s_hc[tid] = (CT)hcnt;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < HK; ++k) {
+        if (!(mk[k] >> 8)) continue;
+        const int lr = wave + 4 * k;
+        const int i = lr * HC + lane;
+        V v = TV<VK>::zero();
+        uint32_t c = 0;
+        if (VK != VK_NONE) v = s_v[i];
+        if (CNT) c = s_c[i];
+        uint32_t m = mk[k] >> 8;
+        while (m) {
+          const int n = __builtin_ctz(m);
+          m &= m - 1;
+          const int h = halo_id(lr + 1 + nb_dr(n), lane + 1 + nb_dc(n));
+          if (VK != VK_NONE) v = TV<VK>::add(v, s_hv[h]);
+          if (CNT) c += s_hc[h];
+        }
+        if (VK != VK_NONE) s_v[i] = v;
+        if (CNT) s_c[i] = (CT)c;
+      }
+      __syncthreads();
+      for (int w = tid; w < HN / 2; w += HT) s_lev[w] = 0u;
+    }
     // 3. Pointer jumping: after round j every pointer spans 2^(j+1) edges or
     // ends at a root; a path inside the tile has fewer than HN edges.
     for (int j = 0; j <= 12; ++j) {
@@ -416,8 +463,7 @@ __global__ __launch_bounds__(HT, 3) void k_d8t(D8Params P, int ntiles) {
     }
     // 4. Depths (a cell whose path never reaches a root lies on or above a
     // cycle: malformed codes); the level histogram of the cells with
-    // in-tile donors; phase A: the roots of the inlets; phase C: the halo's
-    // totals into LDS (over the masks, which every thread has read).
+    // in-tile donors; phase A: the roots of the inlets.
     uint32_t ls[HK];  // level | slot << 16 (level NO_LEVEL: nothing to do)
     int dmax = 0;
     bool cyc = false;
@@ -445,15 +491,9 @@ __global__ __launch_bounds__(HT, 3) void k_d8t(D8Params P, int ntiles) {
     if (UP && cyc) set_status(P.status, FR_ERR_NOTDAG);
     dmax = wave_max(dmax);
     if (lane == 0) s_int[wave] = dmax;
-    if (!UP && tid < NHALO) {
-      if (VK != VK_NONE) s_hv[tid] = hv;
-      if (CNT) s_hc[tid] = hcnt;
-    }
     __syncthreads();
     const int D = max(max(s_int[0], s_int[1]), max(s_int[2], s_int[3]));
-    // 5. Level offsets (exclusive prefix sums, 8 levels per thread); in
-    // phase C the inlets add their out-of-tile donors' totals in neighbour
-    // order.
+    // 5. Level offsets (exclusive prefix sums, 8 levels per thread).
     uint32_t hl[8], run = 0;
     {
       const uint4 w4 = reinterpret_cast<const uint4*>(s_lev)[tid];
@@ -473,28 +513,6 @@ __global__ __launch_bounds__(HT, 3) void k_d8t(D8Params P, int ntiles) {
       if (lane >= o) incl += y;
     }
     if (lane == 63) s_int[8 + wave] = (int)incl;
-    if (!UP) {
-#pragma unroll
-      for (int k = 0; k < HK; ++k) {
-        if (!(mk[k] >> 8)) continue;
-        const int lr = wave + 4 * k;
-        const int i = lr * HC + lane;
-        V v = TV<VK>::zero();
-        uint64_t c = 0;
-        if (VK != VK_NONE) v = s_v[i];
-        if (CNT) c = s_c[i];
-        uint32_t m = mk[k] >> 8;
-        while (m) {
-          const int n = __builtin_ctz(m);
-          m &= m - 1;
-          const int h = halo_id(lr + 1 + nb_dr(n), lane + 1 + nb_dc(n));
-          if (VK != VK_NONE) v = TV<VK>::add(v, s_hv[h]);
-          if (CNT) c += s_hc[h];
-        }
-        if (VK != VK_NONE) s_v[i] = v;
-        if (CNT) s_c[i] = c;
-      }
-    }
     __syncthreads();
     {
       uint32_t base = incl - run;
@@ -530,8 +548,8 @@ __global__ __launch_bounds__(HT, 3) void k_d8t(D8Params P, int ntiles) {
       for (int L = D - 1; L >= 0; --L) {
         const int nn0 = L >= 2 ? (int)s_off[L - 2] : 0;
         const uint32_t ne = L > 0 && lane < o0 - n0 ? s_x[n0 + lane] : 0u;
-        if (lane < o1 - o0) level_cell<VK, CNT>(s_v, s_c, e);
-        for (int j = o0 + 64 + lane; j < o1; j += 64) level_cell<VK, CNT>(s_v, s_c, s_x[j]);  // wide levels
+        if (lane < o1 - o0) level_cell<VK, CNT, CT>(s_v, s_c, e);
+        for (int j = o0 + 64 + lane; j < o1; j += 64) level_cell<VK, CNT, CT>(s_v, s_c, s_x[j]);  // wide levels
         __builtin_amdgcn_wave_barrier();
         e = ne;
         o1 = o0;
@@ -604,7 +622,7 @@ __global__ __launch_bounds__(HT, 3) void k_d8t(D8Params P, int ntiles) {
             P.ex_lo[idx] = v.lo;
           }
           if constexpr (VK == VK_F64) P.ex_d[idx] = s_v[i];
-          if (CNT) P.ex_cnt[0][idx] = s_c[i];
+          if (CNT) P.ex_cnt[0][idx] = (uint64_t)s_c[i];
         }
       }
     } else {
@@ -625,7 +643,7 @@ __global__ __launch_bounds__(HT, 3) void k_d8t(D8Params P, int ntiles) {
           if (P.q64) P.q64[g] = v;
           if ((smask >> k) & 1u) m_sink += v;
         }
-        if (CNT) P.cnt[g] = s_c[i];
+        if (CNT) P.cnt[g] = (uint64_t)s_c[i];
       }
       if (P.mass_part) {
 #pragma unroll
