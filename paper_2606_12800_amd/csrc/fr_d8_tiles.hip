@@ -271,6 +271,22 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
   uint32_t* s_lev = UP ? s_lev_a : reinterpret_cast<uint32_t*>(s_mb);
   uint16_t* s_off = reinterpret_cast<uint16_t*>(s_lev);
   const int64_t nr = P.nrows, nc = P.ncols;
+  // The wavefront that sweeps the levels (any one wavefront of the group
+  // gives the same result): the one on SIMD (workgroup slot mod 4), read
+  // from the hardware's wave identity register (SIMD in bits 5:4, the
+  // workgroup's slot on its compute unit in bits 19:16), so that the level
+  // sweeps of the workgroups sharing a compute unit issue on different
+  // SIMDs.  Published in LDS so that the choice is uniform in the group.
+  __shared__ int s_simd[5];
+  {
+    const uint32_t hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);
+    if ((threadIdx.x & 63) == 0) s_simd[threadIdx.x >> 6] = (int)((hw >> 4) & 3u);
+    if (threadIdx.x == 0) s_simd[4] = (int)((hw >> 16) & 3u);
+  }
+  __syncthreads();
+  int lw = 0;
+  for (int w = 3; w >= 0; --w)
+    if (s_simd[w] == s_simd[4]) lw = w;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const TT T = tile_at(P, t, ntiles);
     // The thread index, opaque to the compiler once per tile: offsets derived
@@ -534,20 +550,22 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
       }
     }
     __syncthreads();
-    // 7. Levels, deepest first, on wavefront 0 alone: a cell's in-tile
+    // 7. Levels, deepest first, on one wavefront alone: a cell's in-tile
     // donors are one level deeper and final.  The LDS processes one
     // wavefront's instructions in order, so a level's reads see the previous
     // level's writes with no barrier or wait between them (the compiler is
     // only kept from moving LDS accesses across levels); the next level's
     // entries are read a level ahead.
-    if (wave == 0 && D > 0) {
+    if (wave == lw && D > 0) {
       // Level L spans entries [off[L], off[L + 1]); offsets are read two
-      // levels ahead, entries one.
-      int o1 = s_off[D], o0 = s_off[D - 1], n0 = D >= 2 ? (int)s_off[D - 2] : 0;
-      uint32_t e = lane < o1 - o0 ? s_x[o0 + lane] : 0u;
+      // levels ahead, entries one, unconditionally (clamped indexes; off[0]
+      // is 0), so that no branch keeps the compiler from leaving them in
+      // flight.
+      int o1 = s_off[D], o0 = s_off[D - 1], n0 = s_off[max(D - 2, 0)];
+      uint32_t e = s_x[min(o0 + lane, HN - 1)];
       for (int L = D - 1; L >= 0; --L) {
-        const int nn0 = L >= 2 ? (int)s_off[L - 2] : 0;
-        const uint32_t ne = L > 0 && lane < o0 - n0 ? s_x[n0 + lane] : 0u;
+        const int nn0 = s_off[max(L - 2, 0)];
+        const uint32_t ne = s_x[min(n0 + lane, HN - 1)];
         if (lane < o1 - o0) level_cell<VK, CNT, CT>(s_v, s_c, e);
         for (int j = o0 + 64 + lane; j < o1; j += 64) level_cell<VK, CNT, CT>(s_v, s_c, s_x[j]);  // wide levels
         __builtin_amdgcn_wave_barrier();
