@@ -33,7 +33,7 @@ size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr size_t kCtlBytes = kAlign;
 
 struct Layout {
-  size_t vlo, ext, done, rs32, iw32, iw64, stamp, list0, list1, ctr, partial, total;
+  size_t vlo, ext, done, rs32, iw32, d32, iw64, stamp, list0, list1, ctr, partial, total;
 };
 
 int64_t tiles_of(int64_t nrows, int64_t ncols) {
@@ -53,6 +53,7 @@ Layout layout(int64_t nrows, int64_t ncols, int rule, int vdtype) {
   L.done = o; o += up(n + 4);
   L.rs32 = o; if (rule == FR_MFD && vdtype == FR_F32) o += up(n * sizeof(float));
   L.iw32 = o; if (rule == FR_MFD && vdtype == FR_F32) o += up(n * sizeof(float));
+  L.d32 = o; if (rule == FR_MFD && vdtype == FR_F32) o += up(n * sizeof(float));
   L.iw64 = o; if (rule == FR_MFD && vdtype == FR_F64) o += up(n * sizeof(double));
   L.stamp = o; o += up(nt * sizeof(int32_t));
   L.list0 = o; o += up(nt * sizeof(int32_t));
@@ -254,6 +255,7 @@ EngineParams engine_params(int64_t nrows, int64_t ncols, const uint8_t* code, co
   P.vlo = reinterpret_cast<float*>(body + L.vlo);
   P.rs32 = reinterpret_cast<float*>(body + L.rs32);
   P.iw32 = reinterpret_cast<float*>(body + L.iw32);
+  P.d32 = reinterpret_cast<float*>(body + L.d32);
   P.iw64 = reinterpret_cast<double*>(body + L.iw64);
   P.stamp = reinterpret_cast<int32_t*>(body + L.stamp);
   P.list0 = reinterpret_cast<int32_t*>(body + L.list0);

@@ -62,10 +62,13 @@ __device__ __forceinline__ ff ff_add(ff x, ff y) {
   return ff_fast_two_sum(s.hi, e);
 }
 
-// x * f for a float32 factor f.
-__device__ __forceinline__ ff ff_mul_f(ff x, float f) {
+// x * f * (1 + d) for a float32 fraction f and the small correction d of
+// its cell's fractions (the d term goes into the low part).
+__device__ __forceinline__ ff ff_mul_fd(ff x, float f, float d) {
   const float p = x.hi * f;
-  const float e = fmaf(x.hi, f, -p) + x.lo * f;
+  float e = fmaf(x.hi, f, -p);
+  e = fmaf(x.lo, f, e);
+  e = fmaf(p, d, e);
   return ff_fast_two_sum(p, e);
 }
 
@@ -153,8 +156,23 @@ __global__ __launch_bounds__(256) void k_engine_init(EngineParams P) {
           if (rr < 0 || rr >= P.nrows || cc < 0 || cc >= P.ncols) continue;
           sum += mfd_t32(zi, P.z[rr * P.ncols + cc], k, rs, (float)P.p);
         }
+        const float iw = sum > 0.0f ? 1.0f / sum : 0.0f;
+        // The rounded fractions f_k = t_k * iw do not sum to 1 exactly, and
+        // along a long flow path the excess would compound: with their
+        // exact (float-float) sum s, every contribution is scaled by
+        // 1 + d, d = 1 - s, which restores the sum to first order.  The
+        // f_k here are computed exactly as the edges recompute them.
+        ff es{0.0f, 0.0f};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (!is_recv(RK, ci, k)) continue;
+          const int64_t rr = r + nb_dr(k), cc = c + nb_dc(k);
+          if (rr < 0 || rr >= P.nrows || cc < 0 || cc >= P.ncols) continue;
+          es = ff_add(es, ff{mfd_t32(zi, P.z[rr * P.ncols + cc], k, rs, (float)P.p) * iw, 0.0f});
+        }
         P.rs32[i] = rs;
-        P.iw32[i] = sum > 0.0f ? 1.0f / sum : 0.0f;
+        P.iw32[i] = iw;
+        P.d32[i] = sum > 0.0f ? -((es.hi - 1.0f) + es.lo) : 0.0f;
       } else if (VK == VK_F64) {
         double sum = 0.0;
 #pragma unroll
@@ -205,6 +223,7 @@ struct TileLds {
   float z[RK == RK_MULTI ? NH : 1];
   float rs[(RK == RK_MULTI && VK == VK_FF) ? NH : 1];
   float iw[(RK == RK_MULTI && VK == VK_FF) ? NH : 1];
+  float dd[(RK == RK_MULTI && VK == VK_FF) ? NH : 1];
   double iw64[(RK == RK_MULTI && VK == VK_F64) ? NH : 1];
 };
 
@@ -283,10 +302,11 @@ __device__ __forceinline__ void signal_external(const EngineParams& P, int it, i
 // Fraction of the water on the edge between cell h and its neighbour hn in
 // direction k (from h): forward solves pull along donor -> h edges (the
 // donor's split), adjoint solves along h -> receiver edges (h's split).
+// Float32 mode: x times the fraction, with the splitting cell's correction.
 template <int DIR, class L>
-__device__ __forceinline__ float edge_f32(const L& S, int h, int hn, int k, float p) {
-  if (DIR == DIR_FWD) return mfd_t32(S.z[hn], S.z[h], 7 - k, S.rs[hn], p) * S.iw[hn];
-  return mfd_t32(S.z[h], S.z[hn], k, S.rs[h], p) * S.iw[h];
+__device__ __forceinline__ ff edge_ff(const L& S, ff x, int h, int hn, int k, float p) {
+  if (DIR == DIR_FWD) return ff_mul_fd(x, mfd_t32(S.z[hn], S.z[h], 7 - k, S.rs[hn], p) * S.iw[hn], S.dd[hn]);
+  return ff_mul_fd(x, mfd_t32(S.z[h], S.z[hn], k, S.rs[h], p) * S.iw[h], S.dd[h]);
 }
 template <int DIR, class L>
 __device__ __forceinline__ double edge_f64(const L& S, int h, int hn, int k, double p) {
@@ -346,6 +366,7 @@ __device__ __forceinline__ void engine_iter(TileLds<RK, VK, CNT>& S, const Engin
         if (VK == VK_FF) {
           S.rs[h] = in_grid ? P.rs32[g] : 0.0f;
           S.iw[h] = in_grid ? P.iw32[g] : 0.0f;
+          S.dd[h] = in_grid ? P.d32[g] : 0.0f;
         } else if (VK == VK_F64) {
           S.iw64[h] = in_grid ? P.iw64[g] : 0.0;
         }
@@ -418,7 +439,7 @@ __device__ __forceinline__ void engine_iter(TileLds<RK, VK, CNT>& S, const Engin
         const int64_t gn = g + nb_dr(k) * P.ncols + nb_dc(k);
         if (VK == VK_FF) {
           ff vj = same ? ff{P.vhi[gn], P.vlo[gn]} : ff{ld_dev(P.vhi + gn), ld_dev(P.vlo + gn)};
-          if (RK == RK_MULTI) vj = ff_mul_f(vj, edge_f32<DIR>(S, h, hn, k, pf));
+          if (RK == RK_MULTI) vj = edge_ff<DIR>(S, vj, h, hn, k, pf);
           vf = ff_add(vf, vj);
         }
         if (VK == VK_F64) {
@@ -478,7 +499,7 @@ __device__ __forceinline__ void engine_iter(TileLds<RK, VK, CNT>& S, const Engin
             if (S.st[ln] & ST_PREV) continue;  // already in the known part
             if (VK == VK_FF) {
               ff vj = S.vff[ln];
-              if (RK == RK_MULTI) vj = ff_mul_f(vj, edge_f32<DIR>(S, h, hn, k, pf));
+              if (RK == RK_MULTI) vj = edge_ff<DIR>(S, vj, h, hn, k, pf);
               vf = ff_add(vf, vj);
             }
             if (VK == VK_F64) {

@@ -48,6 +48,7 @@ struct EngineParams {
   uint64_t* cnt;               // exact counts (D8 forward), or NULL
   float* rs32;                 // MFD: 1 / steepest slope of the cell (float32 mode)
   float* iw32;                 // MFD: 1 / sum of normalised weights (float32 mode)
+  float* d32;                  // MFD: 1 - sum of the cell's float32 fractions (float32 mode)
   double* iw64;                // MFD: 1 / sum of weights (float64 mode)
   uint8_t* ext;                // per cell: inputs in other tiles not yet finished
   uint8_t* done;               // per cell: 1 once its value is final
