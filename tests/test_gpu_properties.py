@@ -7,7 +7,9 @@ The bars are those of the fixed parity cases: receivers and counts
 bit-exact, float32 water within 1e-6 (per cell for single receivers, 2-norm
 for MFD) and float64 water within 1e-10 per cell of the float64 oracle,
 mass balance within 1e-6 / 1e-11, the transpose solve within 1e-10 of the
-largest |rbar|, depression filling bit-exact.
+largest |rbar|, depression filling bit-exact; batches of up to 8 drawn
+tiles under every launch plan; the paper's block iterations with drawn
+block shapes, whose iteration counts must equal the oracle's.
 """
 import numpy as np
 import pytest
@@ -146,3 +148,77 @@ def test_fill_matches_oracle(c, rule, eps):
     f = host(fr.fill_depressions(dev(z), rule, eps=eps))
     ref = oracle.fill_depressions(z, 8 if rule == "d8" else 4, eps)
     assert np.array_equal(f.view(np.uint32), ref.view(np.uint32))
+
+
+small_side = st.one_of(st.integers(1, 48), st.integers(49, 300))
+batch_tile = st.tuples(st.sampled_from(["dem", "filled", "noise", "steps"]), st.integers(0, 10_000), small_side,
+                       small_side, st.sampled_from(["d8", "d4", "mfd"]), st.booleans(), st.booleans())
+
+
+@settings(derandomize=True, max_examples=40, deadline=None)
+@given(st.lists(batch_tile, min_size=1, max_size=8), st.sampled_from([None, (0, "given"), (64, "rows"),
+                                                                        (16, "cells")]))
+def test_batch_matches_oracle(specs, plan):
+    """One persistent launch over drawn tiles (any mix of shapes, terrains,
+    rules and outputs) against the oracle tile by tile."""
+    print(f"batch {len(specs)} tiles plan {plan}: " + " ".join(f"{s[4]}:{s[0]}:{s[2]}x{s[3]}" for s in specs),
+          flush=True)
+    tiles, ref = [], []
+    for kind, seed, nr, nc, rule, with_rain, want_q in specs:
+        z = terrain(kind, seed, nr, nc)
+        rain = synth.rain(seed, nr, nc) if with_rain else None
+        t = {"z": dev(z), "rule": rule, "code": torch.empty((nr, nc), dtype=torch.uint8, device="cuda")}
+        if rain is not None:
+            t["rain"] = dev(rain)
+        if rule == "mfd" or want_q:
+            t["q"] = torch.empty((nr, nc), dtype=torch.float32, device="cuda")
+        else:
+            t["counts"] = torch.empty((nr, nc), dtype=torch.int64, device="cuda")
+        tiles.append(t)
+        ref.append((z, rain))
+    b = fr.Batch(tiles)
+    if plan is None:
+        b.run()
+    else:
+        order = {"given": fr.ORDER_GIVEN, "rows": fr.ORDER_ROWS_DESC, "cells": fr.ORDER_CELLS_DESC}[plan[1]]
+        b.run(plan=fr.BatchPlan(plan[0], order))
+    torch.cuda.synchronize()
+    for t, (z, rain) in zip(tiles, ref):
+        rule = t["rule"]
+        code = host(t["code"])
+        if rule == "mfd":
+            assert np.array_equal(code, oracle.mfd_fractions(z)[0])
+            assert relnorm(host(t["q"]), oracle.accumulate_mfd(z, rain)) <= 1e-6, z.shape
+            continue
+        assert np.array_equal(code, oracle.receivers(z, oracle.D8 if rule == "d8" else oracle.D4)), z.shape
+        qref, cref = oracle.accumulate_single(code, rain, z=z)
+        if "counts" in t:
+            assert np.array_equal(host(t["counts"]).astype(np.uint64), cref), z.shape
+        else:
+            assert relmax(host(t["q"]), qref) <= 1e-6, z.shape
+
+
+@settings(derandomize=True, max_examples=40, deadline=None)
+@given(st.sampled_from(["dem", "filled", "noise", "steps"]), st.integers(0, 10_000), st.integers(1, 400),
+       st.integers(1, 400), st.sampled_from(["d8", "d4"]), st.sampled_from(["ix", "imx_ix"]),
+       st.sampled_from([32, 64, 128, 256, 100_000]), st.sampled_from([256, 512, 100_000]))
+def test_block_iterations_match_oracle(kind, seed, nr, nc, rule, scheme, brows, bcols):
+    """The paper's block iterations (exact per-block solves) on drawn grids
+    and block shapes: water, counts and the iteration count equal the
+    oracle's run of the same scheme."""
+    print(f"block iterations {scheme} {rule} {kind} {nr}x{nc} seed {seed} block {brows}x{bcols}", flush=True)
+    r = oracle.D8 if rule == "d8" else oracle.D4
+    z = terrain(kind, seed, nr, nc)
+    rain = synth.rain(seed, nr, nc)
+    code_h = oracle.receivers(z, r)
+    ref_q, _ = oracle.accumulate_single(code_h, rain, z=z)
+    _, ref_c = oracle.accumulate_single(code_h, None, z=z)
+    _, _, ref_it = oracle.block_richardson(z, (brows, bcols), r, None, 0 if scheme == "ix" else 1)
+    # A budget a little above the oracle's count: a run that does not reach
+    # the fixed point ends with an error instead of iterating on.
+    q, cnt, it = fr.block_iterations(dev(code_h), dev(rain), rule, scheme=scheme, block=(brows, bcols),
+                                     max_iter=ref_it + 4)
+    torch.cuda.synchronize()
+    assert relmax(host(q), ref_q) <= 1e-10
+    assert np.array_equal(host(cnt).astype(np.uint64), ref_c)
+    assert it == ref_it
