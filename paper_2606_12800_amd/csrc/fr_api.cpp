@@ -358,7 +358,7 @@ int enqueue_d8(const uint8_t* code, int64_t nrows, int64_t ncols, const void* ra
   T.flags = reinterpret_cast<int32_t*>(P.n_exits + 20);
   ph = phase_begin("d8_tiles", s);
   if (launch_d8t_gate(C, tiles_only, s) != hipSuccess || launch_d8t(true, vk, counts, T, s) != hipSuccess ||
-      launch_d8_forest(vk, counts, false, T, s) != hipSuccess || launch_d8t(false, vk, counts, T, s) != hipSuccess)
+      launch_d8_forest_queue(vk, counts, T, s) != hipSuccess || launch_d8t(false, vk, counts, T, s) != hipSuccess)
     return FR_ERR_HIP;
   if (mass_out && launch_d8t_mass(T.mass_part, d8t_tiles(nrows, ncols), mass_out, C, s) != hipSuccess)
     return FR_ERR_HIP;

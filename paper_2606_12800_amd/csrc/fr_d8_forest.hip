@@ -37,6 +37,7 @@ __global__ __launch_bounds__(256) void k_d8_link(D8Params P) {
       P.ex_cnt[1][i] = 0;
       P.ex_cnt[2][i] = 0;
     }
+    P.anc[1][i] = 0;  // the work-queue forest counts children here
     const uint32_t ec = P.ex_cell[i];
     uint32_t a = NONE;
     if (ec == NONE) {  // a hole of a phase-A chunk: no water, no parent
@@ -154,6 +155,222 @@ __global__ __launch_bounds__(256) void k_d8_round(D8Params P, int j, int last) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// The exit forest by a work queue (tile-forest path, where the forest holds
+// tens of millions of exits and is about a thousand deep, so that pointer
+// doubling would move every exit's sum through ten rounds of random
+// atomics).  Each exit waits for its children; once the last one has added
+// its total, the exit is final and enters the queue; whoever takes it adds
+// its total to its parent, once.  Sums stay 128-bit integers (the order of
+// the atomics changes no bit).  Children are counted in anc[1], the queue
+// holds exit + 1 (0: not yet written) in the second pending-additions
+// buffer (both cleared by the link step); the third pending buffer stays
+// zero for the totals.  Every access to the forest's shared words here is a
+// device-coherent atomic, so the XCDs' caches need no write-back or
+// invalidation; a finished exit's reads of its sums depend on the queue
+// word that named it.  Every wait ends: a wavefront that sees the queue's
+// tail stand still for KF_STALL_TICKS gives up (a cycle of exits, from
+// malformed codes) and reports FR_ERR_NOTDAG.
+constexpr int KF_HEAD = 8, KF_TAIL = 9;          // slots of P.flags
+constexpr uint64_t KF_STALL_TICKS = 5000000ull;  // 50 ms of the 100 MHz clock
+
+__device__ __forceinline__ uint32_t* kf_children(const D8Params& P) { return P.anc[1]; }
+template <int VK>
+__device__ __forceinline__ uint32_t* kf_queue(const D8Params& P) {
+  return VK != VK_NONE ? reinterpret_cast<uint32_t*>(P.ex_fx[1]) : reinterpret_cast<uint32_t*>(P.ex_cnt[1]);
+}
+
+// Appends up to KF_PER_LANE items per lane (bit k of `mask`: par[k]) with
+// one atomic per wavefront.
+template <int K>
+__device__ __forceinline__ void kf_push_many(const D8Params& P, uint32_t* q, uint32_t mask, const uint32_t (&par)[K]) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t incl = (uint32_t)__popc(mask);
+  const uint32_t mine = incl;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)incl, o, 64);
+    if (lane >= (uint32_t)o) incl += y;
+  }
+  const uint32_t tot = (uint32_t)__shfl((int)incl, 63, 64);
+  if (tot == 0u) return;  // uniform
+  uint32_t base = 0;
+  if (lane == 0)
+    base = __hip_atomic_fetch_add(reinterpret_cast<uint32_t*>(&P.flags[KF_TAIL]), tot, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t at = (uint32_t)__shfl((int)base, 0, 64) + incl - mine;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if ((mask >> k) & 1u) {
+      __hip_atomic_store(&q[at], par[k] + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ++at;
+    }
+  }
+}
+
+// Children per exit.
+__global__ __launch_bounds__(256) void k_kf_count(D8Params P) {
+  const uint32_t n = *P.n_exits;
+  if (n > P.cap) return;  // uniform
+  uint32_t* ch = kf_children(P);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t a = P.anc[0][i];
+    if (a != NONE) atomicAdd(&ch[a], 1u);
+  }
+}
+
+// The leaves (holes included) into the queue: each workgroup scans a chunk
+// of KF_LEAF_CHUNK exits and reserves its slots with one atomic (the queue's
+// tail is one word: atomics on it serialise).
+constexpr uint32_t KF_LEAF_PER_THREAD = 16;
+constexpr uint32_t KF_LEAF_CHUNK = 256u * KF_LEAF_PER_THREAD;
+
+template <int VK>
+__global__ __launch_bounds__(256) void k_kf_leaves(D8Params P) {
+  const uint32_t n = *P.n_exits;
+  if (n > P.cap || n == 0u) return;  // uniform
+  if (blockIdx.x == 0 && threadIdx.x == 0) P.ctl->forest_final = 2;  // pending buffer 2 stays zero
+  const uint32_t* ch = kf_children(P);
+  uint32_t* q = kf_queue<VK>(P);
+  __shared__ uint32_t s_cnt[4], s_base;
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (uint32_t c0 = blockIdx.x * KF_LEAF_CHUNK; c0 < n; c0 += gridDim.x * KF_LEAF_CHUNK) {  // uniform
+    // Item j of the thread: exit c0 + 256 j + threadIdx.x.
+    uint32_t mine = 0, leaf = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < KF_LEAF_PER_THREAD; ++j) {
+      const uint32_t i = c0 + 256u * j + threadIdx.x;
+      if (i < n && ch[i] == 0u) {
+        leaf |= 1u << j;
+        ++mine;
+      }
+    }
+    // Exclusive prefix of the counts over the workgroup (wave scan, then
+    // the four wave totals).
+    uint32_t incl = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)incl, o, 64);
+      if (lane >= (uint32_t)o) incl += y;
+    }
+    if (lane == 63) s_cnt[wave] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint32_t tot = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+      s_base = tot ? __hip_atomic_fetch_add(reinterpret_cast<uint32_t*>(&P.flags[KF_TAIL]), tot, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT)
+                   : 0u;
+    }
+    __syncthreads();
+    uint32_t at = s_base + incl - mine;
+    for (uint32_t w = 0; w < wave; ++w) at += s_cnt[w];
+#pragma unroll
+    for (uint32_t j = 0; j < KF_LEAF_PER_THREAD; ++j) {
+      if ((leaf >> j) & 1u) {
+        __hip_atomic_store(&q[at], c0 + 256u * j + threadIdx.x + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ++at;
+      }
+    }
+    __syncthreads();  // s_cnt and s_base are reused
+  }
+}
+
+__device__ __forceinline__ u128 kf_load_fx(const u128* p) {
+  const unsigned long long* w = reinterpret_cast<const unsigned long long*>(p);
+  const u128 lo = __hip_atomic_load(const_cast<unsigned long long*>(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const u128 hi = __hip_atomic_load(const_cast<unsigned long long*>(w + 1), __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+  return lo | (hi << 64);
+}
+
+// Persistent: each wavefront takes KF_SLOTS queue slots at a time (lane l
+// holds slots base + 64 k + l) and each lane finishes the exits its slots
+// receive, in whatever order they arrive; a slot is written only once its
+// exit is final, and every exit is written exactly once, so all n slots
+// fill (a cycle aside).
+constexpr int KF_PER_LANE = 8;
+constexpr uint32_t KF_SLOTS = 64u * KF_PER_LANE;
+
+template <int VK, bool CNT>
+__device__ __forceinline__ bool kf_finish(const D8Params& P, uint32_t* ch, uint32_t e, uint32_t n,
+                                          uint32_t& parent) {
+  const uint32_t a = P.anc[0][e];
+  if (a == NONE || a >= n) return false;
+  if (VK != VK_NONE) {
+    const u128 x = kf_load_fx(&P.ex_fx[0][e]);
+    if (x != 0) atomic_add_fx(&P.ex_fx[0][a], x);
+  }
+  if (CNT) {
+    const unsigned long long c = __hip_atomic_load(reinterpret_cast<unsigned long long*>(&P.ex_cnt[0][e]),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (c != 0ull) atomicAdd(reinterpret_cast<unsigned long long*>(&P.ex_cnt[0][a]), c);
+  }
+  // The last child makes the parent final: the additions above have
+  // completed (every access to the forest here is a device-coherent atomic,
+  // so no cache needs writing back) before the count goes down, and the
+  // parent is queued only after its count has reached zero.
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  const uint32_t left = __hip_atomic_fetch_add(&ch[a], 0xFFFFFFFFu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  parent = a;
+  return left == 1u;
+}
+
+template <int VK, bool CNT>
+__global__ __launch_bounds__(256) void k_kf_run(D8Params P) {
+  const uint32_t n = *P.n_exits;
+  if (n > P.cap || n == 0u) return;  // uniform
+  uint32_t* ch = kf_children(P);
+  uint32_t* q = kf_queue<VK>(P);
+  uint32_t* head = reinterpret_cast<uint32_t*>(&P.flags[KF_HEAD]);
+  const uint32_t* tail = reinterpret_cast<const uint32_t*>(&P.flags[KF_TAIL]);
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t tail_seen = 0;
+  uint64_t t_seen = __builtin_amdgcn_s_memrealtime();
+  for (;;) {
+    uint32_t base = 0;
+    if (lane == 0) base = __hip_atomic_fetch_add(head, KF_SLOTS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    base = (uint32_t)__shfl((int)base, 0, 64);
+    if (base >= n) return;  // uniform: every slot has been taken
+    uint32_t todo = 0;  // bit k: slot base + 64 k + lane not finished
+#pragma unroll
+    for (int k = 0; k < KF_PER_LANE; ++k)
+      if (base + 64u * k + lane < n) todo |= 1u << k;
+    while (__ballot(todo != 0u)) {  // uniform
+      // The parents made final in this pass go into the queue together,
+      // with one atomic for the wavefront.
+      uint32_t pmask = 0, par[KF_PER_LANE];
+#pragma unroll
+      for (int k = 0; k < KF_PER_LANE; ++k) {
+        par[k] = 0;
+        if ((todo >> k) & 1u) {
+          const uint32_t v = __hip_atomic_load(&q[base + 64u * k + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (v != 0u) {
+            todo &= ~(1u << k);
+            if (kf_finish<VK, CNT>(P, ch, v - 1u, n, par[k])) pmask |= 1u << k;
+          }
+        }
+      }
+      kf_push_many(P, q, pmask, par);
+      if (__ballot(todo != 0u)) {
+        // Waiting for slots still empty: give up when the queue stops
+        // growing (the exits left form a cycle).
+        uint32_t tl = 0;
+        if (lane == 0) tl = __hip_atomic_load(tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        tl = (uint32_t)__shfl((int)tl, 0, 64);
+        const uint64_t now = __builtin_amdgcn_s_memrealtime();
+        if (tl != tail_seen) {
+          tail_seen = tl;
+          t_seen = now;
+        } else if (now - t_seen > KF_STALL_TICKS) {
+          if (lane == 0) set_status(P.status, FR_ERR_NOTDAG);
+          return;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+  }
+}
+
 // The totals -- sums plus the last round's pending additions -- back from
 // fixed point into float-float or float64, where phase C reads them (the
 // pointer buffers' memory, free again); counts into sum buffer 0.
@@ -227,6 +444,41 @@ hipError_t forest_t(const D8Params& P, hipStream_t s) {
   for (int j = 0; j < R; ++j) hipLaunchKernelGGL((k_d8_round<VK, CNT>), g, b, 0, s, P, j, j == R - 1 ? 1 : 0);
   hipLaunchKernelGGL((k_d8_totals<VK, CNT>), g, b, 0, s, P);
   return hipGetLastError();
+}
+
+// Workgroups of the queue kernel: as many as stay resident.
+template <int VK, bool CNT>
+unsigned kf_grid() {
+  static unsigned g = 0;
+  if (g == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_kf_run<VK, CNT>, 256, 0) != hipSuccess ||
+        cus <= 0 || per <= 0) {
+      cus = 256;
+      per = 2;
+    }
+    g = (unsigned)(cus * per);
+  }
+  return g;
+}
+
+template <int VK, bool CNT>
+hipError_t forest_queue_t(const D8Params& P, hipStream_t s) {
+  const dim3 g(forest_grid(P.cap)), b(256);
+  hipLaunchKernelGGL((k_d8_link<VK, CNT, false>), g, b, 0, s, P);
+  hipLaunchKernelGGL(k_kf_count, g, b, 0, s, P);
+  hipLaunchKernelGGL((k_kf_leaves<VK>), g, b, 0, s, P);
+  hipLaunchKernelGGL((k_kf_run<VK, CNT>), dim3(kf_grid<VK, CNT>()), b, 0, s, P);
+  hipLaunchKernelGGL((k_d8_totals<VK, CNT>), g, b, 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_d8_forest_queue(ValKind vk, bool cnt, const D8Params& P, hipStream_t s) {
+  if (vk == VK_FF) return cnt ? forest_queue_t<VK_FF, true>(P, s) : forest_queue_t<VK_FF, false>(P, s);
+  if (vk == VK_F64) return cnt ? forest_queue_t<VK_F64, true>(P, s) : forest_queue_t<VK_F64, false>(P, s);
+  return forest_queue_t<VK_NONE, true>(P, s);
 }
 
 hipError_t launch_d8_forest(ValKind vk, bool cnt, bool iter, const D8Params& P, hipStream_t s) {

@@ -186,6 +186,8 @@ hipError_t launch_d8t_mass(const double* part, int64_t ntiles, double* out, Call
 // iteration variants (blocks of P.bt_r x P.bt_c tiles).
 hipError_t launch_d8_up(ValKind vk, bool cnt, bool iter, const D8Params& P, hipStream_t s);
 hipError_t launch_d8_forest(ValKind vk, bool cnt, bool iter, const D8Params& P, hipStream_t s);
+// The same forest by a work queue over the exits (the tile-forest path).
+hipError_t launch_d8_forest_queue(ValKind vk, bool cnt, const D8Params& P, hipStream_t s);
 hipError_t launch_d8_down(ValKind vk, bool cnt, bool iter, const D8Params& P, hipStream_t s);
 // Element-wise steps of the (I - X)(I + X) iteration on float64 values and
 // uint64 (wrap-around) counts; either array pair may be NULL.
