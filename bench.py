@@ -33,7 +33,7 @@ PHASE_BYTES = {
     "d8_tiles": (1 + 4) + (1 + 4 + 4 + 8),
 }
 PHASE_KERNEL = {"receivers": "k_receivers", "d8_up": "k_d8_a (root + local sweep)", "d8_down": "k_d8_c",
-                "d8_tiles": "k_d8t (tile forest, phases A and C) + exit forest rounds"}
+                "d8_tiles": "k_d8t (tile forest, phases A and C) + exit forest work queue"}
 ACC_BYTES = 1 + 4 + 4 + 8     # whole accumulate call: code, rain in; q, counts out
 ROUTE_BYTES = 4 + 1 + ACC_BYTES  # whole route: receivers (z in, code out) + accumulate
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs calibrated
@@ -46,9 +46,9 @@ MEASURED_TRAFFIC = {
         "d8_up": (1.3366e10, "profiles/d8_43360_hbm_traffic.md"),
         "d8_down": (3.3176e10, "profiles/d8_43360_hbm_traffic.md"),
     },
-    # The tile phase of the filled route: both tile kernels, link, rounds
-    # and totals.
-    ("d8_filled", 43360, 43360): {"d8_tiles": (1.5932e11, "profiles/d8_43360_filled_tile_forest.md")},
+    # The tile phase of the filled route: both tile kernels and the exit
+    # forest's work queue (link, children, leaves, queue, totals).
+    ("d8_filled", 43360, 43360): {"d8_tiles": (9.5216e10, "profiles/d8_43360_filled_tile_forest.md")},
     ("mfd", 16384, 16384): {"row_sweep": (5.3063e9, "profiles/mfd_16384_row_sweep.md")},
     ("adjoint", 4096, 4096): {"sweep": (6.987e8, "profiles/sweep_and_batch_hbm_traffic.md")},
     ("batched", 512): {"batch": (2.472e10, "profiles/sweep_and_batch_hbm_traffic.md")},
