@@ -335,6 +335,7 @@ __global__ __launch_bounds__(256) void k_kf_run(D8Params P) {
 #pragma unroll
     for (int k = 0; k < KF_PER_LANE; ++k)
       if (base + 64u * k + lane < n) todo |= 1u << k;
+    uint32_t avail = n;  // slots below the tail seen last (the others cannot be written yet)
     while (__ballot(todo != 0u)) {  // uniform
       // The parents made final in this pass go into the queue together,
       // with one atomic for the wavefront.
@@ -342,7 +343,7 @@ __global__ __launch_bounds__(256) void k_kf_run(D8Params P) {
 #pragma unroll
       for (int k = 0; k < KF_PER_LANE; ++k) {
         par[k] = 0;
-        if ((todo >> k) & 1u) {
+        if (((todo >> k) & 1u) && base + 64u * k + lane < avail) {
           const uint32_t v = __hip_atomic_load(&q[base + 64u * k + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (v != 0u) {
             todo &= ~(1u << k);
@@ -357,6 +358,7 @@ __global__ __launch_bounds__(256) void k_kf_run(D8Params P) {
         uint32_t tl = 0;
         if (lane == 0) tl = __hip_atomic_load(tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         tl = (uint32_t)__shfl((int)tl, 0, 64);
+        avail = tl;
         const uint64_t now = __builtin_amdgcn_s_memrealtime();
         if (tl != tail_seen) {
           tail_seen = tl;

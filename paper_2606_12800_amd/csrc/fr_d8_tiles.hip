@@ -162,26 +162,40 @@ __device__ __forceinline__ int nb_off(int n) {
   return (int)((0x8281804240020100ull >> (8 * n)) & 0xFFull) - 65;
 }
 
+// Level entries (one 32-bit word per cell with in-tile donors): the cell in
+// bits 0-10, its in-tile donor mask (bit n: neighbour n gives it water) in
+// bits 11-18, and the directions of its first four donors, 3 bits each, from
+// bit 19.  Value and count arrays hold one more slot, LV_ZERO, that stays
+// zero: a missing donor reads it.
+constexpr int LV_ZERO = HN;
+
+__device__ __forceinline__ uint32_t level_entry(int i, uint32_t mask) {
+  uint32_t d = 0, m = mask;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    d |= ((uint32_t)__builtin_ctz(m | 0x100u) & 7u) << (3 * q);
+    m &= m - 1;
+  }
+  return (uint32_t)i | (mask << 11) | (d << 19);
+}
+
 // One cell of a level: its value (rain and out-of-tile inflow so far) plus
 // the finished values of its in-tile donors, in neighbour order.  The first
 // four donors are read at once and added without branches (a missing donor
-// adds an exact zero, which changes no bit of the sum); float-float sums are
-// normalised once.  Cells with more donors finish in a loop (rare).
+// reads the zero slot and adds an exact zero, which changes no bit of the
+// sum); float-float sums are normalised once.  Cells with more donors finish
+// in a loop (rare).
 template <int VK, bool CNT, class CT>
 __device__ __forceinline__ void level_cell(typename TV<VK>::T* s_v, CT* s_c, uint32_t ent) {
   using V = typename TV<VK>::T;
-  const int i = (int)(ent & 0xFFFFu);
-  uint32_t m = ent >> 16;
-  const int kq = __popc(m);
+  const int i = (int)(ent & 0x7FFu);
+  const uint32_t mask = (ent >> 11) & 0xFFu;
+  const int kq = __popc(mask);
   int a[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int n = __builtin_ctz(m | 0x100u);  // 8 once no bit is left: the cell itself
-    a[q] = n < 8 ? min(max(i + nb_off(n), 0), HN - 1) : i;
-    m &= m - 1;
-  }
+  for (int q = 0; q < 4; ++q) a[q] = q < kq ? i + nb_off((int)((ent >> (19 + 3 * q)) & 7u)) : LV_ZERO;
   V own{}, x[4];
-  uint64_t cown = 0, y[4];
+  uint32_t cown = 0, y[4];
   if (VK != VK_NONE) {
     own = s_v[i];
 #pragma unroll
@@ -192,16 +206,21 @@ __device__ __forceinline__ void level_cell(typename TV<VK>::T* s_v, CT* s_c, uin
 #pragma unroll
     for (int q = 0; q < 4; ++q) y[q] = s_c[a[q]];
   }
+  uint32_t rest = 0;  // donors after the fourth (rare)
+  if (kq > 4) {
+    rest = mask;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rest &= rest - 1;
+  }
   if constexpr (VK == VK_FF) {
     float h = own.hi, e = own.lo;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const float xh = q < kq ? x[q].hi : 0.0f, xl = q < kq ? x[q].lo : 0.0f;
-      const ff t = ff_two_sum(h, xh);
+      const ff t = ff_two_sum(h, x[q].hi);
       h = t.hi;
-      e += t.lo + xl;
+      e += t.lo + x[q].lo;
     }
-    for (uint32_t r = m; r; r &= r - 1) {
+    for (uint32_t r = rest; r; r &= r - 1) {
       const ff xv = s_v[i + nb_off(__builtin_ctz(r))];
       const ff t = ff_two_sum(h, xv.hi);
       h = t.hi;
@@ -212,15 +231,15 @@ __device__ __forceinline__ void level_cell(typename TV<VK>::T* s_v, CT* s_c, uin
   if constexpr (VK == VK_F64) {
     double v = own;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v += q < kq ? x[q] : 0.0;
-    for (uint32_t r = m; r; r &= r - 1) v += s_v[i + nb_off(__builtin_ctz(r))];
+    for (int q = 0; q < 4; ++q) v += x[q];
+    for (uint32_t r = rest; r; r &= r - 1) v += s_v[i + nb_off(__builtin_ctz(r))];
     s_v[i] = v;
   }
   if (CNT) {
-    uint64_t c = cown;
+    uint32_t c = cown;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) c += q < kq ? y[q] : 0ull;
-    for (uint32_t r = m; r; r &= r - 1) c += s_c[i + nb_off(__builtin_ctz(r))];
+    for (int q = 0; q < 4; ++q) c += y[q];
+    for (uint32_t r = rest; r; r &= r - 1) c += s_c[i + nb_off(__builtin_ctz(r))];
     s_c[i] = (CT)c;
   }
 }
@@ -239,13 +258,13 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
   using RT = typename RainReg<RAIN>::T;
   constexpr int NCODE = (HR + 2) * HW;
   constexpr int NCU = (NCODE + HT - 1) / HT;  // code loads per thread
-  constexpr int VB = VK == VK_NONE ? 0 : HN * 8;
+  constexpr int VB = VK == VK_NONE ? 0 : (HN + 2) * 8;  // one more slot (zero), 16-byte multiple
   // Counts in LDS: phase A holds local counts (at most the tile's 2048
   // cells: 16 bits), phase C final counts (at most the grid's cell count,
   // below 2^31: 32 bits).  With the level histogram over the donor masks in
   // phase C, either phase's LDS stays within a quarter of a compute unit's.
   using CT = typename std::conditional<UP, uint16_t, uint32_t>::type;
-  constexpr int CB = CNT ? HN * (int)sizeof(CT) : 0;
+  constexpr int CB = CNT ? (HN + 8) * (int)sizeof(CT) : 0;  // one more slot (zero), 16-byte multiple
   constexpr int HB = (UP ? 0 : NHALO * ((VK == VK_NONE ? 0 : 8) + (CNT ? 4 : 0)));
   constexpr int MB = HN * 2 > HB ? HN * 2 : HB;
   __shared__ __align__(16) unsigned char s_buf[VB + CB];  // values, counts
@@ -287,6 +306,12 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
   int lw = 0;
   for (int w = 3; w >= 0; --w)
     if (s_simd[w] == s_simd[4]) lw = w;
+  // The zero slot that missing donors read (no tile writes it; the tile
+  // loop's barriers order this before any level).
+  if (threadIdx.x == 0) {
+    if (VK != VK_NONE) s_v[LV_ZERO] = TV<VK>::zero();
+    if (CNT) s_c[LV_ZERO] = (CT)0;
+  }
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const TT T = tile_at(P, t, ntiles);
     // The thread index, opaque to the compiler once per tile: offsets derived
@@ -546,7 +571,7 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
     for (int k = 0; k < HK; ++k) {
       if ((ls[k] & 0xFFFFu) != NO_LEVEL) {
         const int i = (wave + 4 * k) * HC + lane;
-        s_x[s_off[ls[k] & 0xFFFFu] + (ls[k] >> 16)] = (uint32_t)i | ((mk[k] & 0xFFu) << 16);
+        s_x[s_off[ls[k] & 0xFFFFu] + (ls[k] >> 16)] = level_entry(i, mk[k] & 0xFFu);
       }
     }
     __syncthreads();
