@@ -292,31 +292,8 @@ constexpr int KF_PER_LANE = 8;
 constexpr uint32_t KF_SLOTS = 64u * KF_PER_LANE;
 
 template <int VK, bool CNT>
-__device__ __forceinline__ bool kf_finish(const D8Params& P, uint32_t* ch, uint32_t e, uint32_t n,
-                                          uint32_t& parent) {
-  const uint32_t a = P.anc[0][e];
-  if (a == NONE || a >= n) return false;
-  if (VK != VK_NONE) {
-    const u128 x = kf_load_fx(&P.ex_fx[0][e]);
-    if (x != 0) atomic_add_fx(&P.ex_fx[0][a], x);
-  }
-  if (CNT) {
-    const unsigned long long c = __hip_atomic_load(reinterpret_cast<unsigned long long*>(&P.ex_cnt[0][e]),
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (c != 0ull) atomicAdd(reinterpret_cast<unsigned long long*>(&P.ex_cnt[0][a]), c);
-  }
-  // The last child makes the parent final: the additions above have
-  // completed (every access to the forest here is a device-coherent atomic,
-  // so no cache needs writing back) before the count goes down, and the
-  // parent is queued only after its count has reached zero.
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  const uint32_t left = __hip_atomic_fetch_add(&ch[a], 0xFFFFFFFFu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  parent = a;
-  return left == 1u;
-}
-
-template <int VK, bool CNT>
 __global__ __launch_bounds__(256) void k_kf_run(D8Params P) {
+  constexpr int K = KF_PER_LANE;
   const uint32_t n = *P.n_exits;
   if (n > P.cap || n == 0u) return;  // uniform
   uint32_t* ch = kf_children(P);
@@ -333,22 +310,82 @@ __global__ __launch_bounds__(256) void k_kf_run(D8Params P) {
     if (base >= n) return;  // uniform: every slot has been taken
     uint32_t todo = 0;  // bit k: slot base + 64 k + lane not finished
 #pragma unroll
-    for (int k = 0; k < KF_PER_LANE; ++k)
+    for (int k = 0; k < K; ++k)
       if (base + 64u * k + lane < n) todo |= 1u << k;
     uint32_t avail = n;  // slots below the tail seen last (the others cannot be written yet)
     while (__ballot(todo != 0u)) {  // uniform
-      // The parents made final in this pass go into the queue together,
-      // with one atomic for the wavefront.
-      uint32_t pmask = 0, par[KF_PER_LANE];
+      // The lane's exits that have arrived are finished together, each step
+      // issued for all of them before its results are waited for: the
+      // queue words, the parents, the sums, the additions to the parents
+      // (low words with their carries first), then one wait, then the
+      // count-downs.  The parents made final go into the queue together.
+      uint32_t e[K], par[K];
 #pragma unroll
-      for (int k = 0; k < KF_PER_LANE; ++k) {
-        par[k] = 0;
-        if (((todo >> k) & 1u) && base + 64u * k + lane < avail) {
-          const uint32_t v = __hip_atomic_load(&q[base + 64u * k + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (v != 0u) {
-            todo &= ~(1u << k);
-            if (kf_finish<VK, CNT>(P, ch, v - 1u, n, par[k])) pmask |= 1u << k;
+      for (int k = 0; k < K; ++k) {
+        e[k] = 0u;
+        if (((todo >> k) & 1u) && base + 64u * k + lane < avail)
+          e[k] = __hip_atomic_load(&q[base + 64u * k + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        par[k] = NONE;
+        if (e[k] != 0u) {
+          todo &= ~(1u << k);
+          e[k] -= 1u;
+          const uint32_t a = P.anc[0][e[k]];
+          par[k] = a < n ? a : NONE;
+        }
+      }
+      u128 x[K];
+      unsigned long long c[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        x[k] = 0;
+        c[k] = 0ull;
+        if (par[k] != NONE) {
+          if (VK != VK_NONE) x[k] = kf_load_fx(&P.ex_fx[0][e[k]]);
+          if (CNT)
+            c[k] = __hip_atomic_load(reinterpret_cast<unsigned long long*>(&P.ex_cnt[0][e[k]]), __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      if (VK != VK_NONE) {
+        // Exact 128-bit additions from two 64-bit ones: the low word's carry
+        // reaches the high word once.
+        unsigned long long old[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          old[k] = 0ull;
+          if (par[k] != NONE && x[k] != 0)
+            old[k] = atomicAdd(reinterpret_cast<unsigned long long*>(&P.ex_fx[0][par[k]]), (unsigned long long)x[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          if (par[k] != NONE && x[k] != 0) {
+            const unsigned long long xl = (unsigned long long)x[k], xh = (unsigned long long)(x[k] >> 64);
+            const unsigned long long h = xh + ((old[k] + xl < old[k]) ? 1ull : 0ull);
+            if (h) atomicAdd(reinterpret_cast<unsigned long long*>(&P.ex_fx[0][par[k]]) + 1, h);
           }
+        }
+      }
+      if (CNT) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+          if (par[k] != NONE && c[k] != 0ull)
+            atomicAdd(reinterpret_cast<unsigned long long*>(&P.ex_cnt[0][par[k]]), c[k]);
+      }
+      // The last child makes the parent final: the additions above have
+      // completed (every access to the forest here is a device-coherent
+      // atomic, so no cache needs writing back) before the counts go down,
+      // and a parent is queued only after its count has reached zero.
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      uint32_t pmask = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (par[k] != NONE) {
+          const uint32_t left =
+              __hip_atomic_fetch_add(&ch[par[k]], 0xFFFFFFFFu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (left == 1u) pmask |= 1u << k;
         }
       }
       kf_push_many(P, q, pmask, par);
