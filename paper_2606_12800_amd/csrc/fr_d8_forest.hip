@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) void k_kf_count(D8Params P) {
   uint32_t* ch = kf_children(P);
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const uint32_t a = P.anc[0][i];
-    if (a != NONE) atomicAdd(&ch[a], 1u);
+    if (a < n) atomicAdd(&ch[a], 1u);  // the link step leaves no other parent than NONE
   }
 }
 
