@@ -184,14 +184,16 @@ def test_graph_replay_equals_eager_adjoint(rule, dtype, shape, seed):
     check_replays(g, out, eager_fn, swap)
 
 
-@pytest.mark.parametrize("path", ["engine", "sweep"])
+@pytest.mark.parametrize("path", ["engine", "sweep", "tiles"])
 def test_graph_replay_forced_paths(path):
-    """The fallback paths captured on their own: the engine is one
-    persistent launch behind the control block's gate; the sweep runs its
-    passes under device control."""
+    """The other paths captured on their own: the engine is one persistent
+    launch behind the control block's gate; the sweep runs its passes under
+    device control; the tile forest (on a filled DEM, flow in every
+    direction) joins its tiles with a persistent work queue."""
     print(f"capture forced path {path}", flush=True)
     shape = (300, 517)
-    z_h = synth.dem(44, *shape)
+    z_h = synth.dem(44, *shape) if path != "tiles" else oracle.fill_depressions(
+        synth.dem(44, *shape, tilt=0.0), 8, True)
     rain_h = synth.rain(44, *shape)
     z, rain = dev(z_h), dev(rain_h)
     with fr.accumulate_path(path):
