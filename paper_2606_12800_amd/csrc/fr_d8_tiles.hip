@@ -133,6 +133,14 @@ __device__ __forceinline__ int wave_max(int x) {
   for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, 64));
   return x;
 }
+__device__ __forceinline__ double wave_max_d(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
+// A tile's exits lie on its perimeter.
+constexpr int D8T_MAX_EXITS = 2 * HC + 2 * (HR - 2);
 
 // Halo positions (the ring of cells around the tile): top row, bottom row,
 // then the left and right columns.
@@ -267,7 +275,10 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
   constexpr int CB = CNT ? (HN + 8) * (int)sizeof(CT) : 0;  // one more slot (zero), 16-byte multiple
   constexpr int HB = (UP ? 0 : NHALO * ((VK == VK_NONE ? 0 : 8) + (CNT ? 4 : 0)));
   constexpr int MB = HN * 2 > HB ? HN * 2 : HB;
-  __shared__ __align__(16) unsigned char s_buf[VB + CB];  // values, counts
+  // Phase C: values and counts; phase A: the exits' fixed-point sums and
+  // counts (two 64-bit words and one 32-bit word per exit).
+  constexpr int AB = D8T_MAX_EXITS * (8 + 8 + 4);
+  __shared__ __align__(16) unsigned char s_buf[UP ? (AB + 15) / 16 * 16 : VB + CB];
   // Donor masks (16 bits per cell: in-tile donors, out-of-tile donors);
   // once read, the forest totals of the halo cells, and once those are
   // added, the level histogram (phase C).
@@ -308,7 +319,7 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
     if (s_simd[w] == s_simd[4]) lw = w;
   // The zero slot that missing donors read (no tile writes it; the tile
   // loop's barriers order this before any level).
-  if (threadIdx.x == 0) {
+  if (!UP && threadIdx.x == 0) {
     if (VK != VK_NONE) s_v[LV_ZERO] = TV<VK>::zero();
     if (CNT) s_c[LV_ZERO] = (CT)0;
   }
@@ -354,22 +365,25 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
     }
     for (int w = tid; w < HN / 2; w += HT) {
       s_msk[w] = 0u;
-      if (UP) s_lev[w] = 0u;
     }
     if (tid < 16) s_open[tid] = 0;
 #pragma unroll
     for (int u = 0; u < NCU; ++u)
       if (tid + u * HT < NCODE) s_code[tid + u * HT] = (uint8_t)cv[u];
     // Sources: rain (unit rain: 1) and one cell each.
-    double m_rain = 0.0;
+    double m_rain = 0.0, rmax = 0.0;
     bool nonfinite = false;
 #pragma unroll
     for (int k = 0; k < HK; ++k) {
       const int i = (wave + 4 * k) * HC + lane;
       const bool ok = (vmask >> k) & 1u;
       const double r = (double)rq[k];
-      if (UP) nonfinite |= ok && !isfinite(r);
-      else m_rain += ok ? r : 0.0;
+      if (UP) {
+        nonfinite |= ok && !isfinite(r);
+        if (ok && isfinite(r)) rmax = fmax(rmax, fabs(r));
+        continue;  // phase A sums per exit (below), not per cell
+      }
+      m_rain += ok ? r : 0.0;
       if constexpr (VK == VK_FF) {
         const float hi = (float)rq[k];
         s_v[i] = ok ? ff{hi, RAIN == RAIN_F64 ? (float)((double)rq[k] - (double)hi) : 0.0f} : ff{0.0f, 0.0f};
@@ -516,7 +530,7 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
       cyc |= on && !(pd[k] & PT_TERM);
       if (ok) dmax = max(dmax, L);
       ls[k] = NO_LEVEL;
-      if (ok && (mk[k] & 0xFFu)) {
+      if (!UP && ok && (mk[k] & 0xFFu)) {
         const uint32_t old = atomicAdd(&s_lev[L >> 1], 1u << (16 * (L & 1)));
         ls[k] = (uint32_t)L | (((old >> (16 * (L & 1))) & 0xFFFFu) << 16);
       }
@@ -533,6 +547,7 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
     dmax = wave_max(dmax);
     if (lane == 0) s_int[wave] = dmax;
     __syncthreads();
+    if constexpr (!UP) {
     const int D = max(max(s_int[0], s_int[1]), max(s_int[2], s_int[3]));
     // 5. Level offsets (exclusive prefix sums, 8 levels per thread).
     uint32_t hl[8], run = 0;
@@ -601,10 +616,17 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
       }
     }
     __syncthreads();
+    }  // phase C's levels
     if (UP) {
-      // 8a. Exits (a root that is not a sink) into consecutive slots of the
-      // list: one atomic per tile.  Slot order inside the wavefront: cell k
-      // of every lane before cell k + 1 of any lane.
+      // 8a. Phase A needs only each exit's upstream sum, not every cell's
+      // value: the cells whose root is an exit add their rain to it, in a
+      // 128-bit fixed point whose unit 2^Et follows from the tile's largest
+      // |rain| (at most 2048 terms each below 2^113 units), with integer
+      // atomics, so that the order of the additions changes no bit.  The
+      // exits take consecutive slots of the list (one atomic per tile; slot
+      // order inside the wavefront: cell k of every lane before cell k + 1
+      // of any lane), and the sums are rounded back to float-float /
+      // float64 once.
       const uint64_t lower = lane == 0 ? 0ull : (~0ull >> (64 - lane));
       uint32_t off[HK], wtot = 0;
 #pragma unroll
@@ -613,14 +635,72 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
         off[k] = wtot + (uint32_t)__popcll(m & lower);
         wtot += (uint32_t)__popcll(m);
       }
-      float lmf = 0.0f;
-      double lmd = 0.0;
+      rmax = wave_max_d(rmax);
+      if (lane == 0) {
+        s_int[4 + wave] = (int)wtot;
+        s_dbl[4 + wave] = rmax;
+      }
+      // Accumulators of the tile's exits (in the value and count area, which
+      // phase A does not use otherwise) and the map cell -> exit slot (in the
+      // histogram area).
+      unsigned long long* acc_lo = reinterpret_cast<unsigned long long*>(s_buf);
+      unsigned long long* acc_hi = acc_lo + D8T_MAX_EXITS;
+      uint32_t* acc_c = reinterpret_cast<uint32_t*>(acc_hi + D8T_MAX_EXITS);
+      uint16_t* s_map = reinterpret_cast<uint16_t*>(s_lev);
+      if (tid < D8T_MAX_EXITS) {
+        acc_lo[tid] = 0ull;
+        acc_hi[tid] = 0ull;
+        acc_c[tid] = 0u;
+      }
+      __syncthreads();
+      uint32_t lbase = 0;
+      for (int w = 0; w < wave; ++w) lbase += (uint32_t)s_int[4 + w];
 #pragma unroll
       for (int k = 0; k < HK; ++k) {
-        if (!((xmask >> k) & 1u)) continue;
         const int i = (wave + 4 * k) * HC + lane;
-        if constexpr (VK == VK_FF) lmf = fmaxf(lmf, fabsf(s_v[i].hi));
-        if constexpr (VK == VK_F64) lmd = fmax(lmd, fabs(s_v[i]));
+        s_map[i] = ((xmask >> k) & 1u) ? (uint16_t)(lbase + off[k]) : (uint16_t)0xFFFFu;
+      }
+      const double tmax = fmax(fmax(s_dbl[4], s_dbl[5]), fmax(s_dbl[6], s_dbl[7]));
+      int et = 0;
+      if (tmax > 0.0) (void)frexp(tmax, &et);  // tmax < 2^et
+      const int Et = et + 11 + 2 - 126;
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < HK; ++k) {
+        if (!((vmask >> k) & 1u) || !(pd[k] & PT_TERM)) continue;
+        const uint32_t slot = s_map[pd[k] & 0x7FFFu];
+        if (slot == 0xFFFFu) continue;  // drains to a sink inside the tile
+        if (VK != VK_NONE) {
+          const u128 x = (u128)fx_from(rq[k], Et);
+          if (x != 0) {
+            const unsigned long long xl = (unsigned long long)x, xh = (unsigned long long)(x >> 64);
+            const unsigned long long old = atomicAdd(&acc_lo[slot], xl);
+            const unsigned long long h = xh + ((old + xl < old) ? 1ull : 0ull);
+            if (h) atomicAdd(&acc_hi[slot], h);
+          }
+        }
+        if (CNT) atomicAdd(&acc_c[slot], 1u);
+      }
+      __syncthreads();
+      float lmf = 0.0f;
+      double lmd = 0.0;
+      ff vf[HK];
+      double vd[HK];
+#pragma unroll
+      for (int k = 0; k < HK; ++k) {
+        vf[k] = ff{0.0f, 0.0f};
+        vd[k] = 0.0;
+        if (!((xmask >> k) & 1u)) continue;
+        const uint32_t slot = lbase + off[k];
+        const i128 v = (i128)(((u128)acc_hi[slot] << 64) | (u128)acc_lo[slot]);
+        if constexpr (VK == VK_FF) {
+          vf[k] = fx_to_ff(v, Et);
+          lmf = fmaxf(lmf, fabsf(vf[k].hi));
+        }
+        if constexpr (VK == VK_F64) {
+          vd[k] = fx_to_double(v, Et);
+          lmd = fmax(lmd, fabs(vd[k]));
+        }
       }
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
@@ -628,7 +708,6 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
         lmd = fmax(lmd, __shfl_xor(lmd, o, 64));
       }
       if (lane == 0) {
-        s_int[4 + wave] = (int)wtot;
         s_flt[wave] = lmf;
         s_dbl[wave] = lmd;
       }
@@ -648,24 +727,21 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
         }
       }
       __syncthreads();
-      uint32_t base = (uint32_t)s_int[12];
-      for (int w = 0; w < wave; ++w) base += (uint32_t)s_int[4 + w];
+      const uint32_t base = (uint32_t)s_int[12] + lbase;
 #pragma unroll
       for (int k = 0; k < HK; ++k) {
         if (!((xmask >> k) & 1u)) continue;
-        const int i = (wave + 4 * k) * HC + lane;
         const int64_t g = (T.r0 + wave + 4 * k) * nc + T.c0 + lane;
         const uint32_t idx = base + off[k];
         if (idx < P.cap) {
           P.node_of[g] = idx;
           P.ex_cell[idx] = (uint32_t)g;
           if constexpr (VK == VK_FF) {
-            const ff v = s_v[i];
-            P.ex_hi[idx] = v.hi;
-            P.ex_lo[idx] = v.lo;
+            P.ex_hi[idx] = vf[k].hi;
+            P.ex_lo[idx] = vf[k].lo;
           }
-          if constexpr (VK == VK_F64) P.ex_d[idx] = s_v[i];
-          if (CNT) P.ex_cnt[0][idx] = (uint64_t)s_c[i];
+          if constexpr (VK == VK_F64) P.ex_d[idx] = vd[k];
+          if (CNT) P.ex_cnt[0][idx] = (uint64_t)acc_c[lbase + off[k]];
         }
       }
     } else {
