@@ -20,21 +20,25 @@
 //   2. pointer jumping over those receivers: each cell's root -- the sink or
 //      exit where its in-tile path ends -- and its depth, the number of
 //      in-tile edges to the root, in about log2(depth) rounds;
-//   3. a counting sort of the cells with donors inside the tile by depth;
-//   4. the levels of depth, deepest first, on one wavefront.  A cell's
-//      donors inside the tile lie exactly one level deeper, so each cell of
-//      the level reads its finished donors at once (the LDS serves one
-//      wavefront's accesses in order: no barrier between levels) and adds
-//      them in neighbour order: a fixed order, so results repeat bit for
-//      bit.
-// Counts live in LDS as 16 bits in phase A (local counts, at most 2048) and
-// 32 bits in phase C (at most the grid's cell count, below 2^31), so that
-// four workgroups fit on a compute unit.
+//   3. phase A (up) needs only each exit's upstream sum: every cell whose
+//      root is an exit adds its rain to the exit's accumulator, a 128-bit
+//      fixed point in LDS (unit from the tile's largest |rain|; integer
+//      atomics, so the order of the additions changes no bit);
+//   4. phase C (down) needs every cell's value: a counting sort of the cells
+//      with donors inside the tile by depth, then the levels of depth,
+//      deepest first, on one wavefront.  A cell's donors inside the tile lie
+//      exactly one level deeper, so each cell of the level reads its
+//      finished donors at once (the LDS serves one wavefront's accesses in
+//      order: no barrier between levels) and adds them in neighbour order:
+//      a fixed order, so results repeat bit for bit.
+// Phase C's counts live in LDS as 32 bits (at most the grid's cell count,
+// below 2^31), so that four workgroups fit on a compute unit; phase A holds
+// no per-cell values at all.
 // Global loads that depend on nothing else (codes, rain, the exit indices of
 // the halo) are issued together at the start of a tile, and the halo's
 // forest totals while the tile's own work runs.
-// Phase A (up) stores the local sums of the exits in the exit list and, for
-// every cell receiving water over the tile's edge (inlet), its root.  Phase C
+// Phase A stores the local sums of the exits in the exit list and, for every
+// cell receiving water over the tile's edge (inlet), its root.  Phase C
 // (down) starts the inlets from their out-of-tile donors' forest totals;
 // its values are final and go out with the tile's mass-balance partial.
 //
@@ -267,11 +271,11 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
   constexpr int NCODE = (HR + 2) * HW;
   constexpr int NCU = (NCODE + HT - 1) / HT;  // code loads per thread
   constexpr int VB = VK == VK_NONE ? 0 : (HN + 2) * 8;  // one more slot (zero), 16-byte multiple
-  // Counts in LDS: phase A holds local counts (at most the tile's 2048
-  // cells: 16 bits), phase C final counts (at most the grid's cell count,
-  // below 2^31: 32 bits).  With the level histogram over the donor masks in
-  // phase C, either phase's LDS stays within a quarter of a compute unit's.
-  using CT = typename std::conditional<UP, uint16_t, uint32_t>::type;
+  // Phase C's counts in LDS: at most the grid's cell count, below 2^31 (32
+  // bits); with the level histogram over the donor masks its LDS stays
+  // within a quarter of a compute unit's.  (Phase A keeps no per-cell
+  // values.)
+  using CT = uint32_t;
   constexpr int CB = CNT ? (HN + 8) * (int)sizeof(CT) : 0;  // one more slot (zero), 16-byte multiple
   constexpr int HB = (UP ? 0 : NHALO * ((VK == VK_NONE ? 0 : 8) + (CNT ? 4 : 0)));
   constexpr int MB = HN * 2 > HB ? HN * 2 : HB;
