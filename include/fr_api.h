@@ -407,7 +407,10 @@ int fr_set_autotune_cache(const char* path);
  * fr_set_accumulate_path -- process-wide choice of the accumulation path of
  * fr_accumulate and fr_accumulate_adjoint, for tests and diagnostics:
  * FR_PATH_AUTO (the default: row sweeps and exit forest for single
- * receivers -- the tile forest when their exit list overflows --, the row
+ * receivers -- the tile forest when a sample of the codes predicts flow in
+ * every direction (more than 1.5x an eighth of the cells draining sideways
+ * or to the next row, on grids of 2^18 cells and more) or their exit list
+ * overflows --, the row
  * sweep or the wavefront sweep for MFD, the peeling engine when a sweep
  * gives up), FR_PATH_SWEEP (wavefront sweep, then the engine),
  * FR_PATH_ENGINE (the peeling engine alone) or FR_PATH_TILES (the tile
@@ -429,7 +432,8 @@ int fr_set_accumulate_path(int path);
  *   FR_SERVED_ROWS       row sweeps and exit forest (D8 / D4, Section 2.1)
  *   FR_SERVED_TILES      tile forest: 32 x 64-cell tiles solved in LDS, joined
  *                        by the exit forest (D8 / D4 with flow in every
- *                        direction, when the row sweeps' exit list overflowed)
+ *                        direction: predicted by the code sample, or the
+ *                        row sweeps' exit list overflowed)
  *   FR_SERVED_ROW_SWEEP  MFD row sweep
  *   FR_SERVED_SWEEP      wavefront sweep
  *   FR_SERVED_ENGINE     peeling engine

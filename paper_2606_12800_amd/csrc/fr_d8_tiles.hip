@@ -826,11 +826,12 @@ __global__ __launch_bounds__(256) void k_d8_probe(D8Params P) {
   if (threadIdx.x == 0 && s_cnt) atomicAdd(&P.ctl->probe_cnt, s_cnt);
 }
 
-// Predicted exits above 1.5 x capacity: mark the list overflowed.
-__global__ void k_d8_probe_decide(D8Params P, uint64_t sampled) {
+// Predicted exits above the limit: mark the list overflowed, so that the
+// row sweeps return at once and the tile forest serves the call.
+__global__ void k_d8_probe_decide(D8Params P, uint64_t sampled, double limit) {
   if (threadIdx.x != 0) return;
   const double est = (double)P.ctl->probe_cnt * ((double)(P.nrows * P.ncols) / (double)sampled);
-  if (est > 1.5 * (double)P.cap) *P.n_exits = P.cap + 1u;
+  if (est > limit) *P.n_exits = P.cap + 1u;
 }
 
 // Mass-balance partials of the tiles, first stage: each workgroup sums a
@@ -934,13 +935,13 @@ size_t d8t_mass_words(int64_t nrows, int64_t ncols) {
   return (size_t)(2 * (nt + (nt + D8T_MASS_RUN - 1) / D8T_MASS_RUN));
 }
 
-hipError_t launch_d8_probe(const D8Params& P, hipStream_t s) {
+hipError_t launch_d8_probe(const D8Params& P, double limit, hipStream_t s) {
   const int64_t nsr = P.nrows > PROBE_STRIDE / 2 ? (P.nrows - PROBE_STRIDE / 2 + PROBE_STRIDE - 1) / PROBE_STRIDE : 1;
   const int64_t total = nsr * P.ncols;
   int64_t b = (total + 255) / 256;
   if (b > 1024) b = 1024;
   hipLaunchKernelGGL(k_d8_probe, dim3((unsigned)(b < 1 ? 1 : b)), dim3(256), 0, s, P);
-  hipLaunchKernelGGL(k_d8_probe_decide, dim3(1), dim3(64), 0, s, P, (uint64_t)(total > 0 ? total : 1));
+  hipLaunchKernelGGL(k_d8_probe_decide, dim3(1), dim3(64), 0, s, P, (uint64_t)(total > 0 ? total : 1), limit);
   return hipGetLastError();
 }
 

@@ -174,7 +174,7 @@ hipError_t launch_d8t(bool up, ValKind vk, bool cnt, const D8Params& P, hipStrea
 // sweeps' exit list, the list is marked overflowed at once (its count set
 // above capacity), so that the row sweeps return at once and the tile
 // forest serves the call.
-hipError_t launch_d8_probe(const D8Params& P, hipStream_t s);
+hipError_t launch_d8_probe(const D8Params& P, double limit, hipStream_t s);
 // Sums the tiles' mass partials into out[0..1] when the gate is open.
 hipError_t launch_d8t_mass(const double* part, int64_t ntiles, double* out, CallCtl* C, hipStream_t s);
 
