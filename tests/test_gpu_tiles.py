@@ -1,8 +1,9 @@
 """GPU parity of the tile-forest path (single receivers, flow in every
 direction): 32 x 64-cell tiles solved in LDS and joined by the exit forest.
 It serves D8 / D4 calls whose cells drain to the previous row too rarely for
-the row sweeps (their exit list overflows, on grids above 2^22 cells), and
-any call under the "tiles" path choice.  The solution is the same unique one
+the row sweeps (predicted from a sample of the codes on grids of 2^18 cells
+and more, or when their exit list overflows), and any call under the
+"tiles" path choice.  The solution is the same unique one
 (Section 2.2), so the bars are those of the other single-receiver paths:
 counts bit-exact, float32 water within 1e-6 and float64 water within 1e-10
 relative per cell of the float64 oracle, mass balance (Section 4) within
@@ -132,6 +133,25 @@ def test_overflow_takes_the_tile_forest():
     rain_h = synth.rain(58, nr, nc)
     q, cnt, m = _route(code, dev(rain_h), "d8", torch.float32, path="auto")
     assert fr.served_by() == "tiles"
+    qref, cref = oracle.accumulate_single(code, rain_h, oracle.order(z))
+    assert np.array_equal(host(cnt), cref)
+    assert relmax(host(q), qref) <= 1e-6
+    s, t = host(m).tolist()
+    assert abs(s - t) <= 1e-6 * t
+
+
+@pytest.mark.parametrize("nr,nc,want", [(1024, 1536, "tiles"), (400, 500, "rows")])
+def test_filled_grids_below_the_list_limit(nr, nc, want):
+    """Under the automatic choice, on depression-filled DEMs below 2^22 cells
+    (where the row sweeps' list holds every cell): from 2^18 cells on, the
+    code sample predicts flow in every direction and the tile forest
+    serves the call; smaller grids stay on the row sweeps.  Both against
+    the oracle."""
+    z = oracle.fill_depressions(synth.dem(59, nr, nc, tilt=0.0), 8, True)
+    code = oracle.receivers(z)
+    rain_h = synth.rain(59, nr, nc)
+    q, cnt, m = _route(code, dev(rain_h), "d8", torch.float32, path="auto")
+    assert fr.served_by() == want
     qref, cref = oracle.accumulate_single(code, rain_h, oracle.order(z))
     assert np.array_equal(host(cnt), cref)
     assert relmax(host(q), qref) <= 1e-6
