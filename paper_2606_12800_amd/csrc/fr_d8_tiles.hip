@@ -31,12 +31,17 @@
 //      finished donors at once (the LDS serves one wavefront's accesses in
 //      order: no barrier between levels) and adds them in neighbour order:
 //      a fixed order, so results repeat bit for bit.
+// Steps 1 and 2 run once: phase A leaves every cell a 32-bit word (its
+// depth, its in-tile and out-of-tile donor masks, a sink flag) in the
+// output buffer (q, or the low half of each 64-bit value or count), and
+// phase C reads the word back instead of the codes, then overwrites it with
+// the cell's result; phase C fetches only the forest totals of the halo
+// cells that drain into the tile.
 // Phase C's counts live in LDS as 32 bits (at most the grid's cell count,
 // below 2^31), so that four workgroups fit on a compute unit; phase A holds
 // no per-cell values at all.
-// Global loads that depend on nothing else (codes, rain, the exit indices of
-// the halo) are issued together at the start of a tile, and the halo's
-// forest totals while the tile's own work runs.
+// Global loads that depend on nothing else (codes or words, rain, the exit
+// indices of the halo) are issued together at the start of a tile.
 // Phase A stores the local sums of the exits in the exit list and, for every
 // cell receiving water over the tile's edge (inlet), its root.  Phase C
 // (down) starts the inlets from their out-of-tile donors' forest totals;
@@ -145,6 +150,19 @@ __device__ __forceinline__ double wave_max_d(double x) {
 
 // A tile's exits lie on its perimeter.
 constexpr int D8T_MAX_EXITS = 2 * HC + 2 * (HR - 2);
+
+// Between the two phases each cell's structure travels in the output buffer
+// (32-bit words: q as float32, or the low half of a float64 / count slot),
+// which phase C then overwrites with the cell's result: its depth in bits
+// 0-11 (CW_NOLEVEL when its path ends on a cycle), its donor mask (in-tile
+// donors | out-of-tile donors << 8) in bits 12-27, bit 28 when it is a sink.
+constexpr uint32_t CW_NOLEVEL = 0xFFFu;
+template <int VK>
+__device__ __forceinline__ uint32_t* cw_at(const D8Params& P, int64_t g) {
+  if (VK == VK_FF) return reinterpret_cast<uint32_t*>(P.q32) + g;
+  if (VK == VK_F64) return reinterpret_cast<uint32_t*>(P.q64) + 2 * g;
+  return reinterpret_cast<uint32_t*>(P.cnt) + 2 * g;
+}
 
 // Halo positions (the ring of cells around the tile): top row, bottom row,
 // then the left and right columns.
@@ -294,6 +312,8 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
   __shared__ uint8_t s_code[NCODE];
   __shared__ int s_int[16];
   __shared__ int s_open[16];
+  constexpr int NEED_WORDS = (NHALO + 31) / 32;
+  __shared__ uint32_t s_need[NEED_WORDS];  // phase C: halo cells that drain into the tile
   __shared__ double s_dbl[8];
   __shared__ float s_flt[4];
   V* s_v = reinterpret_cast<V*>(s_buf);
@@ -339,17 +359,22 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
     // together: the codes with a one-cell halo (off the grid: sinks), the
     // rain of the own cells, and in phase C the exit index of each halo
     // cell (used only where the halo cell drains into the tile).
+    // Phase C reads, instead of the codes, the words phase A left for its
+    // own cells (depth, donor masks, sink).
     uint32_t cv[NCU];
+    if (UP) {
 #pragma unroll
-    for (int u = 0; u < NCU; ++u) {
-      const int e = tid + u * HT;
-      const int hr = e / HW, hc = e - (e / HW) * HW;
-      const int64_t r = T.r0 + hr - 1, c = T.c0 + hc - 1;
-      const bool in = e < NCODE && r >= 0 && r < nr && c >= 0 && c < nc;
-      cv[u] = in ? (uint32_t)P.code[r * nc + c] : (uint32_t)SINK;
+      for (int u = 0; u < NCU; ++u) {
+        const int e = tid + u * HT;
+        const int hr = e / HW, hc = e - (e / HW) * HW;
+        const int64_t r = T.r0 + hr - 1, c = T.c0 + hc - 1;
+        const bool in = e < NCODE && r >= 0 && r < nr && c >= 0 && c < nc;
+        cv[u] = in ? (uint32_t)P.code[r * nc + c] : (uint32_t)SINK;
+      }
     }
     uint32_t vmask = 0;  // bit k: own cell k lies on the grid
     RT rq[HK];
+    uint32_t cw[HK];
 #pragma unroll
     for (int k = 0; k < HK; ++k) {
       const int lr = wave + 4 * k;
@@ -359,6 +384,7 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
       if (RAIN == RAIN_F32) rq[k] = P.rain32[g];
       else if (RAIN == RAIN_F64) rq[k] = P.rain64[g];
       else rq[k] = (RT)1;
+      cw[k] = (!UP && ok) ? *cw_at<VK>(P, g) : 0u;
     }
     int hh_r = 0, hh_c = 0;
     uint32_t hnd = NONE;
@@ -367,13 +393,15 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
       const int64_t r = T.r0 + hh_r - 1, c = T.c0 + hh_c - 1;
       if (r >= 0 && r < nr && c >= 0 && c < nc) hnd = P.node_of[r * nc + c];
     }
-    for (int w = tid; w < HN / 2; w += HT) {
-      s_msk[w] = 0u;
-    }
-    if (tid < 16) s_open[tid] = 0;
+    if (UP) {
+      for (int w = tid; w < HN / 2; w += HT) s_msk[w] = 0u;
+      if (tid < 16) s_open[tid] = 0;
 #pragma unroll
-    for (int u = 0; u < NCU; ++u)
-      if (tid + u * HT < NCODE) s_code[tid + u * HT] = (uint8_t)cv[u];
+      for (int u = 0; u < NCU; ++u)
+        if (tid + u * HT < NCODE) s_code[tid + u * HT] = (uint8_t)cv[u];
+    } else if (tid < NEED_WORDS) {
+      s_need[tid] = 0u;
+    }
     // Sources: rain (unit rain: 1) and one cell each.
     double m_rain = 0.0, rmax = 0.0;
     bool nonfinite = false;
@@ -400,9 +428,42 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
     // 2. Own cells: receiver inside the tile or not; each cell marks itself
     // in its receiver's donor mask (bit n: the donor lies in direction n).
     // Halo cells that drain into the tile mark the out-of-tile bits.
+    // (Phase C takes all of this, and step 3's depths, from the words.)
     uint32_t pd[HK];  // receiver or root (| PT_TERM once it is a root), depth << 16
     uint32_t smask = 0, xmask = 0;  // bit k: own cell k is a sink / an exit
     bool bad = false;
+    uint32_t mk[HK];  // in-tile donors | out-of-tile donors << 8
+    V hv = TV<VK>::zero();
+    uint64_t hcnt = 0;
+    if constexpr (!UP) {
+#pragma unroll
+      for (int k = 0; k < HK; ++k) {
+        const int lr = wave + 4 * k;
+        const bool ok = (vmask >> k) & 1u;
+        const uint32_t L = cw[k] & 0xFFFu;
+        mk[k] = ok ? (cw[k] >> 12) & 0xFFFFu : 0u;
+        smask |= (ok && ((cw[k] >> 28) & 1u)) ? 1u << k : 0u;
+        pd[k] = !ok ? PT_TERM : (L == CW_NOLEVEL ? 0u : (PT_TERM | (L << 16)));
+        // The halo cells this cell takes water from.
+        for (uint32_t m = mk[k] >> 8; m; m &= m - 1) {
+          const int n = __builtin_ctz(m);
+          const int h = halo_id(lr + 1 + nb_dr(n), lane + 1 + nb_dc(n));
+          atomicOr(&s_need[h >> 5], 1u << (h & 31));
+        }
+      }
+      __syncthreads();
+      // Their forest totals, for the inlets.
+      if (tid < NHALO && ((s_need[tid >> 5] >> (tid & 31)) & 1u)) {
+        if (hnd < n_ex) {
+          if constexpr (VK == VK_FF) hv = ff{P.tot_hi[hnd], P.tot_lo[hnd]};
+          if constexpr (VK == VK_F64) hv = P.tot_d[hnd];
+          if (CNT) hcnt = P.ex_cnt[0][hnd];
+        } else {
+          set_status(P.status, FR_ERR_BADCODE);  // inconsistent bookkeeping: never follow it
+        }
+      }
+    }
+    if constexpr (UP) {
 #pragma unroll
     for (int k = 0; k < HK; ++k) {
       const int lr = wave + 4 * k;
@@ -431,8 +492,6 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
       pd[k] = inside ? ((uint32_t)rcv | (1u << 16)) : ((uint32_t)i | PT_TERM);
       s_x[i] = pd[k];
     }
-    V hv = TV<VK>::zero();
-    uint64_t hcnt = 0;
     if (tid < NHALO) {
       const uint32_t cd = s_code[hh_r * HW + hh_c];
       if (cd <= 7u) {
@@ -440,27 +499,17 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
         if (tr >= 0 && tr < T.h && tc >= 0 && tc < T.w) {
           const int rcv = tr * HC + tc;
           atomicOr(&s_msk[rcv >> 1], (1u << (8 + 7 - cd)) << (16 * (rcv & 1)));
-          if (!UP) {
-            // Its forest total, loaded while the tile's own work goes on.
-            if (hnd < n_ex) {
-              if constexpr (VK == VK_FF) hv = ff{P.tot_hi[hnd], P.tot_lo[hnd]};
-              if constexpr (VK == VK_F64) hv = P.tot_d[hnd];
-              if (CNT) hcnt = P.ex_cnt[0][hnd];
-            } else {
-              set_status(P.status, FR_ERR_BADCODE);  // inconsistent bookkeeping: never follow it
-            }
-          }
         }
       }
     }
-    if (UP && bad) set_status(P.status, FR_ERR_BADCODE);
+    if (bad) set_status(P.status, FR_ERR_BADCODE);
     __syncthreads();
-    uint32_t mk[HK];  // in-tile donors | out-of-tile donors << 8
 #pragma unroll
     for (int k = 0; k < HK; ++k) {
       const int i = (wave + 4 * k) * HC + lane;
       mk[k] = (vmask >> k) & 1u ? (s_msk[i >> 1] >> (16 * (i & 1))) & 0xFFFFu : 0u;
     }
+    }  // phase A's step 2
     if (!UP) {
       // Phase C: the halo's forest totals into LDS over the masks (every
       // thread has read its own), then the inlets add their out-of-tile
@@ -494,9 +543,11 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
       }
       __syncthreads();
       for (int w = tid; w < HN / 2; w += HT) s_lev[w] = 0u;
+      __syncthreads();  // cleared before any wave counts into it (step 4)
     }
     // 3. Pointer jumping: after round j every pointer spans 2^(j+1) edges or
     // ends at a root; a path inside the tile has fewer than HN edges.
+    if constexpr (UP)
     for (int j = 0; j <= 12; ++j) {
       uint32_t np[HK];
       bool open = false;
@@ -537,6 +588,12 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
       if (!UP && ok && (mk[k] & 0xFFu)) {
         const uint32_t old = atomicAdd(&s_lev[L >> 1], 1u << (16 * (L & 1)));
         ls[k] = (uint32_t)L | (((old >> (16 * (L & 1))) & 0xFFFFu) << 16);
+      }
+      if (UP && on) {
+        // The cell's word for phase C.
+        const uint32_t lw = (pd[k] & PT_TERM) ? (uint32_t)L : CW_NOLEVEL;
+        *cw_at<VK>(P, (T.r0 + wave + 4 * k) * nc + T.c0 + lane) =
+            lw | (mk[k] << 12) | (((smask >> k) & 1u) << 28);
       }
       if (UP && on && (mk[k] >> 8)) {
         uint32_t rt = NONE;
