@@ -167,7 +167,9 @@ int fr_receivers(const float* z, int64_t nrows, int64_t ncols, int rule, uint8_t
  * Enqueues its kernels and returns without synchronising (see Streams); the
  * outputs are complete when the stream has passed the call.  For FR_F32 and
  * FR_F64 the outputs are the same, bit for bit, on every run with the same
- * inputs.
+ * inputs.  q_out, counts_out and mass_out must not overlap z, code, rain,
+ * the workspace or one another (no in-place routing: the solvers read the
+ * inputs after they have written outputs): FR_ERR_ARG otherwise.
  */
 int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t ncols, int rule,
                   double mfd_p, const void* rain, int rain_dtype, int q_dtype, void* q_out,

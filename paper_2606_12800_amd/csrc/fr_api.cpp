@@ -171,6 +171,13 @@ struct Counters {
 
 bool valid_rule(int rule) { return rule == FR_D8 || rule == FR_D4 || rule == FR_MFD; }
 
+// True when the byte ranges [a, a + na) and [b, b + nb) share a byte.
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b || na == 0 || nb == 0) return false;
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + nb && y < x + na;
+}
+
 int cu_count() {
   static int cache[64];
   int dev = 0;
@@ -631,6 +638,22 @@ int fr_accumulate(const float* z, const uint8_t* code, int64_t nrows, int64_t nc
   if (q_dtype == FR_NONE && !counts_out) return FR_ERR_ARG;
   if (ncols > kMaxCells / nrows) return FR_ERR_TOOLARGE;
   if (!code || (rule == FR_MFD && !z)) return FR_ERR_ARG;
+  {
+    // No output may share memory with an input, the workspace or another
+    // output: the solvers read inputs after writing outputs (the tile forest
+    // keeps per-cell structure in q or counts between its two passes).
+    const size_t n = (size_t)(nrows * ncols);
+    const void* in[4] = {z, code, rain, ws};
+    const size_t in_b[4] = {4 * n, n, rain_dtype == FR_F64 ? 8 * n : 4 * n, ws_bytes};
+    const void* out[3] = {q_out, counts_out, mass_out};
+    const size_t out_b[3] = {q_dtype == FR_F64 ? 8 * n : 4 * n, 8 * n, 16};
+    for (int o = 0; o < 3; ++o) {
+      for (int i = 0; i < 4; ++i)
+        if (overlaps(out[o], out_b[o], in[i], in_b[i])) return FR_ERR_ARG;
+      for (int o2 = o + 1; o2 < 3; ++o2)
+        if (overlaps(out[o], out_b[o], out[o2], out_b[o2])) return FR_ERR_ARG;
+    }
+  }
   if (!ws || ws_bytes < fr_workspace_bytes(FR_FN_ACCUMULATE, nrows, ncols, rule, q_dtype)) return FR_ERR_WORKSPACE;
   char* base = aligned_base(ws);
   CallCtl* C = reinterpret_cast<CallCtl*>(base);

@@ -16,8 +16,10 @@ __device__ __forceinline__ int64_t blk_col(const D8Params& P, int64_t c) { retur
 // pending buffers cleared), and its parent -- the exit its water reaches
 // next (block iterations: only inside its block).  An exit list that
 // overflowed its capacity opens the engine's gate instead (block
-// iterations: an error).
-template <int VK, bool CNT, bool ITER>
+// iterations: an error).  For the work-queue forest (QUEUE) each exit also
+// counts itself among its parent's children (kf_children_of), starting
+// from the zero that the tile pass that listed the exits left there.
+template <int VK, bool CNT, bool ITER, bool QUEUE = false>
 __global__ __launch_bounds__(256) void k_d8_link(D8Params P) {
   const uint32_t n = *P.n_exits;
   if (n > P.cap) {  // uniform
@@ -37,7 +39,6 @@ __global__ __launch_bounds__(256) void k_d8_link(D8Params P) {
       P.ex_cnt[1][i] = 0;
       P.ex_cnt[2][i] = 0;
     }
-    P.anc[1][i] = 0;  // the work-queue forest counts children here
     const uint32_t ec = P.ex_cell[i];
     uint32_t a = NONE;
     if (ec == NONE) {  // a hole of a phase-A chunk: no water, no parent
@@ -78,6 +79,10 @@ __global__ __launch_bounds__(256) void k_d8_link(D8Params P) {
       set_status(P.status, FR_ERR_BADCODE);
     }
     P.anc[0][i] = a;
+    if (QUEUE && a < n) {
+      if (CNT) atomicAdd(reinterpret_cast<unsigned long long*>(&P.ex_cnt[0][a]), 1ull);
+      else atomicAdd(&P.anc[1][a], 1u);
+    }
   }
 }
 
@@ -162,9 +167,10 @@ __global__ __launch_bounds__(256) void k_d8_round(D8Params P, int j, int last) {
 // atomics).  Each exit waits for its children; once the last one has added
 // its total, the exit is final and enters the queue; whoever takes it adds
 // its total to its parent, once.  Sums stay 128-bit integers (the order of
-// the atomics changes no bit).  Children are counted in anc[1], the queue
-// holds exit + 1 (0: not yet written) in the second pending-additions
-// buffer (both cleared by the link step); the third pending buffer stays
+// the atomics changes no bit).  Children are counted by the link step
+// (kf_children_of), the queue holds exit + 1 (0: not yet written) in the
+// second pending-additions buffer (cleared by the link step); the third
+// pending buffer stays
 // zero for the totals.  Every access to the forest's shared words here is a
 // device-coherent atomic, so the XCDs' caches need no write-back or
 // invalidation; a finished exit's reads of its sums depend on the queue
@@ -174,7 +180,14 @@ __global__ __launch_bounds__(256) void k_d8_round(D8Params P, int j, int last) {
 constexpr int KF_HEAD = 8, KF_TAIL = 9;          // slots of P.flags
 constexpr uint64_t KF_STALL_TICKS = 5000000ull;  // 50 ms of the 100 MHz clock
 
-__device__ __forceinline__ uint32_t* kf_children(const D8Params& P) { return P.anc[1]; }
+// An exit's count of children not yet final.  With counts it shares the
+// 64-bit word of the exit's count sum (count << 32 | children; counts stay
+// below 2^31), so that one atomic both adds a child's count and counts the
+// child off; without counts it lives in anc[1].
+template <bool CNT>
+__device__ __forceinline__ uint32_t kf_children_of(const D8Params& P, uint32_t i) {
+  return CNT ? (uint32_t)P.ex_cnt[0][i] : P.anc[1][i];
+}
 template <int VK>
 __device__ __forceinline__ uint32_t* kf_queue(const D8Params& P) {
   return VK != VK_NONE ? reinterpret_cast<uint32_t*>(P.ex_fx[1]) : reinterpret_cast<uint32_t*>(P.ex_cnt[1]);
@@ -208,29 +221,17 @@ __device__ __forceinline__ void kf_push_many(const D8Params& P, uint32_t* q, uin
   }
 }
 
-// Children per exit.
-__global__ __launch_bounds__(256) void k_kf_count(D8Params P) {
-  const uint32_t n = *P.n_exits;
-  if (n > P.cap) return;  // uniform
-  uint32_t* ch = kf_children(P);
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint32_t a = P.anc[0][i];
-    if (a < n) atomicAdd(&ch[a], 1u);  // the link step leaves no other parent than NONE
-  }
-}
-
 // The leaves (holes included) into the queue: each workgroup scans a chunk
 // of KF_LEAF_CHUNK exits and reserves its slots with one atomic (the queue's
 // tail is one word: atomics on it serialise).
 constexpr uint32_t KF_LEAF_PER_THREAD = 16;
 constexpr uint32_t KF_LEAF_CHUNK = 256u * KF_LEAF_PER_THREAD;
 
-template <int VK>
+template <int VK, bool CNT>
 __global__ __launch_bounds__(256) void k_kf_leaves(D8Params P) {
   const uint32_t n = *P.n_exits;
   if (n > P.cap || n == 0u) return;  // uniform
   if (blockIdx.x == 0 && threadIdx.x == 0) P.ctl->forest_final = 2;  // pending buffer 2 stays zero
-  const uint32_t* ch = kf_children(P);
   uint32_t* q = kf_queue<VK>(P);
   __shared__ uint32_t s_cnt[4], s_base;
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(256) void k_kf_leaves(D8Params P) {
 #pragma unroll
     for (uint32_t j = 0; j < KF_LEAF_PER_THREAD; ++j) {
       const uint32_t i = c0 + 256u * j + threadIdx.x;
-      if (i < n && ch[i] == 0u) {
+      if (i < n && kf_children_of<CNT>(P, i) == 0u) {
         leaf |= 1u << j;
         ++mine;
       }
@@ -296,7 +297,6 @@ __global__ __launch_bounds__(256) void k_kf_run(D8Params P) {
   constexpr int K = KF_PER_LANE;
   const uint32_t n = *P.n_exits;
   if (n > P.cap || n == 0u) return;  // uniform
-  uint32_t* ch = kf_children(P);
   uint32_t* q = kf_queue<VK>(P);
   uint32_t* head = reinterpret_cast<uint32_t*>(&P.flags[KF_HEAD]);
   const uint32_t* tail = reinterpret_cast<const uint32_t*>(&P.flags[KF_TAIL]);
@@ -344,9 +344,9 @@ __global__ __launch_bounds__(256) void k_kf_run(D8Params P) {
         c[k] = 0ull;
         if (par[k] != NONE) {
           if (VK != VK_NONE) x[k] = kf_load_fx(&P.ex_fx[0][e[k]]);
-          if (CNT)
+          if (CNT)  // the exit's count (its children are all final: the low word is 0)
             c[k] = __hip_atomic_load(reinterpret_cast<unsigned long long*>(&P.ex_cnt[0][e[k]]), __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
+                                     __HIP_MEMORY_SCOPE_AGENT) >> 32;
         }
       }
       if (VK != VK_NONE) {
@@ -368,23 +368,23 @@ __global__ __launch_bounds__(256) void k_kf_run(D8Params P) {
           }
         }
       }
-      if (CNT) {
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-          if (par[k] != NONE && c[k] != 0ull)
-            atomicAdd(reinterpret_cast<unsigned long long*>(&P.ex_cnt[0][par[k]]), c[k]);
-      }
       // The last child makes the parent final: the additions above have
       // completed (every access to the forest here is a device-coherent
-      // atomic, so no cache needs writing back) before the counts go down,
-      // and a parent is queued only after its count has reached zero.
+      // atomic, so no cache needs writing back) before the children go
+      // down, and a parent is queued only after its children have reached
+      // zero.  With counts, one atomic adds the count and counts the child
+      // off (count << 32, minus one).
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       uint32_t pmask = 0;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (par[k] != NONE) {
-          const uint32_t left =
-              __hip_atomic_fetch_add(&ch[par[k]], 0xFFFFFFFFu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          uint32_t left;
+          if (CNT)
+            left = (uint32_t)__hip_atomic_fetch_add(reinterpret_cast<unsigned long long*>(&P.ex_cnt[0][par[k]]),
+                                                    (c[k] << 32) - 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          else
+            left = __hip_atomic_fetch_add(&P.anc[1][par[k]], 0xFFFFFFFFu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (left == 1u) pmask |= 1u << k;
         }
       }
@@ -412,15 +412,16 @@ __global__ __launch_bounds__(256) void k_kf_run(D8Params P) {
 
 // The totals -- sums plus the last round's pending additions -- back from
 // fixed point into float-float or float64, where phase C reads them (the
-// pointer buffers' memory, free again); counts into sum buffer 0.
-template <int VK, bool CNT>
+// pointer buffers' memory, free again); counts into sum buffer 0 (the work
+// queue's count words shifted down past their children).
+template <int VK, bool CNT, bool QUEUE = false>
 __global__ __launch_bounds__(256) void k_d8_totals(D8Params P) {
   const uint32_t n = *P.n_exits;
   if (n > P.cap) return;  // uniform
   const int f = P.ctl->forest_final;
   const int E = VK != VK_NONE ? fx_exponent<VK>(P, n) : 0;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    if (CNT) P.ex_cnt[0][i] += P.ex_cnt[f][i];
+    if (CNT) P.ex_cnt[0][i] = (QUEUE ? P.ex_cnt[0][i] >> 32 : P.ex_cnt[0][i]) + P.ex_cnt[f][i];
     if (VK == VK_NONE) continue;
     const i128 v = (i128)(P.ex_fx[0][i] + P.ex_fx[f][i]);
     if (VK == VK_FF) {
@@ -506,11 +507,10 @@ unsigned kf_grid() {
 template <int VK, bool CNT>
 hipError_t forest_queue_t(const D8Params& P, hipStream_t s) {
   const dim3 g(forest_grid(P.cap)), b(256);
-  hipLaunchKernelGGL((k_d8_link<VK, CNT, false>), g, b, 0, s, P);
-  hipLaunchKernelGGL(k_kf_count, g, b, 0, s, P);
-  hipLaunchKernelGGL((k_kf_leaves<VK>), g, b, 0, s, P);
+  hipLaunchKernelGGL((k_d8_link<VK, CNT, false, true>), g, b, 0, s, P);
+  hipLaunchKernelGGL((k_kf_leaves<VK, CNT>), g, b, 0, s, P);
   hipLaunchKernelGGL((k_kf_run<VK, CNT>), dim3(kf_grid<VK, CNT>()), b, 0, s, P);
-  hipLaunchKernelGGL((k_d8_totals<VK, CNT>), g, b, 0, s, P);
+  hipLaunchKernelGGL((k_d8_totals<VK, CNT, true>), g, b, 0, s, P);
   return hipGetLastError();
 }
 

@@ -797,12 +797,14 @@ __global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
         if (idx < P.cap) {
           P.node_of[g] = idx;
           P.ex_cell[idx] = (uint32_t)g;
+          if (!CNT) P.anc[1][idx] = 0u;  // the exit forest's child count (the link step adds)
           if constexpr (VK == VK_FF) {
             P.ex_hi[idx] = vf[k].hi;
             P.ex_lo[idx] = vf[k].lo;
           }
           if constexpr (VK == VK_F64) P.ex_d[idx] = vd[k];
-          if (CNT) P.ex_cnt[0][idx] = (uint64_t)acc_c[lbase + off[k]];
+          // With counts, the count sits above the exit forest's child count.
+          if (CNT) P.ex_cnt[0][idx] = (uint64_t)acc_c[lbase + off[k]] << 32;
         }
       }
     } else {

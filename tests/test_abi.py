@@ -91,8 +91,14 @@ def test_receivers_validation(lib):
     assert lib.fr_receivers(FAKE, 1 << 16, 1 << 16, fr.D8, FAKE, NULL, NULL) == fr.ERR_TOOLARGE
 
 
-def _acc(lib, z=FAKE, code=FAKE, nr=8, nc=8, rule=fr.D8, p=1.1, rain=NULL, rdt=fr.F32, qdt=fr.F32,
-         q=FAKE, cnt=NULL, mass=NULL, ws=FAKE, wsb=1 << 40):
+# Distinct fake buffers (an 8 x 8 grid's largest array is 512 bytes); the
+# workspace's 2^40 bytes lie above all of them.
+Z, CODE, RAIN, Q, CNT, MASS, WS = (ctypes.c_void_p(a) for a in
+                                   (0x10000, 0x20000, 0x30000, 0x40000, 0x50000, 0x60000, 1 << 44))
+
+
+def _acc(lib, z=Z, code=CODE, nr=8, nc=8, rule=fr.D8, p=1.1, rain=NULL, rdt=fr.F32, qdt=fr.F32,
+         q=Q, cnt=NULL, mass=NULL, ws=WS, wsb=1 << 40):
     return lib.fr_accumulate(z, code, nr, nc, rule, p, rain, rdt, qdt, q, cnt, mass, NULL, ws, wsb, NULL)
 
 
@@ -116,6 +122,17 @@ def test_accumulate_validation(lib):
     assert _acc(lib, wsb=need - 1) == fr.ERR_WORKSPACE
     assert _acc(lib, nr=1 << 16, nc=1 << 16) == fr.ERR_TOOLARGE
     assert _acc(lib, nr=0, q=NULL, code=NULL, ws=NULL) == fr.OK  # empty grid: no-op
+    # Outputs overlapping an input, the workspace or one another.
+    assert _acc(lib, rain=Q) == fr.ERR_ARG                                    # in place over rain
+    assert _acc(lib, rain=ctypes.c_void_p(0x40000 - 255)) == fr.ERR_ARG       # rain's last byte under q
+    assert _acc(lib, q=CODE) == fr.ERR_ARG
+    assert _acc(lib, q=Z, rule=fr.MFD) == fr.ERR_ARG
+    assert _acc(lib, cnt=ctypes.c_void_p(0x40000 + 128)) == fr.ERR_ARG        # counts inside q
+    assert _acc(lib, mass=ctypes.c_void_p(0x40000 + 252)) == fr.ERR_ARG       # mass over q's last word
+    assert _acc(lib, q=ctypes.c_void_p((1 << 44) + 4096)) == fr.ERR_ARG       # q inside the workspace
+    # Adjacent buffers are fine: validation goes on to the next check.
+    assert _acc(lib, rain=ctypes.c_void_p(0x40000 - 256), ws=NULL) == fr.ERR_WORKSPACE
+    assert _acc(lib, cnt=ctypes.c_void_p(0x40000 + 256), ws=NULL) == fr.ERR_WORKSPACE
 
 
 def test_adjoint_validation(lib):
