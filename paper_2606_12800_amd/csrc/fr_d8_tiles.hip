@@ -279,8 +279,12 @@ struct RainReg {
   using T = typename std::conditional<RAIN == RAIN_F64, double, float>::type;
 };
 
+// Waves per SIMD the register budget is cut for: phase A holds no per-cell
+// values, so six of its waves fit (five with float64 rain, whose registers
+// would spill), and its 22.6 KB of LDS allows that many workgroups; phase C
+// is held to four by its LDS.
 template <bool UP, int VK, bool CNT, int RAIN>
-__global__ __launch_bounds__(HT, 4) void k_d8t(D8Params P, int ntiles) {
+__global__ __launch_bounds__(HT, UP ? (RAIN == RAIN_F64 ? 5 : 6) : 4) void k_d8t(D8Params P, int ntiles) {
   if (__hip_atomic_load(&P.ctl->d8_tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;  // uniform
   const uint32_t n_ex = *P.n_exits;
   if (!UP && n_ex > P.cap) return;  // uniform: the engine takes over
