@@ -9,9 +9,10 @@
 // direction, in LDS, so that only the cells whose receiver lies in another
 // tile are exits -- at most the tile's perimeter, 188 of its 2048 cells.
 // Like the paper's per-process solves (Section 2.4, Section 3.3), the tiles
-// are independent blocks; the exits then feed the same fixed-point forest
-// as the row sweeps (link, pointer-doubling rounds, totals), which joins
-// them, and a second pass over every tile adds its donors' totals.
+// are independent blocks; the exits then feed a fixed-point exit forest
+// (fr_d8_forest.hip: the row sweeps' link and totals, with a work queue in
+// place of their pointer-doubling rounds), which joins them, and a second
+// pass over every tile adds its donors' totals.
 //
 // Inside a tile (one workgroup of 256 threads, 8 cells each):
 //   1. the codes with a one-cell halo into LDS; each cell's receiver inside
