@@ -12,8 +12,16 @@ namespace {
 __device__ __forceinline__ int64_t blk_row(const D8Params& P, int64_t r) { return r / ((int64_t)P.th * P.bt_r); }
 __device__ __forceinline__ int64_t blk_col(const D8Params& P, int64_t c) { return c / ((int64_t)TW * P.bt_c); }
 
+// The work-queue forest's queue (below): one 32-bit word per exit in the
+// second pending-additions buffer, which that forest does not use otherwise.
+template <int VK>
+__device__ __forceinline__ uint32_t* kf_queue(const D8Params& P) {
+  return VK != VK_NONE ? reinterpret_cast<uint32_t*>(P.ex_fx[1]) : reinterpret_cast<uint32_t*>(P.ex_cnt[1]);
+}
+
 // Link: each exit's local sum into fixed point (sum buffer 0; both
-// pending buffers cleared), and its parent -- the exit its water reaches
+// pending buffers cleared -- for the work-queue forest only its queue
+// word), and its parent -- the exit its water reaches
 // next (block iterations: only inside its block).  An exit list that
 // overflowed its capacity opens the engine's gate instead (block
 // iterations: an error).  For the work-queue forest (QUEUE) each exit also
@@ -31,13 +39,17 @@ __global__ __launch_bounds__(256) void k_d8_link(D8Params P) {
   }
   const int E = VK != VK_NONE ? fx_exponent<VK>(P, n) : 0;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    if (VK != VK_NONE) {
-      P.ex_fx[1][i] = 0;
-      P.ex_fx[2][i] = 0;
-    }
-    if (CNT) {
-      P.ex_cnt[1][i] = 0;
-      P.ex_cnt[2][i] = 0;
+    if (QUEUE) {
+      kf_queue<VK>(P)[i] = 0u;
+    } else {
+      if (VK != VK_NONE) {
+        P.ex_fx[1][i] = 0;
+        P.ex_fx[2][i] = 0;
+      }
+      if (CNT) {
+        P.ex_cnt[1][i] = 0;
+        P.ex_cnt[2][i] = 0;
+      }
     }
     const uint32_t ec = P.ex_cell[i];
     uint32_t a = NONE;
@@ -168,10 +180,9 @@ __global__ __launch_bounds__(256) void k_d8_round(D8Params P, int j, int last) {
 // its total, the exit is final and enters the queue; whoever takes it adds
 // its total to its parent, once.  Sums stay 128-bit integers (the order of
 // the atomics changes no bit).  Children are counted by the link step
-// (kf_children_of), the queue holds exit + 1 (0: not yet written) in the
-// second pending-additions buffer (cleared by the link step); the third
-// pending buffer stays
-// zero for the totals.  Every access to the forest's shared words here is a
+// (kf_children_of), the queue holds exit + 1 (0: not yet written)
+// (kf_queue, cleared by the link step), and no addition is left pending
+// for the totals.  Every access to the forest's shared words here is a
 // device-coherent atomic, so the XCDs' caches need no write-back or
 // invalidation; a finished exit's reads of its sums depend on the queue
 // word that named it.  Every wait ends: a wavefront that sees the queue's
@@ -187,10 +198,6 @@ constexpr uint64_t KF_STALL_TICKS = 5000000ull;  // 50 ms of the 100 MHz clock
 template <bool CNT>
 __device__ __forceinline__ uint32_t kf_children_of(const D8Params& P, uint32_t i) {
   return CNT ? (uint32_t)P.ex_cnt[0][i] : P.anc[1][i];
-}
-template <int VK>
-__device__ __forceinline__ uint32_t* kf_queue(const D8Params& P) {
-  return VK != VK_NONE ? reinterpret_cast<uint32_t*>(P.ex_fx[1]) : reinterpret_cast<uint32_t*>(P.ex_cnt[1]);
 }
 
 // Appends up to KF_PER_LANE items per lane (bit k of `mask`: par[k]) with
@@ -231,7 +238,6 @@ template <int VK, bool CNT>
 __global__ __launch_bounds__(256) void k_kf_leaves(D8Params P) {
   const uint32_t n = *P.n_exits;
   if (n > P.cap || n == 0u) return;  // uniform
-  if (blockIdx.x == 0 && threadIdx.x == 0) P.ctl->forest_final = 2;  // pending buffer 2 stays zero
   uint32_t* q = kf_queue<VK>(P);
   __shared__ uint32_t s_cnt[4], s_base;
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -412,18 +418,19 @@ __global__ __launch_bounds__(256) void k_kf_run(D8Params P) {
 
 // The totals -- sums plus the last round's pending additions -- back from
 // fixed point into float-float or float64, where phase C reads them (the
-// pointer buffers' memory, free again); counts into sum buffer 0 (the work
-// queue's count words shifted down past their children).
+// pointer buffers' memory, free again); counts into sum buffer 0.  The
+// work-queue forest leaves no pending additions, and its count words are
+// shifted down past their children.
 template <int VK, bool CNT, bool QUEUE = false>
 __global__ __launch_bounds__(256) void k_d8_totals(D8Params P) {
   const uint32_t n = *P.n_exits;
   if (n > P.cap) return;  // uniform
-  const int f = P.ctl->forest_final;
+  const int f = QUEUE ? 0 : P.ctl->forest_final;
   const int E = VK != VK_NONE ? fx_exponent<VK>(P, n) : 0;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    if (CNT) P.ex_cnt[0][i] = (QUEUE ? P.ex_cnt[0][i] >> 32 : P.ex_cnt[0][i]) + P.ex_cnt[f][i];
+    if (CNT) P.ex_cnt[0][i] = QUEUE ? P.ex_cnt[0][i] >> 32 : P.ex_cnt[0][i] + P.ex_cnt[f][i];
     if (VK == VK_NONE) continue;
-    const i128 v = (i128)(P.ex_fx[0][i] + P.ex_fx[f][i]);
+    const i128 v = (i128)(QUEUE ? P.ex_fx[0][i] : P.ex_fx[0][i] + P.ex_fx[f][i]);
     if (VK == VK_FF) {
       const ff t = fx_to_ff(v, E);
       P.tot_hi[i] = t.hi;
