@@ -288,6 +288,11 @@ using i128 = __int128;
 
 __device__ __forceinline__ int ceil_log2_p1(uint32_t n) { return n == 0 ? 0 : 32 - __clz((int)n); }
 
+// The tile path's exit totals: one 16-byte record per exit (the total's
+// bits -- float-float hi | lo << 32, or float64 -- then the count) in the
+// third fixed-point buffer, which the work-queue forest leaves unused.
+__device__ __forceinline__ unsigned __int128* tile_total_rec(const D8Params& P, uint32_t i) { return P.ex_fx[2] + i; }
+
 template <int VK>
 __device__ __forceinline__ int fx_exponent(const D8Params& P, uint32_t n) {
   int e = 0;

@@ -460,9 +460,16 @@ __global__ __launch_bounds__(HT, UP ? (RAIN == RAIN_F64 ? 5 : 6) : 4) void k_d8t
       // Their forest totals, for the inlets.
       if (tid < NHALO && ((s_need[tid >> 5] >> (tid & 31)) & 1u)) {
         if (hnd < n_ex) {
-          if constexpr (VK == VK_FF) hv = ff{P.tot_hi[hnd], P.tot_lo[hnd]};
-          if constexpr (VK == VK_F64) hv = P.tot_d[hnd];
-          if (CNT) hcnt = P.ex_cnt[0][hnd];
+          if constexpr (VK != VK_NONE) {
+            // The exit's total and count, one 16-byte record.
+            const ulonglong2 rec = *reinterpret_cast<const ulonglong2*>(tile_total_rec(P, hnd));
+            if constexpr (VK == VK_FF)
+              hv = ff{__uint_as_float((uint32_t)rec.x), __uint_as_float((uint32_t)(rec.x >> 32))};
+            if constexpr (VK == VK_F64) hv = __longlong_as_double((long long)rec.x);
+            if (CNT) hcnt = rec.y;
+          } else {
+            hcnt = P.ex_cnt[0][hnd];
+          }
         } else {
           set_status(P.status, FR_ERR_BADCODE);  // inconsistent bookkeeping: never follow it
         }
