@@ -332,29 +332,30 @@ __global__ __launch_bounds__(256) void k_kf_run(D8Params P) {
         if (((todo >> k) & 1u) && base + 64u * k + lane < avail)
           e[k] = __hip_atomic_load(&q[base + 64u * k + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        par[k] = NONE;
-        if (e[k] != 0u) {
-          todo &= ~(1u << k);
-          e[k] -= 1u;
-          const uint32_t a = P.anc[0][e[k]];
-          par[k] = a < n ? a : NONE;
-        }
-      }
+      // The arrived exits' parents, sums and counts, loaded together (none
+      // of them depends on another; a root's sums are loaded and unused).
+      uint32_t got = 0;
       u128 x[K];
       unsigned long long c[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
+        par[k] = NONE;
         x[k] = 0;
         c[k] = 0ull;
-        if (par[k] != NONE) {
+        if (e[k] != 0u) {
+          got |= 1u << k;
+          e[k] -= 1u;
+          par[k] = P.anc[0][e[k]];
           if (VK != VK_NONE) x[k] = kf_load_fx(&P.ex_fx[0][e[k]]);
           if (CNT)  // the exit's count (its children are all final: the low word is 0)
             c[k] = __hip_atomic_load(reinterpret_cast<unsigned long long*>(&P.ex_cnt[0][e[k]]), __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_AGENT) >> 32;
         }
       }
+      todo &= ~got;
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (par[k] >= n) par[k] = NONE;
       if (VK != VK_NONE) {
         // Exact 128-bit additions from two 64-bit ones: the low word's carry
         // reaches the high word once.
