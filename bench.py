@@ -49,7 +49,7 @@ MEASURED_TRAFFIC = {
     # The tile phase of the filled route: both tile kernels and the exit
     # forest's work queue (link with the children's counts, leaves, queue,
     # totals).
-    ("d8_filled", 43360, 43360): {"d8_tiles": (9.4609e10, "profiles/d8_43360_filled_tile_forest.md")},
+    ("d8_filled", 43360, 43360): {"d8_tiles": (9.3017e10, "profiles/d8_43360_filled_tile_forest.md")},
     ("mfd", 16384, 16384): {"row_sweep": (5.3063e9, "profiles/mfd_16384_row_sweep.md")},
     ("adjoint", 4096, 4096): {"sweep": (6.987e8, "profiles/sweep_and_batch_hbm_traffic.md")},
     ("batched", 512): {"batch": (2.472e10, "profiles/sweep_and_batch_hbm_traffic.md")},

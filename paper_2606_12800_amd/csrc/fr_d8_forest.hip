@@ -12,6 +12,24 @@ namespace {
 __device__ __forceinline__ int64_t blk_row(const D8Params& P, int64_t r) { return r / ((int64_t)P.th * P.bt_r); }
 __device__ __forceinline__ int64_t blk_col(const D8Params& P, int64_t c) { return c / ((int64_t)TW * P.bt_c); }
 
+// The work-queue forest's sums (below) are held split, v = hi * 2^56 + lo
+// with 0 <= lo < 2^56 for every term added, so that the low word never
+// carries: an exit receives its own term and at most 196 children's (one per
+// cell of the ring around its tile), below 2^64 together, and both words
+// take their additions with no returned value to wait for.  Its unit is 2^6
+// coarser than the doubling forest's (sums below 2^118 units), so that the
+// high words stay below 2^62 in magnitude.
+constexpr int KF_FX_HEAD = 6;
+constexpr unsigned long long KF_LO_MASK = (1ull << 56) - 1ull;
+__device__ __forceinline__ u128 kf_split(i128 v) {
+  const unsigned long long lo = (unsigned long long)(u128)v & KF_LO_MASK;
+  const unsigned long long hi = (unsigned long long)(long long)(v >> 56);
+  return (u128)lo | ((u128)hi << 64);
+}
+__device__ __forceinline__ i128 kf_join(u128 w) {
+  return (i128)(long long)(unsigned long long)(w >> 64) * ((i128)1 << 56) + (i128)(unsigned long long)w;
+}
+
 // The work-queue forest's queue (below): one 32-bit word per exit in the
 // second pending-additions buffer, which that forest does not use otherwise.
 template <int VK>
@@ -37,7 +55,7 @@ __global__ __launch_bounds__(256) void k_d8_link(D8Params P) {
     }
     return;
   }
-  const int E = VK != VK_NONE ? fx_exponent<VK>(P, n) : 0;
+  const int E = VK != VK_NONE ? fx_exponent<VK>(P, n) + (QUEUE ? KF_FX_HEAD : 0) : 0;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     if (QUEUE) {
       kf_queue<VK>(P)[i] = 0u;
@@ -59,8 +77,10 @@ __global__ __launch_bounds__(256) void k_d8_link(D8Params P) {
       P.anc[0][i] = NONE;
       continue;
     }
-    if (VK == VK_FF) P.ex_fx[0][i] = (u128)(fx_from(P.ex_hi[i], E) + fx_from(P.ex_lo[i], E));
-    if (VK == VK_F64) P.ex_fx[0][i] = (u128)fx_from(P.ex_d[i], E);
+    if (VK != VK_NONE) {
+      const i128 v = VK == VK_FF ? fx_from(P.ex_hi[i], E) + fx_from(P.ex_lo[i], E) : fx_from(P.ex_d[i], E);
+      P.ex_fx[0][i] = QUEUE ? kf_split(v) : (u128)v;
+    }
     const int64_t e = ec;
     const int cd = P.code[e];
     const int64_t x = e + (int64_t)nb_dr(cd) * P.ncols + nb_dc(cd);
@@ -323,7 +343,7 @@ __global__ __launch_bounds__(256) void k_kf_run(D8Params P) {
       // The lane's exits that have arrived are finished together, each step
       // issued for all of them before its results are waited for: the
       // queue words, the parents, the sums, the additions to the parents
-      // (low words with their carries first), then one wait, then the
+      // (both words at once: they never carry), then one wait, then the
       // count-downs.  The parents made final go into the queue together.
       uint32_t e[K], par[K];
 #pragma unroll
@@ -357,21 +377,18 @@ __global__ __launch_bounds__(256) void k_kf_run(D8Params P) {
       for (int k = 0; k < K; ++k)
         if (par[k] >= n) par[k] = NONE;
       if (VK != VK_NONE) {
-        // Exact 128-bit additions from two 64-bit ones: the low word's carry
-        // reaches the high word once.
-        unsigned long long old[K];
+        // The exit's total, split again, into its parent's two words: no
+        // carry, no returned value.
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          old[k] = 0ull;
-          if (par[k] != NONE && x[k] != 0)
-            old[k] = atomicAdd(reinterpret_cast<unsigned long long*>(&P.ex_fx[0][par[k]]), (unsigned long long)x[k]);
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          if (par[k] != NONE && x[k] != 0) {
-            const unsigned long long xl = (unsigned long long)x[k], xh = (unsigned long long)(x[k] >> 64);
-            const unsigned long long h = xh + ((old[k] + xl < old[k]) ? 1ull : 0ull);
-            if (h) atomicAdd(reinterpret_cast<unsigned long long*>(&P.ex_fx[0][par[k]]) + 1, h);
+          if (par[k] != NONE) {
+            const u128 w = kf_split(kf_join(x[k]));
+            unsigned long long* pw = reinterpret_cast<unsigned long long*>(&P.ex_fx[0][par[k]]);
+            if ((unsigned long long)w != 0ull)
+              __hip_atomic_fetch_add(pw, (unsigned long long)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((unsigned long long)(w >> 64) != 0ull)
+              __hip_atomic_fetch_add(pw + 1, (unsigned long long)(w >> 64), __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
           }
         }
       }
@@ -429,10 +446,10 @@ __global__ __launch_bounds__(256) void k_d8_totals(D8Params P) {
   const uint32_t n = *P.n_exits;
   if (n > P.cap) return;  // uniform
   const int f = QUEUE ? 0 : P.ctl->forest_final;
-  const int E = VK != VK_NONE ? fx_exponent<VK>(P, n) : 0;
+  const int E = VK != VK_NONE ? fx_exponent<VK>(P, n) + (QUEUE ? KF_FX_HEAD : 0) : 0;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     if (QUEUE && VK != VK_NONE) {
-      const i128 v = (i128)P.ex_fx[0][i];
+      const i128 v = kf_join(P.ex_fx[0][i]);
       uint64_t w0;
       if (VK == VK_FF) {
         const ff t = fx_to_ff(v, E);
