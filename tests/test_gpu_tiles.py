@@ -9,8 +9,10 @@ counts bit-exact, float32 water within 1e-6 and float64 water within 1e-10
 relative per cell of the float64 oracle, mass balance (Section 4) within
 1e-6 / 1e-11.  Terrains: the paper's workflow (an untilted fractal DEM,
 depression-filled), white noise (short paths, many pits), on grids of a few
-million cells with ragged tile tails in both directions; small and
-degenerate shapes run under the same path in the general parity tests.
+million cells with ragged tile tails in both directions, and hand-made
+codes where one exit gathers almost its whole ring (the most children an
+exit can have); small and degenerate shapes run under the same path in the
+general parity tests.
 """
 import numpy as np
 import pytest
@@ -208,3 +210,68 @@ def test_tiles_report_malformed_input():
     rain[1234, 567] = np.inf
     print("tiles: non-finite rain", flush=True)
     _expect_status(code, dev(rain), fr.ERR_NONFINITE)
+
+
+def _ring_funnel_codes():
+    """D8 codes on 3 x 3 tiles (96 x 192 cells) where one exit of the middle
+    tile gathers the whole middle tile and 195 exits of the ring around it:
+    X = (32, 64), the middle tile's top-left cell, drains to (31, 63) and up
+    column 63 to a sink at (0, 63); every other middle-tile cell drains
+    toward X; every ring cell except (31, 63) drains into the middle tile;
+    all other cells are sinks."""
+    S = 0xFF
+    UL, U, UR, L, R, DL, D = 0, 1, 2, 3, 4, 5, 6
+    code = np.full((96, 192), S, dtype=np.uint8)
+    r0, r1, c0, c1 = 32, 63, 64, 127  # the middle tile, inclusive
+    for r in range(r0, r1 + 1):
+        for c in range(c0, c1 + 1):
+            code[r, c] = UL if (r > r0 and c > c0) else (L if r == r0 else U)
+    code[r0, c0] = UL                    # X leaves its tile
+    code[1:32, 63] = U                   # X's receiver and the path to the sink
+    code[0, 63] = S
+    code[31, c0:c1 + 1] = D              # top ring
+    code[31, c1 + 1] = DL
+    code[64, c0:c1 + 1] = U              # bottom ring
+    code[64, c0 - 1] = UR
+    code[64, c1 + 1] = UL
+    code[r0:r1 + 1, c0 - 1] = R          # left ring
+    code[r0:r1 + 1, c1 + 1] = L          # right ring
+    return code
+
+
+def _donors_first(code):
+    """An order in which every cell follows all cells upstream of it: by
+    decreasing number of steps to the cell's sink."""
+    dr = np.array([-1, -1, -1, 0, 0, 1, 1, 1])
+    dc = np.array([-1, 0, 1, -1, 1, -1, 0, 1])
+    nr, nc = code.shape
+    steps = np.zeros(nr * nc, dtype=np.int64)
+    for i in range(nr * nc):
+        r, c, s = i // nc, i % nc, 0
+        while code[r, c] != 0xFF:
+            k = int(code[r, c])
+            r, c, s = r + dr[k], c + dc[k], s + 1
+        steps[i] = s
+    return np.argsort(-steps, kind="stable").astype(np.int64)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_exit_with_the_most_children(dtype):
+    """The exit forest's sums add each child's total into its parent's low
+    word without a carry, which holds while an exit has at most 196 children
+    (one per cell of the ring around its tile).  Here one exit has 195, and
+    the rain spans twenty binary orders of magnitude, so the low words of the
+    fixed-point sums are full: values within the usual bars of the oracle,
+    counts exact."""
+    code = _ring_funnel_codes()
+    order = _donors_first(code)
+    n = code.size
+    mant = synth.uniform(56, synth.STREAM_NOISE, n).astype(np.float64) + 0.5
+    expo = synth.integers(57, synth.STREAM_PICK, n, -10, 11).astype(np.float64)
+    rain_h = (mant * np.exp2(expo)).astype(np.float32).reshape(code.shape)
+    q, cnt, m = _route(code, dev(rain_h), "d8", dtype)
+    assert fr.served_by() == "tiles"
+    qref, cref = oracle.accumulate_single(code, rain_h, order)
+    assert cref[32, 64] == 32 * 64 + 195
+    assert np.array_equal(host(cnt), cref)
+    assert relmax(host(q), qref) <= (1e-6 if dtype == torch.float32 else 1e-10)
